@@ -1,0 +1,262 @@
+"""Oracle: classical (Ruge-Stueben) AMG setup, plain serial FP64.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import this package; the product path never
+does.  It shares no code with the HIP library.
+
+Follows the paper's review of AMG (Section 2): a C/F splitting driven by
+strength of connection, interpolation P_l, restriction R_l = P_l^T and the
+Galerkin product A_{l+1} = R_l A_l P_l, repeated until the coarsest level is
+small enough for a direct solve.  The paper leaves the AMG components to its
+host library; the readings used here are:
+
+* strength: j strongly influences i iff j != i, m_i = max_{k != i}(-a_ik) > 0
+  and -a_ij >= theta * m_i * (1 - 1e-12)   (theta = 0.25)
+* classical RS first pass only, ties broken by the smallest index, coarse
+  points numbered in increasing fine index
+* direct interpolation (Stueben), positive off-diagonals lumped into the
+  diagonal, empty rows for F-points without strong C-neighbours
+* Galerkin coarse operator on the *symbolic* product pattern (no dropping of
+  exact cancellations); values from the product R (A P)
+* stop at <= max_coarse points, when a level produces no C-point or no
+  reduction, or at max_levels levels
+
+Every floating-point row sum is accumulated sequentially in ascending column
+order (the order a reader would write by hand).
+"""
+
+from __future__ import annotations
+
+import heapq
+from dataclasses import dataclass, field
+from typing import List
+
+import numpy as np
+from scipy import sparse
+
+C_PT = 1
+F_PT = -1
+U_PT = 0
+
+STRENGTH_SLACK = 1e-12
+
+
+def _csr(A) -> sparse.csr_matrix:
+    A = sparse.csr_matrix(A)
+    A.sort_indices()
+    return A
+
+
+def row_ids(A: sparse.csr_matrix) -> np.ndarray:
+    return np.repeat(np.arange(A.shape[0]), np.diff(A.indptr))
+
+
+def seq_row_sum(indptr: np.ndarray, vals: np.ndarray) -> np.ndarray:
+    """Per-row sum of vals, added one entry at a time in storage order
+    (0 + v0 + v1 + ...).  Vectorised over rows, sequential within a row."""
+    n = len(indptr) - 1
+    lens = np.diff(indptr)
+    out = np.zeros(n, dtype=np.float64)
+    start = indptr[:-1]
+    for k in range(int(lens.max()) if n else 0):
+        m = lens > k
+        out[m] += vals[start[m] + k]
+    return out
+
+
+def strength(A: sparse.csr_matrix, theta: float = 0.25) -> sparse.csr_matrix:
+    """Strength matrix S (CSR pattern, sorted): row i lists S_i, the points
+    that strongly influence i (Section 2: strong influence decided by the
+    relative size of the entries of A)."""
+    A = _csr(A)
+    n = A.shape[0]
+    r = row_ids(A)
+    c = A.indices
+    off = c != r
+    m = np.full(n, -np.inf)
+    np.maximum.at(m, r[off], -A.data[off])
+    mr = m[r]
+    strong = off & (mr > 0) & (-A.data >= theta * mr * (1.0 - STRENGTH_SLACK))
+    S = sparse.csr_matrix((np.ones(int(strong.sum())), (r[strong], c[strong])), shape=(n, n))
+    S.sort_indices()
+    return S
+
+
+def rs_first_pass(S: sparse.csr_matrix) -> np.ndarray:
+    """Classical Ruge-Stueben first-pass C/F splitting.
+
+    lambda_i = |S^T_i| (how many points i strongly influences).  Repeatedly the
+    undecided point of largest lambda (smallest index on ties) becomes C; the
+    undecided points it strongly influences become F; every undecided point
+    that strongly influences a new F-point gains 1; every undecided point that
+    strongly influences the new C-point loses 1.  When the largest remaining
+    lambda is 0, each remaining point becomes F if it has a strong C-neighbour
+    and C otherwise.  Points with no strong connection in either direction are
+    F (they get an empty interpolation row).
+
+    Returns int8 array: +1 = C, -1 = F."""
+    n = S.shape[0]
+    S = _csr(S)
+    ST = _csr(S.T)
+    Sp, Sj = S.indptr, S.indices
+    Tp, Tj = ST.indptr, ST.indices
+    lam = np.diff(Tp).astype(np.int64)
+    state = np.zeros(n, dtype=np.int8)
+    nS = np.diff(Sp)
+    isolated = (nS == 0) & (lam == 0)
+    state[isolated] = F_PT
+    heap = [(-int(lam[i]), i) for i in range(n) if state[i] == U_PT]
+    heapq.heapify(heap)
+    lam_l = lam.tolist()
+    st = state.tolist()
+    while heap:
+        nl, i = heapq.heappop(heap)
+        if st[i] != U_PT or -nl != lam_l[i]:
+            continue
+        if lam_l[i] == 0:
+            rest = [u for u in range(n) if st[u] == U_PT]
+            for u in rest:
+                has_c = any(st[k] == C_PT for k in Sj[Sp[u]:Sp[u + 1]])
+                st[u] = F_PT if has_c else C_PT
+            break
+        st[i] = C_PT
+        new_f = [j for j in Tj[Tp[i]:Tp[i + 1]] if st[j] == U_PT]
+        for j in new_f:
+            st[j] = F_PT
+        for j in new_f:
+            for k in Sj[Sp[j]:Sp[j + 1]]:
+                if st[k] == U_PT:
+                    lam_l[k] += 1
+                    heapq.heappush(heap, (-lam_l[k], k))
+        for j in Sj[Sp[i]:Sp[i + 1]]:
+            if st[j] == U_PT:
+                lam_l[j] -= 1
+                heapq.heappush(heap, (-lam_l[j], j))
+    return np.asarray(st, dtype=np.int8)
+
+
+def direct_interpolation(A: sparse.csr_matrix, S: sparse.csr_matrix, cf: np.ndarray) -> sparse.csr_matrix:
+    """Direct interpolation P (N_l x N_{l+1}), coarse ids in increasing fine index.
+
+    C-point i: injection, P[i, c(i)] = 1.
+    F-point i with interpolatory set P_i = C intersect S_i (non-empty):
+        w_ik = -alpha_i a_ik / at_ii,  k in P_i
+        alpha_i = (sum_{j != i} min(a_ij, 0)) / (sum_{k in P_i} a_ik)
+        at_ii   = a_ii + sum_{j != i} max(a_ij, 0)
+    F-point with empty P_i: empty row."""
+    A = _csr(A)
+    S = _csr(S)
+    n = A.shape[0]
+    is_c = cf == C_PT
+    cidx = np.cumsum(is_c) - 1
+    nc = int(is_c.sum())
+    r = row_ids(A)
+    off = A.indices != r
+    vals = A.data
+    neg = np.where(off, np.minimum(vals, 0.0), 0.0)
+    pos = np.where(off, np.maximum(vals, 0.0), 0.0)
+    neg_sum = seq_row_sum(A.indptr, neg)
+    pos_sum = seq_row_sum(A.indptr, pos)
+    diag = A.diagonal()
+    # membership of each A entry in the interpolatory set: strong and C
+    Sr = row_ids(S)
+    skey = Sr.astype(np.int64) * n + S.indices
+    akey = r.astype(np.int64) * n + A.indices
+    in_s = np.isin(akey, skey)
+    in_p = in_s & is_c[A.indices] & ~is_c[r]
+    den = seq_row_sum(A.indptr, np.where(in_p, vals, 0.0))
+    at = diag + pos_sum
+    rows, cols, ws = [], [], []
+    # C rows
+    ci = np.nonzero(is_c)[0]
+    rows.append(ci)
+    cols.append(cidx[ci])
+    ws.append(np.ones(ci.size))
+    # F rows
+    ent = np.nonzero(in_p)[0]
+    fi = r[ent]
+    alpha = neg_sum[fi] / den[fi]
+    w = -alpha * vals[ent] / at[fi]
+    rows.append(fi)
+    cols.append(cidx[A.indices[ent]])
+    ws.append(w)
+    rows = np.concatenate(rows)
+    cols = np.concatenate(cols)
+    ws = np.concatenate(ws)
+    P = sparse.csr_matrix((ws, (rows, cols)), shape=(n, nc))
+    P.sort_indices()
+    return P
+
+
+def symbolic_pattern(A: sparse.csr_matrix, P: sparse.csr_matrix) -> sparse.csr_matrix:
+    """Pattern of P^T A P without numerical cancellation: the product of the
+    0/1 patterns has strictly positive entries wherever a product term exists."""
+    Ab = A.copy()
+    Ab.data = np.ones_like(Ab.data)
+    Pb = P.copy()
+    Pb.data = np.ones_like(Pb.data)
+    G = _csr(Pb.T @ (Ab @ Pb))
+    return G
+
+
+def galerkin(A: sparse.csr_matrix, P: sparse.csr_matrix) -> sparse.csr_matrix:
+    """A_{l+1} = R (A P) with R = P^T, stored on the symbolic product pattern
+    (exact zeros kept as explicit entries)."""
+    A = _csr(A)
+    P = _csr(P)
+    R = _csr(P.T)
+    AP = A @ P
+    RAP = _csr(R @ AP)
+    G = symbolic_pattern(A, P)
+    nc = P.shape[1]
+    gkey = row_ids(G).astype(np.int64) * nc + G.indices
+    rkey = row_ids(RAP).astype(np.int64) * nc + RAP.indices
+    pos = np.searchsorted(gkey, rkey)
+    assert np.all(gkey[pos] == rkey), "value outside symbolic pattern"
+    vals = np.zeros(G.nnz)
+    vals[pos] = RAP.data
+    out = sparse.csr_matrix((vals, G.indices.copy(), G.indptr.copy()), shape=(nc, nc))
+    return out
+
+
+@dataclass
+class Hierarchy:
+    A: List[sparse.csr_matrix]
+    P: List[sparse.csr_matrix]
+    R: List[sparse.csr_matrix]
+    cf: List[np.ndarray]
+    S: List[sparse.csr_matrix] = field(default_factory=list)
+
+    @property
+    def L(self) -> int:
+        """Index of the coarsest level."""
+        return len(self.A) - 1
+
+    def l1_diag(self, l: int) -> np.ndarray:
+        """l1-Jacobi diagonal: d_i = sum_j |a_ij| over the full row of A_l."""
+        A = self.A[l]
+        return seq_row_sum(A.indptr, np.abs(A.data))
+
+    def coarse_dense(self) -> np.ndarray:
+        return self.A[-1].toarray()
+
+
+def setup(A0, theta: float = 0.25, max_coarse: int = 16, max_levels: int = 25) -> Hierarchy:
+    """Build the AMG hierarchy {A_l, P_l, R_l} (Section 2)."""
+    A = _csr(A0).astype(np.float64)
+    As, Ps, Rs, cfs, Ss = [A], [], [], [], []
+    while A.shape[0] > max_coarse and len(As) < max_levels:
+        S = strength(A, theta)
+        cf = rs_first_pass(S)
+        nc = int((cf == C_PT).sum())
+        if nc == 0 or nc == A.shape[0]:
+            break
+        P = direct_interpolation(A, S, cf)
+        Ac = galerkin(A, P)
+        Ss.append(S)
+        cfs.append(cf)
+        Ps.append(P)
+        Rs.append(_csr(P.T))
+        As.append(Ac)
+        A = Ac
+    return Hierarchy(A=As, P=Ps, R=Rs, cf=cfs, S=Ss)

@@ -1,0 +1,292 @@
+"""Seeded synthetic inputs for the AMG-DD solve phase.
+
+This module builds the *inputs* of the method only: structured-grid diffusion
+operators (cell-centred finite differences, homogeneous Dirichlet nodes
+eliminated), log-normal coefficient fields, block partitions into subdomains,
+right-hand sides and face lists.  It contains none of the multigrid arithmetic
+(no coarsening, interpolation, composite grids or cycles); both the oracle and
+the GPU path consume what it returns.
+
+The paper's workloads (Section 5) are finite-element discretisations of
+-div(K grad u) = f on regular meshes partitioned by METIS; these generators
+stand in for them with 5-point (2D) and 7-point (3D) stencils on block
+partitions.
+
+Conventions
+-----------
+* Grid points are numbered lexicographically with x fastest:
+  i = x + nx*y (+ nx*ny*z).  Arrays of grid values have numpy shape
+  (nz, ny, nx) / (ny, nx) so that C-order flattening gives that numbering.
+* Face coefficient of an interior face (i, j): harmonic mean
+  2 k_i k_j / (k_i + k_j).  Face coefficient of a boundary face of cell i: k_i.
+* A_ii = sum of the coefficients of the faces of i; A_ij = -c_f for the
+  interior face f = (i, j).  No h^-2 scaling.  With k == 1 this is the
+  standard 5/7-point Laplacian (diagonal 4/6, off-diagonals -1).
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+from scipy import ndimage, sparse
+
+__all__ = [
+    "Faces",
+    "Problem",
+    "grid_faces",
+    "face_coefficients",
+    "assemble",
+    "grf",
+    "block_partition",
+    "uniform_rhs",
+    "make_problem",
+    "config",
+    "batch_config",
+    "CONFIG_NAMES",
+]
+
+
+@dataclass
+class Faces:
+    """Face list of a structured grid.
+
+    inner_i, inner_j : int64 arrays, the two cells of each interior face (i < j)
+    bnd_i            : int64 array, the cell of each boundary face (a corner
+                       cell appears once per boundary side it touches)
+    """
+
+    inner_i: np.ndarray
+    inner_j: np.ndarray
+    bnd_i: np.ndarray
+
+    @property
+    def n_inner(self) -> int:
+        return int(self.inner_i.size)
+
+    @property
+    def n_faces(self) -> int:
+        return int(self.inner_i.size + self.bnd_i.size)
+
+
+def _np_shape(dims: Sequence[int]) -> Tuple[int, ...]:
+    # dims are given as (nx, ny[, nz]); numpy arrays use the reversed order
+    return tuple(int(d) for d in reversed(dims))
+
+
+def grid_faces(dims: Sequence[int]) -> Faces:
+    """Interior and boundary faces of an nx x ny (x nz) cell grid."""
+    shape = _np_shape(dims)
+    n = int(np.prod(shape))
+    idx = np.arange(n, dtype=np.int64).reshape(shape)
+    inner_i, inner_j, bnd = [], [], []
+    nd = len(shape)
+    # axis order: x (last numpy axis) first, then y, then z
+    for ax in range(nd - 1, -1, -1):
+        lo = [slice(None)] * nd
+        hi = [slice(None)] * nd
+        lo[ax] = slice(0, shape[ax] - 1)
+        hi[ax] = slice(1, shape[ax])
+        inner_i.append(idx[tuple(lo)].ravel())
+        inner_j.append(idx[tuple(hi)].ravel())
+        first = [slice(None)] * nd
+        last = [slice(None)] * nd
+        first[ax] = 0
+        last[ax] = shape[ax] - 1
+        bnd.append(idx[tuple(first)].ravel())
+        bnd.append(idx[tuple(last)].ravel())
+    return Faces(np.concatenate(inner_i), np.concatenate(inner_j), np.concatenate(bnd))
+
+
+def face_coefficients(k: np.ndarray, faces: Faces) -> np.ndarray:
+    """Face coefficients: harmonic mean of the two cells for interior faces,
+    the cell value for boundary faces.  Returned in face order
+    (interior faces first, then boundary faces)."""
+    kf = np.asarray(k, dtype=np.float64).ravel()
+    ki = kf[faces.inner_i]
+    kj = kf[faces.inner_j]
+    c_in = 2.0 * ki * kj / (ki + kj)
+    c_bd = kf[faces.bnd_i]
+    return np.concatenate([c_in, c_bd])
+
+
+def assemble(n: int, faces: Faces, c: np.ndarray) -> sparse.csr_matrix:
+    """CSR matrix of the diffusion operator for face coefficients c.
+
+    Rows have sorted column indices, int32 indices, float64 values.  The
+    diagonal accumulates face coefficients in face order."""
+    c = np.asarray(c, dtype=np.float64)
+    ni = faces.n_inner
+    c_in = c[:ni]
+    c_bd = c[ni:]
+    diag = np.zeros(n, dtype=np.float64)
+    np.add.at(diag, faces.inner_i, c_in)
+    np.add.at(diag, faces.inner_j, c_in)
+    np.add.at(diag, faces.bnd_i, c_bd)
+    rows = np.concatenate([np.arange(n), faces.inner_i, faces.inner_j])
+    cols = np.concatenate([np.arange(n), faces.inner_j, faces.inner_i])
+    vals = np.concatenate([diag, -c_in, -c_in])
+    A = sparse.coo_matrix((vals, (rows, cols)), shape=(n, n)).tocsr()
+    A.sum_duplicates()
+    A.sort_indices()
+    A.indices = A.indices.astype(np.int32)
+    A.indptr = A.indptr.astype(np.int32)
+    return A
+
+
+def grf(dims: Sequence[int], sigma: float, corr_len: float, seed: int) -> np.ndarray:
+    """Gaussian random field with squared-exponential covariance
+    exp(-r^2 / (2 l^2)), l = corr_len cells, periodic filtering, standardised
+    to zero mean and standard deviation sigma.  Returns numpy shape
+    (nz, ny, nx) / (ny, nx)."""
+    rng = np.random.default_rng(seed)
+    shape = _np_shape(dims)
+    w = rng.standard_normal(shape)
+    g = ndimage.gaussian_filter(w, sigma=corr_len / np.sqrt(2.0), mode="wrap", truncate=4.0)
+    g = (g - g.mean()) / g.std()
+    return sigma * g
+
+
+def block_partition(dims: Sequence[int], parts: Sequence[int]) -> np.ndarray:
+    """Subdomain id of every grid point for a block partition with parts[a]
+    blocks along axis a (x first).  Block coordinate along an axis of length n
+    with P blocks is floor(x * P / n); ids are lexicographic over block
+    coordinates, x fastest."""
+    dims = [int(d) for d in dims]
+    parts = [int(p) for p in parts]
+    assert len(dims) == len(parts)
+    coords = np.meshgrid(*[np.arange(d) for d in reversed(dims)], indexing="ij")
+    # coords[0] is the slowest axis (z or y), coords[-1] is x
+    bid = np.zeros(_np_shape(dims), dtype=np.int64)
+    stride = 1
+    for a in range(len(dims)):
+        x = coords[len(dims) - 1 - a]
+        bc = (x * parts[a]) // dims[a]
+        bid += bc * stride
+        stride *= parts[a]
+    return bid.ravel().astype(np.int32)
+
+
+def uniform_rhs(n: int, seed: int, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return rng.uniform(lo, hi, size=n)
+
+
+@dataclass
+class Problem:
+    """One linear system A u = b with its subdomain partition and solver
+    parameters.  `k` is the cell coefficient field (None for k == 1)."""
+
+    name: str
+    dims: Tuple[int, ...]
+    A: sparse.csr_matrix
+    b: np.ndarray
+    part: np.ndarray
+    nparts: int
+    eta: int
+    n_fac: int
+    faces: Faces
+    c: np.ndarray
+    k: Optional[np.ndarray] = None
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.A.shape[0])
+
+
+def make_problem(
+    dims: Sequence[int],
+    parts: Sequence[int],
+    eta: int = 1,
+    n_fac: int = 1,
+    k: Optional[np.ndarray] = None,
+    rhs_seed: int = 0,
+    rhs_range: Tuple[float, float] = (-1.0, 1.0),
+    name: str = "",
+) -> Problem:
+    dims = tuple(int(d) for d in dims)
+    n = int(np.prod(dims))
+    faces = grid_faces(dims)
+    kk = np.ones(_np_shape(dims)) if k is None else np.asarray(k, dtype=np.float64)
+    c = face_coefficients(kk, faces)
+    A = assemble(n, faces, c)
+    b = uniform_rhs(n, rhs_seed, *rhs_range)
+    part = block_partition(dims, parts)
+    return Problem(
+        name=name or "x".join(map(str, dims)),
+        dims=dims,
+        A=A,
+        b=b,
+        part=part,
+        nparts=int(np.prod(parts)),
+        eta=int(eta),
+        n_fac=int(n_fac),
+        faces=faces,
+        c=c,
+        k=None if k is None else kk,
+    )
+
+
+CONFIG_NAMES = ("cfg1", "cfg2", "cfg3", "cfg4", "cfg5")
+
+
+def config(name: str, scale: Optional[int] = None) -> Problem:
+    """The named single-problem workloads.
+
+    cfg1  2D 5-point Laplacian, 64^2, 2x2 subdomains, padding 1, 1 FAC cycle
+    cfg2  3D 7-point Laplacian, 128^3, 4^3 subdomains of 32^3, padding 1, 2 FAC cycles
+    cfg3  3D 7-point diffusion, 192^3, k = exp(GRF sigma 1, l = 8, seed 1),
+          8^3 subdomains of 24^3, padding 2, 2 FAC cycles
+    cfg4  3D 7-point diffusion, 96^3, k = exp(GRF sigma 0.5, l = 8, seed 2),
+          f ~ U[0,1] (seed 3), 3^3 subdomains of 32^3, padding 1, 2 FAC cycles;
+          extra['u_target'] ~ U[0,1] (seed 4)
+
+    `scale` replaces the grid side while keeping the subdomain count (reduced
+    instances for tests)."""
+    if name == "cfg1":
+        s = scale or 64
+        return make_problem((s, s), (2, 2), eta=1, n_fac=1, rhs_seed=0, name="cfg1")
+    if name == "cfg2":
+        s = scale or 128
+        return make_problem((s, s, s), (4, 4, 4), eta=1, n_fac=2, rhs_seed=0, name="cfg2")
+    if name == "cfg3":
+        s = scale or 192
+        dims = (s, s, s)
+        k = np.exp(grf(dims, 1.0, 8.0, seed=1))
+        return make_problem(dims, (8, 8, 8), eta=2, n_fac=2, k=k, rhs_seed=0, name="cfg3")
+    if name == "cfg4":
+        s = scale or 96
+        dims = (s, s, s)
+        k = np.exp(grf(dims, 0.5, 8.0, seed=2))
+        parts = (3, 3, 3) if s >= 24 else (2, 2, 2)
+        p = make_problem(dims, parts, eta=1, n_fac=2, k=k, rhs_seed=3, rhs_range=(0.0, 1.0), name="cfg4")
+        p.extra["u_target"] = uniform_rhs(p.n, 4, 0.0, 1.0)
+        return p
+    raise KeyError(name)
+
+
+def batch_config(n_problems: int = 256, seed0: int = 5000, side_range=(64, 512), parts_range=(2, 8),
+                 eta_range=(1, 3)) -> List[Problem]:
+    """Batched uneven workload: independent 2D 5-point diffusion problems.
+
+    Problem i draws from default_rng(seed0 + i): side s ~ U{lo..hi} (square
+    s x s grid), blocks Px, Py ~ U{2..8}, padding eta ~ U{1..3}; k = exp(GRF
+    sigma 1, l = 8) and b ~ U[-1, 1] from further seeds derived from the same
+    generator."""
+    probs = []
+    for i in range(n_problems):
+        rng = np.random.default_rng(seed0 + i)
+        s = int(rng.integers(side_range[0], side_range[1] + 1))
+        px = int(rng.integers(parts_range[0], parts_range[1] + 1))
+        py = int(rng.integers(parts_range[0], parts_range[1] + 1))
+        eta = int(rng.integers(eta_range[0], eta_range[1] + 1))
+        kseed = int(rng.integers(0, 2**31 - 1))
+        bseed = int(rng.integers(0, 2**31 - 1))
+        px = min(px, s)
+        py = min(py, s)
+        dims = (s, s)
+        k = np.exp(grf(dims, 1.0, 8.0, seed=kseed))
+        probs.append(make_problem(dims, (px, py), eta=eta, n_fac=2, k=k, rhs_seed=bseed, name=f"b{i}"))
+    return probs
