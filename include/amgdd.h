@@ -1,0 +1,219 @@
+/*
+ * amgdd.h -- C ABI of the MI355X AMG-DD solve-phase library.
+ *
+ * Method: Mitchell, Strzodka, Falgout, "Parallel Performance of Algebraic
+ * Multigrid Domain Decomposition (AMG-DD)".
+ *   - AMG hierarchy (Section 2): classical Ruge-Stueben first-pass coarsening,
+ *     direct interpolation, R = P^T, Galerkin A_{l+1} = R A P, down to a
+ *     small coarsest level solved directly.
+ *   - Composite grids (Section 3, Figure 1): per subdomain, padding eta_l
+ *     through the graph of A_l on every level, C-points carried down, the
+ *     coarsest level stored whole; ghost layer Dbar_l (Section 4.1).
+ *   - AlgFAC cycle (Algorithm 4, Section 4.4) on every composite grid.
+ *   - AMG-DD outer iteration (Algorithm 2): fine residual, restriction to all
+ *     levels, composite right-hand sides, local AlgFAC, correction patched on
+ *     each owned subdomain.
+ *   - AMG V(1,1) cycle (Algorithm 1) on the same hierarchy.
+ * The linear system is given by its fine-grid matrix alone, as the paper
+ * states the problem (Section 2), plus a partition into subdomains
+ * (Section 3) and the padding / number of AlgFAC cycles (Section 5.1).
+ *
+ * Relaxation is point l1-Jacobi: u <- u + (f - A u) / d, d_i = sum_j |a_ij|.
+ *
+ * Conventions for every entry point:
+ *   - Host arrays are borrowed for the duration of the call and copied.
+ *   - Device pointers (suffix _dev) are caller-owned HIP device memory on the
+ *     handle's device (for example torch tensor storage); they must stay valid
+ *     until the call returns.  All device work is enqueued on the handle's
+ *     stream; the solve calls synchronise that stream once per outer iteration
+ *     to read the residual norms, and return with the stream drained.
+ *   - Nothing aborts.  Every call returns a status; amgdd_last_error() gives a
+ *     thread-local message for the last non-OK status.
+ *   - A handle is used by one host thread at a time.
+ *   - Batched handles (amgdd_setup_composite_batch) see device vectors as the
+ *     concatenation of the problems' vectors in setup order.
+ */
+#ifndef AMGDD_H
+#define AMGDD_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct amgdd_ctx *amgdd_handle; /* opaque, owned by the library */
+
+typedef enum {
+  AMGDD_OK = 0,
+  AMGDD_EINVAL = 1,       /* malformed input; nothing was modified */
+  AMGDD_ENOMEM = 2,       /* host or device allocation failed */
+  AMGDD_EDEVICE = 3,      /* HIP error, or a device call on a host-only handle */
+  AMGDD_ENOCONV = 4,      /* maxit reached above rtol; x holds the last iterate */
+  AMGDD_EBREAKDOWN = 5,   /* non-finite residual norm */
+  AMGDD_EUNSUPPORTED = 6  /* valid input outside what this build supports */
+} amgdd_status;
+
+typedef enum { AMGDD_FP64 = 0, AMGDD_MIXED = 1 } amgdd_precision;
+
+typedef struct {
+  double theta;     /* strength threshold, default 0.25 */
+  int max_coarse;   /* stop coarsening at <= this many points, default 16 */
+  int max_levels;   /* default 25 */
+  int padding;      /* eta_l on every level below the coarsest, default 1 */
+  int n_fac;        /* AlgFAC cycles per AMG-DD iteration, default 2 */
+  int precision;    /* amgdd_precision, default AMGDD_FP64 */
+  int device;       /* HIP device ordinal; -1 = host-only handle (setup and
+                       introspection only, every solve returns EDEVICE) */
+  int use_graph;    /* 1 = replay each outer iteration as a HIP graph (default) */
+} amgdd_params;
+
+typedef struct {
+  int iters;            /* outer iterations (or V-cycles) performed */
+  double relres;        /* max over problems of ||r_k|| / ||r_0|| */
+  double rho_asym;      /* geometric-mean factor over the last <= 5 iterations */
+  double solve_s;       /* device time of the iterations (HIP events) */
+  double setup_s;       /* host setup time of the handle */
+} amgdd_info;
+
+typedef struct {
+  int n_problems;
+  int n_grids;              /* composite grids (subdomains) over all problems */
+  int max_levels;           /* deepest hierarchy over all problems */
+  long long fine_rows;      /* sum of N_0 */
+  long long global_nnz;     /* sum over problems and levels of nnz(A_l) */
+  long long composite_real_nnz; /* nnz of A_l rows at real points, all grids/levels */
+  long long composite_rows;     /* sum over grids and levels of |Dbar_l| */
+  long long composite_real_rows;/* sum over grids and levels of |D_l| */
+  long long composite_stored_nnz;/* device nnz of composite A, P, R (incl. padding) */
+  long long omissions;      /* interpolation entries dropped (Section 4.2) */
+  double composite_overhead;/* composite_real_nnz / global_nnz (Section 5.1) */
+  double setup_hierarchy_s; /* host time: strength, RS, interpolation, Galerkin */
+  double setup_composite_s; /* host time: composite sets, local operators */
+  double setup_pack_s;      /* host time: batched layouts */
+  double setup_upload_s;    /* device allocation and upload */
+  long long device_bytes;   /* device memory owned by the handle */
+} amgdd_stats;
+
+void amgdd_params_default(amgdd_params *prm);
+
+/*
+ * Build the AMG hierarchy and every subdomain's composite grid on the host,
+ * then upload the batched device layout (unless prm->device == -1).
+ *   n, rowptr[n+1], colind[nnz], val[nnz]: fine-grid matrix A_0, CSR, 0-based,
+ *       int32 indices, columns sorted and unique in each row, a positive
+ *       diagonal entry in every row.  The graph of A_0 must be symmetric.
+ *   part[n]: subdomain of every fine point, values in [0, nparts), every
+ *       subdomain non-empty (Omega_0^p of Section 3).
+ *   prm: NULL for defaults.  hip_stream: hipStream_t (NULL = default stream).
+ * Errors: EINVAL for malformed CSR / partition / parameters,
+ *         EUNSUPPORTED for n <= max_coarse or a coarsest level > 1024 points.
+ */
+amgdd_status amgdd_setup_composite(int n, const int *rowptr, const int *colind, const double *val,
+                                   const int *part, int nparts, const amgdd_params *prm,
+                                   void *hip_stream, amgdd_handle *out);
+
+/*
+ * Batched form: nprob independent problems with their own matrices,
+ * partitions and paddings, all composite grids of all problems in one
+ * batched layout.  Fields of prm[0] other than padding (theta, max_coarse,
+ * max_levels, n_fac, precision, device, use_graph) apply to the whole batch;
+ * padding is taken per problem from prm[i].
+ */
+amgdd_status amgdd_setup_composite_batch(int nprob, const int *n, const int *const *rowptr,
+                                         const int *const *colind, const double *const *val,
+                                         const int *const *part, const int *nparts,
+                                         const amgdd_params *prm, void *hip_stream,
+                                         amgdd_handle *out);
+
+/*
+ * AMG-DD iterations (Algorithm 2 with n_fac AlgFAC cycles, Algorithm 4) on
+ * A x = b.  b_dev, x_dev: device FP64 vectors of length sum of N_0; x is the
+ * initial guess on entry and the last iterate on return.  Stops when every
+ * problem has ||b - A x|| <= rtol ||b - A x_0|| or after maxit iterations;
+ * rtol <= 0 runs exactly maxit iterations and returns OK.  info may be NULL.
+ */
+amgdd_status amgdd_solve(amgdd_handle h, const double *b_dev, double *x_dev, double rtol, int maxit,
+                         amgdd_info *info);
+
+/* AMG V(1,1) cycles (Algorithm 1) on the same hierarchy, same conventions. */
+amgdd_status amgv_solve(amgdd_handle h, const double *b_dev, double *x_dev, double rtol, int maxit,
+                        amgdd_info *info);
+
+/*
+ * Adjoint solve A^T lambda = g with the same hierarchy and composite grids.
+ * Supported when every A_0 given at setup is symmetric (checked at setup):
+ * then A^T = A and the forward operators are the transposed ones.  Returns
+ * EUNSUPPORTED for a non-symmetric handle.  lambda_dev is in/out like x_dev.
+ */
+amgdd_status amgdd_solve_adjoint(amgdd_handle h, const double *g_dev, double *lambda_dev, double rtol,
+                                 int maxit, amgdd_info *info);
+
+/*
+ * Face gradient of a loss through A(c) u = f with A = sum_f c_f E_f:
+ *   interior face (i, j): dL/dc_f = -(lambda_i - lambda_j)(u_i - u_j)
+ *   boundary face (i, -1): dL/dc_f = -lambda_i u_i
+ * u_dev, lambda_dev: device FP64 of length sum N_0; face_i_dev, face_j_dev:
+ * device int32 of length nfaces (j = -1 marks a boundary face; indices into
+ * the concatenated vectors); dLdc_dev: device FP64 output of length nfaces.
+ */
+amgdd_status amgdd_face_gradient(amgdd_handle h, const double *u_dev, const double *lambda_dev,
+                                 const int *face_i_dev, const int *face_j_dev, int nfaces,
+                                 double *dLdc_dev);
+
+/* ---- introspection (host copies into caller-allocated arrays) ---------- */
+
+amgdd_status amgdd_get_stats(amgdd_handle h, amgdd_stats *st);
+
+/* Level count and per-level sizes of problem prob (arrays of length >= nlevels;
+ * pass NULL to query nlevels only). */
+amgdd_status amgdd_get_levels(amgdd_handle h, int prob, int *nlevels, int *n_per_level,
+                              long long *nnz_per_level);
+
+/* C/F splitting of level `level` < nlevels-1: +1 C, -1 F, length N_level. */
+amgdd_status amgdd_get_cf(amgdd_handle h, int prob, int level, signed char *cf);
+
+/* Global operator of problem prob: which = 0 A_l, 1 P_l.  Call with NULL
+ * arrays to get nrows/nnz, then again with rowptr[nrows+1], col[nnz], val[nnz]. */
+amgdd_status amgdd_get_operator(amgdd_handle h, int prob, int level, int which, int *nrows, int *nnz,
+                                int *rowptr, int *col, double *val);
+
+/* Composite grid of subdomain p of problem prob on `level`: n_real = |D_l|,
+ * n_bar = |Dbar_l|; gids (length n_bar, may be NULL) = global ids on that
+ * level, real points first in increasing id, then ghost points in increasing
+ * id; omissions = dropped interpolation entries for this grid and level. */
+amgdd_status amgdd_get_composite(amgdd_handle h, int prob, int p, int level, int *n_real, int *n_bar,
+                                 int *gids, int *omissions);
+
+/* Residual-norm history of problem prob from the last solve (length <= cap). */
+amgdd_status amgdd_get_history(amgdd_handle h, int prob, double *hist, int cap, int *len);
+
+/* Per-launch-site timing of the solve iteration (measurement only).
+ * Runs `reps` iterations of kind 0 (AMG-DD) or 1 (V-cycle) from the handle's
+ * internal state, launching kernel by kernel (no graph) with a HIP event pair
+ * around every launch on the handle's stream.  Sites are aggregated by
+ * (kernel name, level): launches = launches per iteration, ms = device time
+ * per iteration, bytes = algorithmic bytes per iteration (stored nonzeros,
+ * each vector entry touched once).  Fills up to cap entries of out, sets *n to
+ * the number of sites. */
+typedef struct {
+  char name[24];
+  int level;
+  int launches;
+  double ms;
+  double bytes;
+} amgdd_kernel_time;
+
+amgdd_status amgdd_profile(amgdd_handle h, int kind, int reps, amgdd_kernel_time *out, int cap, int *n);
+
+/* Change the stream used by later calls. */
+amgdd_status amgdd_set_stream(amgdd_handle h, void *hip_stream);
+
+const char *amgdd_last_error(void);
+
+/* Frees every device and host allocation of the handle; NULL is accepted. */
+void amgdd_destroy(amgdd_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AMGDD_H */

@@ -1,0 +1,311 @@
+"""ctypes binding of libamgdd.so (include/amgdd.h).
+
+Argument marshalling only: setup runs in the library's C++ host code and
+every solve step runs in its HIP kernels.  Device vectors are torch tensors
+on the handle's device; their storage is passed as raw pointers and the
+solve runs on torch's current stream.  The library must be built
+(python -m paper_1906_10575_amd.build); importing this module raises if it
+is not.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libamgdd.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, EBREAKDOWN, EUNSUPPORTED = range(7)
+FP64, MIXED = 0, 1
+STATUS_NAMES = ["OK", "EINVAL", "ENOMEM", "EDEVICE", "ENOCONV", "EBREAKDOWN", "EUNSUPPORTED"]
+
+
+class AmgddError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES[status] if 0 <= status < 7 else status}: {msg}")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [("theta", C.c_double), ("max_coarse", C.c_int), ("max_levels", C.c_int), ("padding", C.c_int),
+                ("n_fac", C.c_int), ("precision", C.c_int), ("device", C.c_int), ("use_graph", C.c_int)]
+
+
+class Info(C.Structure):
+    _fields_ = [("iters", C.c_int), ("relres", C.c_double), ("rho_asym", C.c_double), ("solve_s", C.c_double),
+                ("setup_s", C.c_double)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_problems", C.c_int), ("n_grids", C.c_int), ("max_levels", C.c_int),
+                ("fine_rows", C.c_longlong), ("global_nnz", C.c_longlong), ("composite_real_nnz", C.c_longlong),
+                ("composite_rows", C.c_longlong), ("composite_real_rows", C.c_longlong),
+                ("composite_stored_nnz", C.c_longlong), ("omissions", C.c_longlong),
+                ("composite_overhead", C.c_double), ("setup_hierarchy_s", C.c_double),
+                ("setup_composite_s", C.c_double), ("setup_pack_s", C.c_double), ("setup_upload_s", C.c_double),
+                ("device_bytes", C.c_longlong)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class KernelTime(C.Structure):
+    _fields_ = [("name", C.c_char * 24), ("level", C.c_int), ("launches", C.c_int), ("ms", C.c_double),
+                ("bytes", C.c_double)]
+
+
+_P = C.c_void_p
+_I = C.c_int
+_D = C.c_double
+_IP = C.POINTER(C.c_int)
+_DP = C.POINTER(C.c_double)
+_LLP = C.POINTER(C.c_longlong)
+_H = C.c_void_p
+
+# name -> (restype, argtypes); every function declared in include/amgdd.h
+SIGNATURES = {
+    "amgdd_params_default": (None, [C.POINTER(Params)]),
+    "amgdd_setup_composite": (_I, [_I, _IP, _IP, _DP, _IP, _I, C.POINTER(Params), _P, C.POINTER(_H)]),
+    "amgdd_setup_composite_batch": (_I, [_I, _IP, C.POINTER(_IP), C.POINTER(_IP), C.POINTER(_DP), C.POINTER(_IP),
+                                         _IP, C.POINTER(Params), _P, C.POINTER(_H)]),
+    "amgdd_solve": (_I, [_H, _P, _P, _D, _I, C.POINTER(Info)]),
+    "amgv_solve": (_I, [_H, _P, _P, _D, _I, C.POINTER(Info)]),
+    "amgdd_solve_adjoint": (_I, [_H, _P, _P, _D, _I, C.POINTER(Info)]),
+    "amgdd_face_gradient": (_I, [_H, _P, _P, _P, _P, _I, _P]),
+    "amgdd_get_stats": (_I, [_H, C.POINTER(Stats)]),
+    "amgdd_get_levels": (_I, [_H, _I, _IP, _IP, _LLP]),
+    "amgdd_get_cf": (_I, [_H, _I, _I, C.POINTER(C.c_byte)]),
+    "amgdd_get_operator": (_I, [_H, _I, _I, _I, _IP, _IP, _IP, _IP, _DP]),
+    "amgdd_get_composite": (_I, [_H, _I, _I, _I, _IP, _IP, _IP, _IP]),
+    "amgdd_get_history": (_I, [_H, _I, _DP, _I, _IP]),
+    "amgdd_profile": (_I, [_H, _I, _I, C.POINTER(KernelTime), _I, _IP]),
+    "amgdd_set_stream": (_I, [_H, _P]),
+    "amgdd_last_error": (C.c_char_p, []),
+    "amgdd_destroy": (None, [_H]),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libamgdd.so and declare every exported signature."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_1906_10575_amd.build`")
+    lib = C.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(st: int):
+    if st != OK:
+        raise AmgddError(st, load().amgdd_last_error().decode())
+
+
+def _iptr(a: np.ndarray):
+    return a.ctypes.data_as(_IP)
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(_DP)
+
+
+def default_params() -> Params:
+    p = Params()
+    load().amgdd_params_default(C.byref(p))
+    return p
+
+
+def _csr_arrays(A):
+    indptr = np.ascontiguousarray(A.indptr, dtype=np.int32)
+    indices = np.ascontiguousarray(A.indices, dtype=np.int32)
+    data = np.ascontiguousarray(A.data, dtype=np.float64)
+    return indptr, indices, data
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_ptr(t, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float64 tensor on the HIP device")
+    return C.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """Handle over one problem or a batch of independent problems.
+
+    A: scipy CSR matrix (or a list of them for a batch), part: int array(s) of
+    subdomain ids, nparts: int(s), padding: int(s).  device=-1 gives a
+    host-only handle (setup and introspection, no solve)."""
+
+    def __init__(self, A, part, nparts, padding=1, n_fac=2, precision="fp64", device=0, theta=0.25,
+                 max_coarse=16, max_levels=25, use_graph=True, stream=None):
+        lib = load()
+        batch = isinstance(A, (list, tuple))
+        As = list(A) if batch else [A]
+        parts = list(part) if batch else [part]
+        nps = list(nparts) if batch else [nparts]
+        pads = list(padding) if isinstance(padding, (list, tuple)) else [padding] * len(As)
+        prm = default_params()
+        prm.theta = theta
+        prm.max_coarse = max_coarse
+        prm.max_levels = max_levels
+        prm.n_fac = n_fac
+        prm.precision = MIXED if precision in ("mixed", MIXED) else FP64
+        prm.device = device
+        prm.use_graph = 1 if use_graph else 0
+        if stream is None and device >= 0:
+            torch = _torch()
+            stream = torch.cuda.current_stream(device).cuda_stream
+        self._keep = []
+        h = _H()
+        arrs = [_csr_arrays(a) for a in As]
+        pts = [np.ascontiguousarray(p, dtype=np.int32) for p in parts]
+        self.sizes = [int(a.shape[0]) for a in As]
+        self.offsets = np.concatenate([[0], np.cumsum(self.sizes)]).astype(np.int64)
+        if not batch:
+            prm.padding = pads[0]
+            st = lib.amgdd_setup_composite(self.sizes[0], _iptr(arrs[0][0]), _iptr(arrs[0][1]), _dptr(arrs[0][2]),
+                                           _iptr(pts[0]), int(nps[0]), C.byref(prm), C.c_void_p(stream), C.byref(h))
+        else:
+            n = len(As)
+            prms = (Params * n)()
+            for i in range(n):
+                prms[i] = prm
+                prms[i].padding = int(pads[i])
+            ns = np.array(self.sizes, dtype=np.int32)
+            rp = (_IP * n)(*[_iptr(a[0]) for a in arrs])
+            ci = (_IP * n)(*[_iptr(a[1]) for a in arrs])
+            va = (_DP * n)(*[_dptr(a[2]) for a in arrs])
+            pp = (_IP * n)(*[_iptr(p) for p in pts])
+            npa = np.array(nps, dtype=np.int32)
+            st = lib.amgdd_setup_composite_batch(n, _iptr(ns), rp, ci, va, pp, _iptr(npa), prms, C.c_void_p(stream),
+                                                 C.byref(h))
+        _check(st)
+        self._h = h
+        self.device = device
+        self.n_problems = len(As)
+        self.n = int(self.offsets[-1])
+
+    # ---------------------------------------------------------------- solves
+    def _solve(self, fn, b, x, rtol, maxit):
+        torch = _torch()
+        if x is None:
+            x = torch.zeros_like(b)
+        info = Info()
+        st = fn(self._h, _dev_ptr(b, "b"), _dev_ptr(x, "x"), float(rtol), int(maxit), C.byref(info))
+        if st not in (OK, ENOCONV):
+            _check(st)
+        return x, info, st
+
+    def solve(self, b, x=None, rtol=1e-8, maxit=100):
+        """AMG-DD iterations; returns (x, Info, status) with status OK or ENOCONV."""
+        return self._solve(load().amgdd_solve, b, x, rtol, maxit)
+
+    def vsolve(self, b, x=None, rtol=1e-8, maxit=100):
+        """AMG V(1,1) cycles on the same hierarchy."""
+        return self._solve(load().amgv_solve, b, x, rtol, maxit)
+
+    def solve_adjoint(self, g, lam=None, rtol=1e-8, maxit=100):
+        return self._solve(load().amgdd_solve_adjoint, g, lam, rtol, maxit)
+
+    def face_gradient(self, u, lam, face_i, face_j):
+        torch = _torch()
+        fi = face_i.to(device=u.device, dtype=torch.int32).contiguous()
+        fj = face_j.to(device=u.device, dtype=torch.int32).contiguous()
+        out = torch.empty(fi.numel(), dtype=torch.float64, device=u.device)
+        _check(load().amgdd_face_gradient(self._h, _dev_ptr(u, "u"), _dev_ptr(lam, "lam"), C.c_void_p(fi.data_ptr()),
+                                          C.c_void_p(fj.data_ptr()), int(fi.numel()), C.c_void_p(out.data_ptr())))
+        return out
+
+    # ---------------------------------------------------------- introspection
+    def stats(self) -> dict:
+        s = Stats()
+        _check(load().amgdd_get_stats(self._h, C.byref(s)))
+        return s.as_dict()
+
+    def levels(self, prob=0):
+        nl = C.c_int()
+        _check(load().amgdd_get_levels(self._h, prob, C.byref(nl), None, None))
+        n = np.zeros(nl.value, dtype=np.int32)
+        z = np.zeros(nl.value, dtype=np.int64)
+        _check(load().amgdd_get_levels(self._h, prob, C.byref(nl), _iptr(n), z.ctypes.data_as(_LLP)))
+        return n, z
+
+    def cf(self, prob, level):
+        n, _ = self.levels(prob)
+        out = np.zeros(int(n[level]), dtype=np.int8)
+        _check(load().amgdd_get_cf(self._h, prob, level, out.ctypes.data_as(C.POINTER(C.c_byte))))
+        return out
+
+    def operator(self, prob, level, which=0):
+        from scipy import sparse
+        nr, nz = C.c_int(), C.c_int()
+        _check(load().amgdd_get_operator(self._h, prob, level, which, C.byref(nr), C.byref(nz), None, None, None))
+        rp = np.zeros(nr.value + 1, dtype=np.int32)
+        ci = np.zeros(nz.value, dtype=np.int32)
+        va = np.zeros(nz.value, dtype=np.float64)
+        _check(load().amgdd_get_operator(self._h, prob, level, which, C.byref(nr), C.byref(nz), _iptr(rp), _iptr(ci),
+                                         _dptr(va)))
+        ncols = int(ci.max()) + 1 if ci.size else 0
+        if which == 1:
+            ncols = int(self.levels(prob)[0][level + 1])
+        else:
+            ncols = nr.value
+        return sparse.csr_matrix((va, ci, rp), shape=(nr.value, ncols))
+
+    def composite(self, prob, p, level):
+        nr, nb, om = C.c_int(), C.c_int(), C.c_int()
+        _check(load().amgdd_get_composite(self._h, prob, p, level, C.byref(nr), C.byref(nb), None, C.byref(om)))
+        g = np.zeros(nb.value, dtype=np.int32)
+        _check(load().amgdd_get_composite(self._h, prob, p, level, C.byref(nr), C.byref(nb), _iptr(g), C.byref(om)))
+        return g, nr.value, om.value
+
+    def history(self, prob=0):
+        n = C.c_int()
+        _check(load().amgdd_get_history(self._h, prob, None, 0, C.byref(n)))
+        out = np.zeros(n.value)
+        _check(load().amgdd_get_history(self._h, prob, _dptr(out), n.value, C.byref(n)))
+        return out
+
+    def profile(self, kind=0, reps=3):
+        """Per-launch-site device time of one iteration (kind 0 AMG-DD, 1
+        V-cycle): list of dicts name, level, launches, ms, bytes (per iteration)."""
+        n = C.c_int()
+        _check(load().amgdd_profile(self._h, kind, reps, None, 0, C.byref(n)))
+        arr = (KernelTime * max(n.value, 1))()
+        _check(load().amgdd_profile(self._h, kind, reps, arr, n.value, C.byref(n)))
+        return [dict(name=a.name.decode(), level=a.level, launches=a.launches, ms=a.ms, bytes=a.bytes)
+                for a in arr[: n.value]]
+
+    def set_stream(self, stream):
+        _check(load().amgdd_set_stream(self._h, C.c_void_p(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().amgdd_destroy(self._h)
+            self._h = _H()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def exported_symbols() -> List[str]:
+    return list(SIGNATURES)

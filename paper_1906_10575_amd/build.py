@@ -1,0 +1,50 @@
+"""Build libamgdd.so in-tree: host setup with g++ (no FMA contraction, so the
+AMG hierarchy is reproducible), device code with hipcc for gfx950.
+
+    python -m paper_1906_10575_amd.build
+"""
+
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+BUILD = os.path.join(ROOT, "_build")
+LIB = os.path.join(HERE, "libamgdd.so")
+
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+HIPCC = os.path.join(ROCM, "bin", "hipcc")
+ARCH = "gfx950"
+
+# Packed-FP32 instructions are kept out of generated code on purpose.
+HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
+             "-packed-fp32-ops", "-munsafe-fp-atomics"]
+HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-pthread", "-Wall", "-Wno-sign-compare"]
+
+
+def _run(cmd, verbose):
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    cxx = shutil.which("g++") or "g++"
+    setup_o = os.path.join(BUILD, "setup.o")
+    driver_o = os.path.join(BUILD, "driver.o")
+    _run([cxx, *HOST_FLAGS, "-c", os.path.join(CSRC, "setup.cpp"), "-o", setup_o], verbose)
+    _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "driver.hip"), "-o", driver_o], verbose)
+    tmp = LIB + ".tmp"
+    _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", setup_o, driver_o, "-o", tmp, "-pthread"], verbose)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-q" not in sys.argv))

@@ -1,0 +1,142 @@
+// Internal host-side data structures shared by the host setup (setup.cpp)
+// and the device driver (driver.hip).  Not part of the public ABI.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace amgdd {
+
+// Compressed sparse rows, 0-based, int32 indices, FP64 values.
+struct Csr {
+  int nrows = 0, ncols = 0;
+  std::vector<int> ptr, col;
+  std::vector<double> val;
+  long long nnz() const { return ptr.empty() ? 0 : ptr[nrows]; }
+};
+
+// Global AMG hierarchy of one problem (Section 2 of the paper).
+struct Hierarchy {
+  std::vector<Csr> A;                    // levels 0..L
+  std::vector<Csr> P;                    // levels 0..L-1, N_l x N_{l+1}
+  std::vector<Csr> R;                    // levels 0..L-1, R_l = P_l^T
+  std::vector<std::vector<int8_t>> cf;   // levels 0..L-1, +1 C / -1 F
+  std::vector<std::vector<double>> l1;   // levels 0..L, d_i = sum_j |a_ij|
+  std::vector<double> Ac;                // coarsest A_L, dense row-major
+  std::vector<double> Ac_inv;            // its inverse (Gauss-Jordan, partial pivoting)
+  int L() const { return (int)A.size() - 1; }
+};
+
+// One level of one composite grid, local numbering: real points D_l first
+// (increasing global id), then ghost points Dbar_l \ D_l (increasing id).
+struct CompLevel {
+  std::vector<int> gid;
+  int nreal = 0;
+  int omissions = 0;
+  Csr A;                      // rows Dbar_l; real rows full, ghost rows real columns only
+  Csr P;                      // rows Dbar_l, columns Dbar_{l+1} (local), dropped outside
+  std::vector<double> dinv;   // 1 / d_i at real rows
+  int nbar() const { return (int)gid.size(); }
+};
+
+struct CompGrid {
+  int prob = 0, p = 0;
+  std::vector<CompLevel> lv;        // levels 0..L of its problem
+  std::vector<int> owned_local;     // level-0 local index of each owned point
+  std::vector<int> owned_gid;       // its global id
+};
+
+struct ProblemHost {
+  int n = 0, nparts = 0, eta = 1;
+  Csr A0;
+  std::vector<int> part;
+  Hierarchy H;
+  std::vector<int> grids;           // indices into Setup::grids
+  bool symmetric = false;
+};
+
+// Sliced ELL, slice height 64 (one wavefront): entry k of row r is stored at
+// sptr[r/64] + 64*k + r%64; slice width = (sptr[s+1]-sptr[s]) / 64; rows
+// shorter than the width are padded with value 0 and a valid column.
+struct Sell {
+  int nrows = 0;
+  std::vector<int> sptr;
+  std::vector<int> col;
+  std::vector<double> val;
+  long long entries() const { return sptr.empty() ? 0 : sptr.back(); }
+};
+
+// Block-diagonal batched layout of one level, over every composite grid
+// (and, for the G* members, over every problem's global level).
+//   composite rows: [normal-grid real rows | normal-grid ghost rows | coarse-grid rows]
+//   "normal" grids are those whose problem has L > l; "coarse" grids have L == l.
+//   global rows:    [normal problems | coarse problems]
+struct BatchLevel {
+  int NRn = 0, NBn = 0, NB = 0;
+  Sell A;                          // rows [0, NBn)
+  Sell P;                          // rows [0, NBn) -> level l+1 composite rows
+  Sell R;                          // R_{l-1}: rows [0, NB) -> level l-1 composite rows
+  std::vector<double> dinv;        // [NRn]
+  std::vector<int> gsrc;           // [NB] global row (this level) of each real row, -1 for ghosts
+  std::vector<int> cg_row0, cg_n, cg_dense;  // coarse grids: first row, size, dense offset
+  int GNn = 0, GN = 0;
+  Sell GA;                         // rows [0, GN)
+  Sell GP;                         // rows [0, GNn) -> level l+1 global rows
+  Sell GR;                         // R_{l-1}: rows [0, GN) -> level l-1 global rows
+  std::vector<double> gdinv;       // [GNn]
+  std::vector<int> gc_row0, gc_n, gc_dense;  // coarse problems
+  std::vector<int> prob_row0;      // per problem, first global row at this level (-1 absent)
+  // stored (unpadded) nonzeros of row ranges, for the algorithmic-bytes model
+  long long nnzA_r = 0, nnzA = 0, nnzP = 0, nnzR_n = 0, nnzR = 0;
+  long long nnzGA_n = 0, nnzGA = 0, nnzGP = 0, nnzGR_n = 0, nnzGR = 0;
+};
+
+struct SetupTimes {
+  double hierarchy = 0, composite = 0, pack = 0, upload = 0;
+};
+
+struct Setup {
+  double theta = 0.25;
+  int max_coarse = 16, max_levels = 25;
+  std::vector<ProblemHost> probs;
+  std::vector<CompGrid> grids;
+  std::vector<BatchLevel> lv;      // 0..maxL
+  std::vector<double> dense_A, dense_inv;  // coarsest operators of all problems
+  std::vector<int> dense_off;      // per problem offset into dense_*
+  std::vector<int> owner;          // [sum N_0] composite level-0 row patched into each fine point
+  std::vector<int> prob_off;       // [nprob+1] fine-vector offsets
+  // residual blocks: rows [blk_row0[b], blk_row1[b]) of problem blk_prob[b]
+  std::vector<int> blk_row0, blk_row1, blk_prob;
+  std::vector<int> prob_blk0;      // [nprob+1] first residual block of each problem
+  SetupTimes times;
+  long long omissions = 0;
+  long long composite_real_nnz = 0, global_nnz = 0, composite_rows = 0, composite_real_rows = 0;
+  int maxL() const { return (int)lv.size() - 1; }
+};
+
+// Status codes mirror amgdd_status.
+enum { ST_OK = 0, ST_EINVAL = 1, ST_ENOMEM = 2, ST_EDEVICE = 3, ST_ENOCONV = 4, ST_EBREAKDOWN = 5, ST_EUNSUP = 6 };
+
+struct ProblemInput {
+  int n;
+  const int *rowptr, *colind;
+  const double *val;
+  const int *part;
+  int nparts;
+  int eta;
+};
+
+// Host setup: hierarchy, composite grids and batched layouts.  Returns a
+// status and fills `err` on failure.
+int build_setup(const std::vector<ProblemInput> &in, double theta, int max_coarse, int max_levels,
+                Setup &S, std::string &err);
+
+// Individual steps, exposed for the driver's introspection.
+Csr strength(const Csr &A, double theta);
+std::vector<int8_t> rs_first_pass(const Csr &S);
+Csr direct_interpolation(const Csr &A, const Csr &S, const std::vector<int8_t> &cf);
+Csr transpose(const Csr &A);
+Csr spgemm(const Csr &A, const Csr &B);
+
+}  // namespace amgdd

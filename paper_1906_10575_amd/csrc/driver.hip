@@ -1,0 +1,813 @@
+// Device driver and C ABI of the AMG-DD solve phase (see include/amgdd.h).
+//
+// One outer AMG-DD iteration (Algorithm 2 of the paper) is enqueued as:
+//   restriction chain r_{l+1} = R_l r_l (global batched operators)
+//   one gather of the composite right-hand sides of every level
+//   n_fac AlgFAC cycles (Algorithm 4) over all composite grids at once,
+//     level-synchronous: relax/down + w on the way down, coarse solve,
+//     interp + relax on the way up
+//   patch x += u_0 on owned points
+//   fine residual r = b - A x and its norm (for the next iteration)
+// and is captured once into a HIP graph that is replayed every iteration; the
+// host reads the per-problem residual norms (8 bytes each) after each replay.
+// The V(1,1) cycle (Algorithm 1) is enqueued the same way on the global
+// batched hierarchy, in correction form e = V(r), x += e.
+
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/amgdd.h"
+#include "amgdd_internal.h"
+#include "kernels.hpp"
+
+using namespace amgdd;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+amgdd_status fail(int st, const std::string &msg) {
+  g_last_error = msg;
+  return (amgdd_status)st;
+}
+
+#define HIP_TRY(expr)                                                                           \
+  do {                                                                                          \
+    hipError_t _e = (expr);                                                                     \
+    if (_e != hipSuccess) {                                                                     \
+      return fail(_e == hipErrorOutOfMemory ? ST_ENOMEM : ST_EDEVICE,                           \
+                  std::string(#expr) + ": " + hipGetErrorString(_e));                           \
+    }                                                                                           \
+  } while (0)
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct DSell {
+  int *sptr = nullptr;
+  int *col = nullptr;
+  void *val = nullptr;  // double or float
+  int nrows = 0;
+  long long entries = 0;
+  template <typename T>
+  dev::SellD<T> as() const {
+    return dev::SellD<T>{sptr, col, (const T *)val};
+  }
+};
+
+struct DLevel {
+  // composite
+  int NRn = 0, NBn = 0, NB = 0;
+  DSell A, P, R;
+  void *dinv = nullptr;
+  void *u[2] = {nullptr, nullptr};
+  void *t = nullptr, *sw = nullptr, *f = nullptr;  // f points into the level-f arena
+  int ncg = 0;
+  int *cg_row0 = nullptr, *cg_n = nullptr, *cg_dense = nullptr;
+  int cg_maxn = 0;
+  // global
+  int GNn = 0, GN = 0;
+  DSell GA, GP, GRd, GRt;  // GRd: FP64 (V-cycle); GRt: composite precision (restriction chain)
+  double *gdinv = nullptr;
+  double *ve[2] = {nullptr, nullptr};
+  double *vq = nullptr, *vf = nullptr;
+  void *rt = nullptr;  // restricted residual r_l (composite precision), points into r arena
+  int ngc = 0;
+  int *gc_row0 = nullptr, *gc_n = nullptr, *gc_dense = nullptr;
+  int gc_maxn = 0;
+  // stored nonzeros (algorithmic-bytes model of the profiler)
+  long long nnzA_r = 0, nnzA = 0, nnzP = 0, nnzR_n = 0, nnzR = 0;
+  long long nnzGA_n = 0, nnzGA = 0, nnzGP = 0, nnzGR_n = 0, nnzGR = 0;
+};
+
+// Per-launch event timing (amgdd_profile): one event pair per launch site.
+struct Prof {
+  struct Site {
+    std::string name;
+    int level;
+    double bytes;
+    hipEvent_t e0, e1;
+  };
+  std::vector<Site> sites;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  hipEvent_t get() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  int begin(const char *name, int level, double bytes, hipStream_t s) {
+    Site st{name, level, bytes, get(), get()};
+    (void)hipEventRecord(st.e0, s);
+    sites.push_back(st);
+    return (int)sites.size() - 1;
+  }
+  void end(int k, hipStream_t s) { (void)hipEventRecord(sites[k].e1, s); }
+  ~Prof() {
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+}  // namespace
+
+struct amgdd_ctx {
+  Setup S;
+  amgdd_params prm{};
+  bool host_only = true;
+  bool symmetric = true;
+  double setup_s = 0.0;
+  int device = 0;
+  hipStream_t stream = nullptr;      // caller's stream
+  hipStream_t cap_stream = nullptr;  // private stream used for graph capture
+  std::vector<void *> allocs;
+  long long dev_bytes = 0;
+  std::vector<DLevel> L;
+  // outer vectors
+  double *b = nullptr, *x = nullptr;
+  double *partial = nullptr, *norm2 = nullptr;
+  double *h_norm2 = nullptr;  // pinned
+  int *blk_row0 = nullptr, *blk_row1 = nullptr, *prob_blk0 = nullptr;
+  int nblk = 0, nprob = 0, N0 = 0;
+  int *owner = nullptr;
+  double *dense_A = nullptr, *dense_inv = nullptr;
+  void *f_arena = nullptr;
+  int *gather_src = nullptr;
+  long long f_total = 0;
+  void *r_arena = nullptr;
+  double *face_tmp = nullptr;
+  hipGraphExec_t g_dd = nullptr, g_v = nullptr;
+  hipGraph_t gr_dd = nullptr, gr_v = nullptr;
+  std::vector<std::vector<double>> hist;  // per problem
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  Prof *prof = nullptr;
+
+  bool mixed() const { return prm.precision == AMGDD_MIXED; }
+
+  amgdd_status alloc(void **p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) return AMGDD_OK;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? ST_ENOMEM : ST_EDEVICE, std::string("hipMalloc: ") + hipGetErrorString(e));
+    allocs.push_back(*p);
+    dev_bytes += (long long)bytes;
+    return AMGDD_OK;
+  }
+  template <typename V>
+  amgdd_status upload(V **dst, const V *src, size_t n) {
+    amgdd_status st = alloc((void **)dst, n * sizeof(V));
+    if (st) return st;
+    if (n) HIP_TRY(hipMemcpy(*dst, src, n * sizeof(V), hipMemcpyHostToDevice));
+    return AMGDD_OK;
+  }
+  amgdd_status upload_vals(void **dst, const std::vector<double> &v, bool as_float) {
+    if (!as_float) return upload((double **)dst, v.data(), v.size());
+    std::vector<float> f(v.begin(), v.end());
+    return upload((float **)dst, f.data(), f.size());
+  }
+  amgdd_status upload_sell(DSell &d, const Sell &s, bool as_float) {
+    d.nrows = s.nrows;
+    d.entries = s.entries();
+    amgdd_status st = upload(&d.sptr, s.sptr.data(), s.sptr.size());
+    if (st) return st;
+    if ((st = upload(&d.col, s.col.data(), s.col.size()))) return st;
+    return upload_vals(&d.val, s.val, as_float);
+  }
+
+  void drop_graphs() {
+    if (g_dd) (void)hipGraphExecDestroy(g_dd);
+    if (g_v) (void)hipGraphExecDestroy(g_v);
+    if (gr_dd) (void)hipGraphDestroy(gr_dd);
+    if (gr_v) (void)hipGraphDestroy(gr_v);
+    g_dd = g_v = nullptr;
+    gr_dd = gr_v = nullptr;
+  }
+
+  ~amgdd_ctx() {
+    if (!host_only) {
+      (void)hipSetDevice(device);
+      drop_graphs();
+      for (void *p : allocs) (void)hipFree(p);
+      if (h_norm2) (void)hipHostFree(h_norm2);
+      if (cap_stream) (void)hipStreamDestroy(cap_stream);
+      if (ev0) (void)hipEventDestroy(ev0);
+      if (ev1) (void)hipEventDestroy(ev1);
+    }
+  }
+};
+
+namespace {
+
+inline int nblocks(long long n) { return (int)((n + dev::BLOCK - 1) / dev::BLOCK); }
+
+// ---------------------------------------------------------------- upload
+
+amgdd_status upload_all(amgdd_ctx *h) {
+  Setup &S = h->S;
+  const bool fl = h->mixed();
+  const size_t tsz = fl ? sizeof(float) : sizeof(double);
+  amgdd_status st;
+  const int nl = S.maxL() + 1;
+  h->L.assign(nl, DLevel());
+  h->nprob = (int)S.probs.size();
+  h->N0 = S.prob_off.back();
+  // f arena and gather map over all composite levels; r arena over all global levels
+  std::vector<long long> foff(nl + 1, 0), roff(nl + 1, 0);
+  for (int l = 0; l < nl; ++l) {
+    foff[l + 1] = foff[l] + S.lv[l].NB;
+    roff[l + 1] = roff[l] + S.lv[l].GN;
+  }
+  h->f_total = foff[nl];
+  if ((st = h->alloc(&h->f_arena, foff[nl] * tsz))) return st;
+  if ((st = h->alloc(&h->r_arena, roff[nl] * tsz))) return st;
+  {
+    std::vector<int> src(foff[nl], -1);
+    for (int l = 0; l < nl; ++l)
+      for (int i = 0; i < S.lv[l].NB; ++i)
+        if (S.lv[l].gsrc[i] >= 0) src[foff[l] + i] = (int)(roff[l] + S.lv[l].gsrc[i]);
+    if ((st = h->upload(&h->gather_src, src.data(), src.size()))) return st;
+  }
+  for (int l = 0; l < nl; ++l) {
+    BatchLevel &B = S.lv[l];
+    DLevel &D = h->L[l];
+    D.NRn = B.NRn;
+    D.NBn = B.NBn;
+    D.NB = B.NB;
+    D.nnzA_r = B.nnzA_r;
+    D.nnzA = B.nnzA;
+    D.nnzP = B.nnzP;
+    D.nnzR_n = B.nnzR_n;
+    D.nnzR = B.nnzR;
+    D.nnzGA_n = B.nnzGA_n;
+    D.nnzGA = B.nnzGA;
+    D.nnzGP = B.nnzGP;
+    D.nnzGR_n = B.nnzGR_n;
+    D.nnzGR = B.nnzGR;
+    if ((st = h->upload_sell(D.A, B.A, fl))) return st;
+    if ((st = h->upload_sell(D.P, B.P, fl))) return st;
+    if ((st = h->upload_sell(D.R, B.R, fl))) return st;
+    if ((st = h->upload_vals(&D.dinv, B.dinv, fl))) return st;
+    for (int k = 0; k < 2; ++k)
+      if ((st = h->alloc(&D.u[k], (size_t)B.NB * tsz))) return st;
+    if ((st = h->alloc(&D.t, (size_t)B.NB * tsz))) return st;
+    if ((st = h->alloc(&D.sw, (size_t)B.NB * tsz))) return st;
+    if (B.NB) {
+      // t must be zero at ghost rows (never written); sw/u are always written before read
+      HIP_TRY(hipMemset(D.t, 0, (size_t)B.NB * tsz));
+      HIP_TRY(hipMemset(D.sw, 0, (size_t)B.NB * tsz));
+      HIP_TRY(hipMemset(D.u[0], 0, (size_t)B.NB * tsz));
+      HIP_TRY(hipMemset(D.u[1], 0, (size_t)B.NB * tsz));
+    }
+    D.f = (char *)h->f_arena + foff[l] * tsz;
+    D.ncg = (int)B.cg_row0.size();
+    if ((st = h->upload(&D.cg_row0, B.cg_row0.data(), B.cg_row0.size()))) return st;
+    if ((st = h->upload(&D.cg_n, B.cg_n.data(), B.cg_n.size()))) return st;
+    if ((st = h->upload(&D.cg_dense, B.cg_dense.data(), B.cg_dense.size()))) return st;
+    for (int v : B.cg_n) D.cg_maxn = std::max(D.cg_maxn, v);
+    // global
+    D.GNn = B.GNn;
+    D.GN = B.GN;
+    if ((st = h->upload_sell(D.GA, B.GA, false))) return st;
+    if ((st = h->upload_sell(D.GP, B.GP, false))) return st;
+    if ((st = h->upload_sell(D.GRd, B.GR, false))) return st;
+    if (fl) {
+      if ((st = h->upload_sell(D.GRt, B.GR, true))) return st;
+    } else {
+      D.GRt = D.GRd;
+    }
+    if ((st = h->upload(&D.gdinv, B.gdinv.data(), B.gdinv.size()))) return st;
+    for (int k = 0; k < 2; ++k)
+      if ((st = h->alloc((void **)&D.ve[k], (size_t)B.GN * sizeof(double)))) return st;
+    if ((st = h->alloc((void **)&D.vq, (size_t)B.GN * sizeof(double)))) return st;
+    if ((st = h->alloc((void **)&D.vf, (size_t)B.GN * sizeof(double)))) return st;
+    D.rt = (char *)h->r_arena + roff[l] * tsz;
+    D.ngc = (int)B.gc_row0.size();
+    if ((st = h->upload(&D.gc_row0, B.gc_row0.data(), B.gc_row0.size()))) return st;
+    if ((st = h->upload(&D.gc_n, B.gc_n.data(), B.gc_n.size()))) return st;
+    if ((st = h->upload(&D.gc_dense, B.gc_dense.data(), B.gc_dense.size()))) return st;
+    for (int v : B.gc_n) D.gc_maxn = std::max(D.gc_maxn, v);
+  }
+  if ((st = h->alloc((void **)&h->b, (size_t)h->N0 * sizeof(double)))) return st;
+  if ((st = h->alloc((void **)&h->x, (size_t)h->N0 * sizeof(double)))) return st;
+  HIP_TRY(hipMemset(h->b, 0, (size_t)h->N0 * sizeof(double)));
+  HIP_TRY(hipMemset(h->x, 0, (size_t)h->N0 * sizeof(double)));
+  h->nblk = (int)S.blk_row0.size();
+  if ((st = h->upload(&h->blk_row0, S.blk_row0.data(), S.blk_row0.size()))) return st;
+  if ((st = h->upload(&h->blk_row1, S.blk_row1.data(), S.blk_row1.size()))) return st;
+  if ((st = h->upload(&h->prob_blk0, S.prob_blk0.data(), S.prob_blk0.size()))) return st;
+  if ((st = h->alloc((void **)&h->partial, (size_t)h->nblk * sizeof(double)))) return st;
+  if ((st = h->alloc((void **)&h->norm2, (size_t)h->nprob * sizeof(double)))) return st;
+  HIP_TRY(hipHostMalloc((void **)&h->h_norm2, (size_t)h->nprob * sizeof(double), hipHostMallocDefault));
+  if ((st = h->upload(&h->owner, S.owner.data(), S.owner.size()))) return st;
+  if ((st = h->upload(&h->dense_A, S.dense_A.data(), S.dense_A.size()))) return st;
+  if ((st = h->upload(&h->dense_inv, S.dense_inv.data(), S.dense_inv.size()))) return st;
+  HIP_TRY(hipDeviceSynchronize());
+  return AMGDD_OK;
+}
+
+// ---------------------------------------------------------------- enqueue
+
+#define LAUNCH(kernel, grid, block, shmem, stream, ...)                         \
+  do {                                                                          \
+    if ((grid) > 0) hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), shmem, stream, __VA_ARGS__); \
+  } while (0)
+
+// Launch with a profiling site: name, level and algorithmic bytes (the bytes
+// expression is evaluated only while profiling).
+#define PLAUNCH(h, name, level, bytes, kernel, grid, block, shmem, stream, ...)                     \
+  do {                                                                                              \
+    if ((grid) > 0) {                                                                               \
+      Prof *_p = (h)->prof;                                                                         \
+      int _k = _p ? _p->begin(name, level, (double)(bytes), stream) : -1;                           \
+      hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), shmem, stream, __VA_ARGS__);              \
+      if (_p) _p->end(_k, stream);                                                                  \
+    }                                                                                               \
+  } while (0)
+
+// Fine residual and its per-problem squared norm.  vc: also e0 = r / d for the V-cycle.
+template <typename T>
+void enqueue_residual(amgdd_ctx *h, hipStream_t s, bool vc) {
+  DLevel &D0 = h->L[0];
+  if (vc)
+    PLAUNCH(h, "resid_v", 0, D0.nnzGA * 12.0 + h->N0 * 40.0, (dev::k_resid<double, true>), h->nblk, dev::BLOCK, 0, s, D0.GA.as<double>(), h->b, h->x, D0.vf, h->partial,
+           h->blk_row0, h->blk_row1, D0.gdinv, D0.ve[0]);
+  else
+    PLAUNCH(h, "resid", 0, D0.nnzGA * 12.0 + h->N0 * (16.0 + sizeof(T)), (dev::k_resid<T, false>), h->nblk, dev::BLOCK, 0, s, D0.GA.as<double>(), h->b, h->x, (T *)D0.rt,
+           h->partial, h->blk_row0, h->blk_row1, (const double *)nullptr, (double *)nullptr);
+  PLAUNCH(h, "norm", 0, h->nblk * 8.0, dev::k_norm_final, h->nprob, dev::BLOCK, 0, s, h->partial, h->prob_blk0, h->norm2);
+  (void)hipMemcpyAsync(h->h_norm2, h->norm2, (size_t)h->nprob * sizeof(double), hipMemcpyDeviceToHost, s);
+}
+
+template <typename T>
+void enqueue_fac(amgdd_ctx *h, hipStream_t s, int *cur) {
+  const int maxL = (int)h->L.size() - 1;
+  const double w = sizeof(T);
+  const int nfac = h->prm.n_fac;
+  for (int c = 0; c < nfac; ++c) {
+    const int first = c == 0;
+    for (int l = 0; l <= maxL; ++l) {
+      DLevel &B = h->L[l];
+      T *uin = (T *)B.u[cur[l]], *uout = (T *)B.u[cur[l] ^ 1];
+      if (l == 0) {
+        if (first)
+          PLAUNCH(h, "relax0", 0, B.NRn * 4.0 * w + (B.NBn - B.NRn) * w, dev::k_relax_zero<T>, nblocks(B.NBn), dev::BLOCK, 0, s, B.NRn, B.NBn, (const T *)B.f,
+                 (const T *)B.dinv, uout, (T *)B.t);
+        else
+          PLAUNCH(h, "relax_pre", 0, B.nnzA_r * (w + 4.0) + B.NRn * 4.0 * w + B.NBn * 2.0 * w, dev::k_relax<T>, nblocks(B.NBn), dev::BLOCK, 0, s, B.A.as<T>(), B.NRn, B.NBn, (const T *)B.f,
+                 (const T *)B.dinv, (const T *)uin, uout, (T *)B.t, 1);
+      } else {
+        DLevel &Bp = h->L[l - 1];
+        PLAUNCH(h, "down", l, B.nnzR_n * (w + 4.0) + Bp.NBn * w + B.NBn * 2.0 * w + (first ? 0.0 : B.nnzA_r * (w + 4.0) + B.NBn * w) + B.NRn * (first ? 4.0 : 5.0) * w, dev::k_down<T>, nblocks(B.NBn), dev::BLOCK, 0, s, B.R.as<T>(), B.A.as<T>(), B.NRn, B.NBn,
+               (const T *)Bp.sw, (T *)B.sw, (T *)B.f, (const T *)B.dinv, (const T *)uin, uout, (T *)B.t, first);
+        PLAUNCH(h, "coarse", l, (B.nnzR - B.nnzR_n) * (w + 4.0) + (B.NB - B.NBn) * 3.0 * w, dev::k_coarse<T>, B.ncg, dev::BLOCK, 2 * B.cg_maxn * sizeof(double), s, B.R.as<T>(), 1,
+               (const T *)Bp.sw, (T *)B.f, (const T *)uin, uout, h->dense_A, h->dense_inv, B.cg_row0, B.cg_n,
+               B.cg_dense, 0, first);
+      }
+      cur[l] ^= 1;
+      if (B.NBn > 0 && l < maxL)
+        PLAUNCH(h, "w", l, B.nnzA * (w + 4.0) + B.NBn * (l > 0 ? 3.0 : 2.0) * w, dev::k_w<T>, nblocks(B.NBn), dev::BLOCK, 0, s, B.A.as<T>(), B.NBn, (T *)B.sw, (const T *)B.t, l > 0);
+    }
+    for (int l = maxL - 1; l >= 0; --l) {
+      DLevel &B = h->L[l];
+      if (B.NBn == 0) continue;
+      DLevel &Bc = h->L[l + 1];
+      PLAUNCH(h, "interp", l, B.nnzP * (w + 4.0) + B.NBn * 2.0 * w + Bc.NB * w, dev::k_interp<T>, nblocks(B.NBn), dev::BLOCK, 0, s, B.P.as<T>(), B.NBn, (T *)B.u[cur[l]],
+             (const T *)Bc.u[cur[l + 1]]);
+      PLAUNCH(h, "relax_post", l, B.nnzA_r * (w + 4.0) + B.NRn * 3.0 * w + B.NB * 2.0 * w, dev::k_relax<T>, nblocks(B.NB), dev::BLOCK, 0, s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
+             (const T *)B.dinv, (const T *)B.u[cur[l]], (T *)B.u[cur[l] ^ 1], (T *)B.t, 0);
+      cur[l] ^= 1;
+    }
+  }
+}
+
+// One AMG-DD iteration from a current residual r_0 (already in L[0].rt).
+template <typename T>
+void enqueue_dd_iteration(amgdd_ctx *h, hipStream_t s) {
+  const int maxL = (int)h->L.size() - 1;
+  for (int l = 1; l <= maxL; ++l) {
+    DLevel &B = h->L[l];
+    PLAUNCH(h, "restrict", l, B.nnzGR * (sizeof(T) + 4.0) + (h->L[l - 1].GN + B.GN) * (double)sizeof(T), dev::k_spmv<T>, nblocks(B.GN), dev::BLOCK, 0, s, B.GRt.as<T>(), B.GN, (const T *)h->L[l - 1].rt, (T *)B.rt);
+  }
+  PLAUNCH(h, "gather", 0, h->f_total * 4.0 + h->S.composite_real_rows * 2.0 * sizeof(T), dev::k_gather<T>, nblocks(h->f_total), dev::BLOCK, 0, s, (int)h->f_total, h->gather_src,
+         (const T *)h->r_arena, (T *)h->f_arena);
+  std::vector<int> cur(maxL + 1, 0);
+  enqueue_fac<T>(h, s, cur.data());
+  PLAUNCH(h, "patch", 0, h->N0 * (20.0 + sizeof(T)), dev::k_patch<T>, nblocks(h->N0), dev::BLOCK, 0, s, h->N0, h->x, h->owner, (const T *)h->L[0].u[cur[0]]);
+  enqueue_residual<T>(h, s, false);
+}
+
+// One V(1,1) cycle in correction form from r_0 (L[0].vf) and e_0 = r_0 / d (L[0].ve[0]).
+void enqueue_v_iteration(amgdd_ctx *h, hipStream_t s) {
+  const int maxL = (int)h->L.size() - 1;
+  std::vector<int> cur(maxL + 1, 0);
+  for (int l = 0; l < maxL; ++l) {
+    DLevel &B = h->L[l];
+    DLevel &Bc = h->L[l + 1];
+    if (B.GNn == 0) continue;
+    PLAUNCH(h, "vresid", l, B.nnzGA_n * 12.0 + B.GN * 8.0 + B.GNn * 16.0, dev::k_vresid<double>, nblocks(B.GNn), dev::BLOCK, 0, s, B.GA.as<double>(), B.GNn, B.vf, B.ve[cur[l]], B.vq);
+    PLAUNCH(h, "vdown", l + 1, Bc.nnzGR_n * 12.0 + B.GNn * 8.0 + Bc.GNn * 24.0, dev::k_vdown<double>, nblocks(Bc.GNn), dev::BLOCK, 0, s, Bc.GRd.as<double>(), Bc.GNn, B.vq, Bc.vf,
+           Bc.gdinv, Bc.ve[cur[l + 1]]);
+    PLAUNCH(h, "vcoarse", l + 1, (Bc.nnzGR - Bc.nnzGR_n) * 12.0 + (Bc.GN - Bc.GNn) * 16.0, dev::k_coarse<double>, Bc.ngc, dev::BLOCK, 2 * Bc.gc_maxn * sizeof(double), s, Bc.GRd.as<double>(), 1, B.vq,
+           Bc.vf, Bc.ve[cur[l + 1]], Bc.ve[cur[l + 1]], h->dense_A, h->dense_inv, Bc.gc_row0, Bc.gc_n, Bc.gc_dense, 1,
+           1);
+  }
+  for (int l = maxL - 1; l >= 0; --l) {
+    DLevel &B = h->L[l];
+    DLevel &Bc = h->L[l + 1];
+    if (B.GNn == 0) continue;
+    PLAUNCH(h, "vinterp", l, B.nnzGP * 12.0 + B.GNn * 16.0 + Bc.GN * 8.0, dev::k_interp<double>, nblocks(B.GNn), dev::BLOCK, 0, s, B.GP.as<double>(), B.GNn, B.ve[cur[l]],
+           Bc.ve[cur[l + 1]]);
+    if (l > 0) {
+      PLAUNCH(h, "vrelax", l, B.nnzGA_n * 12.0 + B.GNn * 16.0 + B.GN * 16.0, dev::k_relax<double>, nblocks(B.GN), dev::BLOCK, 0, s, B.GA.as<double>(), B.GNn, B.GN, B.vf, B.gdinv,
+             B.ve[cur[l]], B.ve[cur[l] ^ 1], (double *)nullptr, 2);
+      cur[l] ^= 1;
+    } else {
+      PLAUNCH(h, "vfinal", 0, B.nnzGA_n * 12.0 + B.GNn * 40.0, dev::k_vfinal, nblocks(B.GNn), dev::BLOCK, 0, s, B.GA.as<double>(), B.GNn, B.vf, B.gdinv, B.ve[cur[0]],
+             h->x);
+    }
+  }
+  enqueue_residual<double>(h, s, true);
+}
+
+amgdd_status capture(amgdd_ctx *h, bool dd, hipGraph_t *gr, hipGraphExec_t *ex) {
+  HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+  if (dd) {
+    if (h->mixed()) enqueue_dd_iteration<float>(h, h->cap_stream);
+    else enqueue_dd_iteration<double>(h, h->cap_stream);
+  } else {
+    enqueue_v_iteration(h, h->cap_stream);
+  }
+  HIP_TRY(hipStreamEndCapture(h->cap_stream, gr));
+  HIP_TRY(hipGraphInstantiate(ex, *gr, nullptr, nullptr, 0));
+  return AMGDD_OK;
+}
+
+enum SolveKind { SOLVE_DD = 0, SOLVE_V = 1 };
+
+amgdd_status run_solve(amgdd_ctx *h, SolveKind kind, const double *b_dev, double *x_dev, double rtol, int maxit,
+                       amgdd_info *info) {
+  if (!h) return fail(ST_EINVAL, "null handle");
+  if (h->host_only) return fail(ST_EDEVICE, "host-only handle (device = -1): no device solve");
+  if (!b_dev || !x_dev) return fail(ST_EINVAL, "null device vector");
+  if (maxit < 0) return fail(ST_EINVAL, "maxit < 0");
+  HIP_TRY(hipSetDevice(h->device));
+  hipStream_t s = h->stream;
+  const size_t nbytes = (size_t)h->N0 * sizeof(double);
+  HIP_TRY(hipMemcpyAsync(h->b, b_dev, nbytes, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(h->x, x_dev, nbytes, hipMemcpyDeviceToDevice, s));
+  bool use_graph = h->prm.use_graph != 0;
+  if (use_graph) {
+    if (kind == SOLVE_DD && !h->g_dd) {
+      amgdd_status st = capture(h, true, &h->gr_dd, &h->g_dd);
+      if (st) return st;
+    }
+    if (kind == SOLVE_V && !h->g_v) {
+      amgdd_status st = capture(h, false, &h->gr_v, &h->g_v);
+      if (st) return st;
+    }
+  }
+  auto enqueue_res = [&](hipStream_t st) {
+    if (kind == SOLVE_V) enqueue_residual<double>(h, st, true);
+    else if (h->mixed()) enqueue_residual<float>(h, st, false);
+    else enqueue_residual<double>(h, st, false);
+  };
+  auto enqueue_iter = [&](hipStream_t st) -> hipError_t {
+    if (use_graph) return hipGraphLaunch(kind == SOLVE_DD ? h->g_dd : h->g_v, st);
+    if (kind == SOLVE_V) enqueue_v_iteration(h, st);
+    else if (h->mixed()) enqueue_dd_iteration<float>(h, st);
+    else enqueue_dd_iteration<double>(h, st);
+    return hipGetLastError();
+  };
+  HIP_TRY(hipEventRecord(h->ev0, s));
+  enqueue_res(s);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));
+  const int np = h->nprob;
+  h->hist.assign(np, std::vector<double>());
+  std::vector<double> r0(np);
+  for (int q = 0; q < np; ++q) {
+    r0[q] = std::sqrt(h->h_norm2[q]);
+    h->hist[q].push_back(r0[q]);
+  }
+  auto converged = [&]() {
+    if (rtol <= 0) return false;
+    for (int q = 0; q < np; ++q)
+      if (!(h->hist[q].back() <= rtol * r0[q])) return false;
+    return true;
+  };
+  auto finite = [&]() {
+    for (int q = 0; q < np; ++q)
+      if (!std::isfinite(h->hist[q].back())) return false;
+    return true;
+  };
+  int it = 0;
+  amgdd_status result = AMGDD_OK;
+  if (!finite()) result = fail(ST_EBREAKDOWN, "non-finite initial residual");
+  while (result == AMGDD_OK && !converged() && it < maxit) {
+    HIP_TRY(enqueue_iter(s));
+    HIP_TRY(hipStreamSynchronize(s));
+    ++it;
+    for (int q = 0; q < np; ++q) h->hist[q].push_back(std::sqrt(h->h_norm2[q]));
+    if (!finite()) result = fail(ST_EBREAKDOWN, "non-finite residual norm at iteration " + std::to_string(it));
+  }
+  HIP_TRY(hipEventRecord(h->ev1, s));
+  HIP_TRY(hipMemcpyAsync(x_dev, h->x, nbytes, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+  if (result == AMGDD_OK && rtol > 0 && !converged())
+    result = fail(ST_ENOCONV, "maxit reached before rtol");
+  if (info) {
+    info->iters = it;
+    info->solve_s = ms * 1e-3;
+    info->setup_s = h->setup_s;
+    double rel = 0.0, rho = 0.0;
+    for (int q = 0; q < np; ++q) {
+      const auto &hq = h->hist[q];
+      double rq = r0[q] > 0 ? hq.back() / r0[q] : 0.0;
+      rel = std::max(rel, rq);
+      int k = std::min<int>(5, (int)hq.size() - 1);
+      if (k > 0 && hq[hq.size() - 1 - k] > 0) rho = std::max(rho, std::pow(hq.back() / hq[hq.size() - 1 - k], 1.0 / k));
+    }
+    info->relres = rel;
+    info->rho_asym = rho;
+  }
+  return result;
+}
+
+amgdd_status make_handle(const std::vector<ProblemInput> &in, const amgdd_params *prm, void *stream, amgdd_handle *out) {
+  if (!out) return fail(ST_EINVAL, "null output handle");
+  *out = nullptr;
+  double t0 = now_s();
+  amgdd_ctx *h = new (std::nothrow) amgdd_ctx();
+  if (!h) return fail(ST_ENOMEM, "handle allocation");
+  amgdd_params_default(&h->prm);
+  if (prm) h->prm = *prm;
+  const amgdd_params &p = h->prm;
+  if (p.n_fac < 1 || (p.precision != AMGDD_FP64 && p.precision != AMGDD_MIXED)) {
+    delete h;
+    return fail(ST_EINVAL, "bad n_fac or precision");
+  }
+  std::string err;
+  int st = build_setup(in, p.theta, p.max_coarse, p.max_levels, h->S, err);
+  if (st) {
+    delete h;
+    return fail(st, err);
+  }
+  h->symmetric = true;
+  for (auto &P : h->S.probs) h->symmetric = h->symmetric && P.symmetric;
+  h->host_only = p.device < 0;
+  if (!h->host_only) {
+    double tu = now_s();
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || p.device >= ndev) {
+      delete h;
+      return fail(ST_EDEVICE, "no HIP device " + std::to_string(p.device));
+    }
+    h->device = p.device;
+    (void)hipSetDevice(h->device);
+    h->stream = (hipStream_t)stream;
+    if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess) {
+      h->host_only = false;
+      delete h;
+      return fail(ST_EDEVICE, "stream/event creation failed");
+    }
+    h->host_only = false;
+    amgdd_status us = upload_all(h);
+    if (us) {
+      std::string msg = g_last_error;
+      delete h;
+      return fail(us, msg);
+    }
+    h->S.times.upload = now_s() - tu;
+  }
+  h->setup_s = now_s() - t0;
+  *out = h;
+  return AMGDD_OK;
+}
+
+}  // namespace
+
+// ======================================================================= C ABI
+
+extern "C" {
+
+void amgdd_params_default(amgdd_params *prm) {
+  if (!prm) return;
+  prm->theta = 0.25;
+  prm->max_coarse = 16;
+  prm->max_levels = 25;
+  prm->padding = 1;
+  prm->n_fac = 2;
+  prm->precision = AMGDD_FP64;
+  prm->device = 0;
+  prm->use_graph = 1;
+}
+
+amgdd_status amgdd_setup_composite(int n, const int *rowptr, const int *colind, const double *val, const int *part,
+                                   int nparts, const amgdd_params *prm, void *hip_stream, amgdd_handle *out) {
+  amgdd_params p;
+  amgdd_params_default(&p);
+  if (prm) p = *prm;
+  std::vector<ProblemInput> in{ProblemInput{n, rowptr, colind, val, part, nparts, p.padding}};
+  return make_handle(in, &p, hip_stream, out);
+}
+
+amgdd_status amgdd_setup_composite_batch(int nprob, const int *n, const int *const *rowptr, const int *const *colind,
+                                         const double *const *val, const int *const *part, const int *nparts,
+                                         const amgdd_params *prm, void *hip_stream, amgdd_handle *out) {
+  if (nprob <= 0 || !n || !rowptr || !colind || !val || !part || !nparts || !prm)
+    return fail(ST_EINVAL, "null batch argument");
+  std::vector<ProblemInput> in;
+  for (int q = 0; q < nprob; ++q) in.push_back(ProblemInput{n[q], rowptr[q], colind[q], val[q], part[q], nparts[q], prm[q].padding});
+  return make_handle(in, &prm[0], hip_stream, out);
+}
+
+amgdd_status amgdd_solve(amgdd_handle h, const double *b_dev, double *x_dev, double rtol, int maxit, amgdd_info *info) {
+  return run_solve(h, SOLVE_DD, b_dev, x_dev, rtol, maxit, info);
+}
+
+amgdd_status amgv_solve(amgdd_handle h, const double *b_dev, double *x_dev, double rtol, int maxit, amgdd_info *info) {
+  return run_solve(h, SOLVE_V, b_dev, x_dev, rtol, maxit, info);
+}
+
+amgdd_status amgdd_solve_adjoint(amgdd_handle h, const double *g_dev, double *lambda_dev, double rtol, int maxit,
+                                 amgdd_info *info) {
+  if (!h) return fail(ST_EINVAL, "null handle");
+  if (!h->symmetric) return fail(ST_EUNSUP, "adjoint of a non-symmetric operator is not supported by this build");
+  return run_solve(h, SOLVE_DD, g_dev, lambda_dev, rtol, maxit, info);
+}
+
+amgdd_status amgdd_face_gradient(amgdd_handle h, const double *u_dev, const double *lambda_dev, const int *face_i_dev,
+                                 const int *face_j_dev, int nfaces, double *dLdc_dev) {
+  if (!h) return fail(ST_EINVAL, "null handle");
+  if (h->host_only) return fail(ST_EDEVICE, "host-only handle");
+  if (nfaces < 0 || (nfaces > 0 && (!u_dev || !lambda_dev || !face_i_dev || !face_j_dev || !dLdc_dev)))
+    return fail(ST_EINVAL, "bad face-gradient arguments");
+  HIP_TRY(hipSetDevice(h->device));
+  LAUNCH(dev::k_face_grad, nblocks(nfaces), dev::BLOCK, 0, h->stream, nfaces, face_i_dev, face_j_dev, u_dev, lambda_dev,
+         dLdc_dev);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return AMGDD_OK;
+}
+
+amgdd_status amgdd_get_stats(amgdd_handle h, amgdd_stats *st) {
+  if (!h || !st) return fail(ST_EINVAL, "null argument");
+  const Setup &S = h->S;
+  std::memset(st, 0, sizeof(*st));
+  st->n_problems = (int)S.probs.size();
+  st->n_grids = (int)S.grids.size();
+  st->max_levels = S.maxL() + 1;
+  st->fine_rows = S.prob_off.back();
+  st->global_nnz = S.global_nnz;
+  st->composite_real_nnz = S.composite_real_nnz;
+  st->composite_rows = S.composite_rows;
+  st->composite_real_rows = S.composite_real_rows;
+  long long e = 0;
+  for (auto &B : S.lv) e += B.A.entries() + B.P.entries() + B.R.entries();
+  st->composite_stored_nnz = e;
+  st->omissions = S.omissions;
+  st->composite_overhead = S.global_nnz ? (double)S.composite_real_nnz / (double)S.global_nnz : 0.0;
+  st->setup_hierarchy_s = S.times.hierarchy;
+  st->setup_composite_s = S.times.composite;
+  st->setup_pack_s = S.times.pack;
+  st->setup_upload_s = S.times.upload;
+  st->device_bytes = h->dev_bytes;
+  return AMGDD_OK;
+}
+
+amgdd_status amgdd_get_levels(amgdd_handle h, int prob, int *nlevels, int *n_per_level, long long *nnz_per_level) {
+  if (!h || !nlevels || prob < 0 || prob >= (int)h->S.probs.size()) return fail(ST_EINVAL, "bad argument");
+  const Hierarchy &H = h->S.probs[prob].H;
+  *nlevels = H.L() + 1;
+  for (int l = 0; l <= H.L(); ++l) {
+    if (n_per_level) n_per_level[l] = H.A[l].nrows;
+    if (nnz_per_level) nnz_per_level[l] = H.A[l].nnz();
+  }
+  return AMGDD_OK;
+}
+
+amgdd_status amgdd_get_cf(amgdd_handle h, int prob, int level, signed char *cf) {
+  if (!h || !cf || prob < 0 || prob >= (int)h->S.probs.size()) return fail(ST_EINVAL, "bad argument");
+  const Hierarchy &H = h->S.probs[prob].H;
+  if (level < 0 || level >= H.L()) return fail(ST_EINVAL, "level has no C/F splitting");
+  std::memcpy(cf, H.cf[level].data(), H.cf[level].size());
+  return AMGDD_OK;
+}
+
+amgdd_status amgdd_get_operator(amgdd_handle h, int prob, int level, int which, int *nrows, int *nnz, int *rowptr,
+                                int *col, double *val) {
+  if (!h || !nrows || !nnz || prob < 0 || prob >= (int)h->S.probs.size()) return fail(ST_EINVAL, "bad argument");
+  const Hierarchy &H = h->S.probs[prob].H;
+  const Csr *M = nullptr;
+  if (which == 0 && level >= 0 && level <= H.L()) M = &H.A[level];
+  if (which == 1 && level >= 0 && level < H.L()) M = &H.P[level];
+  if (!M) return fail(ST_EINVAL, "no such operator");
+  *nrows = M->nrows;
+  *nnz = (int)M->nnz();
+  if (rowptr) std::memcpy(rowptr, M->ptr.data(), M->ptr.size() * sizeof(int));
+  if (col) std::memcpy(col, M->col.data(), M->col.size() * sizeof(int));
+  if (val) std::memcpy(val, M->val.data(), M->val.size() * sizeof(double));
+  return AMGDD_OK;
+}
+
+amgdd_status amgdd_get_composite(amgdd_handle h, int prob, int p, int level, int *n_real, int *n_bar, int *gids,
+                                 int *omissions) {
+  if (!h || prob < 0 || prob >= (int)h->S.probs.size()) return fail(ST_EINVAL, "bad problem");
+  const ProblemHost &P = h->S.probs[prob];
+  if (p < 0 || p >= P.nparts || level < 0 || level > P.H.L()) return fail(ST_EINVAL, "bad subdomain or level");
+  const CompLevel &lv = h->S.grids[P.grids[p]].lv[level];
+  if (n_real) *n_real = lv.nreal;
+  if (n_bar) *n_bar = lv.nbar();
+  if (gids) std::memcpy(gids, lv.gid.data(), lv.gid.size() * sizeof(int));
+  if (omissions) *omissions = lv.omissions;
+  return AMGDD_OK;
+}
+
+amgdd_status amgdd_get_history(amgdd_handle h, int prob, double *hist, int cap, int *len) {
+  if (!h || !len || prob < 0 || prob >= (int)h->S.probs.size()) return fail(ST_EINVAL, "bad argument");
+  if (prob >= (int)h->hist.size()) { *len = 0; return AMGDD_OK; }
+  const auto &v = h->hist[prob];
+  *len = (int)v.size();
+  if (hist)
+    for (int i = 0; i < std::min(cap, (int)v.size()); ++i) hist[i] = v[i];
+  return AMGDD_OK;
+}
+
+amgdd_status amgdd_profile(amgdd_handle h, int kind, int reps, amgdd_kernel_time *out, int cap, int *n) {
+  if (!h || !n || reps < 1 || (kind != 0 && kind != 1)) return fail(ST_EINVAL, "bad profile arguments");
+  if (h->host_only) return fail(ST_EDEVICE, "host-only handle");
+  HIP_TRY(hipSetDevice(h->device));
+  Prof prof;
+  struct Reset {
+    amgdd_ctx *h;
+    ~Reset() { h->prof = nullptr; }
+  } reset{h};
+  hipStream_t s = h->stream;
+  if (kind == 1) enqueue_residual<double>(h, s, true);
+  else if (h->mixed()) enqueue_residual<float>(h, s, false);
+  else enqueue_residual<double>(h, s, false);
+  h->prof = &prof;
+  for (int r = 0; r < reps; ++r) {
+    if (kind == 1) enqueue_v_iteration(h, s);
+    else if (h->mixed()) enqueue_dd_iteration<float>(h, s);
+    else enqueue_dd_iteration<double>(h, s);
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));
+  h->prof = nullptr;
+  struct Agg {
+    std::string name;
+    int level, launches;
+    double ms, bytes;
+  };
+  std::vector<Agg> agg;
+  for (auto &site : prof.sites) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, site.e0, site.e1));
+    Agg *a = nullptr;
+    for (auto &x : agg)
+      if (x.name == site.name && x.level == site.level) a = &x;
+    if (!a) {
+      agg.push_back(Agg{site.name, site.level, 0, 0.0, 0.0});
+      a = &agg.back();
+    }
+    a->launches++;
+    a->ms += ms;
+    a->bytes += site.bytes;
+  }
+  *n = (int)agg.size();
+  for (int i = 0; i < (int)agg.size() && out && i < cap; ++i) {
+    std::memset(&out[i], 0, sizeof(out[i]));
+    std::strncpy(out[i].name, agg[i].name.c_str(), sizeof(out[i].name) - 1);
+    out[i].level = agg[i].level;
+    out[i].launches = agg[i].launches / reps;
+    out[i].ms = agg[i].ms / reps;
+    out[i].bytes = agg[i].bytes / reps;
+  }
+  return AMGDD_OK;
+}
+
+amgdd_status amgdd_set_stream(amgdd_handle h, void *hip_stream) {
+  if (!h) return fail(ST_EINVAL, "null handle");
+  h->stream = (hipStream_t)hip_stream;
+  return AMGDD_OK;
+}
+
+const char *amgdd_last_error(void) { return g_last_error.c_str(); }
+
+void amgdd_destroy(amgdd_handle h) { delete h; }
+
+}  // extern "C"

@@ -1,0 +1,336 @@
+// CDNA4 (gfx950) kernels of the AMG-DD solve phase.
+//
+// Every matrix is a block-diagonal batch over all composite grids (or over
+// all problems for the global hierarchy) stored as sliced ELL with slice
+// height 64: one 64-wide wavefront owns one slice, lane k of the wavefront
+// owns row 64*s + k, and entry j of every row in the slice sits at
+// sptr[s] + 64*j + k, so each load instruction of a wavefront is one
+// contiguous 256-byte (int32) / 512-byte (FP64) segment.  Padding entries
+// carry value 0 and a valid column.
+//
+// The AlgFAC cycle (Algorithm 4 of the paper) is split into level-synchronous
+// passes, each fusing the vector updates of one algorithm step with the
+// mat-vec it needs:
+//   relax        delta = (f - A u) / d at real rows, u += delta, t (+)= delta
+//   w            w = s + A t                       (restrict update, part 1)
+//   down         s = R w_{l-1}; f <- f - A u - s;  (restrict update part 2,
+//                u <- 0; first relaxation from 0    recalculation, initialise)
+//   coarse       f <- f - A u - s; u = A_L^{-1} f   (dense, one workgroup/grid)
+//   interp       u += P u_{l+1}
+// Relaxation never reads and writes the same u buffer (Jacobi): it reads
+// buffer `u_in` and writes `u_out` for every row of the level (copies where it
+// does not relax); the driver flips the buffers.
+//
+// No MFMA: every step is a sparse mat-vec or a vector update (HBM bound).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace amgdd {
+namespace dev {
+
+constexpr int BLOCK = 256;
+constexpr int NXCD = 8;
+
+template <typename T>
+struct SellD {
+  const int *sptr;
+  const int *col;
+  const T *val;
+};
+
+// Workgroups are dispatched round-robin over the 8 XCDs; remap so that each
+// XCD processes one contiguous range of row blocks (neighbouring rows share
+// vector entries, which then stay in that XCD's L2).
+__device__ __forceinline__ int xcd_block() {
+  const int b = blockIdx.x, n = gridDim.x;
+  const int q = n / NXCD, r = n % NXCD;
+  const int x = b % NXCD, i = b / NXCD;
+  return x * q + (x < r ? x : r) + i;
+}
+
+__device__ __forceinline__ int row_of_thread() { return xcd_block() * BLOCK + (int)threadIdx.x; }
+
+// Dot product of row r of a sliced-ELL matrix with x, in stored order.
+// ALIGNED: the whole wavefront lies in one slice (rows assigned 64-aligned),
+// so the slice bounds are wave-uniform scalars.
+template <typename T, typename V, bool ALIGNED = true>
+__device__ __forceinline__ V sell_dot(const SellD<T> &M, int r, const V *__restrict__ x) {
+  int s = r >> 6;
+  if (ALIGNED) s = __builtin_amdgcn_readfirstlane(s);
+  const int beg = M.sptr[s];
+  const int w = (M.sptr[s + 1] - beg) >> 6;
+  const int *__restrict__ c = M.col + beg + (r & 63);
+  const T *__restrict__ v = M.val + beg + (r & 63);
+  V acc = V(0);
+  int k = 0;
+  for (; k + 2 <= w; k += 2) {
+    const int c0 = c[64 * k], c1 = c[64 * (k + 1)];
+    const V v0 = (V)v[64 * k], v1 = (V)v[64 * (k + 1)];
+    const V x0 = x[c0], x1 = x[c1];
+    acc = fma(v0, x0, acc);
+    acc = fma(v1, x1, acc);
+  }
+  if (k < w) acc = fma((V)v[64 * k], x[c[64 * k]], acc);
+  return acc;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Block-wide sum in a fixed order (deterministic).
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double part[BLOCK / 64];
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) part[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < BLOCK / 64; ++i) s += part[i];
+  return s;  // valid in thread 0
+}
+
+// ---------------------------------------------------------------- outer loop
+
+// r = b - A x on the fine level of every problem (FP64), plus per-block
+// partial sums of r^2.  Blocks never straddle two problems (block table).
+// VC: also the V-cycle's first relaxation from zero, e = r / d.
+template <typename TR, bool VC>
+__global__ __launch_bounds__(BLOCK) void k_resid(SellD<double> A, const double *__restrict__ b,
+                                                  const double *__restrict__ x, TR *__restrict__ r_out,
+                                                  double *__restrict__ partial, const int *__restrict__ blk_row0,
+                                                  const int *__restrict__ blk_row1, const double *__restrict__ dinv,
+                                                  double *__restrict__ e_out) {
+  const int blk = xcd_block();
+  const int row = blk_row0[blk] + (int)threadIdx.x;
+  double sq = 0.0;
+  if (row < blk_row1[blk]) {
+    const double r = b[row] - sell_dot<double, double, false>(A, row, x);
+    r_out[row] = (TR)r;
+    if (VC) e_out[row] = r * dinv[row];
+    sq = r * r;
+  }
+  const double s = block_sum(sq);
+  if (threadIdx.x == 0) partial[blk] = s;
+}
+
+// ||r||^2 of every problem from its blocks' partial sums (one workgroup per
+// problem, fixed summation order).
+__global__ __launch_bounds__(BLOCK) void k_norm_final(const double *__restrict__ partial,
+                                                       const int *__restrict__ prob_blk0, double *__restrict__ out) {
+  const int q = blockIdx.x;
+  const int b0 = prob_blk0[q], b1 = prob_blk0[q + 1];
+  double s = 0.0;
+  for (int b = b0 + (int)threadIdx.x; b < b1; b += BLOCK) s += partial[b];
+  s = block_sum(s);
+  if (threadIdx.x == 0) out[q] = s;
+}
+
+// y = M x over rows [0, n) (restriction chain r_{l+1} = R_l r_l).
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_spmv(SellD<T> M, int n, const T *__restrict__ x, T *__restrict__ y) {
+  const int i = row_of_thread();
+  if (i < n) y[i] = sell_dot<T, T>(M, i, x);
+}
+
+// Composite right-hand sides of every level at once: f[k] = r[src[k]] where
+// src[k] >= 0 (real points); ghost entries are left untouched.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_gather(int n, const int *__restrict__ src, const T *__restrict__ r,
+                                                   T *__restrict__ f) {
+  const int i = row_of_thread();
+  if (i < n) {
+    const int s = src[i];
+    if (s >= 0) f[i] = r[s];
+  }
+}
+
+// Correction patched on each owned subdomain: x[g] += u0[owner[g]].
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_patch(int n, double *__restrict__ x, const int *__restrict__ owner,
+                                                  const T *__restrict__ u0) {
+  const int i = row_of_thread();
+  if (i < n) x[i] += (double)u0[owner[i]];
+}
+
+// ---------------------------------------------------------------- AlgFAC
+
+// Level 0, first cycle (u = 0): delta = f / d at real rows; ghosts set to 0.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_relax_zero(int nr, int nb, const T *__restrict__ f,
+                                                       const T *__restrict__ dinv, T *__restrict__ u_out,
+                                                       T *__restrict__ t) {
+  const int i = row_of_thread();
+  if (i < nr) {
+    const T d = f[i] * dinv[i];
+    u_out[i] = d;
+    t[i] = d;
+  } else if (i < nb) {
+    u_out[i] = T(0);
+  }
+}
+
+// l1-Jacobi sweep at rows [0, nr); rows [nr, nb) are copied.
+// tmode: 0 t = delta, 1 t += delta, 2 no t.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_relax(SellD<T> A, int nr, int nb, const T *__restrict__ f,
+                                                  const T *__restrict__ dinv, const T *__restrict__ u_in,
+                                                  T *__restrict__ u_out, T *__restrict__ t, int tmode) {
+  const int i = row_of_thread();
+  if (i < nr) {
+    const T d = (f[i] - sell_dot<T, T>(A, i, u_in)) * dinv[i];
+    u_out[i] = u_in[i] + d;
+    if (tmode == 0) t[i] = d;
+    else if (tmode == 1) t[i] += d;
+  } else if (i < nb) {
+    u_out[i] = u_in[i];
+  }
+}
+
+// w = s + A t over rows [0, nb), in place in the s buffer (s is absent on
+// level 0).  t is zero at ghost points, so ghost rows store real columns only.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_w(SellD<T> A, int nb, T *__restrict__ sw, const T *__restrict__ t,
+                                              int has_s) {
+  const int i = row_of_thread();
+  if (i < nb) {
+    const T at = sell_dot<T, T>(A, i, t);
+    sw[i] = has_s ? sw[i] + at : at;
+  }
+}
+
+// Level l >= 1, normal rows [0, nb): s = R_{l-1} w_{l-1} (stored for the next
+// w pass); at real rows [0, nr) the coarse residual recalculation
+// f <- (f - A u) - s (skipped in the first cycle, where u = 0), then u <- 0
+// and the first relaxation from zero delta = f / d; ghost rows get u = 0.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_down(SellD<T> R, SellD<T> A, int nr, int nb, const T *__restrict__ w_prev,
+                                                 T *__restrict__ sw, T *__restrict__ f, const T *__restrict__ dinv,
+                                                 const T *__restrict__ u_in, T *__restrict__ u_out, T *__restrict__ t,
+                                                 int first) {
+  const int i = row_of_thread();
+  if (i >= nb) return;
+  const T s = sell_dot<T, T>(R, i, w_prev);
+  sw[i] = s;
+  if (i < nr) {
+    T fi = f[i];
+    if (!first) fi -= sell_dot<T, T>(A, i, u_in);
+    fi -= s;
+    f[i] = fi;
+    const T d = fi * dinv[i];
+    u_out[i] = d;
+    t[i] = first ? d : t[i] + d;
+  } else {
+    u_out[i] = T(0);
+  }
+}
+
+// Coarsest level, one workgroup per grid (or per problem):
+//   mode 0 (AlgFAC): f <- (f - A_L u) - R w_prev  (A_L u skipped when first),
+//                    u_out = A_L^{-1} f
+//   mode 1 (V-cycle): f = R w_prev, u_out = A_L^{-1} f
+// Arithmetic in FP64 (the coarsest solve stays FP64 in the mixed form).
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_coarse(SellD<T> R, int has_r, const T *__restrict__ w_prev,
+                                                   T *__restrict__ f, const T *__restrict__ u_in,
+                                                   T *__restrict__ u_out, const double *__restrict__ Ad,
+                                                   const double *__restrict__ Ainv, const int *__restrict__ row0,
+                                                   const int *__restrict__ nn, const int *__restrict__ doff, int mode,
+                                                   int first) {
+  extern __shared__ double sh[];
+  const int g = blockIdx.x;
+  const int r0 = row0[g], n = nn[g];
+  const double *Ag = Ad + doff[g];
+  const double *Ig = Ainv + doff[g];
+  double *fs = sh;       // n
+  double *us = sh + n;   // n
+  for (int i = threadIdx.x; i < n; i += BLOCK) {
+    us[i] = (mode == 0 && !first) ? (double)u_in[r0 + i] : 0.0;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += BLOCK) {
+    double s = 0.0;
+    if (has_r) {
+      // row r0+i of R; not wave-aligned in general
+      s = (double)sell_dot<T, T, false>(R, r0 + i, w_prev);
+    }
+    double fi;
+    if (mode == 0) {
+      fi = (double)f[r0 + i];
+      if (!first) {
+        double au = 0.0;
+        for (int j = 0; j < n; ++j) au = fma(Ag[(size_t)i * n + j], us[j], au);
+        fi -= au;
+      }
+      fi -= s;
+    } else {
+      fi = s;
+    }
+    fs[i] = fi;
+    f[r0 + i] = (T)fi;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += BLOCK) {
+    double u = 0.0;
+    for (int j = 0; j < n; ++j) u = fma(Ig[(size_t)i * n + j], fs[j], u);
+    u_out[r0 + i] = (T)u;
+  }
+}
+
+// u += P u_c over rows [0, nb).
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_interp(SellD<T> P, int nb, T *__restrict__ u, const T *__restrict__ uc) {
+  const int i = row_of_thread();
+  if (i < nb) u[i] += sell_dot<T, T>(P, i, uc);
+}
+
+// ---------------------------------------------------------------- V-cycle
+
+// q = f - A e over rows [0, n).
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_vresid(SellD<T> A, int n, const T *__restrict__ f, const T *__restrict__ e,
+                                                   T *__restrict__ q) {
+  const int i = row_of_thread();
+  if (i < n) q[i] = f[i] - sell_dot<T, T>(A, i, e);
+}
+
+// f = R q_prev, e = f / d (relaxation from zero) over rows [0, n).
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_vdown(SellD<T> R, int n, const T *__restrict__ q_prev, T *__restrict__ f,
+                                                  const T *__restrict__ dinv, T *__restrict__ e) {
+  const int i = row_of_thread();
+  if (i < n) {
+    const T fi = sell_dot<T, T>(R, i, q_prev);
+    f[i] = fi;
+    e[i] = fi * dinv[i];
+  }
+}
+
+// Level-0 post-relaxation fused with the iterate update:
+// x += e + (f - A e) / d.
+__global__ __launch_bounds__(BLOCK) void k_vfinal(SellD<double> A, int n, const double *__restrict__ f,
+                                                   const double *__restrict__ dinv, const double *__restrict__ e,
+                                                   double *__restrict__ x) {
+  const int i = row_of_thread();
+  if (i < n) x[i] += e[i] + (f[i] - sell_dot<double, double>(A, i, e)) * dinv[i];
+}
+
+// ---------------------------------------------------------------- adjoint
+
+// dL/dc_f = -(lam_i - lam_j)(u_i - u_j) (interior), -lam_i u_i (j < 0).
+__global__ __launch_bounds__(BLOCK) void k_face_grad(int nf, const int *__restrict__ fi, const int *__restrict__ fj,
+                                                      const double *__restrict__ u, const double *__restrict__ lam,
+                                                      double *__restrict__ out) {
+  const int k = row_of_thread();
+  if (k < nf) {
+    const int i = fi[k], j = fj[k];
+    out[k] = j >= 0 ? -(lam[i] - lam[j]) * (u[i] - u[j]) : -lam[i] * u[i];
+  }
+}
+
+}  // namespace dev
+}  // namespace amgdd

@@ -1,0 +1,943 @@
+// Host setup of the AMG-DD solve phase: classical AMG hierarchy, composite
+// grids of every subdomain, and the block-diagonal batched layouts that the
+// device kernels consume.
+//
+// Paper references (Mitchell, Strzodka, Falgout, AMG-DD):
+//   Section 2   C/F splitting from strength of connection, interpolation P,
+//               R = P^T, Galerkin coarse operators, direct coarsest solve.
+//   Section 3   composite grids: padding eta_l through the graph of A_l on
+//               every level, C-points carried to the next level, coarsest
+//               level stored whole (Figure 1).
+//   Section 4.1 ghost extension Dbar_l = D_l plus the row stencils of D_l.
+//   Section 4.2 interpolation columns outside Dbar_{l+1} are dropped
+//               (connectivity assumption); the count is reported.
+// The paper runs its setup on the CPU as well and names global-to-local
+// reindexing as its dominant cost; here reindexing uses per-thread stamp
+// arrays and all composite grids are built in parallel.
+//
+// Readings where the paper defers to its host AMG library:
+//   strength: j in S_i iff j != i, m_i = max_{k!=i}(-a_ik) > 0 and
+//             -a_ij >= theta m_i (1 - 1e-12)
+//   RS first pass only; largest measure first, smallest index on ties
+//   direct interpolation with positive off-diagonals lumped into the diagonal
+//   Galerkin product on the symbolic pattern, values from R (A P)
+// Floating-point row sums run sequentially in ascending column order and the
+// file is compiled without FMA contraction, so the hierarchy is reproducible.
+
+#include "amgdd_internal.h"
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <limits>
+#include <mutex>
+#include <queue>
+#include <stdexcept>
+#include <thread>
+
+namespace amgdd {
+
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+bool verbose() {
+  static int v = std::getenv("AMGDD_VERBOSE") ? 1 : 0;
+  return v != 0;
+}
+
+void vlog(const char *what, double t0) {
+  if (verbose()) std::fprintf(stderr, "[amgdd setup] %-28s %8.3f s\n", what, now_s() - t0);
+}
+
+int n_threads() {
+  const char *e = std::getenv("AMGDD_THREADS");
+  int n = e ? std::atoi(e) : (int)std::thread::hardware_concurrency();
+  if (n < 1) n = 1;
+  if (n > 64) n = 64;
+  return n;
+}
+
+// Static chunking: f(begin, end, thread_id).
+void parallel_for(long long n, const std::function<void(long long, long long, int)> &f, long long grain = 4096) {
+  int nt = n_threads();
+  long long maxt = (n + grain - 1) / grain;
+  if (maxt < nt) nt = (int)std::max(1LL, maxt);
+  if (nt <= 1) {
+    f(0, n, 0);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; ++t) {
+    long long b = n * t / nt, e = n * (t + 1) / nt;
+    th.emplace_back([&f, b, e, t] { f(b, e, t); });
+  }
+  for (auto &x : th) x.join();
+}
+
+// Dynamic work queue over items: f(item, thread_id).
+void parallel_items(int n, const std::function<void(int, int)> &f) {
+  int nt = std::min(n_threads(), std::max(1, n));
+  if (nt <= 1) {
+    for (int i = 0; i < n; ++i) f(i, 0);
+    return;
+  }
+  std::atomic<int> next(0);
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; ++t)
+    th.emplace_back([&, t] {
+      for (;;) {
+        int i = next.fetch_add(1);
+        if (i >= n) break;
+        f(i, t);
+      }
+    });
+  for (auto &x : th) x.join();
+}
+
+std::vector<double> l1_rowsum(const Csr &A) {
+  std::vector<double> d(A.nrows);
+  for (int i = 0; i < A.nrows; ++i) {
+    double s = 0.0;
+    for (int jj = A.ptr[i]; jj < A.ptr[i + 1]; ++jj) s += std::fabs(A.val[jj]);
+    d[i] = s;
+  }
+  return d;
+}
+
+Csr pattern_transpose(const Csr &A) {
+  Csr T;
+  T.nrows = A.ncols;
+  T.ncols = A.nrows;
+  T.ptr.assign(T.nrows + 1, 0);
+  for (int jj = 0; jj < (int)A.nnz(); ++jj) T.ptr[A.col[jj] + 1]++;
+  for (int i = 0; i < T.nrows; ++i) T.ptr[i + 1] += T.ptr[i];
+  T.col.resize(A.nnz());
+  std::vector<int> pos(T.ptr.begin(), T.ptr.end() - 1);
+  for (int i = 0; i < A.nrows; ++i)
+    for (int jj = A.ptr[i]; jj < A.ptr[i + 1]; ++jj) T.col[pos[A.col[jj]]++] = i;
+  return T;
+}
+
+// Undirected graph of the stored pattern without the diagonal.
+Csr adjacency(const Csr &A) {
+  Csr T = pattern_transpose(A);
+  Csr G;
+  G.nrows = G.ncols = A.nrows;
+  G.ptr.assign(A.nrows + 1, 0);
+  std::vector<int> buf;
+  std::vector<std::vector<int>> rows(A.nrows);
+  for (int i = 0; i < A.nrows; ++i) {
+    int a = A.ptr[i], ae = A.ptr[i + 1], t = T.ptr[i], te = T.ptr[i + 1];
+    buf.clear();
+    while (a < ae || t < te) {
+      int c;
+      if (t >= te || (a < ae && A.col[a] < T.col[t])) c = A.col[a++];
+      else if (a >= ae || T.col[t] < A.col[a]) c = T.col[t++];
+      else { c = A.col[a]; ++a; ++t; }
+      if (c != i) buf.push_back(c);
+    }
+    G.ptr[i + 1] = G.ptr[i] + (int)buf.size();
+    G.col.insert(G.col.end(), buf.begin(), buf.end());
+  }
+  return G;
+}
+
+// Dense inverse by Gauss-Jordan elimination with partial pivoting.
+bool dense_inverse(int n, const std::vector<double> &A, std::vector<double> &inv) {
+  std::vector<double> M(A);
+  inv.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    double best = std::fabs(M[(size_t)c * n + c]);
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(M[(size_t)r * n + c]) > best) { best = std::fabs(M[(size_t)r * n + c]); piv = r; }
+    if (!(best > 0.0)) return false;
+    if (piv != c)
+      for (int k = 0; k < n; ++k) {
+        std::swap(M[(size_t)c * n + k], M[(size_t)piv * n + k]);
+        std::swap(inv[(size_t)c * n + k], inv[(size_t)piv * n + k]);
+      }
+    double p = M[(size_t)c * n + c];
+    for (int k = 0; k < n; ++k) { M[(size_t)c * n + k] /= p; inv[(size_t)c * n + k] /= p; }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      double f = M[(size_t)r * n + c];
+      if (f == 0.0) continue;
+      for (int k = 0; k < n; ++k) {
+        M[(size_t)r * n + k] -= f * M[(size_t)c * n + k];
+        inv[(size_t)r * n + k] -= f * inv[(size_t)c * n + k];
+      }
+    }
+  }
+  return true;
+}
+
+// CSR (batched, already remapped) -> sliced ELL with slice height 64.
+Sell csr_to_sell(const Csr &M) {
+  Sell S;
+  S.nrows = M.nrows;
+  int ns = (M.nrows + 63) / 64;
+  S.sptr.assign(ns + 1, 0);
+  std::vector<int> width(ns, 0);
+  for (int s = 0; s < ns; ++s) {
+    int w = 0;
+    for (int r = s * 64; r < std::min(M.nrows, s * 64 + 64); ++r) w = std::max(w, M.ptr[r + 1] - M.ptr[r]);
+    width[s] = w;
+  }
+  long long tot = 0;
+  for (int s = 0; s < ns; ++s) {
+    tot += 64LL * width[s];
+    if (tot > std::numeric_limits<int>::max()) throw std::length_error("sliced-ELL layout exceeds 2^31 entries");
+    S.sptr[s + 1] = (int)tot;
+  }
+  S.col.resize(tot);
+  S.val.resize(tot);
+  parallel_for(ns, [&](long long b, long long e, int) {
+    for (long long s = b; s < e; ++s) {
+      int base = S.sptr[s], w = width[s];
+      int beg[64], len[64], pad[64];
+      for (int lane = 0; lane < 64; ++lane) {
+        int r = (int)s * 64 + lane;
+        len[lane] = r < M.nrows ? M.ptr[r + 1] - M.ptr[r] : 0;
+        beg[lane] = r < M.nrows ? M.ptr[r] : 0;
+        pad[lane] = len[lane] > 0 ? M.col[M.ptr[r + 1] - 1] : 0;
+      }
+      for (int k = 0; k < w; ++k) {
+        int *cdst = S.col.data() + (size_t)base + (size_t)k * 64;
+        double *vdst = S.val.data() + (size_t)base + (size_t)k * 64;
+        for (int lane = 0; lane < 64; ++lane) {
+          if (k < len[lane]) {
+            cdst[lane] = M.col[beg[lane] + k];
+            vdst[lane] = M.val[beg[lane] + k];
+          } else {
+            cdst[lane] = pad[lane];
+            vdst[lane] = 0.0;
+          }
+        }
+      }
+    }
+  }, 64);
+  return S;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// AMG components (Section 2)
+
+Csr strength(const Csr &A, double theta) {
+  const int n = A.nrows;
+  Csr S;
+  S.nrows = S.ncols = n;
+  S.ptr.assign(n + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    double m = -std::numeric_limits<double>::infinity();
+    for (int jj = A.ptr[i]; jj < A.ptr[i + 1]; ++jj)
+      if (A.col[jj] != i) m = std::max(m, -A.val[jj]);
+    if (m > 0.0) {
+      double thr = theta * m * (1.0 - 1e-12);
+      for (int jj = A.ptr[i]; jj < A.ptr[i + 1]; ++jj)
+        if (A.col[jj] != i && -A.val[jj] >= thr) S.col.push_back(A.col[jj]);
+    }
+    S.ptr[i + 1] = (int)S.col.size();
+  }
+  return S;
+}
+
+std::vector<int8_t> rs_first_pass(const Csr &S) {
+  const int n = S.nrows;
+  Csr T = pattern_transpose(S);  // row i: points that i strongly influences
+  std::vector<long long> lam(n);
+  std::vector<int8_t> st(n, 0);
+  std::priority_queue<unsigned long long> pq;
+  auto key = [](long long l, int i) -> unsigned long long {
+    return ((unsigned long long)l << 32) | (unsigned long long)(0xFFFFFFFFu - (unsigned)i);
+  };
+  for (int i = 0; i < n; ++i) {
+    lam[i] = T.ptr[i + 1] - T.ptr[i];
+    if (S.ptr[i + 1] == S.ptr[i] && lam[i] == 0) st[i] = -1;
+  }
+  {
+    std::vector<unsigned long long> init;
+    init.reserve(n);
+    for (int i = 0; i < n; ++i)
+      if (st[i] == 0) init.push_back(key(lam[i], i));
+    pq = std::priority_queue<unsigned long long>(std::less<unsigned long long>(), std::move(init));
+  }
+  std::vector<int> newf;
+  while (!pq.empty()) {
+    unsigned long long k = pq.top();
+    pq.pop();
+    int i = (int)(0xFFFFFFFFu - (unsigned)(k & 0xFFFFFFFFull));
+    long long l = (long long)(k >> 32);
+    if (st[i] != 0 || l != lam[i]) continue;
+    if (lam[i] == 0) {
+      for (int u = 0; u < n; ++u) {
+        if (st[u] != 0) continue;
+        bool has_c = false;
+        for (int jj = S.ptr[u]; jj < S.ptr[u + 1]; ++jj)
+          if (st[S.col[jj]] == 1) { has_c = true; break; }
+        st[u] = has_c ? -1 : 1;
+      }
+      break;
+    }
+    st[i] = 1;
+    newf.clear();
+    for (int jj = T.ptr[i]; jj < T.ptr[i + 1]; ++jj)
+      if (st[T.col[jj]] == 0) newf.push_back(T.col[jj]);
+    for (int j : newf) st[j] = -1;
+    for (int j : newf)
+      for (int kk = S.ptr[j]; kk < S.ptr[j + 1]; ++kk) {
+        int q = S.col[kk];
+        if (st[q] == 0) { lam[q] += 1; pq.push(key(lam[q], q)); }
+      }
+    for (int jj = S.ptr[i]; jj < S.ptr[i + 1]; ++jj) {
+      int q = S.col[jj];
+      if (st[q] == 0) { lam[q] -= 1; pq.push(key(lam[q], q)); }
+    }
+  }
+  return st;
+}
+
+Csr direct_interpolation(const Csr &A, const Csr &S, const std::vector<int8_t> &cf) {
+  const int n = A.nrows;
+  std::vector<int> cidx(n, -1);
+  int nc = 0;
+  for (int i = 0; i < n; ++i)
+    if (cf[i] == 1) cidx[i] = nc++;
+  Csr P;
+  P.nrows = n;
+  P.ncols = nc;
+  P.ptr.assign(n + 1, 0);
+  std::vector<char> inp;
+  for (int i = 0; i < n; ++i) {
+    if (cf[i] == 1) {
+      P.col.push_back(cidx[i]);
+      P.val.push_back(1.0);
+    } else {
+      const int a0 = A.ptr[i], a1 = A.ptr[i + 1];
+      inp.assign(a1 - a0, 0);
+      // membership in S_i by a merge of two sorted rows
+      int s = S.ptr[i];
+      for (int jj = a0; jj < a1; ++jj) {
+        int c = A.col[jj];
+        while (s < S.ptr[i + 1] && S.col[s] < c) ++s;
+        bool strong = s < S.ptr[i + 1] && S.col[s] == c;
+        inp[jj - a0] = strong && cf[c] == 1;
+      }
+      double neg = 0.0, pos = 0.0, den = 0.0, diag = 0.0;
+      bool any = false;
+      for (int jj = a0; jj < a1; ++jj) {
+        int c = A.col[jj];
+        double v = A.val[jj];
+        neg += (c != i) ? std::min(v, 0.0) : 0.0;
+        pos += (c != i) ? std::max(v, 0.0) : 0.0;
+        den += inp[jj - a0] ? v : 0.0;
+        if (c == i) diag = v;
+        any = any || inp[jj - a0];
+      }
+      if (any) {
+        double at = diag + pos;
+        double alpha = neg / den;
+        for (int jj = a0; jj < a1; ++jj)
+          if (inp[jj - a0]) {
+            P.col.push_back(cidx[A.col[jj]]);
+            P.val.push_back((-alpha * A.val[jj]) / at);
+          }
+      }
+    }
+    P.ptr[i + 1] = (int)P.col.size();
+  }
+  return P;
+}
+
+Csr transpose(const Csr &A) {
+  Csr T;
+  T.nrows = A.ncols;
+  T.ncols = A.nrows;
+  T.ptr.assign(T.nrows + 1, 0);
+  for (long long jj = 0; jj < A.nnz(); ++jj) T.ptr[A.col[jj] + 1]++;
+  for (int i = 0; i < T.nrows; ++i) T.ptr[i + 1] += T.ptr[i];
+  T.col.resize(A.nnz());
+  T.val.resize(A.nnz());
+  std::vector<int> pos(T.ptr.begin(), T.ptr.end() - 1);
+  for (int i = 0; i < A.nrows; ++i)
+    for (int jj = A.ptr[i]; jj < A.ptr[i + 1]; ++jj) {
+      int p = pos[A.col[jj]]++;
+      T.col[p] = i;
+      T.val[p] = A.val[jj];
+    }
+  return T;
+}
+
+// Row-by-row product; every product term creates an entry (symbolic
+// pattern), accumulated in the order of A's row then B's row.
+Csr spgemm(const Csr &A, const Csr &B) {
+  const int n = A.nrows, m = B.ncols;
+  int nt = n_threads();
+  long long chunks = std::max(1LL, std::min<long long>(4LL * nt, (n + 1023) / 1024));
+  std::vector<std::vector<int>> ccol(chunks), clen(chunks);
+  std::vector<std::vector<double>> cval(chunks);
+  std::atomic<long long> next(0);
+  auto work = [&] {
+    std::vector<double> acc(m, 0.0);
+    std::vector<int> mark(m, -1), list;
+    for (;;) {
+      long long c = next.fetch_add(1);
+      if (c >= chunks) break;
+      int r0 = (int)(n * c / chunks), r1 = (int)(n * (c + 1) / chunks);
+      auto &oc = ccol[c];
+      auto &ov = cval[c];
+      auto &ol = clen[c];
+      for (int i = r0; i < r1; ++i) {
+        list.clear();
+        for (int jj = A.ptr[i]; jj < A.ptr[i + 1]; ++jj) {
+          int k = A.col[jj];
+          double a = A.val[jj];
+          for (int kk = B.ptr[k]; kk < B.ptr[k + 1]; ++kk) {
+            int j = B.col[kk];
+            if (mark[j] != i) { mark[j] = i; acc[j] = 0.0; list.push_back(j); }
+            acc[j] += a * B.val[kk];
+          }
+        }
+        std::sort(list.begin(), list.end());
+        for (int j : list) { oc.push_back(j); ov.push_back(acc[j]); }
+        ol.push_back((int)list.size());
+      }
+    }
+  };
+  int nth = (int)std::min<long long>(nt, chunks);
+  std::vector<std::thread> th;
+  for (int t = 1; t < nth; ++t) th.emplace_back(work);
+  work();
+  for (auto &x : th) x.join();
+  Csr C;
+  C.nrows = n;
+  C.ncols = m;
+  C.ptr.assign(n + 1, 0);
+  long long tot = 0;
+  int row = 0;
+  for (long long c = 0; c < chunks; ++c)
+    for (int len : clen[c]) { tot += len; C.ptr[++row] = (int)tot; }
+  if (tot > std::numeric_limits<int>::max()) throw std::length_error("product exceeds 2^31 nonzeros");
+  C.col.reserve(tot);
+  C.val.reserve(tot);
+  for (long long c = 0; c < chunks; ++c) {
+    C.col.insert(C.col.end(), ccol[c].begin(), ccol[c].end());
+    C.val.insert(C.val.end(), cval[c].begin(), cval[c].end());
+  }
+  return C;
+}
+
+// ---------------------------------------------------------------------------
+
+namespace {
+
+int validate(const ProblemInput &in, int max_coarse, std::string &err) {
+  if (in.n <= 0 || !in.rowptr || !in.colind || !in.val || !in.part) { err = "null array or n <= 0"; return ST_EINVAL; }
+  if (in.nparts <= 0 || in.nparts > in.n) { err = "nparts out of range"; return ST_EINVAL; }
+  if (in.eta < 0) { err = "negative padding"; return ST_EINVAL; }
+  if (in.rowptr[0] != 0) { err = "rowptr[0] != 0"; return ST_EINVAL; }
+  for (int i = 0; i < in.n; ++i) {
+    int a = in.rowptr[i], b = in.rowptr[i + 1];
+    if (b < a) { err = "rowptr not monotone at row " + std::to_string(i); return ST_EINVAL; }
+    bool diag = false;
+    for (int jj = a; jj < b; ++jj) {
+      int c = in.colind[jj];
+      if (c < 0 || c >= in.n) { err = "column out of range in row " + std::to_string(i); return ST_EINVAL; }
+      if (jj > a && c <= in.colind[jj - 1]) { err = "columns not sorted/unique in row " + std::to_string(i); return ST_EINVAL; }
+      if (!std::isfinite(in.val[jj])) { err = "non-finite value in row " + std::to_string(i); return ST_EINVAL; }
+      if (c == i) {
+        diag = true;
+        if (!(in.val[jj] > 0.0)) { err = "non-positive diagonal in row " + std::to_string(i); return ST_EINVAL; }
+      }
+    }
+    if (!diag) { err = "missing diagonal in row " + std::to_string(i); return ST_EINVAL; }
+  }
+  std::vector<int> cnt(in.nparts, 0);
+  for (int i = 0; i < in.n; ++i) {
+    if (in.part[i] < 0 || in.part[i] >= in.nparts) { err = "part value out of range"; return ST_EINVAL; }
+    cnt[in.part[i]]++;
+  }
+  for (int p = 0; p < in.nparts; ++p)
+    if (cnt[p] == 0) { err = "empty subdomain " + std::to_string(p); return ST_EINVAL; }
+  if (in.n <= max_coarse) { err = "problem not larger than max_coarse: no multigrid levels"; return ST_EUNSUP; }
+  return ST_OK;
+}
+
+int build_hierarchy(ProblemHost &P, double theta, int max_coarse, int max_levels, std::string &err) {
+  Hierarchy &H = P.H;
+  H.A.push_back(P.A0);
+  while (H.A.back().nrows > max_coarse && (int)H.A.size() < max_levels) {
+    const Csr &A = H.A.back();
+    Csr S = strength(A, theta);
+    std::vector<int8_t> cf = rs_first_pass(S);
+    int nc = 0;
+    for (auto c : cf) nc += c == 1;
+    if (nc == 0 || nc == A.nrows) break;
+    Csr Pm = direct_interpolation(A, S, cf);
+    Csr R = transpose(Pm);
+    Csr AP = spgemm(A, Pm);
+    Csr Ac = spgemm(R, AP);
+    H.cf.push_back(std::move(cf));
+    H.P.push_back(std::move(Pm));
+    H.R.push_back(std::move(R));
+    H.A.push_back(std::move(Ac));
+  }
+  if (H.L() < 1) { err = "coarsening produced no coarse level"; return ST_EUNSUP; }
+  for (auto &A : H.A) H.l1.push_back(l1_rowsum(A));
+  const Csr &Ac = H.A.back();
+  int nl = Ac.nrows;
+  if (nl > 1024) { err = "coarsest level has " + std::to_string(nl) + " > 1024 points"; return ST_EUNSUP; }
+  H.Ac.assign((size_t)nl * nl, 0.0);
+  for (int i = 0; i < nl; ++i)
+    for (int jj = Ac.ptr[i]; jj < Ac.ptr[i + 1]; ++jj) H.Ac[(size_t)i * nl + Ac.col[jj]] = Ac.val[jj];
+  if (!dense_inverse(nl, H.Ac, H.Ac_inv)) { err = "singular coarsest operator"; return ST_EINVAL; }
+  return ST_OK;
+}
+
+struct Stamp {
+  std::vector<int> mark, idx;
+  int epoch = 0;
+  void size(int n) {
+    if ((int)mark.size() < n) { mark.assign(n, 0); idx.assign(n, 0); epoch = 0; }
+  }
+  int next() {
+    if (++epoch == std::numeric_limits<int>::max()) { std::fill(mark.begin(), mark.end(), 0); epoch = 1; }
+    return epoch;
+  }
+};
+
+struct Scratch {
+  Stamp a, b, c;
+  std::vector<int> front, nxt, list;
+};
+
+// Composite sets of one subdomain (Section 3, Section 4.1).
+void build_sets(const ProblemHost &P, const std::vector<Csr> &G, const std::vector<std::vector<int>> &cmap, int p,
+                CompGrid &cg, Scratch &sc) {
+  const Hierarchy &H = P.H;
+  const int L = H.L();
+  cg.lv.assign(L + 1, CompLevel());
+  std::vector<int> seeds;
+  for (int i = 0; i < P.n; ++i)
+    if (P.part[i] == p) seeds.push_back(i);
+  cg.owned_gid = seeds;
+  for (int l = 0; l <= L; ++l) {
+    const int nl = H.A[l].nrows;
+    sc.a.size(nl);
+    CompLevel &lv = cg.lv[l];
+    std::vector<int> D;
+    if (l == L) {
+      D.resize(nl);
+      for (int i = 0; i < nl; ++i) D[i] = i;
+    } else {
+      int e = sc.a.next();
+      D = seeds;
+      for (int s : seeds) sc.a.mark[s] = e;
+      sc.front = seeds;
+      for (int r = 0; r < P.eta && !sc.front.empty(); ++r) {
+        sc.nxt.clear();
+        for (int v : sc.front)
+          for (int jj = G[l].ptr[v]; jj < G[l].ptr[v + 1]; ++jj) {
+            int u = G[l].col[jj];
+            if (sc.a.mark[u] != e) { sc.a.mark[u] = e; sc.nxt.push_back(u); D.push_back(u); }
+          }
+        std::swap(sc.front, sc.nxt);
+      }
+      std::sort(D.begin(), D.end());
+    }
+    int e = sc.a.next();
+    for (int v : D) sc.a.mark[v] = e;
+    std::vector<int> ghost;
+    for (int v : D)
+      for (int jj = G[l].ptr[v]; jj < G[l].ptr[v + 1]; ++jj) {
+        int u = G[l].col[jj];
+        if (sc.a.mark[u] != e) { sc.a.mark[u] = e; ghost.push_back(u); }
+      }
+    std::sort(ghost.begin(), ghost.end());
+    lv.nreal = (int)D.size();
+    lv.gid = std::move(D);
+    lv.gid.insert(lv.gid.end(), ghost.begin(), ghost.end());
+    if (l < L) {
+      seeds.clear();
+      for (int i = 0; i < lv.nreal; ++i) {
+        int g = lv.gid[i];
+        if (H.cf[l][g] == 1) seeds.push_back(cmap[l][g]);
+      }
+    }
+  }
+}
+
+// Local operators of one composite grid (Sections 4.1, 4.2).
+void build_local_ops(const ProblemHost &P, CompGrid &cg, Scratch &sc) {
+  const Hierarchy &H = P.H;
+  const int L = H.L();
+  Stamp *cur = &sc.a, *nxt = &sc.b;
+  auto map_level = [&](Stamp &st, int l) {
+    st.size(H.A[l].nrows);
+    int e = st.next();
+    const auto &g = cg.lv[l].gid;
+    for (int i = 0; i < (int)g.size(); ++i) { st.mark[g[i]] = e; st.idx[g[i]] = i; }
+    return e;
+  };
+  int ecur = map_level(*cur, 0);
+  for (int l = 0; l <= L; ++l) {
+    CompLevel &lv = cg.lv[l];
+    const Csr &A = H.A[l];
+    const int nb = lv.nbar();
+    lv.A.nrows = lv.A.ncols = nb;
+    lv.A.ptr.assign(nb + 1, 0);
+    for (int i = 0; i < nb; ++i) {
+      int g = lv.gid[i];
+      for (int jj = A.ptr[g]; jj < A.ptr[g + 1]; ++jj) {
+        int c = A.col[jj];
+        if (cur->mark[c] != ecur) continue;  // only ghost rows can reach outside Dbar
+        int li = cur->idx[c];
+        if (i < lv.nreal || li < lv.nreal) { lv.A.col.push_back(li); lv.A.val.push_back(A.val[jj]); }
+      }
+      lv.A.ptr[i + 1] = (int)lv.A.col.size();
+    }
+    lv.dinv.resize(lv.nreal);
+    for (int i = 0; i < lv.nreal; ++i) lv.dinv[i] = 1.0 / H.l1[l][lv.gid[i]];
+    if (l < L) {
+      int enxt = map_level(*nxt, l + 1);
+      const Csr &Pg = H.P[l];
+      lv.P.nrows = nb;
+      lv.P.ncols = cg.lv[l + 1].nbar();
+      lv.P.ptr.assign(nb + 1, 0);
+      for (int i = 0; i < nb; ++i) {
+        int g = lv.gid[i];
+        for (int jj = Pg.ptr[g]; jj < Pg.ptr[g + 1]; ++jj) {
+          int c = Pg.col[jj];
+          if (nxt->mark[c] == enxt) { lv.P.col.push_back(nxt->idx[c]); lv.P.val.push_back(Pg.val[jj]); }
+          else lv.omissions++;
+        }
+        lv.P.ptr[i + 1] = (int)lv.P.col.size();
+      }
+      std::swap(cur, nxt);
+      ecur = enxt;
+    }
+  }
+  // owned points are real level-0 points; local index = position in the sorted real list
+  const auto &g0 = cg.lv[0].gid;
+  cg.owned_local.resize(cg.owned_gid.size());
+  for (size_t k = 0; k < cg.owned_gid.size(); ++k)
+    cg.owned_local[k] = (int)(std::lower_bound(g0.begin(), g0.begin() + cg.lv[0].nreal, cg.owned_gid[k]) - g0.begin());
+}
+
+}  // namespace
+
+int build_setup(const std::vector<ProblemInput> &in, double theta, int max_coarse, int max_levels, Setup &S,
+                std::string &err) {
+  try {
+    S.theta = theta;
+    S.max_coarse = max_coarse;
+    S.max_levels = max_levels;
+    const int nprob = (int)in.size();
+    if (nprob <= 0) { err = "no problems"; return ST_EINVAL; }
+    if (!(theta > 0.0 && theta <= 1.0) || max_coarse < 1 || max_levels < 2) { err = "bad AMG parameters"; return ST_EINVAL; }
+    for (int q = 0; q < nprob; ++q) {
+      int st = validate(in[q], max_coarse, err);
+      if (st) { err = "problem " + std::to_string(q) + ": " + err; return st; }
+    }
+    // ---- hierarchies
+    double t0 = now_s();
+    S.probs.resize(nprob);
+    std::vector<int> status(nprob, ST_OK);
+    std::vector<std::string> errs(nprob);
+    for (int q = 0; q < nprob; ++q) {
+      ProblemHost &P = S.probs[q];
+      P.n = in[q].n;
+      P.nparts = in[q].nparts;
+      P.eta = in[q].eta;
+      P.A0.nrows = P.A0.ncols = P.n;
+      P.A0.ptr.assign(in[q].rowptr, in[q].rowptr + P.n + 1);
+      long long nnz = P.A0.ptr[P.n];
+      P.A0.col.assign(in[q].colind, in[q].colind + nnz);
+      P.A0.val.assign(in[q].val, in[q].val + nnz);
+      P.part.assign(in[q].part, in[q].part + P.n);
+      // exact numerical symmetry (the adjoint then reuses the forward operators)
+      Csr T = transpose(P.A0);
+      P.symmetric = (T.col == P.A0.col && T.val == P.A0.val);
+    }
+    // problems are independent: build the hierarchies in parallel when batched
+    parallel_items(nprob, [&](int q, int) {
+      status[q] = build_hierarchy(S.probs[q], theta, max_coarse, max_levels, errs[q]);
+    });
+    for (int q = 0; q < nprob; ++q)
+      if (status[q]) { err = "problem " + std::to_string(q) + ": " + errs[q]; return status[q]; }
+    S.times.hierarchy = now_s() - t0;
+
+    // ---- composite grids
+    t0 = now_s();
+    int maxL = 0;
+    for (auto &P : S.probs) maxL = std::max(maxL, P.H.L());
+    for (int q = 0; q < nprob; ++q)
+      for (int p = 0; p < S.probs[q].nparts; ++p) {
+        S.probs[q].grids.push_back((int)S.grids.size());
+        CompGrid cg;
+        cg.prob = q;
+        cg.p = p;
+        S.grids.push_back(std::move(cg));
+      }
+    std::vector<std::vector<Csr>> graphs(nprob);
+    std::vector<std::vector<std::vector<int>>> cmaps(nprob);
+    parallel_items(nprob, [&](int q, int) {
+      const Hierarchy &H = S.probs[q].H;
+      for (int l = 0; l <= H.L(); ++l) graphs[q].push_back(adjacency(H.A[l]));
+      for (int l = 0; l < H.L(); ++l) {
+        std::vector<int> cm(H.A[l].nrows, -1);
+        int c = 0;
+        for (int i = 0; i < H.A[l].nrows; ++i)
+          if (H.cf[l][i] == 1) cm[i] = c++;
+        cmaps[q].push_back(std::move(cm));
+      }
+    });
+    int nt = n_threads();
+    std::vector<Scratch> scratch(nt);
+    parallel_items((int)S.grids.size(), [&](int g, int t) {
+      CompGrid &cg = S.grids[g];
+      const ProblemHost &P = S.probs[cg.prob];
+      build_sets(P, graphs[cg.prob], cmaps[cg.prob], cg.p, cg, scratch[t]);
+      build_local_ops(P, cg, scratch[t]);
+    });
+    graphs.clear();
+    cmaps.clear();
+    S.omissions = 0;
+    S.composite_real_nnz = S.global_nnz = S.composite_rows = S.composite_real_rows = 0;
+    for (auto &P : S.probs)
+      for (auto &A : P.H.A) S.global_nnz += A.nnz();
+    for (auto &cg : S.grids) {
+      const Hierarchy &H = S.probs[cg.prob].H;
+      for (int l = 0; l <= H.L(); ++l) {
+        const CompLevel &lv = cg.lv[l];
+        S.omissions += lv.omissions;
+        S.composite_rows += lv.nbar();
+        S.composite_real_rows += lv.nreal;
+        for (int i = 0; i < lv.nreal; ++i) S.composite_real_nnz += H.A[l].ptr[lv.gid[i] + 1] - H.A[l].ptr[lv.gid[i]];
+      }
+    }
+    S.times.composite = now_s() - t0;
+
+    // ---- batched layouts
+    t0 = now_s();
+    S.dense_off.assign(nprob, 0);
+    int doff = 0;
+    for (int q = 0; q < nprob; ++q) {
+      S.dense_off[q] = doff;
+      doff += (int)S.probs[q].H.Ac.size();
+      S.dense_A.insert(S.dense_A.end(), S.probs[q].H.Ac.begin(), S.probs[q].H.Ac.end());
+      S.dense_inv.insert(S.dense_inv.end(), S.probs[q].H.Ac_inv.begin(), S.probs[q].H.Ac_inv.end());
+    }
+    const int ng = (int)S.grids.size();
+    S.lv.assign(maxL + 1, BatchLevel());
+    // composite offsets per level: off[g] for normal real, ghost, or coarse rows
+    std::vector<std::vector<int>> roff(maxL + 1, std::vector<int>(ng, -1)), goff = roff, coff = roff;
+    std::vector<std::vector<int>> gro(maxL + 1, std::vector<int>(nprob, -1)), gco = gro;
+    for (int l = 0; l <= maxL; ++l) {
+      BatchLevel &B = S.lv[l];
+      int r = 0, gh = 0, c = 0;
+      for (int g = 0; g < ng; ++g) {
+        int L = S.probs[S.grids[g].prob].H.L();
+        const CompLevel *lv = l <= L ? &S.grids[g].lv[l] : nullptr;
+        if (!lv) continue;
+        if (L > l) { roff[l][g] = r; r += lv->nreal; goff[l][g] = gh; gh += lv->nbar() - lv->nreal; }
+        else { coff[l][g] = c; c += lv->nbar(); }
+      }
+      B.NRn = r;
+      B.NBn = r + gh;
+      B.NB = B.NBn + c;
+      int gn = 0, gc = 0;
+      for (int q = 0; q < nprob; ++q) {
+        int L = S.probs[q].H.L();
+        if (l > L) continue;
+        if (L > l) { gro[l][q] = gn; gn += S.probs[q].H.A[l].nrows; }
+        else { gco[l][q] = gc; gc += S.probs[q].H.A[l].nrows; }
+      }
+      B.GNn = gn;
+      B.GN = gn + gc;
+      if ((long long)B.NB >= std::numeric_limits<int>::max() / 2) throw std::length_error("level too large");
+    }
+    auto bidx = [&](int g, int l, int i) -> int {
+      const CompLevel &lv = S.grids[g].lv[l];
+      if (roff[l][g] >= 0) return i < lv.nreal ? roff[l][g] + i : S.lv[l].NRn + goff[l][g] + (i - lv.nreal);
+      return S.lv[l].NBn + coff[l][g] + i;
+    };
+    auto gbidx = [&](int q, int l, int i) -> int {
+      if (gro[l][q] >= 0) return gro[l][q] + i;
+      return S.lv[l].GNn + gco[l][q] + i;
+    };
+    vlog("pack: offsets", t0);
+    for (int l = 0; l <= maxL; ++l) {
+      BatchLevel &B = S.lv[l];
+      double tp = now_s();
+      // composite A (normal rows), P (normal rows), dinv, gsrc
+      Csr A, Pm;
+      A.nrows = A.ncols = B.NBn;
+      Pm.nrows = B.NBn;
+      Pm.ncols = l < maxL ? S.lv[l + 1].NB : 0;
+      A.ptr.assign(B.NBn + 1, 0);
+      Pm.ptr.assign(B.NBn + 1, 0);
+      B.dinv.assign(B.NRn, 0.0);
+      B.gsrc.assign(B.NB, -1);
+      std::vector<int> normal;
+      for (int g = 0; g < ng; ++g) {
+        if (roff[l][g] >= 0) normal.push_back(g);
+        else if (coff[l][g] >= 0) {
+          const CompLevel &lv = S.grids[g].lv[l];
+          B.cg_row0.push_back(B.NBn + coff[l][g]);
+          B.cg_n.push_back(lv.nbar());
+          B.cg_dense.push_back(S.dense_off[S.grids[g].prob]);
+          for (int i = 0; i < lv.nbar(); ++i) B.gsrc[B.NBn + coff[l][g] + i] = gbidx(S.grids[g].prob, l, lv.gid[i]);
+        }
+      }
+      for (int g : normal) {
+        const CompLevel &lv = S.grids[g].lv[l];
+        for (int i = 0; i < lv.nbar(); ++i) {
+          int row = bidx(g, l, i);
+          A.ptr[row + 1] = lv.A.ptr[i + 1] - lv.A.ptr[i];
+          Pm.ptr[row + 1] = lv.P.ptr[i + 1] - lv.P.ptr[i];
+        }
+      }
+      for (int i = 0; i < B.NBn; ++i) { A.ptr[i + 1] += A.ptr[i]; Pm.ptr[i + 1] += Pm.ptr[i]; }
+      A.col.resize(A.ptr[B.NBn]);
+      A.val.resize(A.ptr[B.NBn]);
+      Pm.col.resize(Pm.ptr[B.NBn]);
+      Pm.val.resize(Pm.ptr[B.NBn]);
+      parallel_items((int)normal.size(), [&](int k, int) {
+        int g = normal[k];
+        const CompLevel &lv = S.grids[g].lv[l];
+        int q = S.grids[g].prob;
+        for (int i = 0; i < lv.nbar(); ++i) {
+          int row = bidx(g, l, i);
+          int o = A.ptr[row];
+          for (int jj = lv.A.ptr[i]; jj < lv.A.ptr[i + 1]; ++jj, ++o) { A.col[o] = bidx(g, l, lv.A.col[jj]); A.val[o] = lv.A.val[jj]; }
+          o = Pm.ptr[row];
+          for (int jj = lv.P.ptr[i]; jj < lv.P.ptr[i + 1]; ++jj, ++o) { Pm.col[o] = bidx(g, l + 1, lv.P.col[jj]); Pm.val[o] = lv.P.val[jj]; }
+          if (i < lv.nreal) { B.dinv[row] = lv.dinv[i]; B.gsrc[row] = gbidx(q, l, lv.gid[i]); }
+        }
+      });
+      vlog("pack: composite CSR", tp);
+      tp = now_s();
+      B.nnzA_r = A.ptr[B.NRn];
+      B.nnzA = A.ptr[B.NBn];
+      B.nnzP = Pm.nnz();
+      B.A = csr_to_sell(A);
+      vlog("pack:   sell A", tp);
+      B.P = csr_to_sell(Pm);
+      vlog("pack:   sell P", tp);
+      if (l < maxL) {
+        Csr R = transpose(Pm);
+        vlog("pack:   transpose P", tp);
+        S.lv[l + 1].nnzR_n = R.ptr[S.lv[l + 1].NBn];
+        S.lv[l + 1].nnzR = R.nnz();
+        S.lv[l + 1].R = csr_to_sell(R);
+      }
+      vlog("pack: composite SELL+R", tp);
+      tp = now_s();
+      // global level l over problems
+      Csr GA, GP;
+      GA.nrows = GA.ncols = B.GN;
+      GP.nrows = B.GNn;
+      GP.ncols = l < maxL ? S.lv[l + 1].GN : 0;
+      GA.ptr.assign(B.GN + 1, 0);
+      GP.ptr.assign(B.GNn + 1, 0);
+      B.gdinv.assign(B.GNn, 0.0);
+      B.prob_row0.assign(nprob, -1);
+      for (int q = 0; q < nprob; ++q) {
+        const Hierarchy &H = S.probs[q].H;
+        if (l > H.L()) continue;
+        int base = gbidx(q, l, 0);
+        B.prob_row0[q] = base;
+        const Csr &Al = H.A[l];
+        for (int i = 0; i < Al.nrows; ++i) GA.ptr[base + i + 1] = Al.ptr[i + 1] - Al.ptr[i];
+        if (l < H.L())
+          for (int i = 0; i < Al.nrows; ++i) GP.ptr[base + i + 1] = H.P[l].ptr[i + 1] - H.P[l].ptr[i];
+        else {
+          B.gc_row0.push_back(base);
+          B.gc_n.push_back(Al.nrows);
+          B.gc_dense.push_back(S.dense_off[q]);
+        }
+      }
+      for (int i = 0; i < B.GN; ++i) GA.ptr[i + 1] += GA.ptr[i];
+      for (int i = 0; i < B.GNn; ++i) GP.ptr[i + 1] += GP.ptr[i];
+      GA.col.resize(GA.ptr[B.GN]);
+      GA.val.resize(GA.ptr[B.GN]);
+      GP.col.resize(GP.ptr[B.GNn]);
+      GP.val.resize(GP.ptr[B.GNn]);
+      parallel_items(nprob, [&](int q, int) {
+        const Hierarchy &H = S.probs[q].H;
+        if (l > H.L()) return;
+        int base = gbidx(q, l, 0);
+        const Csr &Al = H.A[l];
+        for (int i = 0; i < Al.nrows; ++i) {
+          int o = GA.ptr[base + i];
+          for (int jj = Al.ptr[i]; jj < Al.ptr[i + 1]; ++jj, ++o) { GA.col[o] = base + Al.col[jj]; GA.val[o] = Al.val[jj]; }
+        }
+        if (l < H.L()) {
+          int cbase = gbidx(q, l + 1, 0);
+          const Csr &Pl = H.P[l];
+          for (int i = 0; i < Al.nrows; ++i) {
+            int o = GP.ptr[base + i];
+            for (int jj = Pl.ptr[i]; jj < Pl.ptr[i + 1]; ++jj, ++o) { GP.col[o] = cbase + Pl.col[jj]; GP.val[o] = Pl.val[jj]; }
+            B.gdinv[base + i] = 1.0 / H.l1[l][i];
+          }
+        }
+      });
+      B.nnzGA_n = GA.ptr[B.GNn];
+      B.nnzGA = GA.nnz();
+      B.nnzGP = GP.nnz();
+      B.GA = csr_to_sell(GA);
+      B.GP = csr_to_sell(GP);
+      if (l < maxL) {
+        Csr GR = transpose(GP);
+        S.lv[l + 1].nnzGR_n = GR.ptr[S.lv[l + 1].GNn];
+        S.lv[l + 1].nnzGR = GR.nnz();
+        S.lv[l + 1].GR = csr_to_sell(GR);
+      }
+    }
+    vlog("pack: levels", t0);
+    // fine-vector offsets (every problem is normal on level 0, so problem order)
+    S.prob_off.assign(nprob + 1, 0);
+    for (int q = 0; q < nprob; ++q) S.prob_off[q + 1] = S.prob_off[q] + S.probs[q].n;
+    S.owner.assign(S.prob_off[nprob], -1);
+    for (int g = 0; g < ng; ++g) {
+      const CompGrid &cg = S.grids[g];
+      int base = S.prob_off[cg.prob];
+      for (size_t k = 0; k < cg.owned_gid.size(); ++k) S.owner[base + cg.owned_gid[k]] = bidx(g, 0, cg.owned_local[k]);
+    }
+    for (int v : S.owner)
+      if (v < 0) { err = "internal: fine point without owner"; return ST_EINVAL; }
+    // residual blocks of 256 rows that never straddle two problems
+    S.prob_blk0.assign(nprob + 1, 0);
+    for (int q = 0; q < nprob; ++q) {
+      S.prob_blk0[q] = (int)S.blk_row0.size();
+      for (int r = S.prob_off[q]; r < S.prob_off[q + 1]; r += 256) {
+        S.blk_row0.push_back(r);
+        S.blk_row1.push_back(std::min(r + 256, S.prob_off[q + 1]));
+        S.blk_prob.push_back(q);
+      }
+    }
+    S.prob_blk0[nprob] = (int)S.blk_row0.size();
+    S.times.pack = now_s() - t0;
+    return ST_OK;
+  } catch (const std::bad_alloc &) {
+    err = "host allocation failed during setup";
+    return ST_ENOMEM;
+  } catch (const std::length_error &e) {
+    err = std::string("layout too large: ") + e.what();
+    return ST_EUNSUP;
+  }
+}
+
+}  // namespace amgdd

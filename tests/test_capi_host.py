@@ -1,0 +1,146 @@
+"""CPU tests of the C-ABI library: it loads, exports every symbol the header
+declares, rejects malformed input, and its host setup (RS hierarchy,
+composite grids) matches the oracle bit-exactly.  No device calls: handles
+are created with device = -1 (host-only)."""
+
+import os
+import re
+
+import numpy as np
+import pytest
+from scipy import sparse
+
+from oracle import amg, composite
+from synth import config, grf, make_problem
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+amgdd = pytest.importorskip("paper_1906_10575_amd.amgdd")
+
+
+def _header_functions():
+    txt = open(os.path.join(ROOT, "include", "amgdd.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(amg[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = amgdd.load()
+    names = _header_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(amgdd.SIGNATURES) == names
+
+
+def _host(p, **kw):
+    return amgdd.Solver(p.A, p.part, p.nparts, padding=p.eta, device=-1, **kw)
+
+
+CASES = [
+    ("cfg1", lambda: config("cfg1")),
+    ("2d_var_eta2", lambda: make_problem((40, 36), (3, 2), eta=2, k=np.exp(grf((40, 36), 1.0, 8.0, 3)))),
+    ("3d_16_eta1", lambda: make_problem((16, 16, 16), (2, 2, 2), eta=1)),
+    ("3d_12_var_eta2", lambda: make_problem((12, 12, 12), (2, 3, 2), eta=2, k=np.exp(grf((12, 12, 12), 1.0, 8.0, 1)))),
+    ("cfg4_16", lambda: config("cfg4", scale=16)),
+]
+
+
+@pytest.mark.parametrize("name,make", CASES)
+def test_host_setup_bit_exact_with_oracle(name, make):
+    p = make()
+    s = _host(p)
+    H = amg.setup(p.A)
+    n, z = s.levels(0)
+    assert n.tolist() == [A.shape[0] for A in H.A]
+    assert z.tolist() == [A.nnz for A in H.A]
+    for l in range(H.L):
+        assert np.array_equal(s.cf(0, l), H.cf[l]), f"C/F level {l}"
+        P = s.operator(0, l, 1)
+        assert (P != H.P[l]).nnz == 0 and np.array_equal(P.indptr, H.P[l].indptr)
+        A = s.operator(0, l + 1, 0)
+        assert np.array_equal(A.indptr, H.A[l + 1].indptr) and np.array_equal(A.indices, H.A[l + 1].indices)
+        np.testing.assert_array_equal(A.data, H.A[l + 1].data)
+    comps = composite.build_all(H, p.part, p.nparts, p.eta)
+    for q, cg in enumerate(comps):
+        for l, lv in enumerate(cg.levels):
+            g, nr, om = s.composite(0, q, l)
+            assert nr == lv.n_real and np.array_equal(g, lv.gid), f"p {q} level {l}"
+            assert om == lv.omissions
+    st = s.stats()
+    assert st["n_grids"] == p.nparts
+    assert abs(st["composite_overhead"] - composite.composite_overhead(H, comps)) < 1e-14
+
+
+def test_batched_host_setup_matches_each_problem():
+    probs = [make_problem((24, 20), (2, 2), eta=1), make_problem((33, 33), (3, 3), eta=2),
+             make_problem((10, 10, 10), (2, 2, 1), eta=1, k=np.exp(grf((10, 10, 10), 1.0, 4.0, 5)))]
+    s = amgdd.Solver([p.A for p in probs], [p.part for p in probs], [p.nparts for p in probs],
+                     padding=[p.eta for p in probs], device=-1)
+    st = s.stats()
+    assert st["n_problems"] == 3 and st["n_grids"] == sum(p.nparts for p in probs)
+    for i, p in enumerate(probs):
+        H = amg.setup(p.A)
+        assert s.levels(i)[0].tolist() == [A.shape[0] for A in H.A]
+        for q in range(p.nparts):
+            D, Dbar = composite.composite_sets(H, p.part, q, p.eta)
+            for l in range(H.L + 1):
+                g, nr, _ = s.composite(i, q, l)
+                assert nr == D[l].sum() and set(g.tolist()) == set(np.nonzero(Dbar[l])[0].tolist())
+
+
+def test_cfg2_level0_sets_closed_form():
+    """Full-size 128^3 / 4^3 / eta 1: every subdomain's level-0 real and ghost
+    counts equal the L1-ball closed form (setup only, no solve)."""
+    from tests.test_oracle_composite import l1_ball_counts
+    p = config("cfg2")
+    s = _host(p)
+    d, db = l1_ball_counts((128,) * 3, (4,) * 3, 1)
+    for q in range(p.nparts):
+        g, nr, om = s.composite(0, q, 0)
+        assert (nr, g.size) == (d[q], db[q])
+    st = s.stats()
+    assert st["omissions"] == 0
+
+
+def _bad(A, part=None, nparts=1, **kw):
+    n = A.shape[0]
+    part = np.zeros(n, dtype=np.int32) if part is None else part
+    with pytest.raises(amgdd.AmgddError) as e:
+        amgdd.Solver(A, part, nparts, device=-1, **kw)
+    return e.value.status
+
+
+def test_error_paths():
+    p = make_problem((8, 8), (1, 1))
+    A = p.A.copy()
+    # unsorted columns
+    B = A.copy()
+    B.indices = B.indices.copy()
+    B.indices[[0, 1]] = B.indices[[1, 0]]
+    assert _bad(B) == amgdd.EINVAL
+    # zero diagonal
+    C = A.copy().tolil()
+    C[3, 3] = 0.0
+    C = C.tocsr()
+    C.eliminate_zeros()
+    assert _bad(C) == amgdd.EINVAL
+    # non-finite entry
+    D = A.copy()
+    D.data = D.data.copy()
+    D.data[5] = np.nan
+    assert _bad(D) == amgdd.EINVAL
+    # partition out of range / empty subdomain
+    assert _bad(A, part=np.full(64, 3, dtype=np.int32), nparts=2) == amgdd.EINVAL
+    assert _bad(A, part=np.zeros(64, dtype=np.int32), nparts=2) == amgdd.EINVAL
+    # too small for a hierarchy
+    small = make_problem((4, 4), (1, 1)).A
+    assert _bad(small) == amgdd.EUNSUPPORTED
+    # host-only handle refuses device work
+    s = amgdd.Solver(A, np.zeros(64, dtype=np.int32), 1, device=-1)
+    lib = amgdd.load()
+    info = amgdd.Info()
+    assert lib.amgdd_solve(s._h, None, None, 1e-8, 10, None) in (amgdd.EINVAL, amgdd.EDEVICE)
+    assert lib.amgdd_profile(s._h, 0, 1, None, 0, None) in (amgdd.EINVAL, amgdd.EDEVICE)
+    s.close()
+    s.close()  # idempotent
+    lib.amgdd_destroy(None)  # NULL accepted

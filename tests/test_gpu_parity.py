@@ -1,0 +1,286 @@
+"""GPU parity: the HIP path through the C ABI against the oracle, element by
+element, on seeded inputs.
+
+Bar: FP64 iterates within 1e-12 relative (||x_gpu - x_oracle|| <= 1e-12
+||x_oracle||) after every outer iteration / V-cycle; mixed precision reaches
+1e-8 relative residual evaluated in FP64 and its error against the FP64
+oracle is reported; adjoint gradients within 1e-6 of central differences."""
+
+import sys
+
+import numpy as np
+import pytest
+from scipy.sparse import linalg as spla
+
+from oracle import adjoint, amg, composite, cycles
+from synth import batch_config, config, grf, make_problem
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+amgdd = pytest.importorskip("paper_1906_10575_amd.amgdd")
+
+DEV = "cuda:0"
+
+
+def say(*a):
+    print("[gpu-test]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _t(x):
+    return torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64), device=DEV)
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+CASES = {
+    "cfg1": lambda: config("cfg1"),
+    "2d_var_eta2_nfac3": lambda: make_problem((44, 38), (3, 2), eta=2, n_fac=3, k=np.exp(grf((44, 38), 1.0, 8.0, 3))),
+    "3d_16_eta1": lambda: make_problem((16, 16, 16), (2, 2, 2), eta=1, n_fac=2),
+    "3d_20_var_eta2": lambda: make_problem((20, 18, 20), (2, 2, 3), eta=2, n_fac=2,
+                                           k=np.exp(grf((20, 18, 20), 1.0, 8.0, 1))),
+    "3d_30_ragged_4x4x4": lambda: make_problem((30, 30, 30), (4, 4, 4), eta=1, n_fac=2),
+}
+ITERS = {"cfg1": 10, "2d_var_eta2_nfac3": 5, "3d_16_eta1": 6, "3d_20_var_eta2": 4, "3d_30_ragged_4x4x4": 4}
+
+
+@pytest.fixture(scope="module")
+def oracle_cache():
+    return {}
+
+
+def _oracle(name, cache):
+    if name not in cache:
+        p = CASES[name]()
+        H = amg.setup(p.A)
+        comps = composite.build_all(H, p.part, p.nparts, p.eta)
+        cache[name] = (p, H, comps)
+    return cache[name]
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_amgdd_iterates_match_oracle(name, oracle_cache):
+    p, H, comps = _oracle(name, oracle_cache)
+    say("amgdd iterates", name, p.n, p.nparts, "eta", p.eta, "n_fac", p.n_fac)
+    s = amgdd.Solver(p.A, p.part, p.nparts, padding=p.eta, n_fac=p.n_fac)
+    b = _t(p.b)
+    x = torch.zeros_like(b)
+    xo = np.zeros(p.n)
+    coarse = cycles.CoarseSolver(H.A[H.L])
+    for k in range(ITERS[name]):
+        x, info, st = s.solve(b, x, rtol=0, maxit=1)
+        assert st == amgdd.OK and info.iters == 1
+        xo = cycles.amgdd_iteration(H, comps, p.b, xo, p.n_fac, coarse)
+        err = _rel(_np(x), xo)
+        say(f"  iter {k + 1}: rel err {err:.3e}")
+        assert err <= 1e-12, (k, err)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_vcycle_iterates_match_oracle(name, oracle_cache):
+    p, H, comps = _oracle(name, oracle_cache)
+    say("vcycle iterates", name)
+    s = amgdd.Solver(p.A, p.part, p.nparts, padding=p.eta, n_fac=p.n_fac)
+    b = _t(p.b)
+    x = torch.zeros_like(b)
+    xo = np.zeros(p.n)
+    coarse = cycles.CoarseSolver(H.A[H.L])
+    for k in range(10):
+        x, info, st = s.vsolve(b, x, rtol=0, maxit=1)
+        xo = cycles.vcycle(H, xo, p.b, coarse=coarse)
+        err = _rel(_np(x), xo)
+        assert err <= 1e-12, (k, err)
+
+
+def test_graph_eager_and_repeat_are_bitwise_identical():
+    p = CASES["3d_20_var_eta2"]()
+    say("graph vs eager", p.n)
+    b = _t(p.b)
+    outs = []
+    for use_graph in (True, False, True):
+        s = amgdd.Solver(p.A, p.part, p.nparts, padding=p.eta, n_fac=p.n_fac, use_graph=use_graph)
+        x, info, st = s.solve(b, rtol=0, maxit=5)
+        xv, _, _ = s.vsolve(b, rtol=0, maxit=5)
+        # a second solve on the same handle replays the same graph
+        x2, _, _ = s.solve(b, rtol=0, maxit=5)
+        assert torch.equal(x, x2)
+        outs.append((_np(x), _np(xv)))
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
+
+
+def test_stopping_history_matches_oracle(oracle_cache):
+    p, H, comps = _oracle("3d_16_eta1", oracle_cache)
+    say("rtol stop 1e-8")
+    s = amgdd.Solver(p.A, p.part, p.nparts, padding=p.eta, n_fac=p.n_fac)
+    x, info, st = s.solve(_t(p.b), rtol=1e-8, maxit=100)
+    xo, ho = cycles.amgdd_solve(H, comps, p.b, np.zeros(p.n), p.n_fac, rtol=1e-8, maxit=100)
+    hist = s.history(0)
+    assert st == amgdd.OK and info.iters == len(ho) - 1
+    np.testing.assert_allclose(hist, ho, rtol=1e-9, atol=1e-12 * ho[0])
+    assert info.relres <= 1e-8
+    xv, infov, stv = s.vsolve(_t(p.b), rtol=1e-8, maxit=100)
+    xvo, hvo = cycles.vcycle_solve(H, p.b, np.zeros(p.n), rtol=1e-8, maxit=100)
+    assert infov.iters == len(hvo) - 1
+    assert _rel(_np(xv), xvo) <= 1e-12
+
+
+def test_mixed_precision_reaches_1e8_and_reports_error():
+    """cfg3's shape at reduced size: 3D variable k (sigma 1, l = 8), 4^3
+    subdomains, padding 2.  FP32 inner FAC, FP64 outer residual/patch/coarse."""
+    p = make_problem((32, 32, 32), (4, 4, 4), eta=2, n_fac=2, k=np.exp(grf((32,) * 3, 1.0, 8.0, 1)))
+    say("mixed", p.n)
+    H = amg.setup(p.A)
+    comps = composite.build_all(H, p.part, p.nparts, p.eta)
+    s = amgdd.Solver(p.A, p.part, p.nparts, padding=p.eta, n_fac=2, precision="mixed")
+    b = _t(p.b)
+    x = torch.zeros_like(b)
+    xo = np.zeros(p.n)
+    coarse = cycles.CoarseSolver(H.A[H.L])
+    errs = []
+    for k in range(6):
+        x, info, st = s.solve(b, x, rtol=0, maxit=1)
+        xo = cycles.amgdd_iteration(H, comps, p.b, xo, 2, coarse)
+        errs.append(_rel(_np(x), xo))
+    say("  mixed vs FP64 oracle per iteration:", " ".join(f"{e:.2e}" for e in errs))
+    assert max(errs) < 1e-3  # the FP32 inner cycle perturbs the correction, not the iteration
+    x, info, st = s.solve(b, rtol=1e-8, maxit=100)
+    r = p.b - p.A @ _np(x)
+    assert st == amgdd.OK and np.linalg.norm(r) <= 1e-8 * np.linalg.norm(p.b)
+    s64 = amgdd.Solver(p.A, p.part, p.nparts, padding=p.eta, n_fac=2)
+    _, info64, _ = s64.solve(b, rtol=1e-8, maxit=100)
+    say(f"  iterations to 1e-8: mixed {info.iters}, fp64 {info64.iters}")
+    assert info.iters <= info64.iters + 2
+
+
+def test_batched_uneven_problems_match_oracle():
+    probs = batch_config(n_problems=5, seed0=77, side_range=(40, 90), parts_range=(2, 4))
+    say("batched", [pp.n for pp in probs], [pp.eta for pp in probs])
+    s = amgdd.Solver([pp.A for pp in probs], [pp.part for pp in probs], [pp.nparts for pp in probs],
+                     padding=[pp.eta for pp in probs], n_fac=2)
+    b = _t(np.concatenate([pp.b for pp in probs]))
+    x = torch.zeros_like(b)
+    refs = []
+    for pp in probs:
+        H = amg.setup(pp.A)
+        refs.append((H, composite.build_all(H, pp.part, pp.nparts, pp.eta), cycles.CoarseSolver(H.A[H.L])))
+    xo = [np.zeros(pp.n) for pp in probs]
+    off = np.cumsum([0] + [pp.n for pp in probs])
+    for k in range(4):
+        x, info, st = s.solve(b, x, rtol=0, maxit=1)
+        xg = _np(x)
+        for i, pp in enumerate(probs):
+            H, comps, co = refs[i]
+            xo[i] = cycles.amgdd_iteration(H, comps, pp.b, xo[i], 2, co)
+            err = _rel(xg[off[i]:off[i + 1]], xo[i])
+            assert err <= 1e-12, (k, i, err)
+    # V-cycles on the batch as well
+    xv, _, _ = s.vsolve(b, rtol=0, maxit=3)
+    xg = _np(xv)
+    for i, pp in enumerate(probs):
+        H = refs[i][0]
+        e = np.zeros(pp.n)
+        for _ in range(3):
+            e = cycles.vcycle(H, e, pp.b)
+        assert _rel(xg[off[i]:off[i + 1]], e) <= 1e-12
+    # mixed batch converges for every problem
+    sm = amgdd.Solver([pp.A for pp in probs], [pp.part for pp in probs], [pp.nparts for pp in probs],
+                      padding=[pp.eta for pp in probs], n_fac=2, precision="mixed")
+    xm, info, st = sm.solve(b, rtol=1e-8, maxit=100)
+    assert st == amgdd.OK
+    xg = _np(xm)
+    for i, pp in enumerate(probs):
+        r = pp.b - pp.A @ xg[off[i]:off[i + 1]]
+        assert np.linalg.norm(r) <= 1e-8 * np.linalg.norm(pp.b)
+
+
+def _faces_ij(p):
+    fi = np.concatenate([p.faces.inner_i, p.faces.bnd_i])
+    fj = np.concatenate([p.faces.inner_j, -np.ones(p.faces.bnd_i.size, dtype=np.int64)])
+    return fi, fj
+
+
+def test_face_gradient_kernel_matches_formula():
+    p = make_problem((9, 8, 7), (1, 1, 1))
+    rng = np.random.default_rng(3)
+    u = rng.standard_normal(p.n)
+    lam = rng.standard_normal(p.n)
+    s = amgdd.Solver(p.A, p.part, 1)
+    fi, fj = _faces_ij(p)
+    g = s.face_gradient(_t(u), _t(lam), torch.as_tensor(fi), torch.as_tensor(fj))
+    np.testing.assert_array_equal(_np(g), adjoint.face_gradient(p.faces, u, lam))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_adjoint_gradients_vs_central_differences(precision):
+    """cfg4's operator at 16^3 (2^3 subdomains, padding 1): forward and
+    adjoint AMG-DD to 1e-10; dL/df = lambda on every cell and dL/dc on 64
+    seeded faces against central differences (h = 1e-6) through exact
+    sparse-LU solves; all of dL/dc against the dense adjoint."""
+    from paper_1906_10575_amd.autograd import FaceProblem, diffusion_solve
+    p = config("cfg4", scale=16)
+    ut = p.extra["u_target"]
+    say("adjoint", precision, p.n)
+    fi, fj = _faces_ij(p)
+    prob = FaceProblem(p.n, fi, fj, p.part, p.nparts, padding=1, n_fac=2, precision=precision, rtol=1e-10)
+    c = _t(p.c).requires_grad_(True)
+    f = _t(p.b).requires_grad_(True)
+    u = diffusion_solve(c, f, prob)
+    loss = ((u - _t(ut)) ** 2).sum()
+    loss.backward()
+    gc = _np(c.grad)
+    gf = _np(f.grad)
+    L, u_d, lam_d, gc_d = adjoint.loss_and_grads(p.A, p.faces, p.b, ut)
+    assert _rel(_np(u), u_d) <= 1e-9
+    assert _rel(gf, lam_d) <= 1e-8
+    assert np.abs(gc - gc_d).max() <= 1e-8 * np.abs(gc_d).max()
+    from synth import assemble
+
+    def loss_of(cv, fv):
+        uu = spla.splu(assemble(p.n, p.faces, cv).tocsc()).solve(fv)
+        return float(np.sum((uu - ut) ** 2))
+
+    h = 1e-6
+    lu = spla.splu(p.A.tocsc())
+    Ainv_cols = None
+    fd_f = np.empty(p.n)
+    for i in range(p.n):
+        e = np.zeros(p.n)
+        e[i] = h
+        up = lu.solve(p.b + e)
+        um = lu.solve(p.b - e)
+        fd_f[i] = (np.sum((up - ut) ** 2) - np.sum((um - ut) ** 2)) / (2 * h)
+    assert np.abs(gf - fd_f).max() <= 1e-6 * np.abs(fd_f).max()
+    rng = np.random.default_rng(42)
+    sel = rng.choice(p.faces.n_faces, 64, replace=False)
+    fd_c = []
+    for k in sel:
+        cp = p.c.copy()
+        cp[k] += h
+        cm = p.c.copy()
+        cm[k] -= h
+        fd_c.append((loss_of(cp, p.b) - loss_of(cm, p.b)) / (2 * h))
+    fd_c = np.array(fd_c)
+    assert np.abs(gc[sel] - fd_c).max() <= 1e-6 * np.abs(gc).max()
+
+
+def test_error_paths_on_device():
+    p = CASES["3d_16_eta1"]()
+    s = amgdd.Solver(p.A, p.part, p.nparts, padding=1)
+    b = _t(p.b)
+    bad = b.clone()
+    bad[7] = float("nan")
+    with pytest.raises(amgdd.AmgddError) as e:
+        s.solve(bad, rtol=1e-8, maxit=5)
+    assert e.value.status == amgdd.EBREAKDOWN
+    x, info, st = s.solve(b, rtol=1e-14, maxit=2)
+    assert st == amgdd.ENOCONV and info.iters == 2
+    x2, _, st2 = s.solve(b, rtol=0, maxit=2)
+    assert st2 == amgdd.OK and torch.equal(x, x2)
