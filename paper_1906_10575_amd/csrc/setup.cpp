@@ -258,28 +258,33 @@ std::vector<int8_t> rs_first_pass(const Csr &S) {
   Csr T = pattern_transpose(S);  // row i: points that i strongly influences
   std::vector<long long> lam(n);
   std::vector<int8_t> st(n, 0);
-  std::priority_queue<unsigned long long> pq;
+  // Tournament tree over the undecided points, key = (lambda, smallest index
+  // first); decided points have key 0.  The root is the next C-point.
+  int size = 1;
+  while (size < n) size <<= 1;
+  std::vector<unsigned long long> tree(2 * (size_t)size, 0ull);
   auto key = [](long long l, int i) -> unsigned long long {
-    return ((unsigned long long)l << 32) | (unsigned long long)(0xFFFFFFFFu - (unsigned)i);
+    return ((unsigned long long)(l + 1) << 32) | (unsigned long long)(0xFFFFFFFFu - (unsigned)i);
+  };
+  auto update = [&](int i, unsigned long long k) {
+    size_t pos = (size_t)size + i;
+    tree[pos] = k;
+    for (pos >>= 1; pos >= 1; pos >>= 1) {
+      unsigned long long m = std::max(tree[2 * pos], tree[2 * pos + 1]);
+      if (tree[pos] == m) break;
+      tree[pos] = m;
+    }
   };
   for (int i = 0; i < n; ++i) {
     lam[i] = T.ptr[i + 1] - T.ptr[i];
     if (S.ptr[i + 1] == S.ptr[i] && lam[i] == 0) st[i] = -1;
+    else tree[(size_t)size + i] = key(lam[i], i);
   }
-  {
-    std::vector<unsigned long long> init;
-    init.reserve(n);
-    for (int i = 0; i < n; ++i)
-      if (st[i] == 0) init.push_back(key(lam[i], i));
-    pq = std::priority_queue<unsigned long long>(std::less<unsigned long long>(), std::move(init));
-  }
+  for (size_t pos = (size_t)size - 1; pos >= 1; --pos) tree[pos] = std::max(tree[2 * pos], tree[2 * pos + 1]);
   std::vector<int> newf;
-  while (!pq.empty()) {
-    unsigned long long k = pq.top();
-    pq.pop();
-    int i = (int)(0xFFFFFFFFu - (unsigned)(k & 0xFFFFFFFFull));
-    long long l = (long long)(k >> 32);
-    if (st[i] != 0 || l != lam[i]) continue;
+  while (tree[1] != 0ull) {
+    const unsigned long long k = tree[1];
+    const int i = (int)(0xFFFFFFFFu - (unsigned)(k & 0xFFFFFFFFull));
     if (lam[i] == 0) {
       for (int u = 0; u < n; ++u) {
         if (st[u] != 0) continue;
@@ -291,18 +296,19 @@ std::vector<int8_t> rs_first_pass(const Csr &S) {
       break;
     }
     st[i] = 1;
+    update(i, 0ull);
     newf.clear();
     for (int jj = T.ptr[i]; jj < T.ptr[i + 1]; ++jj)
       if (st[T.col[jj]] == 0) newf.push_back(T.col[jj]);
-    for (int j : newf) st[j] = -1;
+    for (int j : newf) { st[j] = -1; update(j, 0ull); }
     for (int j : newf)
       for (int kk = S.ptr[j]; kk < S.ptr[j + 1]; ++kk) {
         int q = S.col[kk];
-        if (st[q] == 0) { lam[q] += 1; pq.push(key(lam[q], q)); }
+        if (st[q] == 0) { lam[q] += 1; update(q, key(lam[q], q)); }
       }
     for (int jj = S.ptr[i]; jj < S.ptr[i + 1]; ++jj) {
       int q = S.col[jj];
-      if (st[q] == 0) { lam[q] -= 1; pq.push(key(lam[q], q)); }
+      if (st[q] == 0) { lam[q] -= 1; update(q, key(lam[q], q)); }
     }
   }
   return st;
@@ -479,15 +485,25 @@ int build_hierarchy(ProblemHost &P, double theta, int max_coarse, int max_levels
   H.A.push_back(P.A0);
   while (H.A.back().nrows > max_coarse && (int)H.A.size() < max_levels) {
     const Csr &A = H.A.back();
+    double th = now_s();
     Csr S = strength(A, theta);
+    vlog("hier: strength", th);
+    th = now_s();
     std::vector<int8_t> cf = rs_first_pass(S);
+    vlog("hier: rs", th);
+    th = now_s();
     int nc = 0;
     for (auto c : cf) nc += c == 1;
     if (nc == 0 || nc == A.nrows) break;
     Csr Pm = direct_interpolation(A, S, cf);
+    vlog("hier: interp", th);
+    th = now_s();
     Csr R = transpose(Pm);
     Csr AP = spgemm(A, Pm);
+    vlog("hier: AP", th);
+    th = now_s();
     Csr Ac = spgemm(R, AP);
+    vlog("hier: RAP", th);
     H.cf.push_back(std::move(cf));
     H.P.push_back(std::move(Pm));
     H.R.push_back(std::move(R));

@@ -1,0 +1,76 @@
+"""Full-size parity on the benchmark workload (3D Laplacian 128^3, 4x4x4
+subdomains of 32^3, padding 1, 2 AlgFAC cycles, FP64) in the launch
+configuration bench.py times (graph replay, default schedule).
+
+* sampled outputs: the first two AMG-DD iterates and V(1,1) iterates at 2000
+  seeded points and the residual norms, against values written by
+  tests/golden/make_cfg2_samples.py from the oracle alone (1e-12 relative);
+* properties at any size: the solve reaches 1e-8 with the residual recomputed
+  in FP64 on the host, a second solve is bitwise identical, and every
+  subdomain's level-0 composite sets have the closed-form L1-ball sizes."""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+from synth import config
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+amgdd = pytest.importorskip("paper_1906_10575_amd.amgdd")
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "cfg2_samples.json")
+
+
+@pytest.fixture(scope="module")
+def cfg2():
+    p = config("cfg2")
+    print("[gpu-test] cfg2 setup", p.n, flush=True)
+    s = amgdd.Solver(p.A, p.part, p.nparts, padding=p.eta, n_fac=p.n_fac)
+    return p, s
+
+
+def test_cfg2_sampled_iterates_match_oracle(cfg2):
+    if not os.path.exists(GOLD):
+        pytest.skip("golden samples not generated")
+    g = json.load(open(GOLD))
+    p, s = cfg2
+    assert s.levels(0)[0].tolist() == g["levels"]
+    idx = np.array(g["idx"])
+    b = torch.as_tensor(p.b, device="cuda:0")
+    for kind, fn in (("amgdd", s.solve), ("vcycle", s.vsolve)):
+        x = torch.zeros_like(b)
+        for k in (1, 2):
+            x, info, st = fn(b, x, rtol=0, maxit=1)
+            ref = np.array(g[f"{kind}_x{k}"])
+            got = x.cpu().numpy()[idx]
+            err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+            print(f"[gpu-test] {kind} iterate {k}: sampled rel err {err:.2e}", flush=True)
+            assert err <= 1e-12
+            hist = s.history(0)
+            np.testing.assert_allclose(hist[-1], g[f"{kind}_hist"][k], rtol=1e-10)
+
+
+def test_cfg2_solve_properties(cfg2):
+    from tests.test_oracle_composite import l1_ball_counts
+    p, s = cfg2
+    b = torch.as_tensor(p.b, device="cuda:0")
+    x, info, st = s.solve(b, rtol=1e-8, maxit=100)
+    assert st == amgdd.OK
+    r = p.b - p.A @ x.cpu().numpy()
+    rel = np.linalg.norm(r) / np.linalg.norm(p.b)
+    print(f"[gpu-test] cfg2 AMG-DD: {info.iters} iterations, relres {rel:.2e}, {info.solve_s * 1e3:.1f} ms", flush=True)
+    assert rel <= 1e-8
+    x2, _, _ = s.solve(b, rtol=1e-8, maxit=100)
+    assert torch.equal(x, x2)
+    xv, infov, stv = s.vsolve(b, rtol=1e-8, maxit=200)
+    rv = p.b - p.A @ xv.cpu().numpy()
+    assert stv == amgdd.OK and np.linalg.norm(rv) <= 1e-8 * np.linalg.norm(p.b)
+    print(f"[gpu-test] cfg2 V(1,1): {infov.iters} cycles, {infov.solve_s * 1e3:.1f} ms", flush=True)
+    d, db = l1_ball_counts((128,) * 3, (4,) * 3, 1)
+    for q in range(p.nparts):
+        gids, nr, om = s.composite(0, q, 0)
+        assert (nr, gids.size, om) == (d[q], db[q], 0)
