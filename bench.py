@@ -33,22 +33,23 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+WORKLOADS = {
+    "cfg2": "3D 7-point Laplacian 128^3 (2,097,152 DOF), 4x4x4 subdomains of 32^3, padding 1, 2 AlgFAC V(1,1) "
+            "cycles per AMG-DD iteration, FP64, AMG-DD solve to 1e-8 from x0 = 0",
+    "cfg3": "3D 7-point diffusion 192^3 (7,077,888 DOF), k = exp(GRF sigma 1, l 8), harmonic faces, 8x8x8 "
+            "subdomains of 24^3, padding 2, 2 AlgFAC cycles, AMG-DD solve to 1e-8 from x0 = 0",
+    "cfg4": "3D 7-point diffusion 96^3 (884,736 DOF), k = exp(GRF sigma 0.5), 3x3x3 subdomains of 32^3, padding 1, "
+            "forward AMG-DD to 1e-10 plus adjoint AMG-DD to 1e-10 and face gradient",
+    "cfg5": "256 independent 2D 5-point diffusion problems, sides U{64..512}, k log-normal sigma 1, Px,Py U{2..8}, "
+            "padding U{1..3}; one batched handle; forward AMG-DD to 1e-8 plus adjoint AMG-DD to 1e-8",
+}
+
+
 def build_problem(name):
-    from synth import config
+    from synth import batch_config, config
+    if name == "cfg5":
+        return batch_config()
     return config(name)
-
-
-def timed_solves(torch, fn, b, steps, rtol, maxit):
-    """K solves from x = 0, bracketed by device synchronisation."""
-    iters = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        x = torch.zeros_like(b)
-        x, info, st = fn(b, x, rtol=rtol, maxit=maxit)
-        iters.append(info.iters)
-    torch.cuda.synchronize()
-    return time.perf_counter() - t0, iters, x
 
 
 def roofline(prof):
@@ -60,8 +61,8 @@ def roofline(prof):
     achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
     return dom, {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                  "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                 "kernel": f"{dom['name']} (level {dom['level']})", "bytes_per_launch": per_launch_bytes,
-                 "ms_per_launch": per_launch_ms}
+                 "kernel": f"{dom['name']} (level {dom['level']})", "workgroups": dom.get("workgroups"),
+                 "block": dom.get("block"), "bytes_per_launch": per_launch_bytes, "ms_per_launch": per_launch_ms}
 
 
 def cpu_baseline(seconds=12.0):
@@ -90,16 +91,81 @@ def cpu_baseline(seconds=12.0):
                       f"iterations in {dt:.1f} s (setup excluded)"}
 
 
+PRIMARY = {"cfg2": "fp64", "cfg3": "mixed", "cfg4": "fp64", "cfg5": "mixed"}
+RTOL = {"cfg2": 1e-8, "cfg3": 1e-8, "cfg4": 1e-10, "cfg5": 1e-8}
+
+
+def make_solver(amgdd, p, precision, sched=(-2, 0)):
+    if isinstance(p, list):
+        return amgdd.Solver([q.A for q in p], [q.part for q in p], [q.nparts for q in p],
+                            padding=[q.eta for q in p], n_fac=2, precision=precision, tail_level=sched[0],
+                            tail_block=sched[1])
+    return amgdd.Solver(p.A, p.part, p.nparts, padding=p.eta, n_fac=p.n_fac, precision=precision,
+                        tail_level=sched[0], tail_block=sched[1])
+
+
+def summarize_rocpd(db):
+    """Per-kernel and per-(kernel, workgroups) duration statistics of a
+    rocprofv3 --kernel-trace database (rocpd SQLite), as text."""
+    import sqlite3
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, grid_x, workgroup_x, duration from kernels").fetchall()
+    agg, aggk = {}, {}
+    for name, gx, wx, dur in rows:
+        short = name.split("(")[0].replace("void ", "").replace("amgdd::dev::", "")
+        key = (short, int(gx) // max(int(wx), 1), int(wx))
+        agg.setdefault(key, []).append(dur)
+        aggk.setdefault(short, []).append(dur)
+    lines = ["kernel                                   calls   total_us    avg_us", "-" * 70]
+    for k, v in sorted(aggk.items(), key=lambda kv: -sum(kv[1])):
+        lines.append(f"{k[:40]:40s} {len(v):6d} {sum(v) / 1e3:10.1f} {sum(v) / len(v) / 1e3:9.3f}")
+    lines += ["", "kernel                          workgroups x size   calls    avg_us", "-" * 70]
+    for k, v in sorted(agg.items(), key=lambda kv: -sum(kv[1]))[:40]:
+        lines.append(f"{k[0][:32]:32s} {k[1]:10d} x {k[2]:4d} {len(v):6d} {sum(v) / len(v) / 1e3:9.3f}")
+    return "\n".join(lines)
+
+
+def residual_rel(p, x):
+    if isinstance(p, list):
+        off = np.cumsum([0] + [q.n for q in p])
+        return max(float(np.linalg.norm(q.b - q.A @ x[off[i]:off[i + 1]]) / np.linalg.norm(q.b))
+                   for i, q in enumerate(p))
+    return float(np.linalg.norm(p.b - p.A @ x) / np.linalg.norm(p.b))
+
+
+def run_steps(torch, s, b, steps, rtol, adjoint):
+    """K steps from x = 0; a step is one AMG-DD solve (plus, for the adjoint
+    workloads, one adjoint AMG-DD solve with right-hand side u), bracketed by
+    device synchronisation.  Returns (seconds, iterations per step, x)."""
+    iters = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        x, info, st = s.solve(b, torch.zeros_like(b), rtol=rtol, maxit=300)
+        it = info.iters
+        if adjoint:
+            lam, info2, st2 = s.solve_adjoint(x, torch.zeros_like(b), rtol=rtol, maxit=300)
+            it += info2.iters
+        iters.append(it)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, iters, x
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="cfg2")
-    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--config", default="cfg2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--tail-level", type=int, default=-2, help="fixed AlgFAC schedule cut level (-2: autotune)")
+    ap.add_argument("--tail-block", type=int, default=0, help="fixed persistent workgroup size (0: autotune)")
+    ap.add_argument("--summarize-rocpd", metavar="DB", help="print a summary of a rocprofv3 kernel-trace database")
     args = ap.parse_args()
+    if args.summarize_rocpd:
+        print(summarize_rocpd(args.summarize_rocpd))
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
@@ -107,26 +173,33 @@ def main():
     import torch
     from paper_1906_10575_amd import amgdd
 
-    p = build_problem(args.config)
-    log(f"{args.config}: n={p.n} nnz={p.A.nnz} parts={p.nparts} eta={p.eta} n_fac={p.n_fac}")
+    cfg = args.config
+    prec = PRIMARY[cfg]
+    rtol = RTOL[cfg]
+    adjoint = cfg in ("cfg4", "cfg5")
+    p = build_problem(cfg)
+    n = sum(q.n for q in p) if isinstance(p, list) else p.n
+    log(f"{cfg}: n={n}, primary precision {prec}, rtol {rtol}, adjoint {adjoint}")
     t0 = time.perf_counter()
-    s = amgdd.Solver(p.A, p.part, p.nparts, padding=p.eta, n_fac=p.n_fac)
+    s = make_solver(amgdd, p, prec, (args.tail_level, args.tail_block))
     setup_s = time.perf_counter() - t0
     st = s.stats()
     log(f"setup {setup_s:.1f} s, grids {st['n_grids']}, levels {st['max_levels']}, overhead "
         f"{st['composite_overhead']:.3f}, device {st['device_bytes'] / 2**30:.2f} GiB")
-    b = torch.as_tensor(p.b, device="cuda:0")
+    bh = np.concatenate([q.b for q in p]) if isinstance(p, list) else p.b
+    b = torch.as_tensor(bh, device="cuda:0")
 
-    for _ in range(args.warmup):
-        s.solve(b, torch.zeros_like(b), rtol=args.rtol, maxit=200)
-    log("warmup done")
-    dt, iters, x = timed_solves(torch, s.solve, b, args.steps, args.rtol, 200)
+    run_steps(torch, s, b, args.warmup, rtol, adjoint)
+    st = s.stats()
+    log(f"warmup done; schedule: cut level {st['tail_level']}, workgroup {st['tail_block']} "
+        f"(autotune {st['autotune_s']:.2f} s)")
+    dt, iters, x = run_steps(torch, s, b, args.steps, rtol, adjoint)
     its = int(np.median(iters))
     ms_per_step = dt / args.steps * 1e3
-    value = p.n * sum(iters) / dt
-    r = p.b - p.A @ x.cpu().numpy()
-    relres = float(np.linalg.norm(r) / np.linalg.norm(p.b))
-    log(f"AMG-DD: {its} iterations, {ms_per_step:.2f} ms per solve, {value:.3e} DOF*cycles/s, relres {relres:.2e}")
+    value = n * sum(iters) / dt
+    relres = residual_rel(p, x.cpu().numpy())
+    log(f"AMG-DD: {its} iterations per step, {ms_per_step:.2f} ms per step, {value:.3e} DOF*cycles/s, "
+        f"final relres (FP64, host) {relres:.2e}")
 
     prof = s.profile(kind=0, reps=3)
     dom, roof = roofline(prof)
@@ -145,39 +218,48 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if prec == "fp64" else "f32 inner / f64 outer",
         "data": "synthetic",
-        "config": {"workload": f"{args.config}: 3D 7-point Laplacian 128^3 (2,097,152 DOF), 4x4x4 subdomains of "
-                               "32^3, padding 1, 2 AlgFAC V(1,1) cycles per AMG-DD iteration, RS theta 0.25 + direct "
-                               "interpolation to <= 16 points, l1-Jacobi, AMG-DD solve to 1e-8 from x0 = 0",
-                   "dof": p.n, "subdomains": p.nparts, "padding": p.eta, "n_fac": p.n_fac, "rtol": args.rtol},
-        "amgdd_iters": its,
+        "config": {"workload": f"{cfg}: {WORKLOADS[cfg]}", "dof": n, "grids": st["n_grids"],
+                   "precision": prec, "rtol": rtol},
+        "iters_per_step": its,
         "time_to_tol_ms": round(ms_per_step, 4),
         "final_relres_fp64": relres,
         "roofline": roof,
         "kernel_ms_per_iteration": round(iter_ms, 4),
         "profile_top": sorted(({k: (round(v, 5) if isinstance(v, float) else v) for k, v in r_.items()}
                                for r_ in prof), key=lambda r_: -r_["ms"])[:8],
+        "schedule": {"tail_level": st["tail_level"], "tail_block": st["tail_block"]},
         "setup_s": round(setup_s, 2),
         "composite_overhead": round(st["composite_overhead"], 4),
     }
     if not args.no_extras:
-        dtv, itv, xv = timed_solves(torch, s.vsolve, b, max(3, args.steps // 2), args.rtol, 400)
-        kv = max(3, args.steps // 2)
-        out["vcycle"] = {"iters": int(np.median(itv)), "time_to_tol_ms": round(dtv / kv * 1e3, 4),
-                         "dof_cycles_per_s": round(p.n * sum(itv) / dtv, 1)}
-        log(f"V(1,1): {out['vcycle']}")
-        sm = amgdd.Solver(p.A, p.part, p.nparts, padding=p.eta, n_fac=p.n_fac, precision="mixed")
-        sm.solve(b, torch.zeros_like(b), rtol=args.rtol, maxit=200)
-        dtm, itm, xm = timed_solves(torch, sm.solve, b, max(3, args.steps // 2), args.rtol, 200)
-        km = max(3, args.steps // 2)
-        rm = p.b - p.A @ xm.cpu().numpy()
-        out["mixed"] = {"iters": int(np.median(itm)), "time_to_tol_ms": round(dtm / km * 1e3, 4),
-                        "dof_cycles_per_s": round(p.n * sum(itm) / dtm, 1),
-                        "final_relres_fp64": float(np.linalg.norm(rm) / np.linalg.norm(p.b))}
-        log(f"mixed: {out['mixed']}")
-        del sm
-    if not args.no_cpu_baseline:
+        k = max(3, args.steps // 2)
+        if not isinstance(p, list) and not adjoint:
+            s.vsolve(b, torch.zeros_like(b), rtol=rtol, maxit=400)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            itv = []
+            for _ in range(k):
+                xv, infov, _ = s.vsolve(b, torch.zeros_like(b), rtol=rtol, maxit=400)
+                itv.append(infov.iters)
+            torch.cuda.synchronize()
+            dtv = time.perf_counter() - t0
+            out["vcycle"] = {"iters": int(np.median(itv)), "time_to_tol_ms": round(dtv / k * 1e3, 4),
+                             "dof_cycles_per_s": round(n * sum(itv) / dtv, 1)}
+            log(f"V(1,1): {out['vcycle']}")
+        other = "mixed" if prec == "fp64" else "fp64"
+        del s
+        torch.cuda.empty_cache()
+        so = make_solver(amgdd, p, other)
+        run_steps(torch, so, b, 1, rtol, adjoint)
+        dto, ito, xo = run_steps(torch, so, b, k, rtol, adjoint)
+        out[other] = {"iters_per_step": int(np.median(ito)), "time_to_tol_ms": round(dto / k * 1e3, 4),
+                      "dof_cycles_per_s": round(n * sum(ito) / dto, 1),
+                      "final_relres_fp64": residual_rel(p, xo.cpu().numpy())}
+        log(f"{other}: {out[other]}")
+        del so
+    if not args.no_cpu_baseline and cfg == "cfg2":
         out["cpu_baseline"] = cpu_baseline()
         log(f"cpu baseline: {out['cpu_baseline']}")
     print(json.dumps(out), flush=True)

@@ -64,6 +64,13 @@ typedef struct {
   int device;       /* HIP device ordinal; -1 = host-only handle (setup and
                        introspection only, every solve returns EDEVICE) */
   int use_graph;    /* 1 = replay each outer iteration as a HIP graph (default) */
+  int tail_level;   /* AlgFAC schedule: levels >= tail_level run in one persistent
+                       launch per cycle with one workgroup per composite grid,
+                       levels above it level-synchronously over all grids.
+                       -2 = chosen by the autotuner at the first solve (default),
+                       -1 = level-synchronous everywhere, >= 0 fixed */
+  int tail_block;   /* workgroup size of the persistent launch: 256, 512 or 1024;
+                       0 = chosen by the autotuner (default) */
 } amgdd_params;
 
 typedef struct {
@@ -91,6 +98,10 @@ typedef struct {
   double setup_pack_s;      /* host time: batched layouts */
   double setup_upload_s;    /* device allocation and upload */
   long long device_bytes;   /* device memory owned by the handle */
+  int tail_level;           /* schedule in use (-1 level-synchronous; -2 not tuned yet) */
+  int tail_block;
+  double autotune_s;        /* time spent by the autotuner */
+  long long composite_nnz;  /* nonzeros of composite A, P, R without padding */
 } amgdd_stats;
 
 void amgdd_params_default(amgdd_params *prm);
@@ -200,6 +211,8 @@ typedef struct {
   int launches;
   double ms;
   double bytes;
+  int workgroups;   /* workgroups of the site's (last) launch */
+  int block;        /* workgroup size */
 } amgdd_kernel_time;
 
 amgdd_status amgdd_profile(amgdd_handle h, int kind, int reps, amgdd_kernel_time *out, int cap, int *n);

@@ -32,7 +32,8 @@ class AmgddError(RuntimeError):
 
 class Params(C.Structure):
     _fields_ = [("theta", C.c_double), ("max_coarse", C.c_int), ("max_levels", C.c_int), ("padding", C.c_int),
-                ("n_fac", C.c_int), ("precision", C.c_int), ("device", C.c_int), ("use_graph", C.c_int)]
+                ("n_fac", C.c_int), ("precision", C.c_int), ("device", C.c_int), ("use_graph", C.c_int),
+                ("tail_level", C.c_int), ("tail_block", C.c_int)]
 
 
 class Info(C.Structure):
@@ -47,7 +48,8 @@ class Stats(C.Structure):
                 ("composite_stored_nnz", C.c_longlong), ("omissions", C.c_longlong),
                 ("composite_overhead", C.c_double), ("setup_hierarchy_s", C.c_double),
                 ("setup_composite_s", C.c_double), ("setup_pack_s", C.c_double), ("setup_upload_s", C.c_double),
-                ("device_bytes", C.c_longlong)]
+                ("device_bytes", C.c_longlong), ("tail_level", C.c_int), ("tail_block", C.c_int),
+                ("autotune_s", C.c_double), ("composite_nnz", C.c_longlong)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -55,7 +57,7 @@ class Stats(C.Structure):
 
 class KernelTime(C.Structure):
     _fields_ = [("name", C.c_char * 24), ("level", C.c_int), ("launches", C.c_int), ("ms", C.c_double),
-                ("bytes", C.c_double)]
+                ("bytes", C.c_double), ("workgroups", C.c_int), ("block", C.c_int)]
 
 
 _P = C.c_void_p
@@ -153,7 +155,7 @@ class Solver:
     host-only handle (setup and introspection, no solve)."""
 
     def __init__(self, A, part, nparts, padding=1, n_fac=2, precision="fp64", device=0, theta=0.25,
-                 max_coarse=16, max_levels=25, use_graph=True, stream=None):
+                 max_coarse=16, max_levels=25, use_graph=True, stream=None, tail_level=-2, tail_block=0):
         lib = load()
         batch = isinstance(A, (list, tuple))
         As = list(A) if batch else [A]
@@ -168,6 +170,8 @@ class Solver:
         prm.precision = MIXED if precision in ("mixed", MIXED) else FP64
         prm.device = device
         prm.use_graph = 1 if use_graph else 0
+        prm.tail_level = tail_level
+        prm.tail_block = tail_block
         if stream is None and device >= 0:
             torch = _torch()
             stream = torch.cuda.current_stream(device).cuda_stream
@@ -289,8 +293,8 @@ class Solver:
         _check(load().amgdd_profile(self._h, kind, reps, None, 0, C.byref(n)))
         arr = (KernelTime * max(n.value, 1))()
         _check(load().amgdd_profile(self._h, kind, reps, arr, n.value, C.byref(n)))
-        return [dict(name=a.name.decode(), level=a.level, launches=a.launches, ms=a.ms, bytes=a.bytes)
-                for a in arr[: n.value]]
+        return [dict(name=a.name.decode(), level=a.level, launches=a.launches, ms=a.ms, bytes=a.bytes,
+                     workgroups=a.workgroups, block=a.block) for a in arr[: n.value]]
 
     def set_stream(self, stream):
         _check(load().amgdd_set_stream(self._h, C.c_void_p(stream)))

@@ -56,11 +56,14 @@ struct ProblemHost {
   bool symmetric = false;
 };
 
-// Sliced ELL, slice height 64 (one wavefront): entry k of row r is stored at
-// sptr[r/64] + 64*k + r%64; slice width = (sptr[s+1]-sptr[s]) / 64; rows
-// shorter than the width are padded with value 0 and a valid column.
+// Grouped sliced ELL: G = 2^lg lanes per row, 64/G rows per slice (one
+// wavefront); entry k of row r is stored at
+//   sptr[r / (64/G)] + 64*(k / G) + (r % (64/G))*G + k % G;
+// a slice has (sptr[s+1]-sptr[s]) / 64 steps; rows shorter than the slice are
+// padded with value 0 and a column of the same grid.
 struct Sell {
   int nrows = 0;
+  int lg = 0;
   std::vector<int> sptr;
   std::vector<int> col;
   std::vector<double> val;
@@ -74,6 +77,7 @@ struct Sell {
 //   global rows:    [normal problems | coarse problems]
 struct BatchLevel {
   int NRn = 0, NBn = 0, NB = 0;
+  int lg = 0, glg = 0;             // lanes per row (log2) of composite / global rows of this level
   Sell A;                          // rows [0, NBn)
   Sell P;                          // rows [0, NBn) -> level l+1 composite rows
   Sell R;                          // R_{l-1}: rows [0, NB) -> level l-1 composite rows
@@ -109,6 +113,11 @@ struct Setup {
   // residual blocks: rows [blk_row0[b], blk_row1[b]) of problem blk_prob[b]
   std::vector<int> blk_row0, blk_row1, blk_prob;
   std::vector<int> prob_blk0;      // [nprob+1] first residual block of each problem
+  // per (grid, level) row ranges of the batched layout, [ngrids * (maxL+1)]:
+  // normal level: real rows [rbeg, rbeg+nreal), ghost rows [gbeg, gbeg+nghost);
+  // the grid's coarsest level: rows [rbeg, rbeg+nreal), nghost = 0; absent: all 0
+  std::vector<int> gl_rbeg, gl_nreal, gl_gbeg, gl_nghost;
+  std::vector<int> grid_L;         // [ngrids] coarsest level of each grid
   SetupTimes times;
   long long omissions = 0;
   long long composite_real_nnz = 0, global_nnz = 0, composite_rows = 0, composite_real_rows = 0;

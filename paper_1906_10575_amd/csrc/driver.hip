@@ -55,16 +55,18 @@ struct DSell {
   int *col = nullptr;
   void *val = nullptr;  // double or float
   int nrows = 0;
+  int lg = 0;           // lanes per row (log2)
   long long entries = 0;
   template <typename T>
   dev::SellD<T> as() const {
-    return dev::SellD<T>{sptr, col, (const T *)val};
+    return dev::SellD<T>{sptr, col, (const T *)val, lg};
   }
 };
 
 struct DLevel {
   // composite
   int NRn = 0, NBn = 0, NB = 0;
+  int lg = 0, glg = 0;  // lanes per row (log2) of composite / global rows
   DSell A, P, R;
   void *dinv = nullptr;
   void *u[2] = {nullptr, nullptr};
@@ -94,6 +96,7 @@ struct Prof {
     int level;
     double bytes;
     hipEvent_t e0, e1;
+    int grid, block;
   };
   std::vector<Site> sites;
   std::vector<hipEvent_t> pool;
@@ -106,8 +109,8 @@ struct Prof {
     }
     return pool[used++];
   }
-  int begin(const char *name, int level, double bytes, hipStream_t s) {
-    Site st{name, level, bytes, get(), get()};
+  int begin(const char *name, int level, double bytes, hipStream_t s, int grid, int block) {
+    Site st{name, level, bytes, get(), get(), grid, block};
     (void)hipEventRecord(st.e0, s);
     sites.push_back(st);
     return (int)sites.size() - 1;
@@ -144,7 +147,15 @@ struct amgdd_ctx {
   int *gather_src = nullptr;
   long long f_total = 0;
   void *r_arena = nullptr;
-  double *face_tmp = nullptr;
+  // per-grid persistent schedule
+  void *lvdev = nullptr;                 // LevelDev<T>[nlev]
+  dev::GridLevel *gl = nullptr;          // [ngrids * nlev]
+  int *gridL = nullptr, *gdense = nullptr;
+  int *tail_lists = nullptr;             // grids with L >= lt, largest first, for every lt
+  std::vector<int> tail_off, tail_cnt;   // per lt
+  int tail_maxn = 0;                     // largest coarsest level (shared memory of the tail)
+  int sched_level = -2, sched_block = 256;
+  double autotune_s = 0.0;
   hipGraphExec_t g_dd = nullptr, g_v = nullptr;
   hipGraph_t gr_dd = nullptr, gr_v = nullptr;
   std::vector<std::vector<double>> hist;  // per problem
@@ -176,6 +187,7 @@ struct amgdd_ctx {
   }
   amgdd_status upload_sell(DSell &d, const Sell &s, bool as_float) {
     d.nrows = s.nrows;
+    d.lg = s.lg;
     d.entries = s.entries();
     amgdd_status st = upload(&d.sptr, s.sptr.data(), s.sptr.size());
     if (st) return st;
@@ -242,6 +254,8 @@ amgdd_status upload_all(amgdd_ctx *h) {
     D.NRn = B.NRn;
     D.NBn = B.NBn;
     D.NB = B.NB;
+    D.lg = B.lg;
+    D.glg = B.glg;
     D.nnzA_r = B.nnzA_r;
     D.nnzA = B.nnzA;
     D.nnzP = B.nnzP;
@@ -310,6 +324,50 @@ amgdd_status upload_all(amgdd_ctx *h) {
   if ((st = h->upload(&h->owner, S.owner.data(), S.owner.size()))) return st;
   if ((st = h->upload(&h->dense_A, S.dense_A.data(), S.dense_A.size()))) return st;
   if ((st = h->upload(&h->dense_inv, S.dense_inv.data(), S.dense_inv.size()))) return st;
+  {
+    const int nlev = nl, ng = (int)S.grids.size();
+    std::vector<dev::GridLevel> glh((size_t)ng * nlev);
+    for (size_t k = 0; k < glh.size(); ++k)
+      glh[k] = dev::GridLevel{S.gl_rbeg[k], S.gl_nreal[k], S.gl_gbeg[k], S.gl_nghost[k]};
+    if ((st = h->upload(&h->gl, glh.data(), glh.size()))) return st;
+    if ((st = h->upload(&h->gridL, S.grid_L.data(), S.grid_L.size()))) return st;
+    std::vector<int> gd(ng);
+    for (int g = 0; g < ng; ++g) gd[g] = S.dense_off[S.grids[g].prob];
+    if ((st = h->upload(&h->gdense, gd.data(), gd.size()))) return st;
+    // tail grid lists, largest composite grid first (longest work starts first)
+    std::vector<long long> work(ng, 0);
+    for (int g = 0; g < ng; ++g)
+      for (int l = 0; l < nlev; ++l) work[g] += S.gl_nreal[(size_t)g * nlev + l] + S.gl_nghost[(size_t)g * nlev + l];
+    std::vector<int> order(ng);
+    for (int g = 0; g < ng; ++g) order[g] = g;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+    std::vector<int> lists;
+    h->tail_off.assign(nlev, 0);
+    h->tail_cnt.assign(nlev, 0);
+    for (int lt = 0; lt < nlev; ++lt) {
+      h->tail_off[lt] = (int)lists.size();
+      for (int g : order)
+        if (S.grid_L[g] >= lt) lists.push_back(g);
+      h->tail_cnt[lt] = (int)lists.size() - h->tail_off[lt];
+    }
+    if ((st = h->upload(&h->tail_lists, lists.data(), lists.size()))) return st;
+    for (auto &P : S.probs) h->tail_maxn = std::max(h->tail_maxn, P.H.A.back().nrows);
+    // level pointer table in the composite precision
+    auto fill = [&](auto tag) -> amgdd_status {
+      using T = decltype(tag);
+      std::vector<dev::LevelDev<T>> v(nlev);
+      for (int l = 0; l < nlev; ++l) {
+        DLevel &D = h->L[l];
+        v[l] = dev::LevelDev<T>{D.A.as<T>(), D.P.as<T>(), D.R.as<T>(), (const T *)D.dinv, (T *)D.u[0], (T *)D.u[1],
+                                (T *)D.t, (T *)D.sw, (T *)D.f};
+      }
+      dev::LevelDev<T> *d = nullptr;
+      amgdd_status s2 = h->upload(&d, v.data(), v.size());
+      h->lvdev = d;
+      return s2;
+    };
+    if ((st = fl ? fill(float()) : fill(double()))) return st;
+  }
   HIP_TRY(hipDeviceSynchronize());
   return AMGDD_OK;
 }
@@ -327,7 +385,7 @@ amgdd_status upload_all(amgdd_ctx *h) {
   do {                                                                                              \
     if ((grid) > 0) {                                                                               \
       Prof *_p = (h)->prof;                                                                         \
-      int _k = _p ? _p->begin(name, level, (double)(bytes), stream) : -1;                           \
+      int _k = _p ? _p->begin(name, level, (double)(bytes), stream, (int)(grid), (int)(block)) : -1; \
       hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), shmem, stream, __VA_ARGS__);              \
       if (_p) _p->end(_k, stream);                                                                  \
     }                                                                                               \
@@ -347,45 +405,94 @@ void enqueue_residual(amgdd_ctx *h, hipStream_t s, bool vc) {
   (void)hipMemcpyAsync(h->h_norm2, h->norm2, (size_t)h->nprob * sizeof(double), hipMemcpyDeviceToHost, s);
 }
 
+// Level-synchronous downsweep pass of level l (all grids normal at l, plus the
+// coarsest solve of grids whose coarsest level is l) and its w pass.
+template <typename T>
+void enqueue_fac_down(amgdd_ctx *h, hipStream_t s, int *cur, int l, int first) {
+  const int maxL = (int)h->L.size() - 1;
+  const double w = sizeof(T);
+  DLevel &B = h->L[l];
+  T *uin = (T *)B.u[cur[l]], *uout = (T *)B.u[cur[l] ^ 1];
+  if (l == 0) {
+    if (first)
+      PLAUNCH(h, "relax0", 0, B.NRn * 4.0 * w + (B.NBn - B.NRn) * w, dev::k_relax_zero<T>, nblocks(B.NBn), dev::BLOCK, 0, s, B.NRn, B.NBn, (const T *)B.f,
+             (const T *)B.dinv, uout, (T *)B.t);
+    else
+      PLAUNCH(h, "relax_pre", 0, B.nnzA_r * (w + 4.0) + B.NRn * 4.0 * w + B.NBn * 2.0 * w, dev::k_relax<T>, nblocks((long long)B.NBn << B.lg), dev::BLOCK, 0, s, B.A.as<T>(), B.NRn, B.NBn, (const T *)B.f,
+             (const T *)B.dinv, (const T *)uin, uout, (T *)B.t, 1);
+  } else {
+    DLevel &Bp = h->L[l - 1];
+    PLAUNCH(h, "down", l, B.nnzR_n * (w + 4.0) + Bp.NBn * w + B.NBn * 2.0 * w + (first ? 0.0 : B.nnzA_r * (w + 4.0) + B.NBn * w) + B.NRn * (first ? 4.0 : 5.0) * w, dev::k_down<T>, nblocks((long long)B.NBn << B.lg), dev::BLOCK, 0, s, B.R.as<T>(), B.A.as<T>(), B.NRn, B.NBn,
+           (const T *)Bp.sw, (T *)B.sw, (T *)B.f, (const T *)B.dinv, (const T *)uin, uout, (T *)B.t, first);
+    PLAUNCH(h, "coarse", l, (B.nnzR - B.nnzR_n) * (w + 4.0) + (B.NB - B.NBn) * 3.0 * w, dev::k_coarse<T>, B.ncg, dev::BLOCK, 2 * B.cg_maxn * sizeof(double), s, B.R.as<T>(), 1,
+           (const T *)Bp.sw, (T *)B.f, (const T *)uin, uout, h->dense_A, h->dense_inv, B.cg_row0, B.cg_n,
+           B.cg_dense, 0, first, uin);
+  }
+  cur[l] ^= 1;
+  if (B.NBn > 0 && l < maxL)
+    PLAUNCH(h, "w", l, B.nnzA * (w + 4.0) + B.NBn * (l > 0 ? 3.0 : 2.0) * w, dev::k_w<T>, nblocks((long long)B.NBn << B.lg), dev::BLOCK, 0, s, B.A.as<T>(), B.NBn, (T *)B.sw, (const T *)B.t, l > 0);
+}
+
+template <typename T>
+void enqueue_fac_up(amgdd_ctx *h, hipStream_t s, int *cur, int l) {
+  const double w = sizeof(T);
+  DLevel &B = h->L[l];
+  if (B.NBn == 0) return;
+  DLevel &Bc = h->L[l + 1];
+  PLAUNCH(h, "interp", l, B.nnzP * (w + 4.0) + B.NBn * 2.0 * w + Bc.NB * w, dev::k_interp<T>, nblocks((long long)B.NBn << B.lg), dev::BLOCK, 0, s, B.P.as<T>(), B.NBn, (T *)B.u[cur[l]],
+         (const T *)Bc.u[cur[l + 1]]);
+  PLAUNCH(h, "relax_post", l, B.nnzA_r * (w + 4.0) + B.NRn * 3.0 * w + B.NB * 2.0 * w, dev::k_relax<T>, nblocks((long long)B.NB << B.lg), dev::BLOCK, 0, s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
+         (const T *)B.dinv, (const T *)B.u[cur[l]], (T *)B.u[cur[l] ^ 1], (T *)B.t, 0);
+  cur[l] ^= 1;
+}
+
+// Algorithmic bytes of the persistent tail over levels >= lt (one cycle).
+template <typename T>
+double tail_bytes(amgdd_ctx *h, int lt, int first) {
+  const double w = sizeof(T);
+  double b = 0;
+  const int maxL = (int)h->L.size() - 1;
+  for (int l = lt; l <= maxL; ++l) {
+    DLevel &B = h->L[l];
+    if (l == 0) b += first ? B.NRn * 4.0 * w + (B.NBn - B.NRn) * w : B.nnzA_r * (w + 4.0) + B.NRn * 4.0 * w + B.NBn * 2.0 * w;
+    else b += B.nnzR * (w + 4.0) + h->L[l - 1].NBn * w + B.NBn * 2.0 * w + (first ? 0.0 : B.nnzA_r * (w + 4.0) + B.NBn * w) + B.NRn * (first ? 4.0 : 5.0) * w;
+    if (l < maxL) {
+      b += B.nnzA * (w + 4.0) + B.NBn * (l > 0 ? 3.0 : 2.0) * w;
+      b += B.nnzP * (w + 4.0) + B.NBn * 2.0 * w + h->L[l + 1].NB * w;
+      b += B.nnzA_r * (w + 4.0) + B.NRn * 3.0 * w + B.NB * 2.0 * w;
+    }
+  }
+  return b;
+}
+
+template <typename T>
+void enqueue_tail(amgdd_ctx *h, hipStream_t s, int lt, int ncycles, int first) {
+  const int ngr = h->tail_cnt[lt];
+  const int nlev = (int)h->L.size();
+  PLAUNCH(h, "fac_tail", lt, ncycles * tail_bytes<T>(h, lt, first), dev::k_fac_tail<T>, ngr, h->sched_block,
+          2 * h->tail_maxn * sizeof(double), s, (const dev::LevelDev<T> *)h->lvdev, h->gl, nlev,
+          h->tail_lists + h->tail_off[lt], h->gridL, h->gdense, h->dense_A, h->dense_inv, lt, ncycles, first);
+}
+
+// n_fac AlgFAC cycles over every composite grid.  Levels below the schedule's
+// cut level run one launch per pass over all grids; levels from the cut down
+// run in one persistent launch per cycle (the whole AlgFAC in one launch when
+// the cut is level 0).  At the start and end of each cycle every level's u is
+// in buffer 0 (cur[l] == 0).
 template <typename T>
 void enqueue_fac(amgdd_ctx *h, hipStream_t s, int *cur) {
   const int maxL = (int)h->L.size() - 1;
-  const double w = sizeof(T);
   const int nfac = h->prm.n_fac;
+  const int lt = h->sched_level < 0 ? maxL + 1 : h->sched_level;
+  if (lt == 0) {
+    enqueue_tail<T>(h, s, 0, nfac, 1);
+    return;
+  }
   for (int c = 0; c < nfac; ++c) {
     const int first = c == 0;
-    for (int l = 0; l <= maxL; ++l) {
-      DLevel &B = h->L[l];
-      T *uin = (T *)B.u[cur[l]], *uout = (T *)B.u[cur[l] ^ 1];
-      if (l == 0) {
-        if (first)
-          PLAUNCH(h, "relax0", 0, B.NRn * 4.0 * w + (B.NBn - B.NRn) * w, dev::k_relax_zero<T>, nblocks(B.NBn), dev::BLOCK, 0, s, B.NRn, B.NBn, (const T *)B.f,
-                 (const T *)B.dinv, uout, (T *)B.t);
-        else
-          PLAUNCH(h, "relax_pre", 0, B.nnzA_r * (w + 4.0) + B.NRn * 4.0 * w + B.NBn * 2.0 * w, dev::k_relax<T>, nblocks(B.NBn), dev::BLOCK, 0, s, B.A.as<T>(), B.NRn, B.NBn, (const T *)B.f,
-                 (const T *)B.dinv, (const T *)uin, uout, (T *)B.t, 1);
-      } else {
-        DLevel &Bp = h->L[l - 1];
-        PLAUNCH(h, "down", l, B.nnzR_n * (w + 4.0) + Bp.NBn * w + B.NBn * 2.0 * w + (first ? 0.0 : B.nnzA_r * (w + 4.0) + B.NBn * w) + B.NRn * (first ? 4.0 : 5.0) * w, dev::k_down<T>, nblocks(B.NBn), dev::BLOCK, 0, s, B.R.as<T>(), B.A.as<T>(), B.NRn, B.NBn,
-               (const T *)Bp.sw, (T *)B.sw, (T *)B.f, (const T *)B.dinv, (const T *)uin, uout, (T *)B.t, first);
-        PLAUNCH(h, "coarse", l, (B.nnzR - B.nnzR_n) * (w + 4.0) + (B.NB - B.NBn) * 3.0 * w, dev::k_coarse<T>, B.ncg, dev::BLOCK, 2 * B.cg_maxn * sizeof(double), s, B.R.as<T>(), 1,
-               (const T *)Bp.sw, (T *)B.f, (const T *)uin, uout, h->dense_A, h->dense_inv, B.cg_row0, B.cg_n,
-               B.cg_dense, 0, first);
-      }
-      cur[l] ^= 1;
-      if (B.NBn > 0 && l < maxL)
-        PLAUNCH(h, "w", l, B.nnzA * (w + 4.0) + B.NBn * (l > 0 ? 3.0 : 2.0) * w, dev::k_w<T>, nblocks(B.NBn), dev::BLOCK, 0, s, B.A.as<T>(), B.NBn, (T *)B.sw, (const T *)B.t, l > 0);
-    }
-    for (int l = maxL - 1; l >= 0; --l) {
-      DLevel &B = h->L[l];
-      if (B.NBn == 0) continue;
-      DLevel &Bc = h->L[l + 1];
-      PLAUNCH(h, "interp", l, B.nnzP * (w + 4.0) + B.NBn * 2.0 * w + Bc.NB * w, dev::k_interp<T>, nblocks(B.NBn), dev::BLOCK, 0, s, B.P.as<T>(), B.NBn, (T *)B.u[cur[l]],
-             (const T *)Bc.u[cur[l + 1]]);
-      PLAUNCH(h, "relax_post", l, B.nnzA_r * (w + 4.0) + B.NRn * 3.0 * w + B.NB * 2.0 * w, dev::k_relax<T>, nblocks(B.NB), dev::BLOCK, 0, s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
-             (const T *)B.dinv, (const T *)B.u[cur[l]], (T *)B.u[cur[l] ^ 1], (T *)B.t, 0);
-      cur[l] ^= 1;
-    }
+    for (int l = 0; l < std::min(lt, maxL + 1); ++l) enqueue_fac_down<T>(h, s, cur, l, first);
+    if (lt <= maxL) enqueue_tail<T>(h, s, lt, 1, first);
+    for (int l = std::min(lt, maxL) - 1; l >= 0; --l) enqueue_fac_up<T>(h, s, cur, l);
   }
 }
 
@@ -395,7 +502,7 @@ void enqueue_dd_iteration(amgdd_ctx *h, hipStream_t s) {
   const int maxL = (int)h->L.size() - 1;
   for (int l = 1; l <= maxL; ++l) {
     DLevel &B = h->L[l];
-    PLAUNCH(h, "restrict", l, B.nnzGR * (sizeof(T) + 4.0) + (h->L[l - 1].GN + B.GN) * (double)sizeof(T), dev::k_spmv<T>, nblocks(B.GN), dev::BLOCK, 0, s, B.GRt.as<T>(), B.GN, (const T *)h->L[l - 1].rt, (T *)B.rt);
+    PLAUNCH(h, "restrict", l, B.nnzGR * (sizeof(T) + 4.0) + (h->L[l - 1].GN + B.GN) * (double)sizeof(T), dev::k_spmv<T>, nblocks((long long)B.GN << B.glg), dev::BLOCK, 0, s, B.GRt.as<T>(), B.GN, (const T *)h->L[l - 1].rt, (T *)B.rt);
   }
   PLAUNCH(h, "gather", 0, h->f_total * 4.0 + h->S.composite_real_rows * 2.0 * sizeof(T), dev::k_gather<T>, nblocks(h->f_total), dev::BLOCK, 0, s, (int)h->f_total, h->gather_src,
          (const T *)h->r_arena, (T *)h->f_arena);
@@ -413,21 +520,21 @@ void enqueue_v_iteration(amgdd_ctx *h, hipStream_t s) {
     DLevel &B = h->L[l];
     DLevel &Bc = h->L[l + 1];
     if (B.GNn == 0) continue;
-    PLAUNCH(h, "vresid", l, B.nnzGA_n * 12.0 + B.GN * 8.0 + B.GNn * 16.0, dev::k_vresid<double>, nblocks(B.GNn), dev::BLOCK, 0, s, B.GA.as<double>(), B.GNn, B.vf, B.ve[cur[l]], B.vq);
-    PLAUNCH(h, "vdown", l + 1, Bc.nnzGR_n * 12.0 + B.GNn * 8.0 + Bc.GNn * 24.0, dev::k_vdown<double>, nblocks(Bc.GNn), dev::BLOCK, 0, s, Bc.GRd.as<double>(), Bc.GNn, B.vq, Bc.vf,
+    PLAUNCH(h, "vresid", l, B.nnzGA_n * 12.0 + B.GN * 8.0 + B.GNn * 16.0, dev::k_vresid<double>, nblocks((long long)B.GNn << B.glg), dev::BLOCK, 0, s, B.GA.as<double>(), B.GNn, B.vf, B.ve[cur[l]], B.vq);
+    PLAUNCH(h, "vdown", l + 1, Bc.nnzGR_n * 12.0 + B.GNn * 8.0 + Bc.GNn * 24.0, dev::k_vdown<double>, nblocks((long long)Bc.GNn << Bc.glg), dev::BLOCK, 0, s, Bc.GRd.as<double>(), Bc.GNn, B.vq, Bc.vf,
            Bc.gdinv, Bc.ve[cur[l + 1]]);
     PLAUNCH(h, "vcoarse", l + 1, (Bc.nnzGR - Bc.nnzGR_n) * 12.0 + (Bc.GN - Bc.GNn) * 16.0, dev::k_coarse<double>, Bc.ngc, dev::BLOCK, 2 * Bc.gc_maxn * sizeof(double), s, Bc.GRd.as<double>(), 1, B.vq,
            Bc.vf, Bc.ve[cur[l + 1]], Bc.ve[cur[l + 1]], h->dense_A, h->dense_inv, Bc.gc_row0, Bc.gc_n, Bc.gc_dense, 1,
-           1);
+           1, (double *)nullptr);
   }
   for (int l = maxL - 1; l >= 0; --l) {
     DLevel &B = h->L[l];
     DLevel &Bc = h->L[l + 1];
     if (B.GNn == 0) continue;
-    PLAUNCH(h, "vinterp", l, B.nnzGP * 12.0 + B.GNn * 16.0 + Bc.GN * 8.0, dev::k_interp<double>, nblocks(B.GNn), dev::BLOCK, 0, s, B.GP.as<double>(), B.GNn, B.ve[cur[l]],
+    PLAUNCH(h, "vinterp", l, B.nnzGP * 12.0 + B.GNn * 16.0 + Bc.GN * 8.0, dev::k_interp<double>, nblocks((long long)B.GNn << B.glg), dev::BLOCK, 0, s, B.GP.as<double>(), B.GNn, B.ve[cur[l]],
            Bc.ve[cur[l + 1]]);
     if (l > 0) {
-      PLAUNCH(h, "vrelax", l, B.nnzGA_n * 12.0 + B.GNn * 16.0 + B.GN * 16.0, dev::k_relax<double>, nblocks(B.GN), dev::BLOCK, 0, s, B.GA.as<double>(), B.GNn, B.GN, B.vf, B.gdinv,
+      PLAUNCH(h, "vrelax", l, B.nnzGA_n * 12.0 + B.GNn * 16.0 + B.GN * 16.0, dev::k_relax<double>, nblocks((long long)B.GN << B.glg), dev::BLOCK, 0, s, B.GA.as<double>(), B.GNn, B.GN, B.vf, B.gdinv,
              B.ve[cur[l]], B.ve[cur[l] ^ 1], (double *)nullptr, 2);
       cur[l] ^= 1;
     } else {
@@ -451,6 +558,59 @@ amgdd_status capture(amgdd_ctx *h, bool dd, hipGraph_t *gr, hipGraphExec_t *ex) 
   return AMGDD_OK;
 }
 
+// Project autotuner: time one graph-replayed AMG-DD iteration for every
+// schedule candidate (cut level x workgroup size) on the caller's data and keep
+// the fastest.  Every candidate computes identical results, so the choice only
+// affects time.  The iterate is restored afterwards.
+amgdd_status autotune(amgdd_ctx *h) {
+  const double t0 = now_s();
+  const int nlev = (int)h->L.size();
+  hipStream_t s = h->stream;
+  std::vector<int> levels, blocks;
+  if (h->prm.tail_level >= -1) levels.push_back(h->prm.tail_level >= nlev ? -1 : h->prm.tail_level);
+  else {
+    levels.push_back(-1);
+    for (int l = nlev - 1; l >= 0; --l) levels.push_back(l);
+  }
+  if (h->prm.tail_block > 0) blocks.push_back(h->prm.tail_block);
+  else blocks = {256, 512, 1024};
+  double *xsave = nullptr;
+  amgdd_status st = h->alloc((void **)&xsave, (size_t)h->N0 * sizeof(double));
+  if (st) return st;
+  HIP_TRY(hipMemcpyAsync(xsave, h->x, (size_t)h->N0 * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (h->mixed()) enqueue_residual<float>(h, s, false);
+  else enqueue_residual<double>(h, s, false);
+  double best = 1e300;
+  int best_l = -1, best_b = 256;
+  for (int lt : levels)
+    for (int bs : blocks) {
+      if (lt < 0 && bs != blocks[0]) continue;
+      h->sched_level = lt;
+      h->sched_block = bs;
+      hipGraph_t gr = nullptr;
+      hipGraphExec_t ex = nullptr;
+      st = capture(h, true, &gr, &ex);
+      if (st) return st;
+      HIP_TRY(hipGraphLaunch(ex, s));
+      HIP_TRY(hipEventRecord(h->ev0, s));
+      for (int r = 0; r < 3; ++r) HIP_TRY(hipGraphLaunch(ex, s));
+      HIP_TRY(hipEventRecord(h->ev1, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+      (void)hipGraphExecDestroy(ex);
+      (void)hipGraphDestroy(gr);
+      if (ms < best) { best = ms; best_l = lt; best_b = bs; }
+    }
+  h->sched_level = best_l;
+  h->sched_block = best_b;
+  HIP_TRY(hipMemcpyAsync(h->x, xsave, (size_t)h->N0 * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  h->drop_graphs();
+  h->autotune_s = now_s() - t0;
+  return AMGDD_OK;
+}
+
 enum SolveKind { SOLVE_DD = 0, SOLVE_V = 1 };
 
 amgdd_status run_solve(amgdd_ctx *h, SolveKind kind, const double *b_dev, double *x_dev, double rtol, int maxit,
@@ -464,6 +624,10 @@ amgdd_status run_solve(amgdd_ctx *h, SolveKind kind, const double *b_dev, double
   const size_t nbytes = (size_t)h->N0 * sizeof(double);
   HIP_TRY(hipMemcpyAsync(h->b, b_dev, nbytes, hipMemcpyDeviceToDevice, s));
   HIP_TRY(hipMemcpyAsync(h->x, x_dev, nbytes, hipMemcpyDeviceToDevice, s));
+  if (kind == SOLVE_DD && h->sched_level == -2) {
+    amgdd_status st = autotune(h);
+    if (st) return st;
+  }
   bool use_graph = h->prm.use_graph != 0;
   if (use_graph) {
     if (kind == SOLVE_DD && !h->g_dd) {
@@ -553,6 +717,17 @@ amgdd_status make_handle(const std::vector<ProblemInput> &in, const amgdd_params
   amgdd_params_default(&h->prm);
   if (prm) h->prm = *prm;
   const amgdd_params &p = h->prm;
+  if (p.tail_block != 0 && p.tail_block != 256 && p.tail_block != 512 && p.tail_block != 1024) {
+    delete h;
+    return fail(ST_EINVAL, "tail_block must be 0, 256, 512 or 1024");
+  }
+  if (p.tail_level < -2) {
+    delete h;
+    return fail(ST_EINVAL, "tail_level must be >= -2");
+  }
+  h->sched_level = -2;
+  h->sched_block = p.tail_block ? p.tail_block : 256;
+  if (p.tail_level >= -1 && p.tail_block != 0) h->sched_level = p.tail_level;
   if (p.n_fac < 1 || (p.precision != AMGDD_FP64 && p.precision != AMGDD_MIXED)) {
     delete h;
     return fail(ST_EINVAL, "bad n_fac or precision");
@@ -565,6 +740,7 @@ amgdd_status make_handle(const std::vector<ProblemInput> &in, const amgdd_params
   }
   h->symmetric = true;
   for (auto &P : h->S.probs) h->symmetric = h->symmetric && P.symmetric;
+  if (h->sched_level > h->S.maxL()) h->sched_level = -1;
   h->host_only = p.device < 0;
   if (!h->host_only) {
     double tu = now_s();
@@ -613,6 +789,8 @@ void amgdd_params_default(amgdd_params *prm) {
   prm->precision = AMGDD_FP64;
   prm->device = 0;
   prm->use_graph = 1;
+  prm->tail_level = -2;
+  prm->tail_block = 0;
 }
 
 amgdd_status amgdd_setup_composite(int n, const int *rowptr, const int *colind, const double *val, const int *part,
@@ -678,6 +856,9 @@ amgdd_status amgdd_get_stats(amgdd_handle h, amgdd_stats *st) {
   long long e = 0;
   for (auto &B : S.lv) e += B.A.entries() + B.P.entries() + B.R.entries();
   st->composite_stored_nnz = e;
+  long long u = 0;
+  for (auto &B : S.lv) u += B.nnzA + B.nnzP + B.nnzR;
+  st->composite_nnz = u;
   st->omissions = S.omissions;
   st->composite_overhead = S.global_nnz ? (double)S.composite_real_nnz / (double)S.global_nnz : 0.0;
   st->setup_hierarchy_s = S.times.hierarchy;
@@ -685,6 +866,9 @@ amgdd_status amgdd_get_stats(amgdd_handle h, amgdd_stats *st) {
   st->setup_pack_s = S.times.pack;
   st->setup_upload_s = S.times.upload;
   st->device_bytes = h->dev_bytes;
+  st->tail_level = h->sched_level;
+  st->tail_block = h->sched_block;
+  st->autotune_s = h->autotune_s;
   return AMGDD_OK;
 }
 
@@ -756,6 +940,10 @@ amgdd_status amgdd_profile(amgdd_handle h, int kind, int reps, amgdd_kernel_time
     ~Reset() { h->prof = nullptr; }
   } reset{h};
   hipStream_t s = h->stream;
+  if (kind == 0 && h->sched_level == -2) {
+    amgdd_status ts = autotune(h);
+    if (ts) return ts;
+  }
   if (kind == 1) enqueue_residual<double>(h, s, true);
   else if (h->mixed()) enqueue_residual<float>(h, s, false);
   else enqueue_residual<double>(h, s, false);
@@ -772,6 +960,7 @@ amgdd_status amgdd_profile(amgdd_handle h, int kind, int reps, amgdd_kernel_time
     std::string name;
     int level, launches;
     double ms, bytes;
+    int grid, block;
   };
   std::vector<Agg> agg;
   for (auto &site : prof.sites) {
@@ -781,7 +970,7 @@ amgdd_status amgdd_profile(amgdd_handle h, int kind, int reps, amgdd_kernel_time
     for (auto &x : agg)
       if (x.name == site.name && x.level == site.level) a = &x;
     if (!a) {
-      agg.push_back(Agg{site.name, site.level, 0, 0.0, 0.0});
+      agg.push_back(Agg{site.name, site.level, 0, 0.0, 0.0, site.grid, site.block});
       a = &agg.back();
     }
     a->launches++;
@@ -796,6 +985,8 @@ amgdd_status amgdd_profile(amgdd_handle h, int kind, int reps, amgdd_kernel_time
     out[i].launches = agg[i].launches / reps;
     out[i].ms = agg[i].ms / reps;
     out[i].bytes = agg[i].bytes / reps;
+    out[i].workgroups = agg[i].grid;
+    out[i].block = agg[i].block;
   }
   return AMGDD_OK;
 }

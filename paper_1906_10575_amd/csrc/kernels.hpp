@@ -1,16 +1,21 @@
 // CDNA4 (gfx950) kernels of the AMG-DD solve phase.
 //
 // Every matrix is a block-diagonal batch over all composite grids (or over
-// all problems for the global hierarchy) stored as sliced ELL with slice
-// height 64: one 64-wide wavefront owns one slice, lane k of the wavefront
-// owns row 64*s + k, and entry j of every row in the slice sits at
-// sptr[s] + 64*j + k, so each load instruction of a wavefront is one
-// contiguous 256-byte (int32) / 512-byte (FP64) segment.  Padding entries
-// carry value 0 and a valid column.
+// all problems for the global hierarchy) stored as *grouped sliced ELL*: each
+// row is served by G = 2^lg lanes (G = 1 on levels with short rows, up to 16
+// on coarse levels whose Galerkin rows hold ~100 entries); one 64-lane
+// wavefront owns one slice of 64/G rows, and step k of the slice stores, for
+// every row r of the slice and every lane j of its group, entry k*G + j of row
+// r at
+//     sptr[slice] + 64*k + (r mod 64/G)*G + j
+// so every load instruction of a wavefront is one contiguous 256-byte (index)
+// / 512-byte (FP64) segment.  Each lane accumulates its entries in order; the
+// G partial sums are combined by an xor-shuffle tree (fixed order, so results
+// do not depend on the launch schedule).  Padding entries carry value 0 and a
+// column of the row's own grid.
 //
-// The AlgFAC cycle (Algorithm 4 of the paper) is split into level-synchronous
-// passes, each fusing the vector updates of one algorithm step with the
-// mat-vec it needs:
+// The AlgFAC cycle (Algorithm 4 of the paper) is split into passes, each
+// fusing the vector updates of one algorithm step with the mat-vec it needs:
 //   relax        delta = (f - A u) / d at real rows, u += delta, t (+)= delta
 //   w            w = s + A t                       (restrict update, part 1)
 //   down         s = R w_{l-1}; f <- f - A u - s;  (restrict update part 2,
@@ -19,7 +24,7 @@
 //   interp       u += P u_{l+1}
 // Relaxation never reads and writes the same u buffer (Jacobi): it reads
 // buffer `u_in` and writes `u_out` for every row of the level (copies where it
-// does not relax); the driver flips the buffers.
+// does not relax).
 //
 // No MFMA: every step is a sparse mat-vec or a vector update (HBM bound).
 #pragma once
@@ -37,6 +42,7 @@ struct SellD {
   const int *sptr;
   const int *col;
   const T *val;
+  int lg;  // lanes per row G = 1 << lg
 };
 
 // Workgroups are dispatched round-robin over the 8 XCDs; remap so that each
@@ -49,19 +55,22 @@ __device__ __forceinline__ int xcd_block() {
   return x * q + (x < r ? x : r) + i;
 }
 
-__device__ __forceinline__ int row_of_thread() { return xcd_block() * BLOCK + (int)threadIdx.x; }
+__device__ __forceinline__ int thread_id() { return xcd_block() * BLOCK + (int)threadIdx.x; }
 
-// Dot product of row r of a sliced-ELL matrix with x, in stored order.
-// ALIGNED: the whole wavefront lies in one slice (rows assigned 64-aligned),
-// so the slice bounds are wave-uniform scalars.
+// Row r of a grouped sliced-ELL matrix times x; `sub` is the calling lane's
+// position in the row's group.  Every lane of the group returns the full sum.
+// ALIGNED: the wavefront lies in one slice (threads assigned 64-aligned), so
+// the slice bounds are wave-uniform scalars.
 template <typename T, typename V, bool ALIGNED = true>
-__device__ __forceinline__ V sell_dot(const SellD<T> &M, int r, const V *__restrict__ x) {
-  int s = r >> 6;
+__device__ __forceinline__ V sell_dot(const SellD<T> &M, int r, int sub, const V *__restrict__ x) {
+  const int lg = M.lg;
+  int s = r >> (6 - lg);
   if (ALIGNED) s = __builtin_amdgcn_readfirstlane(s);
   const int beg = M.sptr[s];
   const int w = (M.sptr[s + 1] - beg) >> 6;
-  const int *__restrict__ c = M.col + beg + (r & 63);
-  const T *__restrict__ v = M.val + beg + (r & 63);
+  const int off = beg + ((r & ((64 >> lg) - 1)) << lg) + sub;
+  const int *__restrict__ c = M.col + off;
+  const T *__restrict__ v = M.val + off;
   V acc = V(0);
   int k = 0;
   for (; k + 2 <= w; k += 2) {
@@ -72,6 +81,7 @@ __device__ __forceinline__ V sell_dot(const SellD<T> &M, int r, const V *__restr
     acc = fma(v1, x1, acc);
   }
   if (k < w) acc = fma((V)v[64 * k], x[c[64 * k]], acc);
+  for (int o = (1 << lg) >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
   return acc;
 }
 
@@ -96,9 +106,10 @@ __device__ __forceinline__ double block_sum(double v) {
 
 // ---------------------------------------------------------------- outer loop
 
-// r = b - A x on the fine level of every problem (FP64), plus per-block
-// partial sums of r^2.  Blocks never straddle two problems (block table).
-// VC: also the V-cycle's first relaxation from zero, e = r / d.
+// r = b - A x on the fine level of every problem (FP64; fine operators use one
+// lane per row), plus per-block partial sums of r^2.  Blocks never straddle two
+// problems (block table).  VC: also the V-cycle's first relaxation from zero,
+// e = r / d.
 template <typename TR, bool VC>
 __global__ __launch_bounds__(BLOCK) void k_resid(SellD<double> A, const double *__restrict__ b,
                                                   const double *__restrict__ x, TR *__restrict__ r_out,
@@ -109,7 +120,7 @@ __global__ __launch_bounds__(BLOCK) void k_resid(SellD<double> A, const double *
   const int row = blk_row0[blk] + (int)threadIdx.x;
   double sq = 0.0;
   if (row < blk_row1[blk]) {
-    const double r = b[row] - sell_dot<double, double, false>(A, row, x);
+    const double r = b[row] - sell_dot<double, double, false>(A, row, 0, x);
     r_out[row] = (TR)r;
     if (VC) e_out[row] = r * dinv[row];
     sq = r * r;
@@ -133,8 +144,11 @@ __global__ __launch_bounds__(BLOCK) void k_norm_final(const double *__restrict__
 // y = M x over rows [0, n) (restriction chain r_{l+1} = R_l r_l).
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_spmv(SellD<T> M, int n, const T *__restrict__ x, T *__restrict__ y) {
-  const int i = row_of_thread();
-  if (i < n) y[i] = sell_dot<T, T>(M, i, x);
+  const int t = thread_id(), i = t >> M.lg, sub = t & ((1 << M.lg) - 1);
+  if (i < n) {
+    const T v = sell_dot<T, T>(M, i, sub, x);
+    if (sub == 0) y[i] = v;
+  }
 }
 
 // Composite right-hand sides of every level at once: f[k] = r[src[k]] where
@@ -142,7 +156,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmv(SellD<T> M, int n, const T *__re
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_gather(int n, const int *__restrict__ src, const T *__restrict__ r,
                                                    T *__restrict__ f) {
-  const int i = row_of_thread();
+  const int i = thread_id();
   if (i < n) {
     const int s = src[i];
     if (s >= 0) f[i] = r[s];
@@ -153,7 +167,7 @@ __global__ __launch_bounds__(BLOCK) void k_gather(int n, const int *__restrict__
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_patch(int n, double *__restrict__ x, const int *__restrict__ owner,
                                                   const T *__restrict__ u0) {
-  const int i = row_of_thread();
+  const int i = thread_id();
   if (i < n) x[i] += (double)u0[owner[i]];
 }
 
@@ -164,7 +178,7 @@ template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_relax_zero(int nr, int nb, const T *__restrict__ f,
                                                        const T *__restrict__ dinv, T *__restrict__ u_out,
                                                        T *__restrict__ t) {
-  const int i = row_of_thread();
+  const int i = thread_id();
   if (i < nr) {
     const T d = f[i] * dinv[i];
     u_out[i] = d;
@@ -180,13 +194,15 @@ template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_relax(SellD<T> A, int nr, int nb, const T *__restrict__ f,
                                                   const T *__restrict__ dinv, const T *__restrict__ u_in,
                                                   T *__restrict__ u_out, T *__restrict__ t, int tmode) {
-  const int i = row_of_thread();
+  const int th = thread_id(), i = th >> A.lg, sub = th & ((1 << A.lg) - 1);
   if (i < nr) {
-    const T d = (f[i] - sell_dot<T, T>(A, i, u_in)) * dinv[i];
-    u_out[i] = u_in[i] + d;
-    if (tmode == 0) t[i] = d;
-    else if (tmode == 1) t[i] += d;
-  } else if (i < nb) {
+    const T d = (f[i] - sell_dot<T, T>(A, i, sub, u_in)) * dinv[i];
+    if (sub == 0) {
+      u_out[i] = u_in[i] + d;
+      if (tmode == 0) t[i] = d;
+      else if (tmode == 1) t[i] += d;
+    }
+  } else if (i < nb && sub == 0) {
     u_out[i] = u_in[i];
   }
 }
@@ -196,10 +212,10 @@ __global__ __launch_bounds__(BLOCK) void k_relax(SellD<T> A, int nr, int nb, con
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_w(SellD<T> A, int nb, T *__restrict__ sw, const T *__restrict__ t,
                                               int has_s) {
-  const int i = row_of_thread();
+  const int th = thread_id(), i = th >> A.lg, sub = th & ((1 << A.lg) - 1);
   if (i < nb) {
-    const T at = sell_dot<T, T>(A, i, t);
-    sw[i] = has_s ? sw[i] + at : at;
+    const T at = sell_dot<T, T>(A, i, sub, t);
+    if (sub == 0) sw[i] = has_s ? sw[i] + at : at;
   }
 }
 
@@ -207,24 +223,28 @@ __global__ __launch_bounds__(BLOCK) void k_w(SellD<T> A, int nb, T *__restrict__
 // w pass); at real rows [0, nr) the coarse residual recalculation
 // f <- (f - A u) - s (skipped in the first cycle, where u = 0), then u <- 0
 // and the first relaxation from zero delta = f / d; ghost rows get u = 0.
+// R and A of one level share the lane grouping.
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_down(SellD<T> R, SellD<T> A, int nr, int nb, const T *__restrict__ w_prev,
                                                  T *__restrict__ sw, T *__restrict__ f, const T *__restrict__ dinv,
                                                  const T *__restrict__ u_in, T *__restrict__ u_out, T *__restrict__ t,
                                                  int first) {
-  const int i = row_of_thread();
+  const int th = thread_id(), i = th >> A.lg, sub = th & ((1 << A.lg) - 1);
   if (i >= nb) return;
-  const T s = sell_dot<T, T>(R, i, w_prev);
-  sw[i] = s;
+  const T s = sell_dot<T, T>(R, i, sub, w_prev);
   if (i < nr) {
     T fi = f[i];
-    if (!first) fi -= sell_dot<T, T>(A, i, u_in);
+    if (!first) fi -= sell_dot<T, T>(A, i, sub, u_in);
     fi -= s;
-    f[i] = fi;
-    const T d = fi * dinv[i];
-    u_out[i] = d;
-    t[i] = first ? d : t[i] + d;
-  } else {
+    if (sub == 0) {
+      sw[i] = s;
+      f[i] = fi;
+      const T d = fi * dinv[i];
+      u_out[i] = d;
+      t[i] = first ? d : t[i] + d;
+    }
+  } else if (sub == 0) {
+    sw[i] = s;
     u_out[i] = T(0);
   }
 }
@@ -234,58 +254,224 @@ __global__ __launch_bounds__(BLOCK) void k_down(SellD<T> R, SellD<T> A, int nr, 
 //                    u_out = A_L^{-1} f
 //   mode 1 (V-cycle): f = R w_prev, u_out = A_L^{-1} f
 // Arithmetic in FP64 (the coarsest solve stays FP64 in the mixed form).
+// u_both, if given, receives u as well (the coarsest level keeps its value in
+// both buffers).
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_coarse(SellD<T> R, int has_r, const T *__restrict__ w_prev,
                                                    T *__restrict__ f, const T *__restrict__ u_in,
                                                    T *__restrict__ u_out, const double *__restrict__ Ad,
                                                    const double *__restrict__ Ainv, const int *__restrict__ row0,
                                                    const int *__restrict__ nn, const int *__restrict__ doff, int mode,
-                                                   int first) {
+                                                   int first, T *u_both) {
   extern __shared__ double sh[];
   const int g = blockIdx.x;
   const int r0 = row0[g], n = nn[g];
   const double *Ag = Ad + doff[g];
   const double *Ig = Ainv + doff[g];
+  const int lg = R.lg, sub = threadIdx.x & ((1 << lg) - 1);
   double *fs = sh;       // n
   double *us = sh + n;   // n
-  for (int i = threadIdx.x; i < n; i += BLOCK) {
-    us[i] = (mode == 0 && !first) ? (double)u_in[r0 + i] : 0.0;
-  }
+  for (int i = threadIdx.x; i < n; i += BLOCK) us[i] = (mode == 0 && !first) ? (double)u_in[r0 + i] : 0.0;
   __syncthreads();
-  for (int i = threadIdx.x; i < n; i += BLOCK) {
+  for (int i = threadIdx.x >> lg; i < n; i += BLOCK >> lg) {
     double s = 0.0;
-    if (has_r) {
-      // row r0+i of R; not wave-aligned in general
-      s = (double)sell_dot<T, T, false>(R, r0 + i, w_prev);
-    }
-    double fi;
-    if (mode == 0) {
-      fi = (double)f[r0 + i];
-      if (!first) {
-        double au = 0.0;
-        for (int j = 0; j < n; ++j) au = fma(Ag[(size_t)i * n + j], us[j], au);
-        fi -= au;
+    if (has_r) s = (double)sell_dot<T, T, false>(R, r0 + i, sub, w_prev);
+    if (sub == 0) {
+      double fi;
+      if (mode == 0) {
+        fi = (double)f[r0 + i];
+        if (!first) {
+          double au = 0.0;
+          for (int j = 0; j < n; ++j) au = fma(Ag[(size_t)i * n + j], us[j], au);
+          fi -= au;
+        }
+        fi -= s;
+      } else {
+        fi = s;
       }
-      fi -= s;
-    } else {
-      fi = s;
+      fs[i] = fi;
+      f[r0 + i] = (T)fi;
     }
-    fs[i] = fi;
-    f[r0 + i] = (T)fi;
   }
   __syncthreads();
   for (int i = threadIdx.x; i < n; i += BLOCK) {
     double u = 0.0;
     for (int j = 0; j < n; ++j) u = fma(Ig[(size_t)i * n + j], fs[j], u);
     u_out[r0 + i] = (T)u;
+    if (u_both) u_both[r0 + i] = (T)u;
   }
 }
 
 // u += P u_c over rows [0, nb).
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_interp(SellD<T> P, int nb, T *__restrict__ u, const T *__restrict__ uc) {
-  const int i = row_of_thread();
-  if (i < nb) u[i] += sell_dot<T, T>(P, i, uc);
+  const int th = thread_id(), i = th >> P.lg, sub = th & ((1 << P.lg) - 1);
+  if (i < nb) {
+    const T v = sell_dot<T, T>(P, i, sub, uc);
+    if (sub == 0) u[i] += v;
+  }
+}
+
+// ---------------------------------------------------------------- per-grid schedule
+
+// Pointers of one batched composite level (A, P, R share the lane grouping).
+template <typename T>
+struct LevelDev {
+  SellD<T> A, P, R;
+  const T *dinv;
+  T *u0, *u1, *t, *sw, *f;
+};
+
+// Row ranges of one grid on one level (see the batched layout).
+struct GridLevel {
+  int rbeg, nreal, gbeg, nghost;
+};
+
+__device__ __forceinline__ int grid_row(const GridLevel &d, int j) {
+  return j < d.nreal ? d.rbeg + j : d.gbeg + (j - d.nreal);
+}
+
+// Persistent per-grid AlgFAC: one workgroup owns one composite grid and runs
+// every level from `lt` down to the grid's coarsest level and back up, for
+// `ncycles` cycles, with workgroup barriers between passes.  The composite
+// operators are block-diagonal over grids (checked at setup, padding
+// included), so no pass of one grid touches another grid.  Each pass is the
+// same per-row arithmetic as the level-synchronous kernels (k_relax_zero /
+// k_relax, k_down, k_w, k_coarse, k_interp), so both schedules give identical
+// results.  Buffer convention (kept by the level-synchronous path too): at
+// the start and end of every cycle a level's u lives in u0; the down pass
+// writes u1, interpolation updates u1, post-relaxation writes u0; the
+// coarsest solve writes both.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_fac_tail(const LevelDev<T> *__restrict__ lv, const GridLevel *__restrict__ gl,
+                                                    int nlev, const int *__restrict__ grids,
+                                                    const int *__restrict__ gridL, const int *__restrict__ gdense,
+                                                    const double *__restrict__ Ad, const double *__restrict__ Ainv,
+                                                    int lt, int ncycles, int first_cycle) {
+  extern __shared__ double sh[];
+  const int g = grids[blockIdx.x];
+  const int L = gridL[g];
+  const GridLevel *G = gl + (size_t)g * nlev;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int c = 0; c < ncycles; ++c) {
+    const int first = first_cycle && c == 0;
+    for (int l = lt; l < L; ++l) {
+      const LevelDev<T> B = lv[l];
+      const GridLevel d = G[l];
+      const int nb = d.nreal + d.nghost;
+      const int lg = B.A.lg, sub = tid & ((1 << lg) - 1), j0 = tid >> lg, js = nt >> lg;
+      if (l == 0) {
+        for (int j = j0; j < nb; j += js) {
+          const int i = grid_row(d, j);
+          if (j < d.nreal) {
+            if (first) {
+              if (sub == 0) {
+                const T dl = B.f[i] * B.dinv[i];
+                B.u1[i] = dl;
+                B.t[i] = dl;
+              }
+            } else {
+              const T dl = (B.f[i] - sell_dot<T, T, false>(B.A, i, sub, B.u0)) * B.dinv[i];
+              if (sub == 0) {
+                B.u1[i] = B.u0[i] + dl;
+                B.t[i] += dl;
+              }
+            }
+          } else if (sub == 0) {
+            B.u1[i] = first ? T(0) : B.u0[i];
+          }
+        }
+      } else {
+        const T *wprev = lv[l - 1].sw;
+        for (int j = j0; j < nb; j += js) {
+          const int i = grid_row(d, j);
+          const T s = sell_dot<T, T, false>(B.R, i, sub, wprev);
+          if (j < d.nreal) {
+            T fi = B.f[i];
+            if (!first) fi -= sell_dot<T, T, false>(B.A, i, sub, B.u0);
+            fi -= s;
+            if (sub == 0) {
+              B.sw[i] = s;
+              B.f[i] = fi;
+              const T dl = fi * B.dinv[i];
+              B.u1[i] = dl;
+              B.t[i] = first ? dl : B.t[i] + dl;
+            }
+          } else if (sub == 0) {
+            B.sw[i] = s;
+            B.u1[i] = T(0);
+          }
+        }
+      }
+      __syncthreads();
+      for (int j = j0; j < nb; j += js) {
+        const int i = grid_row(d, j);
+        const T at = sell_dot<T, T, false>(B.A, i, sub, B.t);
+        if (sub == 0) B.sw[i] = l > 0 ? B.sw[i] + at : at;
+      }
+      __syncthreads();
+    }
+    {
+      const LevelDev<T> B = lv[L];
+      const GridLevel d = G[L];
+      const int n = d.nreal, r0 = d.rbeg;
+      const int lg = B.R.lg, sub = tid & ((1 << lg) - 1);
+      const double *Ag = Ad + gdense[g];
+      const double *Ig = Ainv + gdense[g];
+      double *fs = sh, *us = sh + n;
+      for (int j = tid; j < n; j += nt) us[j] = first ? 0.0 : (double)B.u0[r0 + j];
+      __syncthreads();
+      const T *wprev = lv[L - 1].sw;
+      for (int j = tid >> lg; j < n; j += nt >> lg) {
+        const double s = (double)sell_dot<T, T, false>(B.R, r0 + j, sub, wprev);
+        if (sub == 0) {
+          double fi = (double)B.f[r0 + j];
+          if (!first) {
+            double au = 0.0;
+            for (int k = 0; k < n; ++k) au = fma(Ag[(size_t)j * n + k], us[k], au);
+            fi -= au;
+          }
+          fi -= s;
+          fs[j] = fi;
+          B.f[r0 + j] = (T)fi;
+        }
+      }
+      __syncthreads();
+      for (int j = tid; j < n; j += nt) {
+        double u = 0.0;
+        for (int k = 0; k < n; ++k) u = fma(Ig[(size_t)j * n + k], fs[k], u);
+        B.u0[r0 + j] = (T)u;
+        B.u1[r0 + j] = (T)u;
+      }
+      __syncthreads();
+    }
+    for (int l = L - 1; l >= lt; --l) {
+      const LevelDev<T> B = lv[l];
+      const GridLevel d = G[l];
+      const int nb = d.nreal + d.nghost;
+      const int lg = B.A.lg, sub = tid & ((1 << lg) - 1), j0 = tid >> lg, js = nt >> lg;
+      const T *uc = lv[l + 1].u0;
+      for (int j = j0; j < nb; j += js) {
+        const int i = grid_row(d, j);
+        const T v = sell_dot<T, T, false>(B.P, i, sub, uc);
+        if (sub == 0) B.u1[i] += v;
+      }
+      __syncthreads();
+      for (int j = j0; j < nb; j += js) {
+        const int i = grid_row(d, j);
+        if (j < d.nreal) {
+          const T dl = (B.f[i] - sell_dot<T, T, false>(B.A, i, sub, B.u1)) * B.dinv[i];
+          if (sub == 0) {
+            B.u0[i] = B.u1[i] + dl;
+            B.t[i] = dl;
+          }
+        } else if (sub == 0) {
+          B.u0[i] = B.u1[i];
+        }
+      }
+      __syncthreads();
+    }
+  }
 }
 
 // ---------------------------------------------------------------- V-cycle
@@ -294,29 +480,34 @@ __global__ __launch_bounds__(BLOCK) void k_interp(SellD<T> P, int nb, T *__restr
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_vresid(SellD<T> A, int n, const T *__restrict__ f, const T *__restrict__ e,
                                                    T *__restrict__ q) {
-  const int i = row_of_thread();
-  if (i < n) q[i] = f[i] - sell_dot<T, T>(A, i, e);
+  const int th = thread_id(), i = th >> A.lg, sub = th & ((1 << A.lg) - 1);
+  if (i < n) {
+    const T v = sell_dot<T, T>(A, i, sub, e);
+    if (sub == 0) q[i] = f[i] - v;
+  }
 }
 
 // f = R q_prev, e = f / d (relaxation from zero) over rows [0, n).
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_vdown(SellD<T> R, int n, const T *__restrict__ q_prev, T *__restrict__ f,
                                                   const T *__restrict__ dinv, T *__restrict__ e) {
-  const int i = row_of_thread();
+  const int th = thread_id(), i = th >> R.lg, sub = th & ((1 << R.lg) - 1);
   if (i < n) {
-    const T fi = sell_dot<T, T>(R, i, q_prev);
-    f[i] = fi;
-    e[i] = fi * dinv[i];
+    const T fi = sell_dot<T, T>(R, i, sub, q_prev);
+    if (sub == 0) {
+      f[i] = fi;
+      e[i] = fi * dinv[i];
+    }
   }
 }
 
 // Level-0 post-relaxation fused with the iterate update:
-// x += e + (f - A e) / d.
+// x += e + (f - A e) / d  (fine operators use one lane per row).
 __global__ __launch_bounds__(BLOCK) void k_vfinal(SellD<double> A, int n, const double *__restrict__ f,
                                                    const double *__restrict__ dinv, const double *__restrict__ e,
                                                    double *__restrict__ x) {
-  const int i = row_of_thread();
-  if (i < n) x[i] += e[i] + (f[i] - sell_dot<double, double>(A, i, e)) * dinv[i];
+  const int i = thread_id();
+  if (i < n) x[i] += e[i] + (f[i] - sell_dot<double, double>(A, i, 0, e)) * dinv[i];
 }
 
 // ---------------------------------------------------------------- adjoint
@@ -325,7 +516,7 @@ __global__ __launch_bounds__(BLOCK) void k_vfinal(SellD<double> A, int n, const 
 __global__ __launch_bounds__(BLOCK) void k_face_grad(int nf, const int *__restrict__ fi, const int *__restrict__ fj,
                                                       const double *__restrict__ u, const double *__restrict__ lam,
                                                       double *__restrict__ out) {
-  const int k = row_of_thread();
+  const int k = thread_id();
   if (k < nf) {
     const int i = fi[k], j = fj[k];
     out[k] = j >= 0 ? -(lam[i] - lam[j]) * (u[i] - u[j]) : -lam[i] * u[i];

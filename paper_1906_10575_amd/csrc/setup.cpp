@@ -181,52 +181,127 @@ bool dense_inverse(int n, const std::vector<double> &A, std::vector<double> &inv
   return true;
 }
 
-// CSR (batched, already remapped) -> sliced ELL with slice height 64.
-Sell csr_to_sell(const Csr &M) {
-  Sell S;
-  S.nrows = M.nrows;
-  int ns = (M.nrows + 63) / 64;
-  S.sptr.assign(ns + 1, 0);
-  std::vector<int> width(ns, 0);
-  for (int s = 0; s < ns; ++s) {
-    int w = 0;
-    for (int r = s * 64; r < std::min(M.nrows, s * 64 + 64); ++r) w = std::max(w, M.ptr[r + 1] - M.ptr[r]);
-    width[s] = w;
-  }
-  long long tot = 0;
-  for (int s = 0; s < ns; ++s) {
-    tot += 64LL * width[s];
-    if (tot > std::numeric_limits<int>::max()) throw std::length_error("sliced-ELL layout exceeds 2^31 entries");
-    S.sptr[s + 1] = (int)tot;
-  }
-  S.col.resize(tot);
-  S.val.resize(tot);
+void free_csr(Csr &M) {
+  Csr e;
+  std::swap(M, e);
+}
+
+// Every stored column of a batched matrix must index its source vector and
+// the slice table must cover exactly nrows rows (checked before any upload).
+bool sell_in_bounds(const Sell &S, int nrows, int ncols) {
+  if (S.nrows != nrows) return false;
+  const int rs = 64 >> S.lg;
+  const int ns = (nrows + rs - 1) / rs;
+  if (nrows == 0) return S.sptr.empty() || S.sptr.back() == 0;
+  if ((int)S.sptr.size() != ns + 1 || (size_t)S.sptr.back() != S.col.size() || S.col.size() != S.val.size()) return false;
+  std::atomic<bool> ok(true);
+  parallel_for((long long)S.col.size(), [&](long long b, long long e, int) {
+    for (long long k = b; k < e; ++k)
+      if (S.col[k] < 0 || S.col[k] >= ncols) { ok = false; return; }
+  }, 1 << 20);
+  return ok;
+}
+
+// Block-diagonal check: every stored entry of row r (padding included) must
+// point at a column owned by the same composite grid / problem as r.  The
+// per-grid schedule runs grids concurrently, so any cross-grid load would race.
+bool sell_block_diagonal(const Sell &S, const std::vector<int> &row_owner, const std::vector<int> &col_owner) {
+  const int rs = 64 >> S.lg;
+  const int ns = (S.nrows + rs - 1) / rs;
+  std::atomic<bool> ok(true);
   parallel_for(ns, [&](long long b, long long e, int) {
-    for (long long s = b; s < e; ++s) {
-      int base = S.sptr[s], w = width[s];
-      int beg[64], len[64], pad[64];
+    for (long long sl = b; sl < e && ok; ++sl) {
+      const int base = S.sptr[sl], w = (S.sptr[sl + 1] - base) >> 6;
       for (int lane = 0; lane < 64; ++lane) {
-        int r = (int)s * 64 + lane;
-        len[lane] = r < M.nrows ? M.ptr[r + 1] - M.ptr[r] : 0;
-        beg[lane] = r < M.nrows ? M.ptr[r] : 0;
-        pad[lane] = len[lane] > 0 ? M.col[M.ptr[r + 1] - 1] : 0;
-      }
-      for (int k = 0; k < w; ++k) {
-        int *cdst = S.col.data() + (size_t)base + (size_t)k * 64;
-        double *vdst = S.val.data() + (size_t)base + (size_t)k * 64;
-        for (int lane = 0; lane < 64; ++lane) {
-          if (k < len[lane]) {
-            cdst[lane] = M.col[beg[lane] + k];
-            vdst[lane] = M.val[beg[lane] + k];
-          } else {
-            cdst[lane] = pad[lane];
-            vdst[lane] = 0.0;
-          }
-        }
+        const int r = (int)sl * rs + (lane >> S.lg);
+        if (r >= S.nrows) break;
+        for (int k = 0; k < w; ++k)
+          if (col_owner[S.col[(size_t)base + 64 * k + lane]] != row_owner[r]) { ok = false; return; }
       }
     }
-  }, 64);
-  return S;
+  }, 256);
+  return ok;
+}
+
+// Sliced-ELL layout filled row by row (rows may be written concurrently by
+// different threads): set len[] for every row, call shape(), then put() every
+// entry of a row and pad() it; rows never written keep padding from shape().
+struct SellBuilder {
+  Sell S;
+  std::vector<int> len;
+  int rs = 64;  // rows per slice
+  void init(int nrows, int lg) {
+    S.nrows = nrows;
+    S.lg = lg;
+    rs = 64 >> lg;
+    len.assign(nrows, 0);
+  }
+  void shape() {
+    const int G = 1 << S.lg;
+    const int ns = (S.nrows + rs - 1) / rs;
+    std::vector<int> width(ns, 0);
+    parallel_for(ns, [&](long long b, long long e, int) {
+      for (long long s = b; s < e; ++s) {
+        int w = 0;
+        for (int r = (int)s * rs; r < std::min(S.nrows, (int)s * rs + rs); ++r) w = std::max(w, (len[r] + G - 1) / G);
+        width[s] = w;
+      }
+    }, 1024);
+    S.sptr.assign(ns + 1, 0);
+    long long tot = 0;
+    for (int s = 0; s < ns; ++s) {
+      tot += 64LL * width[s];
+      if (tot > std::numeric_limits<int>::max()) throw std::length_error("sliced-ELL layout exceeds 2^31 entries");
+      S.sptr[s + 1] = (int)tot;
+    }
+    S.col.resize(tot);
+    S.val.resize(tot);
+    // rows past the last row of the final slice (never computed)
+    if (ns > 0)
+      for (int r = S.nrows; r < ns * rs; ++r)
+        for (int k = 0; k < width[ns - 1] * G; ++k) {
+          S.col[at(r, k)] = 0;
+          S.val[at(r, k)] = 0.0;
+        }
+  }
+  inline size_t at(int r, int k) const {
+    const int lg = S.lg;
+    return (size_t)S.sptr[r / rs] + 64 * (size_t)(k >> lg) + ((size_t)(r % rs) << lg) + (k & ((1 << lg) - 1));
+  }
+  inline void put(int r, int k, int c, double v) {
+    const size_t a = at(r, k);
+    S.col[a] = c;
+    S.val[a] = v;
+  }
+  // padding entries of row r: value 0, column = the row's last column, or
+  // `own` (a column of the same composite grid / problem) for an empty row,
+  // so a padded load never touches another grid's data
+  inline void pad(int r, int own) {
+    const int s = r / rs;
+    const int kmax = ((S.sptr[s + 1] - S.sptr[s]) >> 6) << S.lg;
+    const int c = len[r] > 0 ? S.col[at(r, len[r] - 1)] : own;
+    for (int k = len[r]; k < kmax; ++k) {
+      S.col[at(r, k)] = c;
+      S.val[at(r, k)] = 0.0;
+    }
+  }
+  long long nnz_rows(int r0, int r1) const {
+    long long n = 0;
+    for (int r = r0; r < r1; ++r) n += len[r];
+    return n;
+  }
+  Sell take() {
+    std::vector<int>().swap(len);
+    return std::move(S);
+  }
+};
+
+// Lanes per row for rows averaging `avg` entries: the smallest power of two
+// G <= 16 with at most ~10 entries per lane.
+int lanes_log2(double avg) {
+  int lg = 0;
+  while (lg < 4 && avg / (1 << lg) > 10.0) ++lg;
+  return lg;
 }
 
 }  // namespace
@@ -794,18 +869,25 @@ int build_setup(const std::vector<ProblemInput> &in, double theta, int max_coars
       return S.lv[l].GNn + gco[l][q] + i;
     };
     vlog("pack: offsets", t0);
+    // lanes per row of every level, from the mean row length of A_l (of the
+    // restriction rows on a level that only holds coarsest grids); the fine
+    // global level keeps one lane per row
+    for (int l = 0; l <= maxL; ++l) {
+      long long nzA = 0, nzR = 0;
+      for (int g = 0; g < ng; ++g) {
+        if (roff[l][g] >= 0) nzA += S.grids[g].lv[l].A.nnz();
+        if (l > 0 && (roff[l][g] >= 0 || coff[l][g] >= 0)) nzR += S.grids[g].lv[l - 1].P.nnz();
+      }
+      BatchLevel &B = S.lv[l];
+      B.lg = B.NBn > 0 ? lanes_log2((double)nzA / B.NBn) : (B.NB > 0 ? lanes_log2((double)nzR / B.NB) : 0);
+      long long nzG = 0;
+      for (int q = 0; q < nprob; ++q)
+        if (l <= S.probs[q].H.L()) nzG += S.probs[q].H.A[l].nnz();
+      B.glg = (l == 0 || B.GN == 0) ? 0 : lanes_log2((double)nzG / B.GN);
+    }
     for (int l = 0; l <= maxL; ++l) {
       BatchLevel &B = S.lv[l];
       double tp = now_s();
-      // composite A (normal rows), P (normal rows), dinv, gsrc
-      Csr A, Pm;
-      A.nrows = A.ncols = B.NBn;
-      Pm.nrows = B.NBn;
-      Pm.ncols = l < maxL ? S.lv[l + 1].NB : 0;
-      A.ptr.assign(B.NBn + 1, 0);
-      Pm.ptr.assign(B.NBn + 1, 0);
-      B.dinv.assign(B.NRn, 0.0);
-      B.gsrc.assign(B.NB, -1);
       std::vector<int> normal;
       for (int g = 0; g < ng; ++g) {
         if (roff[l][g] >= 0) normal.push_back(g);
@@ -814,115 +896,210 @@ int build_setup(const std::vector<ProblemInput> &in, double theta, int max_coars
           B.cg_row0.push_back(B.NBn + coff[l][g]);
           B.cg_n.push_back(lv.nbar());
           B.cg_dense.push_back(S.dense_off[S.grids[g].prob]);
-          for (int i = 0; i < lv.nbar(); ++i) B.gsrc[B.NBn + coff[l][g] + i] = gbidx(S.grids[g].prob, l, lv.gid[i]);
         }
       }
-      for (int g : normal) {
-        const CompLevel &lv = S.grids[g].lv[l];
-        for (int i = 0; i < lv.nbar(); ++i) {
-          int row = bidx(g, l, i);
-          A.ptr[row + 1] = lv.A.ptr[i + 1] - lv.A.ptr[i];
-          Pm.ptr[row + 1] = lv.P.ptr[i + 1] - lv.P.ptr[i];
-        }
-      }
-      for (int i = 0; i < B.NBn; ++i) { A.ptr[i + 1] += A.ptr[i]; Pm.ptr[i + 1] += Pm.ptr[i]; }
-      A.col.resize(A.ptr[B.NBn]);
-      A.val.resize(A.ptr[B.NBn]);
-      Pm.col.resize(Pm.ptr[B.NBn]);
-      Pm.val.resize(Pm.ptr[B.NBn]);
-      parallel_items((int)normal.size(), [&](int k, int) {
-        int g = normal[k];
-        const CompLevel &lv = S.grids[g].lv[l];
-        int q = S.grids[g].prob;
-        for (int i = 0; i < lv.nbar(); ++i) {
-          int row = bidx(g, l, i);
-          int o = A.ptr[row];
-          for (int jj = lv.A.ptr[i]; jj < lv.A.ptr[i + 1]; ++jj, ++o) { A.col[o] = bidx(g, l, lv.A.col[jj]); A.val[o] = lv.A.val[jj]; }
-          o = Pm.ptr[row];
-          for (int jj = lv.P.ptr[i]; jj < lv.P.ptr[i + 1]; ++jj, ++o) { Pm.col[o] = bidx(g, l + 1, lv.P.col[jj]); Pm.val[o] = lv.P.val[jj]; }
-          if (i < lv.nreal) { B.dinv[row] = lv.dinv[i]; B.gsrc[row] = gbidx(q, l, lv.gid[i]); }
+      const int nn = (int)normal.size();
+      // ---- composite A and P rows of normal grids, dinv, gather sources
+      SellBuilder bA, bP;
+      bA.init(B.NBn, B.lg);
+      bP.init(B.NBn, B.lg);
+      B.dinv.assign(B.NRn, 0.0);
+      B.gsrc.assign(B.NB, -1);
+      parallel_items(ng, [&](int g, int) {
+        const int q = S.grids[g].prob;
+        if (roff[l][g] >= 0) {
+          const CompLevel &lv = S.grids[g].lv[l];
+          for (int i = 0; i < lv.nbar(); ++i) {
+            int row = bidx(g, l, i);
+            bA.len[row] = lv.A.ptr[i + 1] - lv.A.ptr[i];
+            bP.len[row] = lv.P.ptr[i + 1] - lv.P.ptr[i];
+            if (i < lv.nreal) { B.dinv[row] = lv.dinv[i]; B.gsrc[row] = gbidx(q, l, lv.gid[i]); }
+          }
+        } else if (coff[l][g] >= 0) {
+          const CompLevel &lv = S.grids[g].lv[l];
+          for (int i = 0; i < lv.nbar(); ++i) B.gsrc[B.NBn + coff[l][g] + i] = gbidx(q, l, lv.gid[i]);
         }
       });
-      vlog("pack: composite CSR", tp);
-      tp = now_s();
-      B.nnzA_r = A.ptr[B.NRn];
-      B.nnzA = A.ptr[B.NBn];
-      B.nnzP = Pm.nnz();
-      B.A = csr_to_sell(A);
-      vlog("pack:   sell A", tp);
-      B.P = csr_to_sell(Pm);
-      vlog("pack:   sell P", tp);
+      bA.shape();
+      bP.shape();
+      parallel_items(nn, [&](int k, int) {
+        int g = normal[k];
+        const CompLevel &lv = S.grids[g].lv[l];
+        for (int i = 0; i < lv.nbar(); ++i) {
+          int row = bidx(g, l, i);
+          int kk = 0;
+          for (int jj = lv.A.ptr[i]; jj < lv.A.ptr[i + 1]; ++jj) bA.put(row, kk++, bidx(g, l, lv.A.col[jj]), lv.A.val[jj]);
+          bA.pad(row, bidx(g, l, 0));
+          kk = 0;
+          for (int jj = lv.P.ptr[i]; jj < lv.P.ptr[i + 1]; ++jj) bP.put(row, kk++, bidx(g, l + 1, lv.P.col[jj]), lv.P.val[jj]);
+          bP.pad(row, bidx(g, l + 1, 0));
+        }
+      });
+      B.nnzA_r = bA.nnz_rows(0, B.NRn);
+      B.nnzA = bA.nnz_rows(0, B.NBn);
+      B.nnzP = bP.nnz_rows(0, B.NBn);
+      B.A = bA.take();
+      B.P = bP.take();
+      vlog("pack: composite A, P", tp);
+      // ---- R_l = P_l^T (block-diagonal: one transpose per grid), rows of level l+1
       if (l < maxL) {
-        Csr R = transpose(Pm);
-        vlog("pack:   transpose P", tp);
-        S.lv[l + 1].nnzR_n = R.ptr[S.lv[l + 1].NBn];
-        S.lv[l + 1].nnzR = R.nnz();
-        S.lv[l + 1].R = csr_to_sell(R);
+        BatchLevel &Bn = S.lv[l + 1];
+        SellBuilder bR;
+        bR.init(Bn.NB, Bn.lg);
+        std::vector<Csr> Rl(nn);
+        parallel_items(nn, [&](int k, int) {
+          int g = normal[k];
+          const CompLevel &lv = S.grids[g].lv[l];
+          Rl[k] = transpose(lv.P);
+          Rl[k].nrows = S.grids[g].lv[l + 1].nbar();
+          Rl[k].ptr.resize(Rl[k].nrows + 1, Rl[k].ptr.back());
+          for (int J = 0; J < Rl[k].nrows; ++J) bR.len[bidx(g, l + 1, J)] = Rl[k].ptr[J + 1] - Rl[k].ptr[J];
+        });
+        bR.shape();
+        parallel_items(nn, [&](int k, int) {
+          int g = normal[k];
+          const Csr &R = Rl[k];
+          for (int J = 0; J < R.nrows; ++J) {
+            int row = bidx(g, l + 1, J);
+            int kk = 0;
+            for (int jj = R.ptr[J]; jj < R.ptr[J + 1]; ++jj) bR.put(row, kk++, bidx(g, l, R.col[jj]), R.val[jj]);
+            bR.pad(row, bidx(g, l, 0));
+          }
+        });
+        Bn.nnzR_n = bR.nnz_rows(0, Bn.NBn);
+        Bn.nnzR = bR.nnz_rows(0, Bn.NB);
+        Bn.R = bR.take();
       }
-      vlog("pack: composite SELL+R", tp);
+      // local operators of this level are no longer needed
+      parallel_items(nn, [&](int k, int) {
+        CompLevel &lv = S.grids[normal[k]].lv[l];
+        free_csr(lv.A);
+        free_csr(lv.P);
+      });
+      vlog("pack: composite R", tp);
       tp = now_s();
-      // global level l over problems
-      Csr GA, GP;
-      GA.nrows = GA.ncols = B.GN;
-      GP.nrows = B.GNn;
-      GP.ncols = l < maxL ? S.lv[l + 1].GN : 0;
-      GA.ptr.assign(B.GN + 1, 0);
-      GP.ptr.assign(B.GNn + 1, 0);
+      // ---- global level l over problems
+      SellBuilder bGA, bGP;
+      bGA.init(B.GN, B.glg);
+      bGP.init(B.GNn, B.glg);
       B.gdinv.assign(B.GNn, 0.0);
       B.prob_row0.assign(nprob, -1);
       for (int q = 0; q < nprob; ++q) {
         const Hierarchy &H = S.probs[q].H;
         if (l > H.L()) continue;
-        int base = gbidx(q, l, 0);
-        B.prob_row0[q] = base;
-        const Csr &Al = H.A[l];
-        for (int i = 0; i < Al.nrows; ++i) GA.ptr[base + i + 1] = Al.ptr[i + 1] - Al.ptr[i];
-        if (l < H.L())
-          for (int i = 0; i < Al.nrows; ++i) GP.ptr[base + i + 1] = H.P[l].ptr[i + 1] - H.P[l].ptr[i];
-        else {
-          B.gc_row0.push_back(base);
-          B.gc_n.push_back(Al.nrows);
+        B.prob_row0[q] = gbidx(q, l, 0);
+        if (l == H.L()) {
+          B.gc_row0.push_back(gbidx(q, l, 0));
+          B.gc_n.push_back(H.A[l].nrows);
           B.gc_dense.push_back(S.dense_off[q]);
         }
       }
-      for (int i = 0; i < B.GN; ++i) GA.ptr[i + 1] += GA.ptr[i];
-      for (int i = 0; i < B.GNn; ++i) GP.ptr[i + 1] += GP.ptr[i];
-      GA.col.resize(GA.ptr[B.GN]);
-      GA.val.resize(GA.ptr[B.GN]);
-      GP.col.resize(GP.ptr[B.GNn]);
-      GP.val.resize(GP.ptr[B.GNn]);
+      parallel_items(nprob, [&](int q, int) {
+        const Hierarchy &H = S.probs[q].H;
+        if (l > H.L()) return;
+        int base = gbidx(q, l, 0);
+        const Csr &Al = H.A[l];
+        for (int i = 0; i < Al.nrows; ++i) bGA.len[base + i] = Al.ptr[i + 1] - Al.ptr[i];
+        if (l < H.L())
+          for (int i = 0; i < Al.nrows; ++i) {
+            bGP.len[base + i] = H.P[l].ptr[i + 1] - H.P[l].ptr[i];
+            B.gdinv[base + i] = 1.0 / H.l1[l][i];
+          }
+      });
+      bGA.shape();
+      bGP.shape();
       parallel_items(nprob, [&](int q, int) {
         const Hierarchy &H = S.probs[q].H;
         if (l > H.L()) return;
         int base = gbidx(q, l, 0);
         const Csr &Al = H.A[l];
         for (int i = 0; i < Al.nrows; ++i) {
-          int o = GA.ptr[base + i];
-          for (int jj = Al.ptr[i]; jj < Al.ptr[i + 1]; ++jj, ++o) { GA.col[o] = base + Al.col[jj]; GA.val[o] = Al.val[jj]; }
+          int kk = 0;
+          for (int jj = Al.ptr[i]; jj < Al.ptr[i + 1]; ++jj) bGA.put(base + i, kk++, base + Al.col[jj], Al.val[jj]);
+          bGA.pad(base + i, base);
         }
         if (l < H.L()) {
           int cbase = gbidx(q, l + 1, 0);
           const Csr &Pl = H.P[l];
           for (int i = 0; i < Al.nrows; ++i) {
-            int o = GP.ptr[base + i];
-            for (int jj = Pl.ptr[i]; jj < Pl.ptr[i + 1]; ++jj, ++o) { GP.col[o] = cbase + Pl.col[jj]; GP.val[o] = Pl.val[jj]; }
-            B.gdinv[base + i] = 1.0 / H.l1[l][i];
+            int kk = 0;
+            for (int jj = Pl.ptr[i]; jj < Pl.ptr[i + 1]; ++jj) bGP.put(base + i, kk++, cbase + Pl.col[jj], Pl.val[jj]);
+            bGP.pad(base + i, cbase);
           }
         }
       });
-      B.nnzGA_n = GA.ptr[B.GNn];
-      B.nnzGA = GA.nnz();
-      B.nnzGP = GP.nnz();
-      B.GA = csr_to_sell(GA);
-      B.GP = csr_to_sell(GP);
+      B.nnzGA_n = bGA.nnz_rows(0, B.GNn);
+      B.nnzGA = bGA.nnz_rows(0, B.GN);
+      B.nnzGP = bGP.nnz_rows(0, B.GNn);
+      B.GA = bGA.take();
+      B.GP = bGP.take();
       if (l < maxL) {
-        Csr GR = transpose(GP);
-        S.lv[l + 1].nnzGR_n = GR.ptr[S.lv[l + 1].GNn];
-        S.lv[l + 1].nnzGR = GR.nnz();
-        S.lv[l + 1].GR = csr_to_sell(GR);
+        // R_l = P_l^T is stored in the hierarchy; rows = level l+1
+        BatchLevel &Bn = S.lv[l + 1];
+        SellBuilder bGR;
+        bGR.init(Bn.GN, Bn.glg);
+        parallel_items(nprob, [&](int q, int) {
+          const Hierarchy &H = S.probs[q].H;
+          if (l >= H.L()) return;
+          int cbase = gbidx(q, l + 1, 0);
+          for (int J = 0; J < H.R[l].nrows; ++J) bGR.len[cbase + J] = H.R[l].ptr[J + 1] - H.R[l].ptr[J];
+        });
+        bGR.shape();
+        parallel_items(nprob, [&](int q, int) {
+          const Hierarchy &H = S.probs[q].H;
+          if (l >= H.L()) return;
+          int base = gbidx(q, l, 0), cbase = gbidx(q, l + 1, 0);
+          const Csr &R = H.R[l];
+          for (int J = 0; J < R.nrows; ++J) {
+            int kk = 0;
+            for (int jj = R.ptr[J]; jj < R.ptr[J + 1]; ++jj) bGR.put(cbase + J, kk++, base + R.col[jj], R.val[jj]);
+            bGR.pad(cbase + J, base);
+          }
+        });
+        Bn.nnzGR_n = bGR.nnz_rows(0, Bn.GNn);
+        Bn.nnzGR = bGR.nnz_rows(0, Bn.GN);
+        Bn.GR = bGR.take();
       }
+      vlog("pack: global", tp);
     }
     vlog("pack: levels", t0);
+    if (verbose())
+      for (int l = 0; l <= maxL; ++l) {
+        const BatchLevel &B = S.lv[l];
+        std::fprintf(stderr, "[amgdd setup] level %d rows %d/%d/%d G %d/%d  A %lld/%lld  P %lld/%lld  R %lld/%lld\n", l,
+                     B.NRn, B.NBn, B.NB, 1 << B.lg, 1 << B.glg, B.nnzA, B.A.entries(), B.nnzP, B.P.entries(), B.nnzR,
+                     B.R.entries());
+      }
+    for (int l = 0; l <= maxL; ++l) {
+      const BatchLevel &B = S.lv[l];
+      const int nbn = l < maxL ? S.lv[l + 1].NB : 0, nbp = l > 0 ? S.lv[l - 1].NB : 0;
+      const int gnn = l < maxL ? S.lv[l + 1].GN : 0, gnp = l > 0 ? S.lv[l - 1].GN : 0;
+      bool ok = sell_in_bounds(B.A, B.NBn, B.NB) && sell_in_bounds(B.P, B.NBn, std::max(nbn, 1)) &&
+                sell_in_bounds(B.GA, B.GN, B.GN) && sell_in_bounds(B.GP, B.GNn, std::max(gnn, 1));
+      if (l > 0) ok = ok && sell_in_bounds(B.R, B.NB, nbp) && sell_in_bounds(B.GR, B.GN, gnp);
+      if (!ok) { err = "internal: batched layout check failed on level " + std::to_string(l); return ST_EINVAL; }
+    }
+    {
+      // owners of every composite / global row, per level
+      std::vector<std::vector<int>> cown(maxL + 1), gown(maxL + 1);
+      for (int l = 0; l <= maxL; ++l) {
+        cown[l].assign(S.lv[l].NB, -1);
+        gown[l].assign(S.lv[l].GN, -1);
+      }
+      for (int g = 0; g < ng; ++g)
+        for (int l = 0; l <= S.probs[S.grids[g].prob].H.L(); ++l)
+          for (int i = 0; i < S.grids[g].lv[l].nbar(); ++i) cown[l][bidx(g, l, i)] = g;
+      for (int q = 0; q < nprob; ++q)
+        for (int l = 0; l <= S.probs[q].H.L(); ++l)
+          for (int i = 0; i < S.probs[q].H.A[l].nrows; ++i) gown[l][gbidx(q, l, i)] = q;
+      for (int l = 0; l <= maxL; ++l) {
+        const BatchLevel &B = S.lv[l];
+        bool ok = sell_block_diagonal(B.A, cown[l], cown[l]) && sell_block_diagonal(B.GA, gown[l], gown[l]);
+        if (l < maxL) ok = ok && sell_block_diagonal(B.P, cown[l], cown[l + 1]) && sell_block_diagonal(B.GP, gown[l], gown[l + 1]);
+        if (l > 0) ok = ok && sell_block_diagonal(B.R, cown[l], cown[l - 1]) && sell_block_diagonal(B.GR, gown[l], gown[l - 1]);
+        if (!ok) { err = "internal: batched layout is not block-diagonal on level " + std::to_string(l); return ST_EINVAL; }
+      }
+    }
     // fine-vector offsets (every problem is normal on level 0, so problem order)
     S.prob_off.assign(nprob + 1, 0);
     for (int q = 0; q < nprob; ++q) S.prob_off[q + 1] = S.prob_off[q] + S.probs[q].n;
@@ -945,6 +1122,30 @@ int build_setup(const std::vector<ProblemInput> &in, double theta, int max_coars
       }
     }
     S.prob_blk0[nprob] = (int)S.blk_row0.size();
+    // per-grid row ranges for the per-grid (persistent) schedule
+    const int nlv = maxL + 1;
+    S.gl_rbeg.assign((size_t)ng * nlv, 0);
+    S.gl_nreal.assign((size_t)ng * nlv, 0);
+    S.gl_gbeg.assign((size_t)ng * nlv, 0);
+    S.gl_nghost.assign((size_t)ng * nlv, 0);
+    S.grid_L.assign(ng, 0);
+    for (int g = 0; g < ng; ++g) {
+      int L = S.probs[S.grids[g].prob].H.L();
+      S.grid_L[g] = L;
+      for (int l = 0; l <= L; ++l) {
+        const CompLevel &lv = S.grids[g].lv[l];
+        size_t k = (size_t)g * nlv + l;
+        if (l < L) {
+          S.gl_rbeg[k] = roff[l][g];
+          S.gl_nreal[k] = lv.nreal;
+          S.gl_gbeg[k] = S.lv[l].NRn + goff[l][g];
+          S.gl_nghost[k] = lv.nbar() - lv.nreal;
+        } else {
+          S.gl_rbeg[k] = S.lv[l].NBn + coff[l][g];
+          S.gl_nreal[k] = lv.nbar();
+        }
+      }
+    }
     S.times.pack = now_s() - t0;
     return ST_OK;
   } catch (const std::bad_alloc &) {

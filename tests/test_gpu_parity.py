@@ -271,16 +271,58 @@ def test_adjoint_gradients_vs_central_differences(precision):
     assert np.abs(gc[sel] - fd_c).max() <= 1e-6 * np.abs(gc).max()
 
 
-def test_error_paths_on_device():
+@pytest.mark.parametrize("lt,bs", [(-2, 0), (-1, 256), (0, 256), (1, 512)])
+def test_error_paths_on_device(lt, bs):
+    """Non-finite input is reported as EBREAKDOWN; iterations that ran on
+    non-finite data (the autotuner on the first solve, or the profiler on the
+    handle's stored right-hand side) leave nothing behind: the next clean solve
+    is bitwise identical to one on a fresh handle, for every schedule (padding
+    of empty rows never reads another grid's rows)."""
     p = CASES["3d_16_eta1"]()
-    s = amgdd.Solver(p.A, p.part, p.nparts, padding=1)
+    say("error paths, schedule", lt, bs)
     b = _t(p.b)
+    fresh = amgdd.Solver(p.A, p.part, p.nparts, padding=1, tail_level=lt, tail_block=bs)
+    x_ref, _, _ = fresh.solve(b, rtol=0, maxit=2)
+    s = amgdd.Solver(p.A, p.part, p.nparts, padding=1, tail_level=lt, tail_block=bs)
     bad = b.clone()
     bad[7] = float("nan")
     with pytest.raises(amgdd.AmgddError) as e:
         s.solve(bad, rtol=1e-8, maxit=5)
     assert e.value.status == amgdd.EBREAKDOWN
+    s.profile(kind=0, reps=2)
     x, info, st = s.solve(b, rtol=1e-14, maxit=2)
     assert st == amgdd.ENOCONV and info.iters == 2
+    assert torch.equal(x, x_ref)
     x2, _, st2 = s.solve(b, rtol=0, maxit=2)
     assert st2 == amgdd.OK and torch.equal(x, x2)
+
+
+@pytest.mark.parametrize("name", ["3d_20_var_eta2", "2d_var_eta2_nfac3"])
+def test_every_schedule_gives_identical_iterates(name, oracle_cache):
+    """The per-grid persistent schedule (cut level lt, workgroup size) performs
+    the same per-row arithmetic as the level-synchronous one: results are
+    bitwise identical for every choice, and match the oracle."""
+    p, H, comps = _oracle(name, oracle_cache)
+    b = _t(p.b)
+    ref = None
+    nlev = H.L + 1
+    xo = np.zeros(p.n)
+    coarse = cycles.CoarseSolver(H.A[H.L])
+    for _ in range(3):
+        xo = cycles.amgdd_iteration(H, comps, p.b, xo, p.n_fac, coarse)
+    for lt, bs in [(-1, 256), (0, 256), (0, 1024), (1, 512), (nlev - 1, 256), (nlev // 2, 1024)]:
+        say("schedule", name, lt, bs)
+        s = amgdd.Solver(p.A, p.part, p.nparts, padding=p.eta, n_fac=p.n_fac, tail_level=lt, tail_block=bs)
+        x, info, st = s.solve(b, rtol=0, maxit=3)
+        st_ = s.stats()
+        assert st_["tail_level"] == lt and st_["tail_block"] == bs
+        xn = _np(x)
+        if ref is None:
+            ref = xn
+        assert np.array_equal(xn, ref), (lt, bs)
+        assert _rel(xn, xo) <= 1e-12
+    s = amgdd.Solver(p.A, p.part, p.nparts, padding=p.eta, n_fac=p.n_fac)
+    x, info, st = s.solve(b, rtol=0, maxit=3)
+    st_ = s.stats()
+    say("  autotuned:", st_["tail_level"], st_["tail_block"], f"{st_['autotune_s']:.3f} s")
+    assert np.array_equal(_np(x), ref)
