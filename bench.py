@@ -52,6 +52,21 @@ def build_problem(name):
     return config(name)
 
 
+def measured_traffic(dom):
+    """HBM bytes per launch of the dominant site from the committed rocprofv3
+    --pmc record in profiles/, or None when no record matches this launch site
+    or the kernel source changed since the counters were taken."""
+    import glob
+    import hashlib
+    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_1906_10575_amd", "csrc", "kernels.hpp"), "rb").read()).hexdigest()
+    for path in glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json")):
+        rec = json.load(open(path))
+        if (rec.get("kernels_sha256") == sha and rec.get("site") == dom["name"] and rec.get("level") == dom["level"]
+                and rec.get("workgroups") == dom.get("workgroups")):
+            return rec["traffic_bytes"]
+    return None
+
+
 def roofline(prof):
     """Dominant launch site of one iteration: algorithmic bytes per launch over
     the average launch duration (HIP events on the launch stream)."""
@@ -60,7 +75,7 @@ def roofline(prof):
     per_launch_bytes = dom["bytes"] / dom["launches"]
     achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
     return dom, {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),
                  "kernel": f"{dom['name']} (level {dom['level']})", "workgroups": dom.get("workgroups"),
                  "block": dom.get("block"), "bytes_per_launch": per_launch_bytes, "ms_per_launch": per_launch_ms}
 
@@ -125,6 +140,25 @@ def summarize_rocpd(db):
     return "\n".join(lines)
 
 
+def summarize_pmc(path):
+    """Mean counter value per (kernel, workgroups) from rocprofv3 --pmc CSV
+    output (counter_collection.csv), as text."""
+    import csv
+    agg = {}
+    with open(path) as fh:
+        for row in csv.DictReader(fh):
+            name = row.get("Kernel_Name", "")
+            short = name.split("(")[0].replace("void ", "").replace("amgdd::dev::", "")
+            grid = int(float(row.get("Grid_Size", 0) or 0))
+            wg = int(float(row.get("Workgroup_Size", 1) or 1))
+            key = (short, grid // max(wg, 1), wg, row.get("Counter_Name", ""))
+            agg.setdefault(key, []).append(float(row.get("Counter_Value", 0) or 0))
+    lines = ["kernel                           workgroups x size  counter        dispatches   mean_value", "-" * 88]
+    for k, v in sorted(agg.items(), key=lambda kv: (kv[0][3], -sum(kv[1]))):
+        lines.append(f"{k[0][:32]:32s} {k[1]:10d} x {k[2]:4d}  {k[3]:14s} {len(v):6d} {sum(v) / len(v):14.1f}")
+    return "\n".join(lines)
+
+
 def residual_rel(p, x):
     if isinstance(p, list):
         off = np.cumsum([0] + [q.n for q in p])
@@ -162,9 +196,15 @@ def main():
     ap.add_argument("--tail-level", type=int, default=-2, help="fixed AlgFAC schedule cut level (-2: autotune)")
     ap.add_argument("--tail-block", type=int, default=0, help="fixed persistent workgroup size (0: autotune)")
     ap.add_argument("--summarize-rocpd", metavar="DB", help="print a summary of a rocprofv3 kernel-trace database")
+    ap.add_argument("--summarize-pmc", metavar="CSV", help="print a summary of rocprofv3 --pmc CSV output")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run 3 elementwise copies of 256 MiB (known HBM traffic, to scale PMC counters)")
     args = ap.parse_args()
     if args.summarize_rocpd:
         print(summarize_rocpd(args.summarize_rocpd))
+        return
+    if args.summarize_pmc:
+        print(summarize_pmc(args.summarize_pmc))
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -200,6 +240,16 @@ def main():
     relres = residual_rel(p, x.cpu().numpy())
     log(f"AMG-DD: {its} iterations per step, {ms_per_step:.2f} ms per step, {value:.3e} DOF*cycles/s, "
         f"final relres (FP64, host) {relres:.2e}")
+
+    if args.calibrate_copy:
+        # y = x + 1 over 2^25 doubles: 256 MiB read, 256 MiB written per launch
+        xc = torch.ones(1 << 25, dtype=torch.float64, device="cuda:0")
+        yc = torch.empty_like(xc)
+        for _ in range(3):
+            torch.add(xc, 1.0, out=yc)
+        torch.cuda.synchronize()
+        del xc, yc
+        log("calibration copies done (3 x 256 MiB read + 256 MiB write)")
 
     prof = s.profile(kind=0, reps=3)
     dom, roof = roofline(prof)

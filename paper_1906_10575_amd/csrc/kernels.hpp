@@ -71,16 +71,24 @@ __device__ __forceinline__ V sell_dot(const SellD<T> &M, int r, int sub, const V
   const int off = beg + ((r & ((64 >> lg) - 1)) << lg) + sub;
   const int *__restrict__ c = M.col + off;
   const T *__restrict__ v = M.val + off;
+  // The matrix streams are read once per pass: non-temporal loads keep them
+  // from evicting the gathered vector from L2 / MALL.  Four entries in flight
+  // per lane; the sum stays in storage order.
   V acc = V(0);
   int k = 0;
-  for (; k + 2 <= w; k += 2) {
-    const int c0 = c[64 * k], c1 = c[64 * (k + 1)];
-    const V v0 = (V)v[64 * k], v1 = (V)v[64 * (k + 1)];
-    const V x0 = x[c0], x1 = x[c1];
+  for (; k + 4 <= w; k += 4) {
+    const int c0 = __builtin_nontemporal_load(c + 64 * k), c1 = __builtin_nontemporal_load(c + 64 * (k + 1));
+    const int c2 = __builtin_nontemporal_load(c + 64 * (k + 2)), c3 = __builtin_nontemporal_load(c + 64 * (k + 3));
+    const V v0 = (V)__builtin_nontemporal_load(v + 64 * k), v1 = (V)__builtin_nontemporal_load(v + 64 * (k + 1));
+    const V v2 = (V)__builtin_nontemporal_load(v + 64 * (k + 2)), v3 = (V)__builtin_nontemporal_load(v + 64 * (k + 3));
+    const V x0 = x[c0], x1 = x[c1], x2 = x[c2], x3 = x[c3];
     acc = fma(v0, x0, acc);
     acc = fma(v1, x1, acc);
+    acc = fma(v2, x2, acc);
+    acc = fma(v3, x3, acc);
   }
-  if (k < w) acc = fma((V)v[64 * k], x[c[64 * k]], acc);
+  for (; k < w; ++k)
+    acc = fma((V)__builtin_nontemporal_load(v + 64 * k), x[__builtin_nontemporal_load(c + 64 * k)], acc);
   for (int o = (1 << lg) >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
   return acc;
 }

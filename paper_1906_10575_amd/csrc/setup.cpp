@@ -296,11 +296,12 @@ struct SellBuilder {
   }
 };
 
-// Lanes per row for rows averaging `avg` entries: the smallest power of two
-// G <= 16 with at most ~10 entries per lane.
+// Lanes per row for rows averaging `avg` entries: one lane up to 20 entries,
+// otherwise the smallest power of two G <= 16 with at most ~12 entries per lane.
 int lanes_log2(double avg) {
-  int lg = 0;
-  while (lg < 4 && avg / (1 << lg) > 10.0) ++lg;
+  if (avg <= 20.0) return 0;
+  int lg = 1;
+  while (lg < 4 && avg / (1 << lg) > 12.0) ++lg;
   return lg;
 }
 
