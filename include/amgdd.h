@@ -9,14 +9,14 @@
  *   - Composite grids (Section 3, Figure 1): per subdomain, padding eta_l
  *     through the graph of A_l on every level, C-points carried down, the
  *     coarsest level stored whole; ghost layer Dbar_l (Section 4.1).
- *   - AlgFAC cycle (Algorithm 4, Section 4.4) on every composite grid.
+ *   - AlgFAC cycle (Algorithm 4, Section 4.5) on every composite grid.
  *   - AMG-DD outer iteration (Algorithm 2): fine residual, restriction to all
  *     levels, composite right-hand sides, local AlgFAC, correction patched on
  *     each owned subdomain.
  *   - AMG V(1,1) cycle (Algorithm 1) on the same hierarchy.
  * The linear system is given by its fine-grid matrix alone, as the paper
  * states the problem (Section 2), plus a partition into subdomains
- * (Section 3) and the padding / number of AlgFAC cycles (Section 5.1).
+ * (Section 3) and the padding / number of AlgFAC cycles (Section 6.1).
  *
  * Relaxation is point l1-Jacobi: u <- u + (f - A u) / d, d_i = sum_j |a_ij|.
  *
@@ -92,7 +92,7 @@ typedef struct {
   long long composite_real_rows;/* sum over grids and levels of |D_l| */
   long long composite_stored_nnz;/* device nnz of composite A, P, R (incl. padding) */
   long long omissions;      /* interpolation entries dropped (Section 4.2) */
-  double composite_overhead;/* composite_real_nnz / global_nnz (Section 5.1) */
+  double composite_overhead;/* composite_real_nnz / global_nnz (Section 6.1) */
   double setup_hierarchy_s; /* host time: strength, RS, interpolation, Galerkin */
   double setup_composite_s; /* host time: composite sets, local operators */
   double setup_pack_s;      /* host time: batched layouts */

@@ -176,7 +176,7 @@ def build_all(H: Hierarchy, part: np.ndarray, nparts: int, eta, brute: bool = Fa
 
 
 def composite_overhead(H: Hierarchy, comps: Sequence[CompositeGrid]) -> float:
-    """Composite-grid overhead (Section 5.1): nonzeros of A_l at real points,
+    """Composite-grid overhead (Section 6.1): nonzeros of A_l at real points,
     summed over all levels and all composite grids, divided by the total
     nonzeros of the global hierarchy."""
     num = 0

@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY (see oracle/amg.py).
 
 * vcycle          -- AMG V(nu1, nu2) cycle, Algorithm 1 of the paper, with
                      l1-Jacobi relaxation and a direct coarsest solve.
-* algfac          -- the AlgFAC V-cycle, Algorithm 4 (Section 4.4), on one
+* algfac          -- the AlgFAC V-cycle, Algorithm 4 (Section 4.5), on one
                      composite grid, taken step by step in the paper's order
                      and notation (u_l, t_l, s_l, f_l).
 * masked_vcycle   -- the plain definition AlgFAC must reproduce (guiding
@@ -12,6 +12,10 @@ TEST INFRASTRUCTURE ONLY (see oracle/amg.py).
                      residual equation in which relaxation is suppressed
                      outside D_l on each level.
 * amgdd           -- the AMG-DD outer iteration, Algorithm 2 (Section 3).
+* hybrid_vcycle   -- the hybrid AMG-DD V-cycle, Algorithm 3 (Section 3.1):
+                     V-cycle levels above a transition level, one AMG-DD
+                     cycle on the transition level's problem as the coarse
+                     solver (partition inherited along the C-points).
 
 Relaxation is point l1-Jacobi with weight 1: u <- u + (f - A u) / d with
 d_i = sum_j |a_ij| over the full row (the paper's smoother is the CF-ordered
@@ -219,6 +223,76 @@ def vcycle_solve(H, b, x0, rtol=1e-8, maxit=100, callback=None):
         if hist[-1] <= rtol * hist[0]:
             break
         x = vcycle(H, x, b, coarse=coarse)
+        if callback:
+            callback(x)
+        hist.append(float(np.linalg.norm(b - H.A[0] @ x)))
+    return x, hist
+
+
+def inherited_partition(H: Hierarchy, part: np.ndarray, level: int) -> np.ndarray:
+    """Subdomain of every point of `level`: a coarse point is a C-point of the
+    level above and keeps the subdomain of that point (Section 5: each
+    processor's subdomain on level l is the part of Omega_l it owns)."""
+    p = np.asarray(part)
+    for l in range(level):
+        p = p[H.cf[l] == 1]
+    return p
+
+
+def sub_hierarchy(H: Hierarchy, level: int) -> Hierarchy:
+    """Levels `level`..L of H as a hierarchy of its own (A_level is its fine
+    matrix)."""
+    return Hierarchy(A=H.A[level:], P=H.P[level:], R=H.R[level:], cf=H.cf[level:], S=H.S[level:])
+
+
+def hybrid_vcycle(H: Hierarchy, Hs: Hierarchy, comps_s, u0: np.ndarray, f0: np.ndarray, lt: int, n_fac: int,
+                  coarse: Optional[CoarseSolver] = None, dtype=np.float64) -> np.ndarray:
+    """One hybrid AMG-DD V(1,1) cycle (Algorithm 3): V-cycle relaxation and
+    residual restriction on levels 0..lt-1, one AMG-DD cycle (Algorithm 2,
+    from a zero initial guess) on A_lt u_lt = f_lt as the coarse solver, then
+    interpolation and relaxation back up.  Hs / comps_s: the hierarchy below
+    lt and the composite grids built on it with the inherited partition.
+
+    dtype = np.float32 runs the level-lt AMG-DD cycle in its mixed form (see
+    amgdd_iteration); the V-cycle levels stay float64."""
+    coarse = coarse or CoarseSolver(Hs.A[Hs.L])
+    d = [H.l1_diag(l) for l in range(lt)]
+    u = [None] * (lt + 1)
+    f = [None] * (lt + 1)
+    u[0] = np.array(u0, dtype=np.float64)
+    f[0] = np.asarray(f0, dtype=np.float64)
+    for l in range(lt):
+        u[l] = u[l] + l1_relax(H.A[l], d[l], u[l], f[l])
+        f[l + 1] = H.R[l] @ (f[l] - H.A[l] @ u[l])
+        u[l + 1] = np.zeros(H.A[l + 1].shape[0])
+    u[lt] = amgdd_iteration(Hs, comps_s, f[lt], np.zeros(H.A[lt].shape[0]), n_fac, coarse, dtype=dtype)
+    for l in range(lt - 1, -1, -1):
+        u[l] = u[l] + H.P[l] @ u[l + 1]
+        u[l] = u[l] + l1_relax(H.A[l], d[l], u[l], f[l])
+    return u[0]
+
+
+def hybrid_setup(H: Hierarchy, part: np.ndarray, nparts: int, eta, lt: int):
+    """Level-lt AMG-DD problem of the hybrid cycle: the sub-hierarchy below
+    lt (clamped to the coarsest level) and its composite grids over the
+    inherited partition.  Returns (lt, Hs, comps)."""
+    from .composite import build_all
+    lt = min(lt, H.L)
+    Hs = sub_hierarchy(H, lt)
+    return lt, Hs, build_all(Hs, inherited_partition(H, part, lt), nparts, eta)
+
+
+def hybrid_solve(H, Hs, comps_s, lt, b, x0, n_fac, rtol=1e-8, maxit=100, dtype=np.float64, callback=None):
+    """Hybrid AMG-DD V-cycles in correction form, x <- x + C(b - A x), until
+    ||b - A x|| <= rtol ||b - A x0|| or maxit.  Returns (x, history)."""
+    coarse = CoarseSolver(Hs.A[Hs.L])
+    x = np.array(x0, dtype=np.float64)
+    hist = [float(np.linalg.norm(b - H.A[0] @ x))]
+    for _ in range(maxit):
+        if hist[-1] <= rtol * hist[0]:
+            break
+        r = b - H.A[0] @ x
+        x = x + hybrid_vcycle(H, Hs, comps_s, np.zeros_like(r), r, lt, n_fac, coarse, dtype=dtype)
         if callback:
             callback(x)
         hist.append(float(np.linalg.norm(b - H.A[0] @ x)))

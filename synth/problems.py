@@ -7,7 +7,7 @@ right-hand sides and face lists.  It contains none of the multigrid arithmetic
 (no coarsening, interpolation, composite grids or cycles); both the oracle and
 the GPU path consume what it returns.
 
-The paper's workloads (Section 5) are finite-element discretisations of
+The paper's workloads (Section 6) are finite-element discretisations of
 -div(K grad u) = f on regular meshes partitioned by METIS; these generators
 stand in for them with 5-point (2D) and 7-point (3D) stencils on block
 partitions.

@@ -126,7 +126,7 @@ def test_exact_coarse_correction_kills_restricted_residual():
 @pytest.mark.parametrize("dims,parts,eta,k_seed,n_fac", [((32, 32), (2, 2), 1, None, 1), ((30, 26), (3, 2), 2, 5, 3),
                                                          ((10, 10, 10), (2, 2, 2), 1, 7, 2), ((64, 64), (2, 2), 1, None, 2)])
 def test_algfac_equals_masked_global_cycle(dims, parts, eta, k_seed, n_fac):
-    """Section 4 guiding principle, with the restriction rewrite (Section 4.3):
+    """Section 4 guiding principle, with the restriction rewrite (Sections 4.3-4.4):
     AlgFAC on the composite grid gives the same level corrections on Dbar_l
     and the same right-hand sides on D_l as the full-grid cycle with
     relaxation suppressed outside D_l."""
