@@ -14,6 +14,9 @@
  *     levels, composite right-hand sides, local AlgFAC, correction patched on
  *     each owned subdomain.
  *   - AMG V(1,1) cycle (Algorithm 1) on the same hierarchy.
+ *   - Hybrid AMG-DD V(1,1) cycle (Algorithm 3, Section 3.1): V-cycle on the
+ *     levels above a transition level, one AMG-DD cycle on the transition
+ *     level's problem as the coarse solver (amgdd_params.hybrid_level).
  * The linear system is given by its fine-grid matrix alone, as the paper
  * states the problem (Section 2), plus a partition into subdomains
  * (Section 3) and the padding / number of AlgFAC cycles (Section 6.1).
@@ -71,6 +74,18 @@ typedef struct {
                        -1 = level-synchronous everywhere, >= 0 fixed */
   int tail_block;   /* workgroup size of the persistent launch: 256, 512 or 1024;
                        0 = chosen by the autotuner (default) */
+  int hybrid_level; /* 0 = AMG-DD on the fine level (default).  L~ >= 1 = hybrid
+                       AMG-DD (Algorithm 3): amgdd_solve runs hybrid V(1,1)
+                       cycles whose coarse solver on level L~ is one AMG-DD
+                       cycle (from zero, n_fac AlgFAC cycles) on A_L~ with the
+                       subdomains inherited along the C-points (a coarse point
+                       keeps the subdomain of its fine point, Section 5);
+                       subdomains without points on L~ are dropped.  Composite
+                       grids are built for the level-L~ problems only.  A
+                       problem whose hierarchy ends at or above L~ runs plain
+                       V(1,1) cycles (its level-L~ AMG-DD would be the direct
+                       solve).  V-cycle levels run in FP64; `precision`
+                       applies to the level-L~ AMG-DD cycle. */
 } amgdd_params;
 
 typedef struct {
@@ -102,6 +117,11 @@ typedef struct {
   int tail_block;
   double autotune_s;        /* time spent by the autotuner */
   long long composite_nnz;  /* nonzeros of composite A, P, R without padding */
+  int hybrid_level;         /* transition level L~ of a hybrid handle, 0 otherwise.
+                               n_grids, composite_* and omissions then describe
+                               the level-L~ problems' grids (levels >= L~), and
+                               composite_overhead = (nnz of A_l, l < L~, plus
+                               composite_real_nnz) / global_nnz */
 } amgdd_stats;
 
 void amgdd_params_default(amgdd_params *prm);
@@ -137,7 +157,7 @@ amgdd_status amgdd_setup_composite_batch(int nprob, const int *n, const int *con
 
 /*
  * AMG-DD iterations (Algorithm 2 with n_fac AlgFAC cycles, Algorithm 4) on
- * A x = b.  b_dev, x_dev: device FP64 vectors of length sum of N_0; x is the
+ * A x = b; hybrid AMG-DD V-cycles (Algorithm 3) on a hybrid handle.  b_dev, x_dev: device FP64 vectors of length sum of N_0; x is the
  * initial guess on entry and the last iterate on return.  Stops when every
  * problem has ||b - A x|| <= rtol ||b - A x_0|| or after maxit iterations;
  * rtol <= 0 runs exactly maxit iterations and returns OK.  info may be NULL.
@@ -190,7 +210,9 @@ amgdd_status amgdd_get_operator(amgdd_handle h, int prob, int level, int which, 
 /* Composite grid of subdomain p of problem prob on `level`: n_real = |D_l|,
  * n_bar = |Dbar_l|; gids (length n_bar, may be NULL) = global ids on that
  * level, real points first in increasing id, then ghost points in increasing
- * id; omissions = dropped interpolation entries for this grid and level. */
+ * id; omissions = dropped interpolation entries for this grid and level.
+ * Hybrid handle: levels >= hybrid_level only; EINVAL for a subdomain without
+ * points on that level or a problem that has no level-L~ AMG-DD problem. */
 amgdd_status amgdd_get_composite(amgdd_handle h, int prob, int p, int level, int *n_real, int *n_bar,
                                  int *gids, int *omissions);
 
@@ -198,7 +220,9 @@ amgdd_status amgdd_get_composite(amgdd_handle h, int prob, int p, int level, int
 amgdd_status amgdd_get_history(amgdd_handle h, int prob, double *hist, int cap, int *len);
 
 /* Per-launch-site timing of the solve iteration (measurement only).
- * Runs `reps` iterations of kind 0 (AMG-DD) or 1 (V-cycle) from the handle's
+ * Runs `reps` iterations of kind 0 (AMG-DD, or hybrid on a hybrid handle;
+ * levels of the level-L~ sites are counted from the fine level) or 1
+ * (V-cycle) from the handle's
  * internal state, launching kernel by kernel (no graph) with a HIP event pair
  * around every launch on the handle's stream.  Sites are aggregated by
  * (kernel name, level): launches = launches per iteration, ms = device time

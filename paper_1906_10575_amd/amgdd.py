@@ -33,7 +33,7 @@ class AmgddError(RuntimeError):
 class Params(C.Structure):
     _fields_ = [("theta", C.c_double), ("max_coarse", C.c_int), ("max_levels", C.c_int), ("padding", C.c_int),
                 ("n_fac", C.c_int), ("precision", C.c_int), ("device", C.c_int), ("use_graph", C.c_int),
-                ("tail_level", C.c_int), ("tail_block", C.c_int)]
+                ("tail_level", C.c_int), ("tail_block", C.c_int), ("hybrid_level", C.c_int)]
 
 
 class Info(C.Structure):
@@ -49,7 +49,7 @@ class Stats(C.Structure):
                 ("composite_overhead", C.c_double), ("setup_hierarchy_s", C.c_double),
                 ("setup_composite_s", C.c_double), ("setup_pack_s", C.c_double), ("setup_upload_s", C.c_double),
                 ("device_bytes", C.c_longlong), ("tail_level", C.c_int), ("tail_block", C.c_int),
-                ("autotune_s", C.c_double), ("composite_nnz", C.c_longlong)]
+                ("autotune_s", C.c_double), ("composite_nnz", C.c_longlong), ("hybrid_level", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -152,10 +152,12 @@ class Solver:
 
     A: scipy CSR matrix (or a list of them for a batch), part: int array(s) of
     subdomain ids, nparts: int(s), padding: int(s).  device=-1 gives a
-    host-only handle (setup and introspection, no solve)."""
+    host-only handle (setup and introspection, no solve).  hybrid_level=L~ > 0
+    makes solve() run hybrid AMG-DD V-cycles with AMG-DD on level L~."""
 
     def __init__(self, A, part, nparts, padding=1, n_fac=2, precision="fp64", device=0, theta=0.25,
-                 max_coarse=16, max_levels=25, use_graph=True, stream=None, tail_level=-2, tail_block=0):
+                 max_coarse=16, max_levels=25, use_graph=True, stream=None, tail_level=-2, tail_block=0,
+                 hybrid_level=0):
         lib = load()
         batch = isinstance(A, (list, tuple))
         As = list(A) if batch else [A]
@@ -172,6 +174,7 @@ class Solver:
         prm.use_graph = 1 if use_graph else 0
         prm.tail_level = tail_level
         prm.tail_block = tail_block
+        prm.hybrid_level = hybrid_level
         if stream is None and device >= 0:
             torch = _torch()
             stream = torch.cuda.current_stream(device).cuda_stream

@@ -141,6 +141,17 @@ struct ProblemInput {
 int build_setup(const std::vector<ProblemInput> &in, double theta, int max_coarse, int max_levels,
                 Setup &S, std::string &err);
 
+// Hybrid AMG-DD setup (Algorithm 3): `outer` holds every input problem's
+// global hierarchy and layouts without composite grids; `inner` holds the
+// level-lt problem (A_lt, levels lt..L, inherited partition with empty
+// subdomains dropped) of every problem with L > lt, with composite grids.
+// inner_of[q]: index of problem q in `inner` (-1: the problem's hierarchy ends
+// at or above lt and its cycle is a plain V-cycle); part_map[q][p]: index of
+// subdomain p in that inner problem (-1: empty on level lt).
+int build_setup_hybrid(const std::vector<ProblemInput> &in, double theta, int max_coarse, int max_levels, int lt,
+                       Setup &outer, Setup &inner, std::vector<int> &inner_of, std::vector<std::vector<int>> &part_map,
+                       std::string &err);
+
 // Individual steps, exposed for the driver's introspection.
 Csr strength(const Csr &A, double theta);
 std::vector<int8_t> rs_first_pass(const Csr &S);

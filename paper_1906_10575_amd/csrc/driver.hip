@@ -11,7 +11,10 @@
 // and is captured once into a HIP graph that is replayed every iteration; the
 // host reads the per-problem residual norms (8 bytes each) after each replay.
 // The V(1,1) cycle (Algorithm 1) is enqueued the same way on the global
-// batched hierarchy, in correction form e = V(r), x += e.
+// batched hierarchy, in correction form e = V(r), x += e.  The hybrid cycle
+// (Algorithm 3) runs the V-cycle's passes above its transition level and a
+// second handle's AMG-DD passes (the level-L~ problems) below it, captured
+// into the same graph.
 
 #include <hip/hip_runtime.h>
 
@@ -161,6 +164,12 @@ struct amgdd_ctx {
   std::vector<std::vector<double>> hist;  // per problem
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   Prof *prof = nullptr;
+  int lbase = 0;  // level of this handle's fine level in the profiling sites
+  // hybrid AMG-DD: the level-L~ AMG-DD problems live in a handle of their own
+  amgdd_ctx *inner = nullptr;
+  int hybrid_lt = 0;                       // transition level L~ (0: not hybrid)
+  std::vector<int> inner_of;               // problem -> its level-L~ problem (-1: none)
+  std::vector<std::vector<int>> part_map;  // subdomain -> level-L~ subdomain (-1: empty)
 
   bool mixed() const { return prm.precision == AMGDD_MIXED; }
 
@@ -205,6 +214,7 @@ struct amgdd_ctx {
   }
 
   ~amgdd_ctx() {
+    delete inner;
     if (!host_only) {
       (void)hipSetDevice(device);
       drop_graphs();
@@ -225,7 +235,8 @@ inline int nblocks(long long n) { return (int)((n + dev::BLOCK - 1) / dev::BLOCK
 
 amgdd_status upload_all(amgdd_ctx *h) {
   Setup &S = h->S;
-  const bool fl = h->mixed();
+  // the outer handle of a hybrid pair runs only FP64 V-cycle passes
+  const bool fl = h->mixed() && h->hybrid_lt == 0;
   const size_t tsz = fl ? sizeof(float) : sizeof(double);
   amgdd_status st;
   const int nl = S.maxL() + 1;
@@ -240,7 +251,8 @@ amgdd_status upload_all(amgdd_ctx *h) {
   }
   h->f_total = foff[nl];
   if ((st = h->alloc(&h->f_arena, foff[nl] * tsz))) return st;
-  if ((st = h->alloc(&h->r_arena, roff[nl] * tsz))) return st;
+  if (!S.grids.empty())
+    if ((st = h->alloc(&h->r_arena, roff[nl] * tsz))) return st;
   {
     std::vector<int> src(foff[nl], -1);
     for (int l = 0; l < nl; ++l)
@@ -303,7 +315,7 @@ amgdd_status upload_all(amgdd_ctx *h) {
       if ((st = h->alloc((void **)&D.ve[k], (size_t)B.GN * sizeof(double)))) return st;
     if ((st = h->alloc((void **)&D.vq, (size_t)B.GN * sizeof(double)))) return st;
     if ((st = h->alloc((void **)&D.vf, (size_t)B.GN * sizeof(double)))) return st;
-    D.rt = (char *)h->r_arena + roff[l] * tsz;
+    D.rt = h->r_arena ? (char *)h->r_arena + roff[l] * tsz : nullptr;
     D.ngc = (int)B.gc_row0.size();
     if ((st = h->upload(&D.gc_row0, B.gc_row0.data(), B.gc_row0.size()))) return st;
     if ((st = h->upload(&D.gc_n, B.gc_n.data(), B.gc_n.size()))) return st;
@@ -385,7 +397,7 @@ amgdd_status upload_all(amgdd_ctx *h) {
   do {                                                                                              \
     if ((grid) > 0) {                                                                               \
       Prof *_p = (h)->prof;                                                                         \
-      int _k = _p ? _p->begin(name, level, (double)(bytes), stream, (int)(grid), (int)(block)) : -1; \
+      int _k = _p ? _p->begin(name, (level) + (h)->lbase, (double)(bytes), stream, (int)(grid), (int)(block)) : -1; \
       hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), shmem, stream, __VA_ARGS__);              \
       if (_p) _p->end(_k, stream);                                                                  \
     }                                                                                               \
@@ -496,9 +508,11 @@ void enqueue_fac(amgdd_ctx *h, hipStream_t s, int *cur) {
   }
 }
 
-// One AMG-DD iteration from a current residual r_0 (already in L[0].rt).
+// One AMG-DD cycle from a current residual r_0 (already in L[0].rt): the
+// restriction chain, composite right-hand sides, n_fac AlgFAC cycles and the
+// patch of u_0 into x (x += u_0; assign: x = u_0, a cycle started from zero).
 template <typename T>
-void enqueue_dd_iteration(amgdd_ctx *h, hipStream_t s) {
+void enqueue_dd_core(amgdd_ctx *h, hipStream_t s, double *x, bool assign) {
   const int maxL = (int)h->L.size() - 1;
   for (int l = 1; l <= maxL; ++l) {
     DLevel &B = h->L[l];
@@ -508,26 +522,50 @@ void enqueue_dd_iteration(amgdd_ctx *h, hipStream_t s) {
          (const T *)h->r_arena, (T *)h->f_arena);
   std::vector<int> cur(maxL + 1, 0);
   enqueue_fac<T>(h, s, cur.data());
-  PLAUNCH(h, "patch", 0, h->N0 * (20.0 + sizeof(T)), dev::k_patch<T>, nblocks(h->N0), dev::BLOCK, 0, s, h->N0, h->x, h->owner, (const T *)h->L[0].u[cur[0]]);
+  if (assign)
+    PLAUNCH(h, "patch", 0, h->N0 * (12.0 + sizeof(T)), (dev::k_patch<T, true>), nblocks(h->N0), dev::BLOCK, 0, s, h->N0, x, h->owner, (const T *)h->L[0].u[cur[0]]);
+  else
+    PLAUNCH(h, "patch", 0, h->N0 * (20.0 + sizeof(T)), dev::k_patch<T>, nblocks(h->N0), dev::BLOCK, 0, s, h->N0, x, h->owner, (const T *)h->L[0].u[cur[0]]);
+}
+
+// One AMG-DD iteration (Algorithm 2) from r_0 in L[0].rt, then the new
+// residual and its norms.
+template <typename T>
+void enqueue_dd_iteration(amgdd_ctx *h, hipStream_t s) {
+  enqueue_dd_core<T>(h, s, h->x, false);
   enqueue_residual<T>(h, s, false);
 }
 
-// One V(1,1) cycle in correction form from r_0 (L[0].vf) and e_0 = r_0 / d (L[0].ve[0]).
-void enqueue_v_iteration(amgdd_ctx *h, hipStream_t s) {
-  const int maxL = (int)h->L.size() - 1;
-  std::vector<int> cur(maxL + 1, 0);
-  for (int l = 0; l < maxL; ++l) {
+// V-cycle downsweep passes of levels 0..lv-1 in correction form: residual
+// q_l = f_l - A_l e_l, then f_{l+1} = R_l q_l with the first relaxation from
+// zero e_{l+1} = f_{l+1} / d (problems continuing below l+1) or the direct
+// solve (problems whose coarsest level is l+1).  hyb (lv = L~ of a hybrid
+// handle): on the last level, the restricted residual of the problems that
+// continue goes, in the level-L~ handle's precision, into that handle's fine
+// residual instead.
+template <typename T>
+void enqueue_v_down(amgdd_ctx *h, hipStream_t s, int *cur, int lv, bool hyb) {
+  for (int l = 0; l < lv; ++l) {
     DLevel &B = h->L[l];
     DLevel &Bc = h->L[l + 1];
     if (B.GNn == 0) continue;
     PLAUNCH(h, "vresid", l, B.nnzGA_n * 12.0 + B.GN * 8.0 + B.GNn * 16.0, dev::k_vresid<double>, nblocks((long long)B.GNn << B.glg), dev::BLOCK, 0, s, B.GA.as<double>(), B.GNn, B.vf, B.ve[cur[l]], B.vq);
-    PLAUNCH(h, "vdown", l + 1, Bc.nnzGR_n * 12.0 + B.GNn * 8.0 + Bc.GNn * 24.0, dev::k_vdown<double>, nblocks((long long)Bc.GNn << Bc.glg), dev::BLOCK, 0, s, Bc.GRd.as<double>(), Bc.GNn, B.vq, Bc.vf,
-           Bc.gdinv, Bc.ve[cur[l + 1]]);
+    if (hyb && l + 1 == lv)
+      PLAUNCH(h, "hrestrict", l + 1, Bc.nnzGR_n * 12.0 + B.GNn * 8.0 + Bc.GNn * (double)sizeof(T), (dev::k_spmv<double, T>), nblocks((long long)Bc.GNn << Bc.glg), dev::BLOCK, 0, s, Bc.GRd.as<double>(), Bc.GNn,
+              (const double *)B.vq, (T *)h->inner->L[0].rt);
+    else
+      PLAUNCH(h, "vdown", l + 1, Bc.nnzGR_n * 12.0 + B.GNn * 8.0 + Bc.GNn * 24.0, dev::k_vdown<double>, nblocks((long long)Bc.GNn << Bc.glg), dev::BLOCK, 0, s, Bc.GRd.as<double>(), Bc.GNn, B.vq, Bc.vf,
+             Bc.gdinv, Bc.ve[cur[l + 1]]);
     PLAUNCH(h, "vcoarse", l + 1, (Bc.nnzGR - Bc.nnzGR_n) * 12.0 + (Bc.GN - Bc.GNn) * 16.0, dev::k_coarse<double>, Bc.ngc, dev::BLOCK, 2 * Bc.gc_maxn * sizeof(double), s, Bc.GRd.as<double>(), 1, B.vq,
            Bc.vf, Bc.ve[cur[l + 1]], Bc.ve[cur[l + 1]], h->dense_A, h->dense_inv, Bc.gc_row0, Bc.gc_n, Bc.gc_dense, 1,
            1, (double *)nullptr);
   }
-  for (int l = maxL - 1; l >= 0; --l) {
+}
+
+// V-cycle upsweep passes of levels lv-1..0: e_l += P_l e_{l+1}, relaxation;
+// on level 0 the final relaxation is fused with x += e_0.
+void enqueue_v_up(amgdd_ctx *h, hipStream_t s, int *cur, int lv) {
+  for (int l = lv - 1; l >= 0; --l) {
     DLevel &B = h->L[l];
     DLevel &Bc = h->L[l + 1];
     if (B.GNn == 0) continue;
@@ -542,12 +580,41 @@ void enqueue_v_iteration(amgdd_ctx *h, hipStream_t s) {
              h->x);
     }
   }
+}
+
+// One V(1,1) cycle in correction form from r_0 (L[0].vf) and e_0 = r_0 / d (L[0].ve[0]).
+void enqueue_v_iteration(amgdd_ctx *h, hipStream_t s) {
+  const int maxL = (int)h->L.size() - 1;
+  std::vector<int> cur(maxL + 1, 0);
+  enqueue_v_down<double>(h, s, cur.data(), maxL, false);
+  enqueue_v_up(h, s, cur.data(), maxL);
   enqueue_residual<double>(h, s, true);
+}
+
+// One hybrid AMG-DD V(1,1) cycle (Algorithm 3) in correction form, same start
+// as the V-cycle: downsweep to L~; one AMG-DD cycle from zero on the level-L~
+// problems (their fine residual is the restricted one) whose iterate becomes
+// e_L~ of those problems (the others took the direct solve on L~); upsweep.
+template <typename T>
+void enqueue_hybrid_iteration(amgdd_ctx *h, hipStream_t s) {
+  const int lt = h->hybrid_lt;
+  std::vector<int> cur(lt + 1, 0);
+  enqueue_v_down<T>(h, s, cur.data(), lt, true);
+  enqueue_dd_core<T>(h->inner, s, h->L[lt].ve[cur[lt]], true);
+  enqueue_v_up(h, s, cur.data(), lt);
+  enqueue_residual<double>(h, s, true);
+}
+
+void enqueue_hybrid(amgdd_ctx *h, hipStream_t s) {
+  if (h->inner->mixed()) enqueue_hybrid_iteration<float>(h, s);
+  else enqueue_hybrid_iteration<double>(h, s);
 }
 
 amgdd_status capture(amgdd_ctx *h, bool dd, hipGraph_t *gr, hipGraphExec_t *ex) {
   HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-  if (dd) {
+  if (dd && h->inner) {
+    enqueue_hybrid(h, h->cap_stream);
+  } else if (dd) {
     if (h->mixed()) enqueue_dd_iteration<float>(h, h->cap_stream);
     else enqueue_dd_iteration<double>(h, h->cap_stream);
   } else {
@@ -622,11 +689,18 @@ amgdd_status run_solve(amgdd_ctx *h, SolveKind kind, const double *b_dev, double
   HIP_TRY(hipSetDevice(h->device));
   hipStream_t s = h->stream;
   const size_t nbytes = (size_t)h->N0 * sizeof(double);
+  // a hybrid handle none of whose problems reaches its transition level runs
+  // V-cycles (the level-L~ AMG-DD of a one-level problem is the direct solve)
+  if (kind == SOLVE_DD && h->hybrid_lt > 0 && !h->inner) kind = SOLVE_V;
+  const bool hybrid = kind == SOLVE_DD && h->inner;
   HIP_TRY(hipMemcpyAsync(h->b, b_dev, nbytes, hipMemcpyDeviceToDevice, s));
   HIP_TRY(hipMemcpyAsync(h->x, x_dev, nbytes, hipMemcpyDeviceToDevice, s));
-  if (kind == SOLVE_DD && h->sched_level == -2) {
-    amgdd_status st = autotune(h);
-    if (st) return st;
+  if (kind == SOLVE_DD) {
+    amgdd_ctx *t = hybrid ? h->inner : h;
+    if (t->sched_level == -2) {
+      amgdd_status st = autotune(t);
+      if (st) return st;
+    }
   }
   bool use_graph = h->prm.use_graph != 0;
   if (use_graph) {
@@ -640,13 +714,14 @@ amgdd_status run_solve(amgdd_ctx *h, SolveKind kind, const double *b_dev, double
     }
   }
   auto enqueue_res = [&](hipStream_t st) {
-    if (kind == SOLVE_V) enqueue_residual<double>(h, st, true);
+    if (kind == SOLVE_V || hybrid) enqueue_residual<double>(h, st, true);
     else if (h->mixed()) enqueue_residual<float>(h, st, false);
     else enqueue_residual<double>(h, st, false);
   };
   auto enqueue_iter = [&](hipStream_t st) -> hipError_t {
     if (use_graph) return hipGraphLaunch(kind == SOLVE_DD ? h->g_dd : h->g_v, st);
     if (kind == SOLVE_V) enqueue_v_iteration(h, st);
+    else if (hybrid) enqueue_hybrid(h, st);
     else if (h->mixed()) enqueue_dd_iteration<float>(h, st);
     else enqueue_dd_iteration<double>(h, st);
     return hipGetLastError();
@@ -732,39 +807,77 @@ amgdd_status make_handle(const std::vector<ProblemInput> &in, const amgdd_params
     delete h;
     return fail(ST_EINVAL, "bad n_fac or precision");
   }
+  if (p.hybrid_level < 0) {
+    delete h;
+    return fail(ST_EINVAL, "hybrid_level must be >= 0");
+  }
   std::string err;
-  int st = build_setup(in, p.theta, p.max_coarse, p.max_levels, h->S, err);
+  Setup inner_S;
+  int st = p.hybrid_level > 0 ? build_setup_hybrid(in, p.theta, p.max_coarse, p.max_levels, p.hybrid_level, h->S, inner_S,
+                                                   h->inner_of, h->part_map, err)
+                              : build_setup(in, p.theta, p.max_coarse, p.max_levels, h->S, err);
   if (st) {
     delete h;
     return fail(st, err);
   }
   h->symmetric = true;
   for (auto &P : h->S.probs) h->symmetric = h->symmetric && P.symmetric;
+  h->hybrid_lt = p.hybrid_level;
+  if (!inner_S.probs.empty()) {
+    // the level-L~ problems: an AMG-DD handle of their own whose fine vectors
+    // are the leading rows of the outer global level L~ (problems that
+    // continue below L~, in problem order)
+    const int lt = h->hybrid_lt;
+    long long n = 0;
+    for (auto &P : inner_S.probs) n += P.n;
+    if (lt > h->S.maxL() || n != h->S.lv[lt].GNn) {
+      delete h;
+      return fail(ST_EINVAL, "internal: hybrid level layout mismatch");
+    }
+    amgdd_ctx *in2 = new (std::nothrow) amgdd_ctx();
+    if (!in2) {
+      delete h;
+      return fail(ST_ENOMEM, "handle allocation");
+    }
+    h->inner = in2;
+    in2->prm = h->prm;
+    in2->prm.hybrid_level = 0;
+    in2->S = std::move(inner_S);
+    in2->symmetric = h->symmetric;
+    in2->sched_level = h->sched_level;
+    in2->sched_block = h->sched_block;
+    in2->lbase = lt;
+    if (in2->sched_level > in2->S.maxL()) in2->sched_level = -1;
+  }
   if (h->sched_level > h->S.maxL()) h->sched_level = -1;
   h->host_only = p.device < 0;
+  if (h->inner) h->inner->host_only = h->host_only;
   if (!h->host_only) {
     double tu = now_s();
     int ndev = 0;
     hipError_t e = hipGetDeviceCount(&ndev);
     if (e != hipSuccess || p.device >= ndev) {
+      h->host_only = true;
+      if (h->inner) h->inner->host_only = true;
       delete h;
       return fail(ST_EDEVICE, "no HIP device " + std::to_string(p.device));
     }
-    h->device = p.device;
-    (void)hipSetDevice(h->device);
-    h->stream = (hipStream_t)stream;
-    if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess) {
-      h->host_only = false;
-      delete h;
-      return fail(ST_EDEVICE, "stream/event creation failed");
-    }
-    h->host_only = false;
-    amgdd_status us = upload_all(h);
-    if (us) {
-      std::string msg = g_last_error;
-      delete h;
-      return fail(us, msg);
+    (void)hipSetDevice(p.device);
+    for (amgdd_ctx *c : {h, h->inner}) {
+      if (!c) continue;
+      c->device = p.device;
+      c->stream = (hipStream_t)stream;
+      if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+        delete h;
+        return fail(ST_EDEVICE, "stream/event creation failed");
+      }
+      amgdd_status us = upload_all(c);
+      if (us) {
+        std::string msg = g_last_error;
+        delete h;
+        return fail(us, msg);
+      }
     }
     h->S.times.upload = now_s() - tu;
   }
@@ -791,6 +904,7 @@ void amgdd_params_default(amgdd_params *prm) {
   prm->use_graph = 1;
   prm->tail_level = -2;
   prm->tail_block = 0;
+  prm->hybrid_level = 0;
 }
 
 amgdd_status amgdd_setup_composite(int n, const int *rowptr, const int *colind, const double *val, const int *part,
@@ -869,6 +983,45 @@ amgdd_status amgdd_get_stats(amgdd_handle h, amgdd_stats *st) {
   st->tail_level = h->sched_level;
   st->tail_block = h->sched_block;
   st->autotune_s = h->autotune_s;
+  if (h->hybrid_lt > 0) {
+    // composite figures of the level-L~ problems; levels above L~ (and whole
+    // hierarchies that end at or above L~) are cycled on the global grids
+    const int lt = h->hybrid_lt;
+    st->hybrid_level = lt;
+    long long upper = 0;
+    for (size_t q = 0; q < S.probs.size(); ++q) {
+      const Hierarchy &H = S.probs[q].H;
+      const int top = h->inner_of[q] >= 0 ? lt : H.L() + 1;
+      for (int l = 0; l < top; ++l) upper += H.A[l].nnz();
+    }
+    st->n_grids = 0;
+    st->composite_real_nnz = st->composite_rows = st->composite_real_rows = 0;
+    st->composite_stored_nnz = st->composite_nnz = st->omissions = 0;
+    st->setup_composite_s = 0.0;
+    st->tail_level = -1;
+    if (const amgdd_ctx *in = h->inner) {
+      const Setup &I = in->S;
+      st->n_grids = (int)I.grids.size();
+      st->composite_real_nnz = I.composite_real_nnz;
+      st->composite_rows = I.composite_rows;
+      st->composite_real_rows = I.composite_real_rows;
+      st->omissions = I.omissions;
+      long long e2 = 0, u2 = 0;
+      for (auto &B : I.lv) {
+        e2 += B.A.entries() + B.P.entries() + B.R.entries();
+        u2 += B.nnzA + B.nnzP + B.nnzR;
+      }
+      st->composite_stored_nnz = e2;
+      st->composite_nnz = u2;
+      st->setup_composite_s = I.times.composite;
+      st->setup_pack_s += I.times.pack;
+      st->device_bytes += in->dev_bytes;
+      st->tail_level = in->sched_level;
+      st->tail_block = in->sched_block;
+      st->autotune_s = in->autotune_s;
+    }
+    st->composite_overhead = S.global_nnz ? (double)(upper + st->composite_real_nnz) / (double)S.global_nnz : 0.0;
+  }
   return AMGDD_OK;
 }
 
@@ -912,7 +1065,18 @@ amgdd_status amgdd_get_composite(amgdd_handle h, int prob, int p, int level, int
   if (!h || prob < 0 || prob >= (int)h->S.probs.size()) return fail(ST_EINVAL, "bad problem");
   const ProblemHost &P = h->S.probs[prob];
   if (p < 0 || p >= P.nparts || level < 0 || level > P.H.L()) return fail(ST_EINVAL, "bad subdomain or level");
-  const CompLevel &lv = h->S.grids[P.grids[p]].lv[level];
+  const Setup *S = &h->S;
+  int q = prob;
+  if (h->hybrid_lt > 0) {
+    q = h->inner_of[prob];
+    if (q < 0 || !h->inner) return fail(ST_EINVAL, "problem has no level-L~ AMG-DD problem (hierarchy ends at or above L~)");
+    if (level < h->hybrid_lt) return fail(ST_EINVAL, "hybrid handle: composite grids exist on levels >= hybrid_level only");
+    p = h->part_map[prob][p];
+    if (p < 0) return fail(ST_EINVAL, "subdomain has no points on the hybrid level");
+    level -= h->hybrid_lt;
+    S = &h->inner->S;
+  }
+  const CompLevel &lv = S->grids[S->probs[q].grids[p]].lv[level];
   if (n_real) *n_real = lv.nreal;
   if (n_bar) *n_bar = lv.nbar();
   if (gids) std::memcpy(gids, lv.gid.data(), lv.gid.size() * sizeof(int));
@@ -937,25 +1101,36 @@ amgdd_status amgdd_profile(amgdd_handle h, int kind, int reps, amgdd_kernel_time
   Prof prof;
   struct Reset {
     amgdd_ctx *h;
-    ~Reset() { h->prof = nullptr; }
+    ~Reset() {
+      h->prof = nullptr;
+      if (h->inner) h->inner->prof = nullptr;
+    }
   } reset{h};
   hipStream_t s = h->stream;
-  if (kind == 0 && h->sched_level == -2) {
-    amgdd_status ts = autotune(h);
-    if (ts) return ts;
+  if (kind == 0 && h->hybrid_lt > 0 && !h->inner) kind = 1;
+  const bool hybrid = kind == 0 && h->inner;
+  if (kind == 0) {
+    amgdd_ctx *t = hybrid ? h->inner : h;
+    if (t->sched_level == -2) {
+      amgdd_status ts = autotune(t);
+      if (ts) return ts;
+    }
   }
-  if (kind == 1) enqueue_residual<double>(h, s, true);
+  if (kind == 1 || hybrid) enqueue_residual<double>(h, s, true);
   else if (h->mixed()) enqueue_residual<float>(h, s, false);
   else enqueue_residual<double>(h, s, false);
   h->prof = &prof;
+  if (h->inner) h->inner->prof = &prof;
   for (int r = 0; r < reps; ++r) {
     if (kind == 1) enqueue_v_iteration(h, s);
+    else if (hybrid) enqueue_hybrid(h, s);
     else if (h->mixed()) enqueue_dd_iteration<float>(h, s);
     else enqueue_dd_iteration<double>(h, s);
   }
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(s));
   h->prof = nullptr;
+  if (h->inner) h->inner->prof = nullptr;
   struct Agg {
     std::string name;
     int level, launches;
@@ -994,6 +1169,7 @@ amgdd_status amgdd_profile(amgdd_handle h, int kind, int reps, amgdd_kernel_time
 amgdd_status amgdd_set_stream(amgdd_handle h, void *hip_stream) {
   if (!h) return fail(ST_EINVAL, "null handle");
   h->stream = (hipStream_t)hip_stream;
+  if (h->inner) h->inner->stream = h->stream;
   return AMGDD_OK;
 }
 

@@ -149,13 +149,14 @@ __global__ __launch_bounds__(BLOCK) void k_norm_final(const double *__restrict__
   if (threadIdx.x == 0) out[q] = s;
 }
 
-// y = M x over rows [0, n) (restriction chain r_{l+1} = R_l r_l).
-template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_spmv(SellD<T> M, int n, const T *__restrict__ x, T *__restrict__ y) {
+// y = M x over rows [0, n) (restriction chain r_{l+1} = R_l r_l), computed in
+// T and stored as TO.
+template <typename T, typename TO = T>
+__global__ __launch_bounds__(BLOCK) void k_spmv(SellD<T> M, int n, const T *__restrict__ x, TO *__restrict__ y) {
   const int t = thread_id(), i = t >> M.lg, sub = t & ((1 << M.lg) - 1);
   if (i < n) {
     const T v = sell_dot<T, T>(M, i, sub, x);
-    if (sub == 0) y[i] = v;
+    if (sub == 0) y[i] = (TO)v;
   }
 }
 
@@ -171,12 +172,16 @@ __global__ __launch_bounds__(BLOCK) void k_gather(int n, const int *__restrict__
   }
 }
 
-// Correction patched on each owned subdomain: x[g] += u0[owner[g]].
-template <typename T>
+// Correction patched on each owned subdomain: x[g] += u0[owner[g]]
+// (ASSIGN: x[g] = u0[owner[g]], the iterate of a cycle started from zero).
+template <typename T, bool ASSIGN = false>
 __global__ __launch_bounds__(BLOCK) void k_patch(int n, double *__restrict__ x, const int *__restrict__ owner,
                                                   const T *__restrict__ u0) {
   const int i = thread_id();
-  if (i < n) x[i] += (double)u0[owner[i]];
+  if (i < n) {
+    if (ASSIGN) x[i] = (double)u0[owner[i]];
+    else x[i] += (double)u0[owner[i]];
+  }
 }
 
 // ---------------------------------------------------------------- AlgFAC

@@ -729,381 +729,390 @@ void build_local_ops(const ProblemHost &P, CompGrid &cg, Scratch &sc) {
 
 }  // namespace
 
-int build_setup(const std::vector<ProblemInput> &in, double theta, int max_coarse, int max_levels, Setup &S,
-                std::string &err) {
-  try {
-    S.theta = theta;
-    S.max_coarse = max_coarse;
-    S.max_levels = max_levels;
-    const int nprob = (int)in.size();
-    if (nprob <= 0) { err = "no problems"; return ST_EINVAL; }
-    if (!(theta > 0.0 && theta <= 1.0) || max_coarse < 1 || max_levels < 2) { err = "bad AMG parameters"; return ST_EINVAL; }
-    for (int q = 0; q < nprob; ++q) {
-      int st = validate(in[q], max_coarse, err);
-      if (st) { err = "problem " + std::to_string(q) + ": " + err; return st; }
-    }
-    // ---- hierarchies
-    double t0 = now_s();
-    S.probs.resize(nprob);
-    std::vector<int> status(nprob, ST_OK);
-    std::vector<std::string> errs(nprob);
-    for (int q = 0; q < nprob; ++q) {
-      ProblemHost &P = S.probs[q];
-      P.n = in[q].n;
-      P.nparts = in[q].nparts;
-      P.eta = in[q].eta;
-      P.A0.nrows = P.A0.ncols = P.n;
-      P.A0.ptr.assign(in[q].rowptr, in[q].rowptr + P.n + 1);
-      long long nnz = P.A0.ptr[P.n];
-      P.A0.col.assign(in[q].colind, in[q].colind + nnz);
-      P.A0.val.assign(in[q].val, in[q].val + nnz);
-      P.part.assign(in[q].part, in[q].part + P.n);
-      // exact numerical symmetry (the adjoint then reuses the forward operators)
-      Csr T = transpose(P.A0);
-      P.symmetric = (T.col == P.A0.col && T.val == P.A0.val);
-    }
-    // problems are independent: build the hierarchies in parallel when batched
-    parallel_items(nprob, [&](int q, int) {
-      status[q] = build_hierarchy(S.probs[q], theta, max_coarse, max_levels, errs[q]);
-    });
-    for (int q = 0; q < nprob; ++q)
-      if (status[q]) { err = "problem " + std::to_string(q) + ": " + errs[q]; return status[q]; }
-    S.times.hierarchy = now_s() - t0;
+namespace {
 
-    // ---- composite grids
-    t0 = now_s();
-    int maxL = 0;
-    for (auto &P : S.probs) maxL = std::max(maxL, P.H.L());
-    for (int q = 0; q < nprob; ++q)
-      for (int p = 0; p < S.probs[q].nparts; ++p) {
-        S.probs[q].grids.push_back((int)S.grids.size());
-        CompGrid cg;
-        cg.prob = q;
-        cg.p = p;
-        S.grids.push_back(std::move(cg));
-      }
-    std::vector<std::vector<Csr>> graphs(nprob);
-    std::vector<std::vector<std::vector<int>>> cmaps(nprob);
-    parallel_items(nprob, [&](int q, int) {
-      const Hierarchy &H = S.probs[q].H;
-      for (int l = 0; l <= H.L(); ++l) graphs[q].push_back(adjacency(H.A[l]));
-      for (int l = 0; l < H.L(); ++l) {
-        std::vector<int> cm(H.A[l].nrows, -1);
-        int c = 0;
-        for (int i = 0; i < H.A[l].nrows; ++i)
-          if (H.cf[l][i] == 1) cm[i] = c++;
-        cmaps[q].push_back(std::move(cm));
-      }
-    });
-    int nt = n_threads();
-    std::vector<Scratch> scratch(nt);
-    parallel_items((int)S.grids.size(), [&](int g, int t) {
-      CompGrid &cg = S.grids[g];
-      const ProblemHost &P = S.probs[cg.prob];
-      build_sets(P, graphs[cg.prob], cmaps[cg.prob], cg.p, cg, scratch[t]);
-      build_local_ops(P, cg, scratch[t]);
-    });
-    graphs.clear();
-    cmaps.clear();
-    S.omissions = 0;
-    S.composite_real_nnz = S.global_nnz = S.composite_rows = S.composite_real_rows = 0;
-    for (auto &P : S.probs)
-      for (auto &A : P.H.A) S.global_nnz += A.nnz();
-    for (auto &cg : S.grids) {
-      const Hierarchy &H = S.probs[cg.prob].H;
-      for (int l = 0; l <= H.L(); ++l) {
-        const CompLevel &lv = cg.lv[l];
-        S.omissions += lv.omissions;
-        S.composite_rows += lv.nbar();
-        S.composite_real_rows += lv.nreal;
-        for (int i = 0; i < lv.nreal; ++i) S.composite_real_nnz += H.A[l].ptr[lv.gid[i] + 1] - H.A[l].ptr[lv.gid[i]];
-      }
-    }
-    S.times.composite = now_s() - t0;
+// Copies and validates every input problem and builds its AMG hierarchy.
+int setup_hierarchies(const std::vector<ProblemInput> &in, double theta, int max_coarse, int max_levels, Setup &S,
+                      std::string &err) {
+  S.theta = theta;
+  S.max_coarse = max_coarse;
+  S.max_levels = max_levels;
+  const int nprob = (int)in.size();
+  if (nprob <= 0) { err = "no problems"; return ST_EINVAL; }
+  if (!(theta > 0.0 && theta <= 1.0) || max_coarse < 1 || max_levels < 2) { err = "bad AMG parameters"; return ST_EINVAL; }
+  for (int q = 0; q < nprob; ++q) {
+    int st = validate(in[q], max_coarse, err);
+    if (st) { err = "problem " + std::to_string(q) + ": " + err; return st; }
+  }
+  double t0 = now_s();
+  S.probs.resize(nprob);
+  std::vector<int> status(nprob, ST_OK);
+  std::vector<std::string> errs(nprob);
+  for (int q = 0; q < nprob; ++q) {
+    ProblemHost &P = S.probs[q];
+    P.n = in[q].n;
+    P.nparts = in[q].nparts;
+    P.eta = in[q].eta;
+    P.A0.nrows = P.A0.ncols = P.n;
+    P.A0.ptr.assign(in[q].rowptr, in[q].rowptr + P.n + 1);
+    long long nnz = P.A0.ptr[P.n];
+    P.A0.col.assign(in[q].colind, in[q].colind + nnz);
+    P.A0.val.assign(in[q].val, in[q].val + nnz);
+    P.part.assign(in[q].part, in[q].part + P.n);
+    // exact numerical symmetry (the adjoint then reuses the forward operators)
+    Csr T = transpose(P.A0);
+    P.symmetric = (T.col == P.A0.col && T.val == P.A0.val);
+  }
+  // problems are independent: build the hierarchies in parallel when batched
+  parallel_items(nprob, [&](int q, int) {
+    status[q] = build_hierarchy(S.probs[q], theta, max_coarse, max_levels, errs[q]);
+  });
+  for (int q = 0; q < nprob; ++q)
+    if (status[q]) { err = "problem " + std::to_string(q) + ": " + errs[q]; return status[q]; }
+  S.times.hierarchy = now_s() - t0;
+  return ST_OK;
+}
 
-    // ---- batched layouts
-    t0 = now_s();
-    S.dense_off.assign(nprob, 0);
-    int doff = 0;
+// Composite grids of every subdomain (when `composite`) and the batched
+// layouts of every level, from the problems' hierarchies.  Without composite
+// grids only the global layouts (V-cycle) are filled.
+int setup_layouts(Setup &S, bool composite, std::string &err) {
+  const int nprob = (int)S.probs.size();
+  // ---- composite grids
+  double t0 = now_s();
+  int maxL = 0;
+  for (auto &P : S.probs) maxL = std::max(maxL, P.H.L());
+  for (int q = 0; q < nprob && composite; ++q)
+    for (int p = 0; p < S.probs[q].nparts; ++p) {
+      S.probs[q].grids.push_back((int)S.grids.size());
+      CompGrid cg;
+      cg.prob = q;
+      cg.p = p;
+      S.grids.push_back(std::move(cg));
+    }
+  std::vector<std::vector<Csr>> graphs(nprob);
+  std::vector<std::vector<std::vector<int>>> cmaps(nprob);
+  parallel_items(nprob, [&](int q, int) {
+    const Hierarchy &H = S.probs[q].H;
+    for (int l = 0; l <= H.L(); ++l) graphs[q].push_back(adjacency(H.A[l]));
+    for (int l = 0; l < H.L(); ++l) {
+      std::vector<int> cm(H.A[l].nrows, -1);
+      int c = 0;
+      for (int i = 0; i < H.A[l].nrows; ++i)
+        if (H.cf[l][i] == 1) cm[i] = c++;
+      cmaps[q].push_back(std::move(cm));
+    }
+  });
+  int nt = n_threads();
+  std::vector<Scratch> scratch(nt);
+  parallel_items((int)S.grids.size(), [&](int g, int t) {
+    CompGrid &cg = S.grids[g];
+    const ProblemHost &P = S.probs[cg.prob];
+    build_sets(P, graphs[cg.prob], cmaps[cg.prob], cg.p, cg, scratch[t]);
+    build_local_ops(P, cg, scratch[t]);
+  });
+  graphs.clear();
+  cmaps.clear();
+  S.omissions = 0;
+  S.composite_real_nnz = S.global_nnz = S.composite_rows = S.composite_real_rows = 0;
+  for (auto &P : S.probs)
+    for (auto &A : P.H.A) S.global_nnz += A.nnz();
+  for (auto &cg : S.grids) {
+    const Hierarchy &H = S.probs[cg.prob].H;
+    for (int l = 0; l <= H.L(); ++l) {
+      const CompLevel &lv = cg.lv[l];
+      S.omissions += lv.omissions;
+      S.composite_rows += lv.nbar();
+      S.composite_real_rows += lv.nreal;
+      for (int i = 0; i < lv.nreal; ++i) S.composite_real_nnz += H.A[l].ptr[lv.gid[i] + 1] - H.A[l].ptr[lv.gid[i]];
+    }
+  }
+  S.times.composite = now_s() - t0;
+
+  // ---- batched layouts
+  t0 = now_s();
+  S.dense_off.assign(nprob, 0);
+  int doff = 0;
+  for (int q = 0; q < nprob; ++q) {
+    S.dense_off[q] = doff;
+    doff += (int)S.probs[q].H.Ac.size();
+    S.dense_A.insert(S.dense_A.end(), S.probs[q].H.Ac.begin(), S.probs[q].H.Ac.end());
+    S.dense_inv.insert(S.dense_inv.end(), S.probs[q].H.Ac_inv.begin(), S.probs[q].H.Ac_inv.end());
+  }
+  const int ng = (int)S.grids.size();
+  S.lv.assign(maxL + 1, BatchLevel());
+  // composite offsets per level: off[g] for normal real, ghost, or coarse rows
+  std::vector<std::vector<int>> roff(maxL + 1, std::vector<int>(ng, -1)), goff = roff, coff = roff;
+  std::vector<std::vector<int>> gro(maxL + 1, std::vector<int>(nprob, -1)), gco = gro;
+  for (int l = 0; l <= maxL; ++l) {
+    BatchLevel &B = S.lv[l];
+    int r = 0, gh = 0, c = 0;
+    for (int g = 0; g < ng; ++g) {
+      int L = S.probs[S.grids[g].prob].H.L();
+      const CompLevel *lv = l <= L ? &S.grids[g].lv[l] : nullptr;
+      if (!lv) continue;
+      if (L > l) { roff[l][g] = r; r += lv->nreal; goff[l][g] = gh; gh += lv->nbar() - lv->nreal; }
+      else { coff[l][g] = c; c += lv->nbar(); }
+    }
+    B.NRn = r;
+    B.NBn = r + gh;
+    B.NB = B.NBn + c;
+    int gn = 0, gc = 0;
     for (int q = 0; q < nprob; ++q) {
-      S.dense_off[q] = doff;
-      doff += (int)S.probs[q].H.Ac.size();
-      S.dense_A.insert(S.dense_A.end(), S.probs[q].H.Ac.begin(), S.probs[q].H.Ac.end());
-      S.dense_inv.insert(S.dense_inv.end(), S.probs[q].H.Ac_inv.begin(), S.probs[q].H.Ac_inv.end());
+      int L = S.probs[q].H.L();
+      if (l > L) continue;
+      if (L > l) { gro[l][q] = gn; gn += S.probs[q].H.A[l].nrows; }
+      else { gco[l][q] = gc; gc += S.probs[q].H.A[l].nrows; }
     }
-    const int ng = (int)S.grids.size();
-    S.lv.assign(maxL + 1, BatchLevel());
-    // composite offsets per level: off[g] for normal real, ghost, or coarse rows
-    std::vector<std::vector<int>> roff(maxL + 1, std::vector<int>(ng, -1)), goff = roff, coff = roff;
-    std::vector<std::vector<int>> gro(maxL + 1, std::vector<int>(nprob, -1)), gco = gro;
-    for (int l = 0; l <= maxL; ++l) {
-      BatchLevel &B = S.lv[l];
-      int r = 0, gh = 0, c = 0;
-      for (int g = 0; g < ng; ++g) {
-        int L = S.probs[S.grids[g].prob].H.L();
-        const CompLevel *lv = l <= L ? &S.grids[g].lv[l] : nullptr;
-        if (!lv) continue;
-        if (L > l) { roff[l][g] = r; r += lv->nreal; goff[l][g] = gh; gh += lv->nbar() - lv->nreal; }
-        else { coff[l][g] = c; c += lv->nbar(); }
-      }
-      B.NRn = r;
-      B.NBn = r + gh;
-      B.NB = B.NBn + c;
-      int gn = 0, gc = 0;
-      for (int q = 0; q < nprob; ++q) {
-        int L = S.probs[q].H.L();
-        if (l > L) continue;
-        if (L > l) { gro[l][q] = gn; gn += S.probs[q].H.A[l].nrows; }
-        else { gco[l][q] = gc; gc += S.probs[q].H.A[l].nrows; }
-      }
-      B.GNn = gn;
-      B.GN = gn + gc;
-      if ((long long)B.NB >= std::numeric_limits<int>::max() / 2) throw std::length_error("level too large");
+    B.GNn = gn;
+    B.GN = gn + gc;
+    if ((long long)B.NB >= std::numeric_limits<int>::max() / 2) throw std::length_error("level too large");
+  }
+  auto bidx = [&](int g, int l, int i) -> int {
+    const CompLevel &lv = S.grids[g].lv[l];
+    if (roff[l][g] >= 0) return i < lv.nreal ? roff[l][g] + i : S.lv[l].NRn + goff[l][g] + (i - lv.nreal);
+    return S.lv[l].NBn + coff[l][g] + i;
+  };
+  auto gbidx = [&](int q, int l, int i) -> int {
+    if (gro[l][q] >= 0) return gro[l][q] + i;
+    return S.lv[l].GNn + gco[l][q] + i;
+  };
+  vlog("pack: offsets", t0);
+  // lanes per row of every level, from the mean row length of A_l (of the
+  // restriction rows on a level that only holds coarsest grids); the fine
+  // global level keeps one lane per row
+  for (int l = 0; l <= maxL; ++l) {
+    long long nzA = 0, nzR = 0;
+    for (int g = 0; g < ng; ++g) {
+      if (roff[l][g] >= 0) nzA += S.grids[g].lv[l].A.nnz();
+      if (l > 0 && (roff[l][g] >= 0 || coff[l][g] >= 0)) nzR += S.grids[g].lv[l - 1].P.nnz();
     }
-    auto bidx = [&](int g, int l, int i) -> int {
-      const CompLevel &lv = S.grids[g].lv[l];
-      if (roff[l][g] >= 0) return i < lv.nreal ? roff[l][g] + i : S.lv[l].NRn + goff[l][g] + (i - lv.nreal);
-      return S.lv[l].NBn + coff[l][g] + i;
-    };
-    auto gbidx = [&](int q, int l, int i) -> int {
-      if (gro[l][q] >= 0) return gro[l][q] + i;
-      return S.lv[l].GNn + gco[l][q] + i;
-    };
-    vlog("pack: offsets", t0);
-    // lanes per row of every level, from the mean row length of A_l (of the
-    // restriction rows on a level that only holds coarsest grids); the fine
-    // global level keeps one lane per row
-    for (int l = 0; l <= maxL; ++l) {
-      long long nzA = 0, nzR = 0;
-      for (int g = 0; g < ng; ++g) {
-        if (roff[l][g] >= 0) nzA += S.grids[g].lv[l].A.nnz();
-        if (l > 0 && (roff[l][g] >= 0 || coff[l][g] >= 0)) nzR += S.grids[g].lv[l - 1].P.nnz();
+    BatchLevel &B = S.lv[l];
+    B.lg = B.NBn > 0 ? lanes_log2((double)nzA / B.NBn) : (B.NB > 0 ? lanes_log2((double)nzR / B.NB) : 0);
+    long long nzG = 0;
+    for (int q = 0; q < nprob; ++q)
+      if (l <= S.probs[q].H.L()) nzG += S.probs[q].H.A[l].nnz();
+    B.glg = (l == 0 || B.GN == 0) ? 0 : lanes_log2((double)nzG / B.GN);
+  }
+  for (int l = 0; l <= maxL; ++l) {
+    BatchLevel &B = S.lv[l];
+    double tp = now_s();
+    std::vector<int> normal;
+    for (int g = 0; g < ng; ++g) {
+      if (roff[l][g] >= 0) normal.push_back(g);
+      else if (coff[l][g] >= 0) {
+        const CompLevel &lv = S.grids[g].lv[l];
+        B.cg_row0.push_back(B.NBn + coff[l][g]);
+        B.cg_n.push_back(lv.nbar());
+        B.cg_dense.push_back(S.dense_off[S.grids[g].prob]);
       }
-      BatchLevel &B = S.lv[l];
-      B.lg = B.NBn > 0 ? lanes_log2((double)nzA / B.NBn) : (B.NB > 0 ? lanes_log2((double)nzR / B.NB) : 0);
-      long long nzG = 0;
-      for (int q = 0; q < nprob; ++q)
-        if (l <= S.probs[q].H.L()) nzG += S.probs[q].H.A[l].nnz();
-      B.glg = (l == 0 || B.GN == 0) ? 0 : lanes_log2((double)nzG / B.GN);
     }
-    for (int l = 0; l <= maxL; ++l) {
-      BatchLevel &B = S.lv[l];
-      double tp = now_s();
-      std::vector<int> normal;
-      for (int g = 0; g < ng; ++g) {
-        if (roff[l][g] >= 0) normal.push_back(g);
-        else if (coff[l][g] >= 0) {
-          const CompLevel &lv = S.grids[g].lv[l];
-          B.cg_row0.push_back(B.NBn + coff[l][g]);
-          B.cg_n.push_back(lv.nbar());
-          B.cg_dense.push_back(S.dense_off[S.grids[g].prob]);
-        }
-      }
-      const int nn = (int)normal.size();
-      // ---- composite A and P rows of normal grids, dinv, gather sources
-      SellBuilder bA, bP;
-      bA.init(B.NBn, B.lg);
-      bP.init(B.NBn, B.lg);
-      B.dinv.assign(B.NRn, 0.0);
-      B.gsrc.assign(B.NB, -1);
-      parallel_items(ng, [&](int g, int) {
-        const int q = S.grids[g].prob;
-        if (roff[l][g] >= 0) {
-          const CompLevel &lv = S.grids[g].lv[l];
-          for (int i = 0; i < lv.nbar(); ++i) {
-            int row = bidx(g, l, i);
-            bA.len[row] = lv.A.ptr[i + 1] - lv.A.ptr[i];
-            bP.len[row] = lv.P.ptr[i + 1] - lv.P.ptr[i];
-            if (i < lv.nreal) { B.dinv[row] = lv.dinv[i]; B.gsrc[row] = gbidx(q, l, lv.gid[i]); }
-          }
-        } else if (coff[l][g] >= 0) {
-          const CompLevel &lv = S.grids[g].lv[l];
-          for (int i = 0; i < lv.nbar(); ++i) B.gsrc[B.NBn + coff[l][g] + i] = gbidx(q, l, lv.gid[i]);
-        }
-      });
-      bA.shape();
-      bP.shape();
-      parallel_items(nn, [&](int k, int) {
-        int g = normal[k];
+    const int nn = (int)normal.size();
+    // ---- composite A and P rows of normal grids, dinv, gather sources
+    SellBuilder bA, bP;
+    bA.init(B.NBn, B.lg);
+    bP.init(B.NBn, B.lg);
+    B.dinv.assign(B.NRn, 0.0);
+    B.gsrc.assign(B.NB, -1);
+    parallel_items(ng, [&](int g, int) {
+      const int q = S.grids[g].prob;
+      if (roff[l][g] >= 0) {
         const CompLevel &lv = S.grids[g].lv[l];
         for (int i = 0; i < lv.nbar(); ++i) {
           int row = bidx(g, l, i);
-          int kk = 0;
-          for (int jj = lv.A.ptr[i]; jj < lv.A.ptr[i + 1]; ++jj) bA.put(row, kk++, bidx(g, l, lv.A.col[jj]), lv.A.val[jj]);
-          bA.pad(row, bidx(g, l, 0));
-          kk = 0;
-          for (int jj = lv.P.ptr[i]; jj < lv.P.ptr[i + 1]; ++jj) bP.put(row, kk++, bidx(g, l + 1, lv.P.col[jj]), lv.P.val[jj]);
-          bP.pad(row, bidx(g, l + 1, 0));
+          bA.len[row] = lv.A.ptr[i + 1] - lv.A.ptr[i];
+          bP.len[row] = lv.P.ptr[i + 1] - lv.P.ptr[i];
+          if (i < lv.nreal) { B.dinv[row] = lv.dinv[i]; B.gsrc[row] = gbidx(q, l, lv.gid[i]); }
         }
-      });
-      B.nnzA_r = bA.nnz_rows(0, B.NRn);
-      B.nnzA = bA.nnz_rows(0, B.NBn);
-      B.nnzP = bP.nnz_rows(0, B.NBn);
-      B.A = bA.take();
-      B.P = bP.take();
-      vlog("pack: composite A, P", tp);
-      // ---- R_l = P_l^T (block-diagonal: one transpose per grid), rows of level l+1
-      if (l < maxL) {
-        BatchLevel &Bn = S.lv[l + 1];
-        SellBuilder bR;
-        bR.init(Bn.NB, Bn.lg);
-        std::vector<Csr> Rl(nn);
-        parallel_items(nn, [&](int k, int) {
-          int g = normal[k];
-          const CompLevel &lv = S.grids[g].lv[l];
-          Rl[k] = transpose(lv.P);
-          Rl[k].nrows = S.grids[g].lv[l + 1].nbar();
-          Rl[k].ptr.resize(Rl[k].nrows + 1, Rl[k].ptr.back());
-          for (int J = 0; J < Rl[k].nrows; ++J) bR.len[bidx(g, l + 1, J)] = Rl[k].ptr[J + 1] - Rl[k].ptr[J];
-        });
-        bR.shape();
-        parallel_items(nn, [&](int k, int) {
-          int g = normal[k];
-          const Csr &R = Rl[k];
-          for (int J = 0; J < R.nrows; ++J) {
-            int row = bidx(g, l + 1, J);
-            int kk = 0;
-            for (int jj = R.ptr[J]; jj < R.ptr[J + 1]; ++jj) bR.put(row, kk++, bidx(g, l, R.col[jj]), R.val[jj]);
-            bR.pad(row, bidx(g, l, 0));
-          }
-        });
-        Bn.nnzR_n = bR.nnz_rows(0, Bn.NBn);
-        Bn.nnzR = bR.nnz_rows(0, Bn.NB);
-        Bn.R = bR.take();
+      } else if (coff[l][g] >= 0) {
+        const CompLevel &lv = S.grids[g].lv[l];
+        for (int i = 0; i < lv.nbar(); ++i) B.gsrc[B.NBn + coff[l][g] + i] = gbidx(q, l, lv.gid[i]);
       }
-      // local operators of this level are no longer needed
+    });
+    bA.shape();
+    bP.shape();
+    parallel_items(nn, [&](int k, int) {
+      int g = normal[k];
+      const CompLevel &lv = S.grids[g].lv[l];
+      for (int i = 0; i < lv.nbar(); ++i) {
+        int row = bidx(g, l, i);
+        int kk = 0;
+        for (int jj = lv.A.ptr[i]; jj < lv.A.ptr[i + 1]; ++jj) bA.put(row, kk++, bidx(g, l, lv.A.col[jj]), lv.A.val[jj]);
+        bA.pad(row, bidx(g, l, 0));
+        kk = 0;
+        for (int jj = lv.P.ptr[i]; jj < lv.P.ptr[i + 1]; ++jj) bP.put(row, kk++, bidx(g, l + 1, lv.P.col[jj]), lv.P.val[jj]);
+        bP.pad(row, bidx(g, l + 1, 0));
+      }
+    });
+    B.nnzA_r = bA.nnz_rows(0, B.NRn);
+    B.nnzA = bA.nnz_rows(0, B.NBn);
+    B.nnzP = bP.nnz_rows(0, B.NBn);
+    B.A = bA.take();
+    B.P = bP.take();
+    vlog("pack: composite A, P", tp);
+    // ---- R_l = P_l^T (block-diagonal: one transpose per grid), rows of level l+1
+    if (l < maxL) {
+      BatchLevel &Bn = S.lv[l + 1];
+      SellBuilder bR;
+      bR.init(Bn.NB, Bn.lg);
+      std::vector<Csr> Rl(nn);
       parallel_items(nn, [&](int k, int) {
-        CompLevel &lv = S.grids[normal[k]].lv[l];
-        free_csr(lv.A);
-        free_csr(lv.P);
+        int g = normal[k];
+        const CompLevel &lv = S.grids[g].lv[l];
+        Rl[k] = transpose(lv.P);
+        Rl[k].nrows = S.grids[g].lv[l + 1].nbar();
+        Rl[k].ptr.resize(Rl[k].nrows + 1, Rl[k].ptr.back());
+        for (int J = 0; J < Rl[k].nrows; ++J) bR.len[bidx(g, l + 1, J)] = Rl[k].ptr[J + 1] - Rl[k].ptr[J];
       });
-      vlog("pack: composite R", tp);
-      tp = now_s();
-      // ---- global level l over problems
-      SellBuilder bGA, bGP;
-      bGA.init(B.GN, B.glg);
-      bGP.init(B.GNn, B.glg);
-      B.gdinv.assign(B.GNn, 0.0);
-      B.prob_row0.assign(nprob, -1);
-      for (int q = 0; q < nprob; ++q) {
-        const Hierarchy &H = S.probs[q].H;
-        if (l > H.L()) continue;
-        B.prob_row0[q] = gbidx(q, l, 0);
-        if (l == H.L()) {
-          B.gc_row0.push_back(gbidx(q, l, 0));
-          B.gc_n.push_back(H.A[l].nrows);
-          B.gc_dense.push_back(S.dense_off[q]);
+      bR.shape();
+      parallel_items(nn, [&](int k, int) {
+        int g = normal[k];
+        const Csr &R = Rl[k];
+        for (int J = 0; J < R.nrows; ++J) {
+          int row = bidx(g, l + 1, J);
+          int kk = 0;
+          for (int jj = R.ptr[J]; jj < R.ptr[J + 1]; ++jj) bR.put(row, kk++, bidx(g, l, R.col[jj]), R.val[jj]);
+          bR.pad(row, bidx(g, l, 0));
         }
-      }
-      parallel_items(nprob, [&](int q, int) {
-        const Hierarchy &H = S.probs[q].H;
-        if (l > H.L()) return;
-        int base = gbidx(q, l, 0);
-        const Csr &Al = H.A[l];
-        for (int i = 0; i < Al.nrows; ++i) bGA.len[base + i] = Al.ptr[i + 1] - Al.ptr[i];
-        if (l < H.L())
-          for (int i = 0; i < Al.nrows; ++i) {
-            bGP.len[base + i] = H.P[l].ptr[i + 1] - H.P[l].ptr[i];
-            B.gdinv[base + i] = 1.0 / H.l1[l][i];
-          }
       });
-      bGA.shape();
-      bGP.shape();
-      parallel_items(nprob, [&](int q, int) {
-        const Hierarchy &H = S.probs[q].H;
-        if (l > H.L()) return;
-        int base = gbidx(q, l, 0);
-        const Csr &Al = H.A[l];
+      Bn.nnzR_n = bR.nnz_rows(0, Bn.NBn);
+      Bn.nnzR = bR.nnz_rows(0, Bn.NB);
+      Bn.R = bR.take();
+    }
+    // local operators of this level are no longer needed
+    parallel_items(nn, [&](int k, int) {
+      CompLevel &lv = S.grids[normal[k]].lv[l];
+      free_csr(lv.A);
+      free_csr(lv.P);
+    });
+    vlog("pack: composite R", tp);
+    tp = now_s();
+    // ---- global level l over problems
+    SellBuilder bGA, bGP;
+    bGA.init(B.GN, B.glg);
+    bGP.init(B.GNn, B.glg);
+    B.gdinv.assign(B.GNn, 0.0);
+    B.prob_row0.assign(nprob, -1);
+    for (int q = 0; q < nprob; ++q) {
+      const Hierarchy &H = S.probs[q].H;
+      if (l > H.L()) continue;
+      B.prob_row0[q] = gbidx(q, l, 0);
+      if (l == H.L()) {
+        B.gc_row0.push_back(gbidx(q, l, 0));
+        B.gc_n.push_back(H.A[l].nrows);
+        B.gc_dense.push_back(S.dense_off[q]);
+      }
+    }
+    parallel_items(nprob, [&](int q, int) {
+      const Hierarchy &H = S.probs[q].H;
+      if (l > H.L()) return;
+      int base = gbidx(q, l, 0);
+      const Csr &Al = H.A[l];
+      for (int i = 0; i < Al.nrows; ++i) bGA.len[base + i] = Al.ptr[i + 1] - Al.ptr[i];
+      if (l < H.L())
+        for (int i = 0; i < Al.nrows; ++i) {
+          bGP.len[base + i] = H.P[l].ptr[i + 1] - H.P[l].ptr[i];
+          B.gdinv[base + i] = 1.0 / H.l1[l][i];
+        }
+    });
+    bGA.shape();
+    bGP.shape();
+    parallel_items(nprob, [&](int q, int) {
+      const Hierarchy &H = S.probs[q].H;
+      if (l > H.L()) return;
+      int base = gbidx(q, l, 0);
+      const Csr &Al = H.A[l];
+      for (int i = 0; i < Al.nrows; ++i) {
+        int kk = 0;
+        for (int jj = Al.ptr[i]; jj < Al.ptr[i + 1]; ++jj) bGA.put(base + i, kk++, base + Al.col[jj], Al.val[jj]);
+        bGA.pad(base + i, base);
+      }
+      if (l < H.L()) {
+        int cbase = gbidx(q, l + 1, 0);
+        const Csr &Pl = H.P[l];
         for (int i = 0; i < Al.nrows; ++i) {
           int kk = 0;
-          for (int jj = Al.ptr[i]; jj < Al.ptr[i + 1]; ++jj) bGA.put(base + i, kk++, base + Al.col[jj], Al.val[jj]);
-          bGA.pad(base + i, base);
+          for (int jj = Pl.ptr[i]; jj < Pl.ptr[i + 1]; ++jj) bGP.put(base + i, kk++, cbase + Pl.col[jj], Pl.val[jj]);
+          bGP.pad(base + i, cbase);
         }
-        if (l < H.L()) {
-          int cbase = gbidx(q, l + 1, 0);
-          const Csr &Pl = H.P[l];
-          for (int i = 0; i < Al.nrows; ++i) {
-            int kk = 0;
-            for (int jj = Pl.ptr[i]; jj < Pl.ptr[i + 1]; ++jj) bGP.put(base + i, kk++, cbase + Pl.col[jj], Pl.val[jj]);
-            bGP.pad(base + i, cbase);
-          }
+      }
+    });
+    B.nnzGA_n = bGA.nnz_rows(0, B.GNn);
+    B.nnzGA = bGA.nnz_rows(0, B.GN);
+    B.nnzGP = bGP.nnz_rows(0, B.GNn);
+    B.GA = bGA.take();
+    B.GP = bGP.take();
+    if (l < maxL) {
+      // R_l = P_l^T is stored in the hierarchy; rows = level l+1
+      BatchLevel &Bn = S.lv[l + 1];
+      SellBuilder bGR;
+      bGR.init(Bn.GN, Bn.glg);
+      parallel_items(nprob, [&](int q, int) {
+        const Hierarchy &H = S.probs[q].H;
+        if (l >= H.L()) return;
+        int cbase = gbidx(q, l + 1, 0);
+        for (int J = 0; J < H.R[l].nrows; ++J) bGR.len[cbase + J] = H.R[l].ptr[J + 1] - H.R[l].ptr[J];
+      });
+      bGR.shape();
+      parallel_items(nprob, [&](int q, int) {
+        const Hierarchy &H = S.probs[q].H;
+        if (l >= H.L()) return;
+        int base = gbidx(q, l, 0), cbase = gbidx(q, l + 1, 0);
+        const Csr &R = H.R[l];
+        for (int J = 0; J < R.nrows; ++J) {
+          int kk = 0;
+          for (int jj = R.ptr[J]; jj < R.ptr[J + 1]; ++jj) bGR.put(cbase + J, kk++, base + R.col[jj], R.val[jj]);
+          bGR.pad(cbase + J, base);
         }
       });
-      B.nnzGA_n = bGA.nnz_rows(0, B.GNn);
-      B.nnzGA = bGA.nnz_rows(0, B.GN);
-      B.nnzGP = bGP.nnz_rows(0, B.GNn);
-      B.GA = bGA.take();
-      B.GP = bGP.take();
-      if (l < maxL) {
-        // R_l = P_l^T is stored in the hierarchy; rows = level l+1
-        BatchLevel &Bn = S.lv[l + 1];
-        SellBuilder bGR;
-        bGR.init(Bn.GN, Bn.glg);
-        parallel_items(nprob, [&](int q, int) {
-          const Hierarchy &H = S.probs[q].H;
-          if (l >= H.L()) return;
-          int cbase = gbidx(q, l + 1, 0);
-          for (int J = 0; J < H.R[l].nrows; ++J) bGR.len[cbase + J] = H.R[l].ptr[J + 1] - H.R[l].ptr[J];
-        });
-        bGR.shape();
-        parallel_items(nprob, [&](int q, int) {
-          const Hierarchy &H = S.probs[q].H;
-          if (l >= H.L()) return;
-          int base = gbidx(q, l, 0), cbase = gbidx(q, l + 1, 0);
-          const Csr &R = H.R[l];
-          for (int J = 0; J < R.nrows; ++J) {
-            int kk = 0;
-            for (int jj = R.ptr[J]; jj < R.ptr[J + 1]; ++jj) bGR.put(cbase + J, kk++, base + R.col[jj], R.val[jj]);
-            bGR.pad(cbase + J, base);
-          }
-        });
-        Bn.nnzGR_n = bGR.nnz_rows(0, Bn.GNn);
-        Bn.nnzGR = bGR.nnz_rows(0, Bn.GN);
-        Bn.GR = bGR.take();
-      }
-      vlog("pack: global", tp);
+      Bn.nnzGR_n = bGR.nnz_rows(0, Bn.GNn);
+      Bn.nnzGR = bGR.nnz_rows(0, Bn.GN);
+      Bn.GR = bGR.take();
     }
-    vlog("pack: levels", t0);
-    if (verbose())
-      for (int l = 0; l <= maxL; ++l) {
-        const BatchLevel &B = S.lv[l];
-        std::fprintf(stderr, "[amgdd setup] level %d rows %d/%d/%d G %d/%d  A %lld/%lld  P %lld/%lld  R %lld/%lld\n", l,
-                     B.NRn, B.NBn, B.NB, 1 << B.lg, 1 << B.glg, B.nnzA, B.A.entries(), B.nnzP, B.P.entries(), B.nnzR,
-                     B.R.entries());
-      }
+    vlog("pack: global", tp);
+  }
+  vlog("pack: levels", t0);
+  if (verbose())
     for (int l = 0; l <= maxL; ++l) {
       const BatchLevel &B = S.lv[l];
-      const int nbn = l < maxL ? S.lv[l + 1].NB : 0, nbp = l > 0 ? S.lv[l - 1].NB : 0;
-      const int gnn = l < maxL ? S.lv[l + 1].GN : 0, gnp = l > 0 ? S.lv[l - 1].GN : 0;
-      bool ok = sell_in_bounds(B.A, B.NBn, B.NB) && sell_in_bounds(B.P, B.NBn, std::max(nbn, 1)) &&
-                sell_in_bounds(B.GA, B.GN, B.GN) && sell_in_bounds(B.GP, B.GNn, std::max(gnn, 1));
-      if (l > 0) ok = ok && sell_in_bounds(B.R, B.NB, nbp) && sell_in_bounds(B.GR, B.GN, gnp);
-      if (!ok) { err = "internal: batched layout check failed on level " + std::to_string(l); return ST_EINVAL; }
+      std::fprintf(stderr, "[amgdd setup] level %d rows %d/%d/%d G %d/%d  A %lld/%lld  P %lld/%lld  R %lld/%lld\n", l,
+                   B.NRn, B.NBn, B.NB, 1 << B.lg, 1 << B.glg, B.nnzA, B.A.entries(), B.nnzP, B.P.entries(), B.nnzR,
+                   B.R.entries());
     }
-    {
-      // owners of every composite / global row, per level
-      std::vector<std::vector<int>> cown(maxL + 1), gown(maxL + 1);
-      for (int l = 0; l <= maxL; ++l) {
-        cown[l].assign(S.lv[l].NB, -1);
-        gown[l].assign(S.lv[l].GN, -1);
-      }
-      for (int g = 0; g < ng; ++g)
-        for (int l = 0; l <= S.probs[S.grids[g].prob].H.L(); ++l)
-          for (int i = 0; i < S.grids[g].lv[l].nbar(); ++i) cown[l][bidx(g, l, i)] = g;
-      for (int q = 0; q < nprob; ++q)
-        for (int l = 0; l <= S.probs[q].H.L(); ++l)
-          for (int i = 0; i < S.probs[q].H.A[l].nrows; ++i) gown[l][gbidx(q, l, i)] = q;
-      for (int l = 0; l <= maxL; ++l) {
-        const BatchLevel &B = S.lv[l];
-        bool ok = sell_block_diagonal(B.A, cown[l], cown[l]) && sell_block_diagonal(B.GA, gown[l], gown[l]);
-        if (l < maxL) ok = ok && sell_block_diagonal(B.P, cown[l], cown[l + 1]) && sell_block_diagonal(B.GP, gown[l], gown[l + 1]);
-        if (l > 0) ok = ok && sell_block_diagonal(B.R, cown[l], cown[l - 1]) && sell_block_diagonal(B.GR, gown[l], gown[l - 1]);
-        if (!ok) { err = "internal: batched layout is not block-diagonal on level " + std::to_string(l); return ST_EINVAL; }
-      }
+  for (int l = 0; l <= maxL; ++l) {
+    const BatchLevel &B = S.lv[l];
+    const int nbn = l < maxL ? S.lv[l + 1].NB : 0, nbp = l > 0 ? S.lv[l - 1].NB : 0;
+    const int gnn = l < maxL ? S.lv[l + 1].GN : 0, gnp = l > 0 ? S.lv[l - 1].GN : 0;
+    bool ok = sell_in_bounds(B.A, B.NBn, B.NB) && sell_in_bounds(B.P, B.NBn, std::max(nbn, 1)) &&
+              sell_in_bounds(B.GA, B.GN, B.GN) && sell_in_bounds(B.GP, B.GNn, std::max(gnn, 1));
+    if (l > 0) ok = ok && sell_in_bounds(B.R, B.NB, nbp) && sell_in_bounds(B.GR, B.GN, gnp);
+    if (!ok) { err = "internal: batched layout check failed on level " + std::to_string(l); return ST_EINVAL; }
+  }
+  {
+    // owners of every composite / global row, per level
+    std::vector<std::vector<int>> cown(maxL + 1), gown(maxL + 1);
+    for (int l = 0; l <= maxL; ++l) {
+      cown[l].assign(S.lv[l].NB, -1);
+      gown[l].assign(S.lv[l].GN, -1);
     }
-    // fine-vector offsets (every problem is normal on level 0, so problem order)
-    S.prob_off.assign(nprob + 1, 0);
-    for (int q = 0; q < nprob; ++q) S.prob_off[q + 1] = S.prob_off[q] + S.probs[q].n;
+    for (int g = 0; g < ng; ++g)
+      for (int l = 0; l <= S.probs[S.grids[g].prob].H.L(); ++l)
+        for (int i = 0; i < S.grids[g].lv[l].nbar(); ++i) cown[l][bidx(g, l, i)] = g;
+    for (int q = 0; q < nprob; ++q)
+      for (int l = 0; l <= S.probs[q].H.L(); ++l)
+        for (int i = 0; i < S.probs[q].H.A[l].nrows; ++i) gown[l][gbidx(q, l, i)] = q;
+    for (int l = 0; l <= maxL; ++l) {
+      const BatchLevel &B = S.lv[l];
+      bool ok = sell_block_diagonal(B.A, cown[l], cown[l]) && sell_block_diagonal(B.GA, gown[l], gown[l]);
+      if (l < maxL) ok = ok && sell_block_diagonal(B.P, cown[l], cown[l + 1]) && sell_block_diagonal(B.GP, gown[l], gown[l + 1]);
+      if (l > 0) ok = ok && sell_block_diagonal(B.R, cown[l], cown[l - 1]) && sell_block_diagonal(B.GR, gown[l], gown[l - 1]);
+      if (!ok) { err = "internal: batched layout is not block-diagonal on level " + std::to_string(l); return ST_EINVAL; }
+    }
+  }
+  // fine-vector offsets (every problem is normal on level 0, so problem order)
+  S.prob_off.assign(nprob + 1, 0);
+  for (int q = 0; q < nprob; ++q) S.prob_off[q + 1] = S.prob_off[q] + S.probs[q].n;
+  if (composite) {
     S.owner.assign(S.prob_off[nprob], -1);
     for (int g = 0; g < ng; ++g) {
       const CompGrid &cg = S.grids[g];
@@ -1112,43 +1121,50 @@ int build_setup(const std::vector<ProblemInput> &in, double theta, int max_coars
     }
     for (int v : S.owner)
       if (v < 0) { err = "internal: fine point without owner"; return ST_EINVAL; }
-    // residual blocks of 256 rows that never straddle two problems
-    S.prob_blk0.assign(nprob + 1, 0);
-    for (int q = 0; q < nprob; ++q) {
-      S.prob_blk0[q] = (int)S.blk_row0.size();
-      for (int r = S.prob_off[q]; r < S.prob_off[q + 1]; r += 256) {
-        S.blk_row0.push_back(r);
-        S.blk_row1.push_back(std::min(r + 256, S.prob_off[q + 1]));
-        S.blk_prob.push_back(q);
+  }
+  // residual blocks of 256 rows that never straddle two problems
+  S.prob_blk0.assign(nprob + 1, 0);
+  for (int q = 0; q < nprob; ++q) {
+    S.prob_blk0[q] = (int)S.blk_row0.size();
+    for (int r = S.prob_off[q]; r < S.prob_off[q + 1]; r += 256) {
+      S.blk_row0.push_back(r);
+      S.blk_row1.push_back(std::min(r + 256, S.prob_off[q + 1]));
+      S.blk_prob.push_back(q);
+    }
+  }
+  S.prob_blk0[nprob] = (int)S.blk_row0.size();
+  // per-grid row ranges for the per-grid (persistent) schedule
+  const int nlv = maxL + 1;
+  S.gl_rbeg.assign((size_t)ng * nlv, 0);
+  S.gl_nreal.assign((size_t)ng * nlv, 0);
+  S.gl_gbeg.assign((size_t)ng * nlv, 0);
+  S.gl_nghost.assign((size_t)ng * nlv, 0);
+  S.grid_L.assign(ng, 0);
+  for (int g = 0; g < ng; ++g) {
+    int L = S.probs[S.grids[g].prob].H.L();
+    S.grid_L[g] = L;
+    for (int l = 0; l <= L; ++l) {
+      const CompLevel &lv = S.grids[g].lv[l];
+      size_t k = (size_t)g * nlv + l;
+      if (l < L) {
+        S.gl_rbeg[k] = roff[l][g];
+        S.gl_nreal[k] = lv.nreal;
+        S.gl_gbeg[k] = S.lv[l].NRn + goff[l][g];
+        S.gl_nghost[k] = lv.nbar() - lv.nreal;
+      } else {
+        S.gl_rbeg[k] = S.lv[l].NBn + coff[l][g];
+        S.gl_nreal[k] = lv.nbar();
       }
     }
-    S.prob_blk0[nprob] = (int)S.blk_row0.size();
-    // per-grid row ranges for the per-grid (persistent) schedule
-    const int nlv = maxL + 1;
-    S.gl_rbeg.assign((size_t)ng * nlv, 0);
-    S.gl_nreal.assign((size_t)ng * nlv, 0);
-    S.gl_gbeg.assign((size_t)ng * nlv, 0);
-    S.gl_nghost.assign((size_t)ng * nlv, 0);
-    S.grid_L.assign(ng, 0);
-    for (int g = 0; g < ng; ++g) {
-      int L = S.probs[S.grids[g].prob].H.L();
-      S.grid_L[g] = L;
-      for (int l = 0; l <= L; ++l) {
-        const CompLevel &lv = S.grids[g].lv[l];
-        size_t k = (size_t)g * nlv + l;
-        if (l < L) {
-          S.gl_rbeg[k] = roff[l][g];
-          S.gl_nreal[k] = lv.nreal;
-          S.gl_gbeg[k] = S.lv[l].NRn + goff[l][g];
-          S.gl_nghost[k] = lv.nbar() - lv.nreal;
-        } else {
-          S.gl_rbeg[k] = S.lv[l].NBn + coff[l][g];
-          S.gl_nreal[k] = lv.nbar();
-        }
-      }
-    }
-    S.times.pack = now_s() - t0;
-    return ST_OK;
+  }
+  S.times.pack = now_s() - t0;
+  return ST_OK;
+}
+
+template <typename F>
+int guarded(std::string &err, F &&f) {
+  try {
+    return f();
   } catch (const std::bad_alloc &) {
     err = "host allocation failed during setup";
     return ST_ENOMEM;
@@ -1156,6 +1172,79 @@ int build_setup(const std::vector<ProblemInput> &in, double theta, int max_coars
     err = std::string("layout too large: ") + e.what();
     return ST_EUNSUP;
   }
+}
+
+}  // namespace
+
+int build_setup(const std::vector<ProblemInput> &in, double theta, int max_coarse, int max_levels, Setup &S,
+                std::string &err) {
+  return guarded(err, [&]() {
+    int st = setup_hierarchies(in, theta, max_coarse, max_levels, S, err);
+    return st ? st : setup_layouts(S, true, err);
+  });
+}
+
+// Hybrid AMG-DD (Algorithm 3, Section 3.1).  The level-lt problem of every
+// problem that coarsens below lt is A_lt with levels lt..L of its hierarchy
+// (classical coarsening depends on the matrix alone, so setting A_lt up from
+// scratch would give the same levels) and the subdomains inherited along the
+// C-points: a coarse point stays in the subdomain of the fine point it was
+// chosen from (the per-level subdomains of Section 5).  Subdomains left without
+// points on level lt are dropped: they would patch nothing.
+int build_setup_hybrid(const std::vector<ProblemInput> &in, double theta, int max_coarse, int max_levels, int lt,
+                       Setup &outer, Setup &inner, std::vector<int> &inner_of, std::vector<std::vector<int>> &part_map,
+                       std::string &err) {
+  return guarded(err, [&]() {
+    if (lt < 1) { err = "hybrid level must be >= 1"; return (int)ST_EINVAL; }
+    int st = setup_hierarchies(in, theta, max_coarse, max_levels, outer, err);
+    if (st) return st;
+    if ((st = setup_layouts(outer, false, err))) return st;
+    const int nprob = (int)outer.probs.size();
+    inner = Setup();
+    inner.theta = theta;
+    inner.max_coarse = max_coarse;
+    inner.max_levels = max_levels;
+    inner_of.assign(nprob, -1);
+    part_map.assign(nprob, std::vector<int>());
+    double t0 = now_s();
+    for (int q = 0; q < nprob; ++q) {
+      const ProblemHost &O = outer.probs[q];
+      part_map[q].assign(O.nparts, -1);
+      if (O.H.L() <= lt) continue;
+      std::vector<int> part = O.part;
+      for (int l = 0; l < lt; ++l) {
+        std::vector<int> next;
+        next.reserve(O.H.A[l + 1].nrows);
+        for (int i = 0; i < O.H.A[l].nrows; ++i)
+          if (O.H.cf[l][i] == 1) next.push_back(part[i]);
+        part = std::move(next);
+      }
+      std::vector<int> count(O.nparts, 0);
+      for (int v : part) count[v]++;
+      int np = 0;
+      for (int p = 0; p < O.nparts; ++p)
+        if (count[p] > 0) part_map[q][p] = np++;
+      for (int &v : part) v = part_map[q][v];
+      inner_of[q] = (int)inner.probs.size();
+      inner.probs.emplace_back();
+      ProblemHost &P = inner.probs.back();
+      P.n = O.H.A[lt].nrows;
+      P.nparts = np;
+      P.eta = O.eta;
+      P.part = std::move(part);
+      P.symmetric = O.symmetric;
+      P.H.A.assign(O.H.A.begin() + lt, O.H.A.end());
+      P.H.P.assign(O.H.P.begin() + lt, O.H.P.end());
+      P.H.R.assign(O.H.R.begin() + lt, O.H.R.end());
+      P.H.cf.assign(O.H.cf.begin() + lt, O.H.cf.end());
+      P.H.l1.assign(O.H.l1.begin() + lt, O.H.l1.end());
+      P.H.Ac = O.H.Ac;
+      P.H.Ac_inv = O.H.Ac_inv;
+    }
+    inner.times.hierarchy = now_s() - t0;
+    if (inner.probs.empty()) return (int)ST_OK;
+    return setup_layouts(inner, true, err);
+  });
 }
 
 }  // namespace amgdd

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 from scipy import sparse
 
-from oracle import amg, composite
+from oracle import amg, composite, cycles
 from synth import config, grf, make_problem
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -144,3 +144,60 @@ def test_error_paths():
     s.close()
     s.close()  # idempotent
     lib.amgdd_destroy(None)  # NULL accepted
+
+
+HYBRID_CASES = [
+    ("2d_var_lt1", lambda: make_problem((40, 36), (3, 2), eta=2, k=np.exp(grf((40, 36), 1.0, 8.0, 3))), 1),
+    ("3d_16_lt2", lambda: make_problem((16, 16, 16), (2, 2, 2), eta=1), 2),
+    ("2d_64parts_lt2", lambda: make_problem((16, 16), (8, 8), eta=1), 2),
+]
+
+
+@pytest.mark.parametrize("name,make,lt", HYBRID_CASES)
+def test_hybrid_host_setup_matches_oracle(name, make, lt):
+    # the level-L~ problems' composite grids equal the oracle's grids built on
+    # the sub-hierarchy with the inherited partition; empty subdomains dropped
+    p = make()
+    s = _host(p, hybrid_level=lt)
+    H = amg.setup(p.A)
+    assert H.L > lt
+    n, _ = s.levels(0)
+    assert n.tolist() == [A.shape[0] for A in H.A]
+    lt_, Hs, comps = cycles.hybrid_setup(H, p.part, p.nparts, p.eta, lt)
+    part = cycles.inherited_partition(H, p.part, lt)
+    nonempty = [q for q in range(p.nparts) if np.any(part == q)]
+    for q in range(p.nparts):
+        if q not in nonempty:
+            with pytest.raises(amgdd.AmgddError):
+                s.composite(0, q, lt)
+            continue
+        for l, lv in enumerate(comps[q].levels):
+            g, nr, om = s.composite(0, q, lt + l)
+            assert nr == lv.n_real and np.array_equal(g, lv.gid), f"p {q} level {lt + l}"
+            assert om == lv.omissions
+    with pytest.raises(amgdd.AmgddError):
+        s.composite(0, nonempty[0], lt - 1)
+    st = s.stats()
+    assert st["hybrid_level"] == lt
+    assert st["n_grids"] == len(nonempty)
+    upper = sum(H.A[l].nnz for l in range(lt))
+    real = sum(composite.composite_overhead(Hs, [comps[q]]) for q in nonempty) * sum(A.nnz for A in Hs.A)
+    want = (upper + real) / sum(A.nnz for A in H.A)
+    assert abs(st["composite_overhead"] - want) < 1e-12
+    assert st["composite_overhead"] < _host(p).stats()["composite_overhead"]
+
+
+def test_hybrid_level_below_every_hierarchy():
+    # L~ at or beyond the coarsest level of every problem: no level-L~ AMG-DD
+    # problem, the handle cycles plain V-cycles and holds no composite grid
+    p = make_problem((24, 24), (2, 2))
+    H = amg.setup(p.A)
+    s = _host(p, hybrid_level=H.L)
+    st = s.stats()
+    assert st["hybrid_level"] == H.L and st["n_grids"] == 0
+    assert abs(st["composite_overhead"] - 1.0) < 1e-15
+    with pytest.raises(amgdd.AmgddError):
+        s.composite(0, 0, H.L)
+    with pytest.raises(amgdd.AmgddError) as e:
+        _host(p, hybrid_level=-1)
+    assert e.value.status == amgdd.EINVAL
