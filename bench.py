@@ -7,7 +7,8 @@ iteration, FP64, b ~ U[-1, 1] (seed 0), x0 = 0.  One step = one AMG-DD solve
 to 1e-8 relative residual (fine residual, restriction chain, composite
 right-hand sides, batched AlgFAC on all 64 composite grids, patch), with all
 inputs resident in HBM.  value = DOF*cycles/s = N_0 * outer iterations /
-solve time.  The V(1,1) cycle on the same hierarchy and the mixed-precision
+solve time.  The V(1,1) cycle on the same hierarchy, the hybrid AMG-DD
+V-cycle (AMG-DD on a transition level, Algorithm 3) and the mixed-precision
 form are timed beside it and reported as extra fields.
 
 Prints one JSON line.  --gpus must be 1 (this build runs on one GPU).
@@ -110,13 +111,13 @@ PRIMARY = {"cfg2": "fp64", "cfg3": "mixed", "cfg4": "fp64", "cfg5": "mixed"}
 RTOL = {"cfg2": 1e-8, "cfg3": 1e-8, "cfg4": 1e-10, "cfg5": 1e-8}
 
 
-def make_solver(amgdd, p, precision, sched=(-2, 0)):
+def make_solver(amgdd, p, precision, sched=(-2, 0), hybrid_level=0):
     if isinstance(p, list):
         return amgdd.Solver([q.A for q in p], [q.part for q in p], [q.nparts for q in p],
                             padding=[q.eta for q in p], n_fac=2, precision=precision, tail_level=sched[0],
-                            tail_block=sched[1])
+                            tail_block=sched[1], hybrid_level=hybrid_level)
     return amgdd.Solver(p.A, p.part, p.nparts, padding=p.eta, n_fac=p.n_fac, precision=precision,
-                        tail_level=sched[0], tail_block=sched[1])
+                        tail_level=sched[0], tail_block=sched[1], hybrid_level=hybrid_level)
 
 
 def summarize_rocpd(db):
@@ -195,6 +196,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--tail-level", type=int, default=-2, help="fixed AlgFAC schedule cut level (-2: autotune)")
     ap.add_argument("--tail-block", type=int, default=0, help="fixed persistent workgroup size (0: autotune)")
+    ap.add_argument("--hybrid-levels", default="1,2,3",
+                    help="transition levels of the hybrid AMG-DD cycles timed beside the primary solve")
     ap.add_argument("--summarize-rocpd", metavar="DB", help="print a summary of a rocprofv3 kernel-trace database")
     ap.add_argument("--summarize-pmc", metavar="CSV", help="print a summary of rocprofv3 --pmc CSV output")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -301,6 +304,25 @@ def main():
         other = "mixed" if prec == "fp64" else "fp64"
         del s
         torch.cuda.empty_cache()
+        if not isinstance(p, list) and not adjoint and args.hybrid_levels:
+            # hybrid AMG-DD V-cycles (Algorithm 3), same precision and tolerance
+            out["hybrid"] = []
+            for lt in [int(v) for v in args.hybrid_levels.split(",") if v.strip()]:
+                t0 = time.perf_counter()
+                sh = make_solver(amgdd, p, prec, hybrid_level=lt)
+                hsetup = time.perf_counter() - t0
+                run_steps(torch, sh, b, 1, rtol, False)
+                dth, ith, xh = run_steps(torch, sh, b, k, rtol, False)
+                sth = sh.stats()
+                rec = {"level": lt, "iters": int(np.median(ith)), "time_to_tol_ms": round(dth / k * 1e3, 4),
+                       "dof_cycles_per_s": round(n * sum(ith) / dth, 1), "grids": sth["n_grids"],
+                       "composite_overhead": round(sth["composite_overhead"], 4), "setup_s": round(hsetup, 2),
+                       "device_gib": round(sth["device_bytes"] / 2**30, 3),
+                       "final_relres_fp64": residual_rel(p, xh.cpu().numpy())}
+                out["hybrid"].append(rec)
+                log(f"hybrid L~={lt}: {rec}")
+                del sh
+                torch.cuda.empty_cache()
         so = make_solver(amgdd, p, other)
         run_steps(torch, so, b, 1, rtol, adjoint)
         dto, ito, xo = run_steps(torch, so, b, k, rtol, adjoint)

@@ -74,3 +74,36 @@ def test_cfg2_solve_properties(cfg2):
     for q in range(p.nparts):
         gids, nr, om = s.composite(0, q, 0)
         assert (nr, gids.size, om) == (d[q], db[q], 0)
+
+
+GOLD_H = os.path.join(os.path.dirname(__file__), "golden", "cfg2_hybrid_samples.json")
+
+
+def test_cfg2_hybrid_sampled_iterates_and_solve():
+    # hybrid AMG-DD V-cycle with AMG-DD on level 2: sampled iterates against
+    # the oracle's values, then a solve to 1e-8 checked in FP64 on the host
+    p = config("cfg2")
+    lt = 2
+    print("[gpu-test] cfg2 hybrid setup", p.n, "L~", lt, flush=True)
+    s = amgdd.Solver(p.A, p.part, p.nparts, padding=p.eta, n_fac=p.n_fac, hybrid_level=lt)
+    b = torch.as_tensor(p.b, device="cuda:0")
+    if os.path.exists(GOLD_H):
+        g = json.load(open(GOLD_H))
+        assert g["hybrid_level"] == lt and s.levels(0)[0].tolist() == g["levels"]
+        idx = np.array(g["idx"])
+        x = torch.zeros_like(b)
+        for k in (1, 2):
+            x, info, st = s.solve(b, x, rtol=0, maxit=1)
+            ref = np.array(g[f"hybrid_x{k}"])
+            err = np.linalg.norm(x.cpu().numpy()[idx] - ref) / np.linalg.norm(ref)
+            print(f"[gpu-test] hybrid iterate {k}: sampled rel err {err:.2e}", flush=True)
+            assert err <= 1e-12
+            np.testing.assert_allclose(s.history(0)[-1], g["hybrid_hist"][k], rtol=1e-10)
+    x, info, st = s.solve(b, rtol=1e-8, maxit=200)
+    assert st == amgdd.OK
+    rel = np.linalg.norm(p.b - p.A @ x.cpu().numpy()) / np.linalg.norm(p.b)
+    st_ = s.stats()
+    print(f"[gpu-test] cfg2 hybrid: {info.iters} cycles, relres {rel:.2e}, {info.solve_s * 1e3:.1f} ms, "
+          f"grids {st_['n_grids']}, overhead {st_['composite_overhead']:.3f}", flush=True)
+    assert rel <= 1e-8
+    assert st_["n_grids"] == p.nparts
