@@ -86,6 +86,13 @@ typedef struct {
                        V(1,1) cycles (its level-L~ AMG-DD would be the direct
                        solve).  V-cycle levels run in FP64; `precision`
                        applies to the level-L~ AMG-DD cycle. */
+  int relax_order;  /* 0 = l1-Jacobi in natural order, every point at once
+                       (default); 1 = CF-ordered l1-Jacobi, the smoother of the
+                       paper's experiments (Section 6): each relaxation is a
+                       Jacobi half-sweep over the level's C-points and then one
+                       over its F-points, the second seeing the first's update,
+                       F-points first on the upsweep.  Applies to AlgFAC, the
+                       V-cycle and the hybrid cycle alike. */
 } amgdd_params;
 
 typedef struct {

@@ -33,7 +33,8 @@ class AmgddError(RuntimeError):
 class Params(C.Structure):
     _fields_ = [("theta", C.c_double), ("max_coarse", C.c_int), ("max_levels", C.c_int), ("padding", C.c_int),
                 ("n_fac", C.c_int), ("precision", C.c_int), ("device", C.c_int), ("use_graph", C.c_int),
-                ("tail_level", C.c_int), ("tail_block", C.c_int), ("hybrid_level", C.c_int)]
+                ("tail_level", C.c_int), ("tail_block", C.c_int), ("hybrid_level", C.c_int),
+                ("relax_order", C.c_int)]
 
 
 class Info(C.Structure):
@@ -153,11 +154,12 @@ class Solver:
     A: scipy CSR matrix (or a list of them for a batch), part: int array(s) of
     subdomain ids, nparts: int(s), padding: int(s).  device=-1 gives a
     host-only handle (setup and introspection, no solve).  hybrid_level=L~ > 0
-    makes solve() run hybrid AMG-DD V-cycles with AMG-DD on level L~."""
+    makes solve() run hybrid AMG-DD V-cycles with AMG-DD on level L~;
+    relax="cf" selects CF-ordered l1-Jacobi."""
 
     def __init__(self, A, part, nparts, padding=1, n_fac=2, precision="fp64", device=0, theta=0.25,
                  max_coarse=16, max_levels=25, use_graph=True, stream=None, tail_level=-2, tail_block=0,
-                 hybrid_level=0):
+                 hybrid_level=0, relax="l1"):
         lib = load()
         batch = isinstance(A, (list, tuple))
         As = list(A) if batch else [A]
@@ -175,6 +177,9 @@ class Solver:
         prm.tail_level = tail_level
         prm.tail_block = tail_block
         prm.hybrid_level = hybrid_level
+        if relax not in ("l1", "cf"):
+            raise ValueError(f"relax must be 'l1' or 'cf', not {relax!r}")
+        prm.relax_order = 1 if relax == "cf" else 0
         if stream is None and device >= 0:
             torch = _torch()
             stream = torch.cuda.current_stream(device).cuda_stream

@@ -73,6 +73,7 @@ struct Sell {
 // Block-diagonal batched layout of one level, over every composite grid
 // (and, for the G* members, over every problem's global level).
 //   composite rows: [normal-grid real rows | normal-grid ghost rows | coarse-grid rows]
+//   (with CF ordering, each grid's real rows are C rows then F rows)
 //   "normal" grids are those whose problem has L > l; "coarse" grids have L == l.
 //   global rows:    [normal problems | coarse problems]
 struct BatchLevel {
@@ -94,6 +95,12 @@ struct BatchLevel {
   // stored (unpadded) nonzeros of row ranges, for the algorithmic-bytes model
   long long nnzA_r = 0, nnzA = 0, nnzP = 0, nnzR_n = 0, nnzR = 0;
   long long nnzGA_n = 0, nnzGA = 0, nnzGP = 0, nnzGR_n = 0, nnzGR = 0;
+  // CF-ordered relaxation only: C/F class (+1 / -1) of the normal real rows
+  // and of the normal global rows; C rows / their nonzeros
+  std::vector<int8_t> cls;         // [NRn]
+  std::vector<int8_t> gcls;        // [GNn]
+  int NRc = 0, GNc = 0;
+  long long nnzA_c = 0, nnzGA_c = 0;
 };
 
 struct SetupTimes {
@@ -103,6 +110,11 @@ struct SetupTimes {
 struct Setup {
   double theta = 0.25;
   int max_coarse = 16, max_levels = 25;
+  // CF-ordered relaxation: class arrays are filled and each grid's real rows
+  // of a level are stored C-points first (Jacobi within a class does not
+  // depend on row order, so results are the same; the half-sweeps then read
+  // contiguous row ranges)
+  bool cf = false;
   std::vector<ProblemHost> probs;
   std::vector<CompGrid> grids;
   std::vector<BatchLevel> lv;      // 0..maxL

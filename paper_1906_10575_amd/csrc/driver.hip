@@ -90,6 +90,11 @@ struct DLevel {
   // stored nonzeros (algorithmic-bytes model of the profiler)
   long long nnzA_r = 0, nnzA = 0, nnzP = 0, nnzR_n = 0, nnzR = 0;
   long long nnzGA_n = 0, nnzGA = 0, nnzGP = 0, nnzGR_n = 0, nnzGR = 0;
+  // CF-ordered relaxation: classes of the composite real rows and of the
+  // normal global rows (null in natural order)
+  signed char *cls = nullptr, *gcls = nullptr;
+  int NRc = 0, GNc = 0;
+  long long nnzA_c = 0, nnzGA_c = 0;
 };
 
 // Per-launch event timing (amgdd_profile): one event pair per launch site.
@@ -172,6 +177,7 @@ struct amgdd_ctx {
   std::vector<std::vector<int>> part_map;  // subdomain -> level-L~ subdomain (-1: empty)
 
   bool mixed() const { return prm.precision == AMGDD_MIXED; }
+  bool cf() const { return S.cf; }
 
   amgdd_status alloc(void **p, size_t bytes) {
     *p = nullptr;
@@ -278,6 +284,14 @@ amgdd_status upload_all(amgdd_ctx *h) {
     D.nnzGP = B.nnzGP;
     D.nnzGR_n = B.nnzGR_n;
     D.nnzGR = B.nnzGR;
+    D.NRc = B.NRc;
+    D.GNc = B.GNc;
+    D.nnzA_c = B.nnzA_c;
+    D.nnzGA_c = B.nnzGA_c;
+    if (S.cf) {
+      if ((st = h->upload((int8_t **)&D.cls, B.cls.data(), B.cls.size()))) return st;
+      if ((st = h->upload((int8_t **)&D.gcls, B.gcls.data(), B.gcls.size()))) return st;
+    }
     if ((st = h->upload_sell(D.A, B.A, fl))) return st;
     if ((st = h->upload_sell(D.P, B.P, fl))) return st;
     if ((st = h->upload_sell(D.R, B.R, fl))) return st;
@@ -371,7 +385,7 @@ amgdd_status upload_all(amgdd_ctx *h) {
       for (int l = 0; l < nlev; ++l) {
         DLevel &D = h->L[l];
         v[l] = dev::LevelDev<T>{D.A.as<T>(), D.P.as<T>(), D.R.as<T>(), (const T *)D.dinv, (T *)D.u[0], (T *)D.u[1],
-                                (T *)D.t, (T *)D.sw, (T *)D.f};
+                                (T *)D.t, (T *)D.sw, (T *)D.f, D.cls};
       }
       dev::LevelDev<T> *d = nullptr;
       amgdd_status s2 = h->upload(&d, v.data(), v.size());
@@ -409,10 +423,10 @@ void enqueue_residual(amgdd_ctx *h, hipStream_t s, bool vc) {
   DLevel &D0 = h->L[0];
   if (vc)
     PLAUNCH(h, "resid_v", 0, D0.nnzGA * 12.0 + h->N0 * 40.0, (dev::k_resid<double, true>), h->nblk, dev::BLOCK, 0, s, D0.GA.as<double>(), h->b, h->x, D0.vf, h->partial,
-           h->blk_row0, h->blk_row1, D0.gdinv, D0.ve[0]);
+           h->blk_row0, h->blk_row1, D0.gdinv, D0.ve[0], (const signed char *)D0.gcls);
   else
     PLAUNCH(h, "resid", 0, D0.nnzGA * 12.0 + h->N0 * (16.0 + sizeof(T)), (dev::k_resid<T, false>), h->nblk, dev::BLOCK, 0, s, D0.GA.as<double>(), h->b, h->x, (T *)D0.rt,
-           h->partial, h->blk_row0, h->blk_row1, (const double *)nullptr, (double *)nullptr);
+           h->partial, h->blk_row0, h->blk_row1, (const double *)nullptr, (double *)nullptr, (const signed char *)nullptr);
   PLAUNCH(h, "norm", 0, h->nblk * 8.0, dev::k_norm_final, h->nprob, dev::BLOCK, 0, s, h->partial, h->prob_blk0, h->norm2);
   (void)hipMemcpyAsync(h->h_norm2, h->norm2, (size_t)h->nprob * sizeof(double), hipMemcpyDeviceToHost, s);
 }
@@ -425,22 +439,33 @@ void enqueue_fac_down(amgdd_ctx *h, hipStream_t s, int *cur, int l, int first) {
   const double w = sizeof(T);
   DLevel &B = h->L[l];
   T *uin = (T *)B.u[cur[l]], *uout = (T *)B.u[cur[l] ^ 1];
+  const bool cf = B.cls != nullptr;
+  const double nzc = cf ? (double)B.nnzA_c : (double)B.nnzA_r, nrc = cf ? B.NRc : B.NRn;
   if (l == 0) {
     if (first)
-      PLAUNCH(h, "relax0", 0, B.NRn * 4.0 * w + (B.NBn - B.NRn) * w, dev::k_relax_zero<T>, nblocks(B.NBn), dev::BLOCK, 0, s, B.NRn, B.NBn, (const T *)B.f,
-             (const T *)B.dinv, uout, (T *)B.t);
+      PLAUNCH(h, "relax0", 0, nrc * 4.0 * w + (B.NBn - nrc) * w + (cf ? B.NRn : 0), dev::k_relax_zero<T>, nblocks(B.NBn), dev::BLOCK, 0, s, B.NRn, B.NBn, (const T *)B.f,
+             (const T *)B.dinv, uout, (T *)B.t, (const signed char *)B.cls);
     else
-      PLAUNCH(h, "relax_pre", 0, B.nnzA_r * (w + 4.0) + B.NRn * 4.0 * w + B.NBn * 2.0 * w, dev::k_relax<T>, nblocks((long long)B.NBn << B.lg), dev::BLOCK, 0, s, B.A.as<T>(), B.NRn, B.NBn, (const T *)B.f,
-             (const T *)B.dinv, (const T *)uin, uout, (T *)B.t, 1);
+      PLAUNCH(h, "relax_pre", 0, nzc * (w + 4.0) + nrc * 4.0 * w + B.NBn * 2.0 * w + (cf ? B.NRn : 0), dev::k_relax<T>, nblocks((long long)B.NBn << B.lg), dev::BLOCK, 0, s, B.A.as<T>(), B.NRn, B.NBn, (const T *)B.f,
+             (const T *)B.dinv, (const T *)uin, uout, (T *)B.t, 1, (const signed char *)B.cls, 1);
   } else {
     DLevel &Bp = h->L[l - 1];
-    PLAUNCH(h, "down", l, B.nnzR_n * (w + 4.0) + Bp.NBn * w + B.NBn * 2.0 * w + (first ? 0.0 : B.nnzA_r * (w + 4.0) + B.NBn * w) + B.NRn * (first ? 4.0 : 5.0) * w, dev::k_down<T>, nblocks((long long)B.NBn << B.lg), dev::BLOCK, 0, s, B.R.as<T>(), B.A.as<T>(), B.NRn, B.NBn,
-           (const T *)Bp.sw, (T *)B.sw, (T *)B.f, (const T *)B.dinv, (const T *)uin, uout, (T *)B.t, first);
+    PLAUNCH(h, "down", l, B.nnzR_n * (w + 4.0) + Bp.NBn * w + B.NBn * 2.0 * w + (first ? 0.0 : B.nnzA_r * (w + 4.0) + B.NBn * w) + B.NRn * (first ? 4.0 : 5.0) * w + (cf ? B.NRn : 0), dev::k_down<T>, nblocks((long long)B.NBn << B.lg), dev::BLOCK, 0, s, B.R.as<T>(), B.A.as<T>(), B.NRn, B.NBn,
+           (const T *)Bp.sw, (T *)B.sw, (T *)B.f, (const T *)B.dinv, (const T *)uin, uout, (T *)B.t, first, (const signed char *)B.cls);
     PLAUNCH(h, "coarse", l, (B.nnzR - B.nnzR_n) * (w + 4.0) + (B.NB - B.NBn) * 3.0 * w, dev::k_coarse<T>, B.ncg, dev::BLOCK, 2 * B.cg_maxn * sizeof(double), s, B.R.as<T>(), 1,
            (const T *)Bp.sw, (T *)B.f, (const T *)uin, uout, h->dense_A, h->dense_inv, B.cg_row0, B.cg_n,
            B.cg_dense, 0, first, uin);
   }
   cur[l] ^= 1;
+  if (cf && B.NBn > 0 && l < maxL) {
+    // F half of the CF sweep (normal grids only; the coarse grids' rows of
+    // this level keep their solve, copied along)
+    const int nrf = B.NRn - B.NRc;
+    T *ui = (T *)B.u[cur[l]], *uo = (T *)B.u[cur[l] ^ 1];
+    PLAUNCH(h, "relax_f", l, (B.nnzA_r - B.nnzA_c) * (w + 4.0) + nrf * 4.0 * w + B.NB * 2.0 * w + B.NRn, dev::k_relax<T>, nblocks((long long)B.NB << B.lg), dev::BLOCK, 0, s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
+            (const T *)B.dinv, (const T *)ui, uo, (T *)B.t, 1, (const signed char *)B.cls, -1);
+    cur[l] ^= 1;
+  }
   if (B.NBn > 0 && l < maxL)
     PLAUNCH(h, "w", l, B.nnzA * (w + 4.0) + B.NBn * (l > 0 ? 3.0 : 2.0) * w, dev::k_w<T>, nblocks((long long)B.NBn << B.lg), dev::BLOCK, 0, s, B.A.as<T>(), B.NBn, (T *)B.sw, (const T *)B.t, l > 0);
 }
@@ -453,8 +478,17 @@ void enqueue_fac_up(amgdd_ctx *h, hipStream_t s, int *cur, int l) {
   DLevel &Bc = h->L[l + 1];
   PLAUNCH(h, "interp", l, B.nnzP * (w + 4.0) + B.NBn * 2.0 * w + Bc.NB * w, dev::k_interp<T>, nblocks((long long)B.NBn << B.lg), dev::BLOCK, 0, s, B.P.as<T>(), B.NBn, (T *)B.u[cur[l]],
          (const T *)Bc.u[cur[l + 1]]);
-  PLAUNCH(h, "relax_post", l, B.nnzA_r * (w + 4.0) + B.NRn * 3.0 * w + B.NB * 2.0 * w, dev::k_relax<T>, nblocks((long long)B.NB << B.lg), dev::BLOCK, 0, s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
-         (const T *)B.dinv, (const T *)B.u[cur[l]], (T *)B.u[cur[l] ^ 1], (T *)B.t, 0);
+  if (B.cls) {
+    const int nrf = B.NRn - B.NRc;
+    PLAUNCH(h, "relax_post_f", l, (B.nnzA_r - B.nnzA_c) * (w + 4.0) + nrf * 3.0 * w + B.NRc * w + B.NB * 2.0 * w + B.NRn, dev::k_relax<T>, nblocks((long long)B.NB << B.lg), dev::BLOCK, 0, s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
+            (const T *)B.dinv, (const T *)B.u[cur[l]], (T *)B.u[cur[l] ^ 1], (T *)B.t, 0, (const signed char *)B.cls, -1);
+    cur[l] ^= 1;
+    PLAUNCH(h, "relax_post_c", l, B.nnzA_c * (w + 4.0) + B.NRc * 4.0 * w + B.NB * 2.0 * w + B.NRn, dev::k_relax<T>, nblocks((long long)B.NB << B.lg), dev::BLOCK, 0, s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
+            (const T *)B.dinv, (const T *)B.u[cur[l]], (T *)B.u[cur[l] ^ 1], (T *)B.t, 1, (const signed char *)B.cls, 1);
+  } else {
+    PLAUNCH(h, "relax_post", l, B.nnzA_r * (w + 4.0) + B.NRn * 3.0 * w + B.NB * 2.0 * w, dev::k_relax<T>, nblocks((long long)B.NB << B.lg), dev::BLOCK, 0, s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
+           (const T *)B.dinv, (const T *)B.u[cur[l]], (T *)B.u[cur[l] ^ 1], (T *)B.t, 0, (const signed char *)nullptr, 1);
+  }
   cur[l] ^= 1;
 }
 
@@ -472,6 +506,8 @@ double tail_bytes(amgdd_ctx *h, int lt, int first) {
       b += B.nnzA * (w + 4.0) + B.NBn * (l > 0 ? 3.0 : 2.0) * w;
       b += B.nnzP * (w + 4.0) + B.NBn * 2.0 * w + h->L[l + 1].NB * w;
       b += B.nnzA_r * (w + 4.0) + B.NRn * 3.0 * w + B.NB * 2.0 * w;
+      // CF order: the extra half-sweeps re-read and re-write the vectors
+      if (B.cls) b += 2.0 * (B.NBn * 2.0 * w + B.NRn) + (B.nnzA_r - B.nnzA_c) * (w + 4.0);
     }
   }
   return b;
@@ -542,9 +578,21 @@ void enqueue_dd_iteration(amgdd_ctx *h, hipStream_t s) {
 // solve (problems whose coarsest level is l+1).  hyb (lv = L~ of a hybrid
 // handle): on the last level, the restricted residual of the problems that
 // continue goes, in the level-L~ handle's precision, into that handle's fine
-// residual instead.
+// residual instead.  CF order: the first relaxation from zero is the C half;
+// an F half-sweep follows on every relaxed level (level 0 included).
+void enqueue_v_relax(amgdd_ctx *h, hipStream_t s, int *cur, int l, int want, const char *name) {
+  DLevel &B = h->L[l];
+  const double nz = want == 1 ? (double)B.nnzGA_c : (double)(B.nnzGA_n - B.nnzGA_c);
+  const double nr = want == 1 ? B.GNc : B.GNn - B.GNc;
+  PLAUNCH(h, name, l, nz * 12.0 + nr * 16.0 + B.GN * 16.0 + B.GNn, dev::k_relax<double>, nblocks((long long)B.GN << B.glg), dev::BLOCK, 0, s, B.GA.as<double>(), B.GNn, B.GN, B.vf, B.gdinv,
+          B.ve[cur[l]], B.ve[cur[l] ^ 1], (double *)nullptr, 2, (const signed char *)B.gcls, want);
+  cur[l] ^= 1;
+}
+
 template <typename T>
 void enqueue_v_down(amgdd_ctx *h, hipStream_t s, int *cur, int lv, bool hyb) {
+  const bool cf = h->cf();
+  if (cf && lv > 0) enqueue_v_relax(h, s, cur, 0, -1, "vrelax_f");
   for (int l = 0; l < lv; ++l) {
     DLevel &B = h->L[l];
     DLevel &Bc = h->L[l + 1];
@@ -554,11 +602,12 @@ void enqueue_v_down(amgdd_ctx *h, hipStream_t s, int *cur, int lv, bool hyb) {
       PLAUNCH(h, "hrestrict", l + 1, Bc.nnzGR_n * 12.0 + B.GNn * 8.0 + Bc.GNn * (double)sizeof(T), (dev::k_spmv<double, T>), nblocks((long long)Bc.GNn << Bc.glg), dev::BLOCK, 0, s, Bc.GRd.as<double>(), Bc.GNn,
               (const double *)B.vq, (T *)h->inner->L[0].rt);
     else
-      PLAUNCH(h, "vdown", l + 1, Bc.nnzGR_n * 12.0 + B.GNn * 8.0 + Bc.GNn * 24.0, dev::k_vdown<double>, nblocks((long long)Bc.GNn << Bc.glg), dev::BLOCK, 0, s, Bc.GRd.as<double>(), Bc.GNn, B.vq, Bc.vf,
-             Bc.gdinv, Bc.ve[cur[l + 1]]);
+      PLAUNCH(h, "vdown", l + 1, Bc.nnzGR_n * 12.0 + B.GNn * 8.0 + Bc.GNn * 24.0 + (cf ? Bc.GNn : 0), dev::k_vdown<double>, nblocks((long long)Bc.GNn << Bc.glg), dev::BLOCK, 0, s, Bc.GRd.as<double>(), Bc.GNn, B.vq, Bc.vf,
+             Bc.gdinv, Bc.ve[cur[l + 1]], (const signed char *)Bc.gcls);
     PLAUNCH(h, "vcoarse", l + 1, (Bc.nnzGR - Bc.nnzGR_n) * 12.0 + (Bc.GN - Bc.GNn) * 16.0, dev::k_coarse<double>, Bc.ngc, dev::BLOCK, 2 * Bc.gc_maxn * sizeof(double), s, Bc.GRd.as<double>(), 1, B.vq,
            Bc.vf, Bc.ve[cur[l + 1]], Bc.ve[cur[l + 1]], h->dense_A, h->dense_inv, Bc.gc_row0, Bc.gc_n, Bc.gc_dense, 1,
            1, (double *)nullptr);
+    if (cf && !(hyb && l + 1 == lv) && Bc.GNn > 0) enqueue_v_relax(h, s, cur, l + 1, -1, "vrelax_f");
   }
 }
 
@@ -571,13 +620,19 @@ void enqueue_v_up(amgdd_ctx *h, hipStream_t s, int *cur, int lv) {
     if (B.GNn == 0) continue;
     PLAUNCH(h, "vinterp", l, B.nnzGP * 12.0 + B.GNn * 16.0 + Bc.GN * 8.0, dev::k_interp<double>, nblocks((long long)B.GNn << B.glg), dev::BLOCK, 0, s, B.GP.as<double>(), B.GNn, B.ve[cur[l]],
            Bc.ve[cur[l + 1]]);
+    const bool cf = B.gcls != nullptr;
+    if (cf) enqueue_v_relax(h, s, cur, l, -1, "vrelax_fu");
     if (l > 0) {
-      PLAUNCH(h, "vrelax", l, B.nnzGA_n * 12.0 + B.GNn * 16.0 + B.GN * 16.0, dev::k_relax<double>, nblocks((long long)B.GN << B.glg), dev::BLOCK, 0, s, B.GA.as<double>(), B.GNn, B.GN, B.vf, B.gdinv,
-             B.ve[cur[l]], B.ve[cur[l] ^ 1], (double *)nullptr, 2);
-      cur[l] ^= 1;
+      if (cf) {
+        enqueue_v_relax(h, s, cur, l, 1, "vrelax_cu");
+      } else {
+        PLAUNCH(h, "vrelax", l, B.nnzGA_n * 12.0 + B.GNn * 16.0 + B.GN * 16.0, dev::k_relax<double>, nblocks((long long)B.GN << B.glg), dev::BLOCK, 0, s, B.GA.as<double>(), B.GNn, B.GN, B.vf, B.gdinv,
+               B.ve[cur[l]], B.ve[cur[l] ^ 1], (double *)nullptr, 2, (const signed char *)nullptr, 1);
+        cur[l] ^= 1;
+      }
     } else {
-      PLAUNCH(h, "vfinal", 0, B.nnzGA_n * 12.0 + B.GNn * 40.0, dev::k_vfinal, nblocks(B.GNn), dev::BLOCK, 0, s, B.GA.as<double>(), B.GNn, B.vf, B.gdinv, B.ve[cur[0]],
-             h->x);
+      PLAUNCH(h, "vfinal", 0, (cf ? B.nnzGA_c : B.nnzGA_n) * 12.0 + B.GNn * 40.0 + (cf ? B.GNn : 0), dev::k_vfinal, nblocks(B.GNn), dev::BLOCK, 0, s, B.GA.as<double>(), B.GNn, B.vf, B.gdinv, B.ve[cur[0]],
+             h->x, (const signed char *)B.gcls);
     }
   }
 }
@@ -811,6 +866,11 @@ amgdd_status make_handle(const std::vector<ProblemInput> &in, const amgdd_params
     delete h;
     return fail(ST_EINVAL, "hybrid_level must be >= 0");
   }
+  if (p.relax_order != 0 && p.relax_order != 1) {
+    delete h;
+    return fail(ST_EINVAL, "relax_order must be 0 (natural) or 1 (CF)");
+  }
+  h->S.cf = p.relax_order == 1;
   std::string err;
   Setup inner_S;
   int st = p.hybrid_level > 0 ? build_setup_hybrid(in, p.theta, p.max_coarse, p.max_levels, p.hybrid_level, h->S, inner_S,
@@ -905,6 +965,7 @@ void amgdd_params_default(amgdd_params *prm) {
   prm->tail_level = -2;
   prm->tail_block = 0;
   prm->hybrid_level = 0;
+  prm->relax_order = 0;
 }
 
 amgdd_status amgdd_setup_composite(int n, const int *rowptr, const int *colind, const double *val, const int *part,

@@ -26,6 +26,14 @@
 // buffer `u_in` and writes `u_out` for every row of the level (copies where it
 // does not relax).
 //
+// CF-ordered relaxation (the smoother of the paper's experiments): a sweep is
+// two Jacobi half-sweeps, C-points then F-points on the way down and F then C
+// on the way up, each over the points of one class and seeing the update of
+// the other.  The relaxing passes then take the class of every real row
+// (cls, +1 C / -1 F) and the class `want` they relax; cls == nullptr is the
+// natural order (every real row relaxes).  Rows of the other class are copied
+// (and keep or clear their t entry as the pass's t mode says).
+//
 // No MFMA: every step is a sparse mat-vec or a vector update (HBM bound).
 #pragma once
 
@@ -93,6 +101,10 @@ __device__ __forceinline__ V sell_dot(const SellD<T> &M, int r, int sub, const V
   return acc;
 }
 
+__device__ __forceinline__ bool relaxes(const signed char *__restrict__ cls, int want, int i) {
+  return cls == nullptr || cls[i] == want;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -117,20 +129,20 @@ __device__ __forceinline__ double block_sum(double v) {
 // r = b - A x on the fine level of every problem (FP64; fine operators use one
 // lane per row), plus per-block partial sums of r^2.  Blocks never straddle two
 // problems (block table).  VC: also the V-cycle's first relaxation from zero,
-// e = r / d.
+// e = r / d (CF order: at C-points only, e = 0 at F-points).
 template <typename TR, bool VC>
 __global__ __launch_bounds__(BLOCK) void k_resid(SellD<double> A, const double *__restrict__ b,
                                                   const double *__restrict__ x, TR *__restrict__ r_out,
                                                   double *__restrict__ partial, const int *__restrict__ blk_row0,
                                                   const int *__restrict__ blk_row1, const double *__restrict__ dinv,
-                                                  double *__restrict__ e_out) {
+                                                  double *__restrict__ e_out, const signed char *__restrict__ cls) {
   const int blk = xcd_block();
   const int row = blk_row0[blk] + (int)threadIdx.x;
   double sq = 0.0;
   if (row < blk_row1[blk]) {
     const double r = b[row] - sell_dot<double, double, false>(A, row, 0, x);
     r_out[row] = (TR)r;
-    if (VC) e_out[row] = r * dinv[row];
+    if (VC) e_out[row] = relaxes(cls, 1, row) ? r * dinv[row] : 0.0;
     sq = r * r;
   }
   const double s = block_sum(sq);
@@ -186,14 +198,15 @@ __global__ __launch_bounds__(BLOCK) void k_patch(int n, double *__restrict__ x, 
 
 // ---------------------------------------------------------------- AlgFAC
 
-// Level 0, first cycle (u = 0): delta = f / d at real rows; ghosts set to 0.
+// Level 0, first cycle (u = 0): delta = f / d at real rows (CF order: at C
+// rows, 0 at F rows); ghosts set to 0.
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_relax_zero(int nr, int nb, const T *__restrict__ f,
                                                        const T *__restrict__ dinv, T *__restrict__ u_out,
-                                                       T *__restrict__ t) {
+                                                       T *__restrict__ t, const signed char *__restrict__ cls) {
   const int i = thread_id();
   if (i < nr) {
-    const T d = f[i] * dinv[i];
+    const T d = relaxes(cls, 1, i) ? f[i] * dinv[i] : T(0);
     u_out[i] = d;
     t[i] = d;
   } else if (i < nb) {
@@ -201,14 +214,17 @@ __global__ __launch_bounds__(BLOCK) void k_relax_zero(int nr, int nb, const T *_
   }
 }
 
-// l1-Jacobi sweep at rows [0, nr); rows [nr, nb) are copied.
-// tmode: 0 t = delta, 1 t += delta, 2 no t.
+// l1-Jacobi sweep at rows [0, nr) of class `want` (all of them when cls is
+// null); other rows of [0, nb) are copied.
+// tmode: 0 t = delta (t = 0 at real rows of the other class), 1 t += delta,
+// 2 no t.
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_relax(SellD<T> A, int nr, int nb, const T *__restrict__ f,
                                                   const T *__restrict__ dinv, const T *__restrict__ u_in,
-                                                  T *__restrict__ u_out, T *__restrict__ t, int tmode) {
+                                                  T *__restrict__ u_out, T *__restrict__ t, int tmode,
+                                                  const signed char *__restrict__ cls, int want) {
   const int th = thread_id(), i = th >> A.lg, sub = th & ((1 << A.lg) - 1);
-  if (i < nr) {
+  if (i < nr && relaxes(cls, want, i)) {
     const T d = (f[i] - sell_dot<T, T>(A, i, sub, u_in)) * dinv[i];
     if (sub == 0) {
       u_out[i] = u_in[i] + d;
@@ -217,6 +233,7 @@ __global__ __launch_bounds__(BLOCK) void k_relax(SellD<T> A, int nr, int nb, con
     }
   } else if (i < nb && sub == 0) {
     u_out[i] = u_in[i];
+    if (i < nr && tmode == 0) t[i] = T(0);
   }
 }
 
@@ -235,13 +252,14 @@ __global__ __launch_bounds__(BLOCK) void k_w(SellD<T> A, int nb, T *__restrict__
 // Level l >= 1, normal rows [0, nb): s = R_{l-1} w_{l-1} (stored for the next
 // w pass); at real rows [0, nr) the coarse residual recalculation
 // f <- (f - A u) - s (skipped in the first cycle, where u = 0), then u <- 0
-// and the first relaxation from zero delta = f / d; ghost rows get u = 0.
-// R and A of one level share the lane grouping.
+// and the first relaxation from zero delta = f / d (CF order: the C half,
+// delta = 0 at F rows); ghost rows get u = 0.  R and A of one level share the
+// lane grouping.
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_down(SellD<T> R, SellD<T> A, int nr, int nb, const T *__restrict__ w_prev,
                                                  T *__restrict__ sw, T *__restrict__ f, const T *__restrict__ dinv,
                                                  const T *__restrict__ u_in, T *__restrict__ u_out, T *__restrict__ t,
-                                                 int first) {
+                                                 int first, const signed char *__restrict__ cls) {
   const int th = thread_id(), i = th >> A.lg, sub = th & ((1 << A.lg) - 1);
   if (i >= nb) return;
   const T s = sell_dot<T, T>(R, i, sub, w_prev);
@@ -252,7 +270,7 @@ __global__ __launch_bounds__(BLOCK) void k_down(SellD<T> R, SellD<T> A, int nr, 
     if (sub == 0) {
       sw[i] = s;
       f[i] = fi;
-      const T d = fi * dinv[i];
+      const T d = relaxes(cls, 1, i) ? fi * dinv[i] : T(0);
       u_out[i] = d;
       t[i] = first ? d : t[i] + d;
     }
@@ -333,6 +351,7 @@ struct LevelDev {
   SellD<T> A, P, R;
   const T *dinv;
   T *u0, *u1, *t, *sw, *f;
+  const signed char *cls;  // C/F class of the real rows (CF order), or null
 };
 
 // Row ranges of one grid on one level (see the batched layout).
@@ -354,7 +373,9 @@ __device__ __forceinline__ int grid_row(const GridLevel &d, int j) {
 // results.  Buffer convention (kept by the level-synchronous path too): at
 // the start and end of every cycle a level's u lives in u0; the down pass
 // writes u1, interpolation updates u1, post-relaxation writes u0; the
-// coarsest solve writes both.
+// coarsest solve writes both.  CF order adds one half-sweep on each side: the
+// down pass writes u1 and its F half u0, interpolation updates u0, the up F
+// half writes u1 and the C half u0.
 template <typename T>
 __global__ __launch_bounds__(1024) void k_fac_tail(const LevelDev<T> *__restrict__ lv, const GridLevel *__restrict__ gl,
                                                     int nlev, const int *__restrict__ grids,
@@ -376,19 +397,18 @@ __global__ __launch_bounds__(1024) void k_fac_tail(const LevelDev<T> *__restrict
       if (l == 0) {
         for (int j = j0; j < nb; j += js) {
           const int i = grid_row(d, j);
-          if (j < d.nreal) {
-            if (first) {
-              if (sub == 0) {
-                const T dl = B.f[i] * B.dinv[i];
-                B.u1[i] = dl;
-                B.t[i] = dl;
-              }
-            } else {
-              const T dl = (B.f[i] - sell_dot<T, T, false>(B.A, i, sub, B.u0)) * B.dinv[i];
-              if (sub == 0) {
-                B.u1[i] = B.u0[i] + dl;
-                B.t[i] += dl;
-              }
+          const bool rc = j < d.nreal && relaxes(B.cls, 1, i);
+          if (j < d.nreal && first) {
+            if (sub == 0) {
+              const T dl = rc ? B.f[i] * B.dinv[i] : T(0);
+              B.u1[i] = dl;
+              B.t[i] = dl;
+            }
+          } else if (rc) {
+            const T dl = (B.f[i] - sell_dot<T, T, false>(B.A, i, sub, B.u0)) * B.dinv[i];
+            if (sub == 0) {
+              B.u1[i] = B.u0[i] + dl;
+              B.t[i] += dl;
             }
           } else if (sub == 0) {
             B.u1[i] = first ? T(0) : B.u0[i];
@@ -406,7 +426,7 @@ __global__ __launch_bounds__(1024) void k_fac_tail(const LevelDev<T> *__restrict
             if (sub == 0) {
               B.sw[i] = s;
               B.f[i] = fi;
-              const T dl = fi * B.dinv[i];
+              const T dl = relaxes(B.cls, 1, i) ? fi * B.dinv[i] : T(0);
               B.u1[i] = dl;
               B.t[i] = first ? dl : B.t[i] + dl;
             }
@@ -417,6 +437,22 @@ __global__ __launch_bounds__(1024) void k_fac_tail(const LevelDev<T> *__restrict
         }
       }
       __syncthreads();
+      if (B.cls) {
+        // F half of the CF sweep: u1 -> u0
+        for (int j = j0; j < nb; j += js) {
+          const int i = grid_row(d, j);
+          if (j < d.nreal && B.cls[i] == -1) {
+            const T dl = (B.f[i] - sell_dot<T, T, false>(B.A, i, sub, B.u1)) * B.dinv[i];
+            if (sub == 0) {
+              B.u0[i] = B.u1[i] + dl;
+              B.t[i] += dl;
+            }
+          } else if (sub == 0) {
+            B.u0[i] = B.u1[i];
+          }
+        }
+        __syncthreads();
+      }
       for (int j = j0; j < nb; j += js) {
         const int i = grid_row(d, j);
         const T at = sell_dot<T, T, false>(B.A, i, sub, B.t);
@@ -464,19 +500,38 @@ __global__ __launch_bounds__(1024) void k_fac_tail(const LevelDev<T> *__restrict
       const int nb = d.nreal + d.nghost;
       const int lg = B.A.lg, sub = tid & ((1 << lg) - 1), j0 = tid >> lg, js = nt >> lg;
       const T *uc = lv[l + 1].u0;
+      T *ucur = B.cls ? B.u0 : B.u1;
       for (int j = j0; j < nb; j += js) {
         const int i = grid_row(d, j);
         const T v = sell_dot<T, T, false>(B.P, i, sub, uc);
-        if (sub == 0) B.u1[i] += v;
+        if (sub == 0) ucur[i] += v;
       }
       __syncthreads();
+      if (B.cls) {
+        // F half (t = delta, cleared at C rows) u0 -> u1, then the C half below
+        for (int j = j0; j < nb; j += js) {
+          const int i = grid_row(d, j);
+          if (j < d.nreal && B.cls[i] == -1) {
+            const T dl = (B.f[i] - sell_dot<T, T, false>(B.A, i, sub, B.u0)) * B.dinv[i];
+            if (sub == 0) {
+              B.u1[i] = B.u0[i] + dl;
+              B.t[i] = dl;
+            }
+          } else if (sub == 0) {
+            B.u1[i] = B.u0[i];
+            if (j < d.nreal) B.t[i] = T(0);
+          }
+        }
+        __syncthreads();
+      }
       for (int j = j0; j < nb; j += js) {
         const int i = grid_row(d, j);
-        if (j < d.nreal) {
+        if (j < d.nreal && relaxes(B.cls, 1, i)) {
           const T dl = (B.f[i] - sell_dot<T, T, false>(B.A, i, sub, B.u1)) * B.dinv[i];
           if (sub == 0) {
             B.u0[i] = B.u1[i] + dl;
-            B.t[i] = dl;
+            if (B.cls) B.t[i] += dl;
+            else B.t[i] = dl;
           }
         } else if (sub == 0) {
           B.u0[i] = B.u1[i];
@@ -500,27 +555,33 @@ __global__ __launch_bounds__(BLOCK) void k_vresid(SellD<T> A, int n, const T *__
   }
 }
 
-// f = R q_prev, e = f / d (relaxation from zero) over rows [0, n).
+// f = R q_prev, e = f / d (relaxation from zero; CF order: the C half, e = 0
+// at F rows) over rows [0, n).
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_vdown(SellD<T> R, int n, const T *__restrict__ q_prev, T *__restrict__ f,
-                                                  const T *__restrict__ dinv, T *__restrict__ e) {
+                                                  const T *__restrict__ dinv, T *__restrict__ e,
+                                                  const signed char *__restrict__ cls) {
   const int th = thread_id(), i = th >> R.lg, sub = th & ((1 << R.lg) - 1);
   if (i < n) {
     const T fi = sell_dot<T, T>(R, i, sub, q_prev);
     if (sub == 0) {
       f[i] = fi;
-      e[i] = fi * dinv[i];
+      e[i] = relaxes(cls, 1, i) ? fi * dinv[i] : T(0);
     }
   }
 }
 
 // Level-0 post-relaxation fused with the iterate update:
-// x += e + (f - A e) / d  (fine operators use one lane per row).
+// x += e + (f - A e) / d  (fine operators use one lane per row; CF order: the
+// closing C half, x += e at F rows).
 __global__ __launch_bounds__(BLOCK) void k_vfinal(SellD<double> A, int n, const double *__restrict__ f,
                                                    const double *__restrict__ dinv, const double *__restrict__ e,
-                                                   double *__restrict__ x) {
+                                                   double *__restrict__ x, const signed char *__restrict__ cls) {
   const int i = thread_id();
-  if (i < n) x[i] += e[i] + (f[i] - sell_dot<double, double>(A, i, 0, e)) * dinv[i];
+  if (i < n) {
+    if (relaxes(cls, 1, i)) x[i] += e[i] + (f[i] - sell_dot<double, double>(A, i, 0, e)) * dinv[i];
+    else x[i] += e[i];
+  }
 }
 
 // ---------------------------------------------------------------- adjoint

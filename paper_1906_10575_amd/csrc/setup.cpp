@@ -868,9 +868,30 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
     B.GN = gn + gc;
     if ((long long)B.NB >= std::numeric_limits<int>::max() / 2) throw std::length_error("level too large");
   }
+  // CF ordering: position of every real row within its grid's real range,
+  // C-points first (each class in local order)
+  std::vector<std::vector<std::vector<int>>> rpos(maxL + 1);
+  if (S.cf) {
+    for (int l = 0; l <= maxL; ++l) rpos[l].resize(ng);
+    parallel_items(ng, [&](int g, int) {
+      const Hierarchy &H = S.probs[S.grids[g].prob].H;
+      for (int l = 0; l < H.L(); ++l) {
+        const CompLevel &lv = S.grids[g].lv[l];
+        std::vector<int> &pos = rpos[l][g];
+        pos.resize(lv.nreal);
+        int k = 0;
+        for (int pass = 0; pass < 2; ++pass)
+          for (int i = 0; i < lv.nreal; ++i)
+            if ((H.cf[l][lv.gid[i]] == 1) == (pass == 0)) pos[i] = k++;
+      }
+    });
+  }
   auto bidx = [&](int g, int l, int i) -> int {
     const CompLevel &lv = S.grids[g].lv[l];
-    if (roff[l][g] >= 0) return i < lv.nreal ? roff[l][g] + i : S.lv[l].NRn + goff[l][g] + (i - lv.nreal);
+    if (roff[l][g] >= 0) {
+      if (i < lv.nreal) return roff[l][g] + (S.cf ? rpos[l][g][i] : i);
+      return S.lv[l].NRn + goff[l][g] + (i - lv.nreal);
+    }
     return S.lv[l].NBn + coff[l][g] + i;
   };
   auto gbidx = [&](int q, int l, int i) -> int {
@@ -946,6 +967,21 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
     });
     B.nnzA_r = bA.nnz_rows(0, B.NRn);
     B.nnzA = bA.nnz_rows(0, B.NBn);
+    if (S.cf) {
+      B.cls.assign(B.NRn, 0);
+      for (int g : normal) {
+        const CompLevel &lv = S.grids[g].lv[l];
+        const Hierarchy &H = S.probs[S.grids[g].prob].H;
+        for (int i = 0; i < lv.nreal; ++i) {
+          const int8_t c = H.cf[l][lv.gid[i]];
+          B.cls[bidx(g, l, i)] = c;
+          if (c == 1) {
+            B.NRc++;
+            B.nnzA_c += lv.A.ptr[i + 1] - lv.A.ptr[i];
+          }
+        }
+      }
+    }
     B.nnzP = bP.nnz_rows(0, B.NBn);
     B.A = bA.take();
     B.P = bP.take();
@@ -1039,6 +1075,21 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
     });
     B.nnzGA_n = bGA.nnz_rows(0, B.GNn);
     B.nnzGA = bGA.nnz_rows(0, B.GN);
+    if (S.cf) {
+      B.gcls.assign(B.GNn, 0);
+      for (int q = 0; q < nprob; ++q) {
+        const Hierarchy &H = S.probs[q].H;
+        if (l >= H.L()) continue;
+        const int base = gbidx(q, l, 0);
+        for (int i = 0; i < H.A[l].nrows; ++i) {
+          B.gcls[base + i] = H.cf[l][i];
+          if (H.cf[l][i] == 1) {
+            B.GNc++;
+            B.nnzGA_c += H.A[l].ptr[i + 1] - H.A[l].ptr[i];
+          }
+        }
+      }
+    }
     B.nnzGP = bGP.nnz_rows(0, B.GNn);
     B.GA = bGA.take();
     B.GP = bGP.take();
@@ -1200,7 +1251,9 @@ int build_setup_hybrid(const std::vector<ProblemInput> &in, double theta, int ma
     if (st) return st;
     if ((st = setup_layouts(outer, false, err))) return st;
     const int nprob = (int)outer.probs.size();
+    const bool cf = outer.cf;
     inner = Setup();
+    inner.cf = cf;
     inner.theta = theta;
     inner.max_coarse = max_coarse;
     inner.max_levels = max_levels;

@@ -201,3 +201,21 @@ def test_hybrid_level_below_every_hierarchy():
     with pytest.raises(amgdd.AmgddError) as e:
         _host(p, hybrid_level=-1)
     assert e.value.status == amgdd.EINVAL
+
+
+def test_cf_handle_setup_and_parameter_check():
+    # CF ordering stores each grid's real rows C-points first internally; the
+    # composite sets reported through the ABI are those of the oracle
+    p = make_problem((40, 36), (3, 2), eta=2, k=np.exp(grf((40, 36), 1.0, 8.0, 3)))
+    s = _host(p, relax="cf")
+    H = amg.setup(p.A)
+    comps = composite.build_all(H, p.part, p.nparts, p.eta)
+    for q, cg in enumerate(comps):
+        for l, lv in enumerate(cg.levels):
+            g, nr, om = s.composite(0, q, l)
+            assert nr == lv.n_real and np.array_equal(g, lv.gid)
+    assert s.stats()["composite_overhead"] == _host(p).stats()["composite_overhead"]
+    with pytest.raises(ValueError):
+        _host(p, relax="gs")
+    prm = amgdd.default_params()
+    assert prm.relax_order == 0
