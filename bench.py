@@ -186,6 +186,61 @@ def run_steps(torch, s, b, steps, rtol, adjoint):
     return time.perf_counter() - t0, iters, x
 
 
+def sweep(torch, amgdd, cfg, args):
+    """The paper's parameter study (Section 6.1) at one-GPU scale: padding
+    eta x AlgFAC cycles per iteration x relaxation order (natural / CF
+    l1-Jacobi), each solved to the workload's tolerance from x0 = 0 in FP64.
+    Per configuration: iterations, asymptotic factor, time to tolerance,
+    composite overhead, and the paper's nnz cost proxy per iteration
+    (composite overhead x AlgFAC cycles, in units of the hierarchy's nnz)."""
+    import dataclasses
+    p0 = build_problem(cfg)
+    if isinstance(p0, list):
+        raise SystemExit("bench.py --sweep: single-problem workloads only")
+    rtol = RTOL[cfg]
+    b = torch.as_tensor(p0.b, device="cuda:0")
+    rows = []
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            x, info, st = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps, x, info, st
+
+    for relax in ("l1", "cf"):
+        for eta in [int(v) for v in args.sweep_eta.split(",")]:
+            p = dataclasses.replace(p0, eta=eta)
+            for nfac in [int(v) for v in args.sweep_nfac.split(",")]:
+                t0 = time.perf_counter()
+                s = amgdd.Solver(p.A, p.part, p.nparts, padding=eta, n_fac=nfac, relax=relax)
+                setup_s = time.perf_counter() - t0
+                ov = s.stats()["composite_overhead"]
+                dt, x, info, st = timed(lambda: s.solve(b, torch.zeros_like(b), rtol=rtol, maxit=300))
+                rec = {"solver": "amgdd", "relax": relax, "eta": eta, "n_fac": nfac, "iters": info.iters,
+                       "rho": round(info.rho_asym, 4), "time_to_tol_ms": round(dt * 1e3, 3),
+                       "ms_per_iter": round(dt * 1e3 / max(info.iters, 1), 4), "composite_overhead": round(ov, 4),
+                       "nnz_cost_per_iter": round(ov * nfac, 3), "status": st, "setup_s": round(setup_s, 2),
+                       "relres_fp64": residual_rel(p, x.cpu().numpy())}
+                rows.append(rec)
+                log(f"sweep {rec}")
+                s.close()
+            if eta == 1:
+                s = amgdd.Solver(p.A, p.part, p.nparts, padding=eta, n_fac=1, relax=relax)
+                dt, x, info, st = timed(lambda: s.vsolve(b, torch.zeros_like(b), rtol=rtol, maxit=400))
+                rec = {"solver": "vcycle", "relax": relax, "iters": info.iters, "rho": round(info.rho_asym, 4),
+                       "time_to_tol_ms": round(dt * 1e3, 3), "ms_per_iter": round(dt * 1e3 / max(info.iters, 1), 4),
+                       "status": st, "relres_fp64": residual_rel(p, x.cpu().numpy())}
+                rows.append(rec)
+                log(f"sweep {rec}")
+                s.close()
+            torch.cuda.empty_cache()
+    print(json.dumps({"sweep": cfg, "workload": WORKLOADS[cfg], "rtol": rtol, "precision": "fp64", "rows": rows}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -200,6 +255,11 @@ def main():
                     help="transition levels of the hybrid AMG-DD cycles timed beside the primary solve")
     ap.add_argument("--summarize-rocpd", metavar="DB", help="print a summary of a rocprofv3 kernel-trace database")
     ap.add_argument("--summarize-pmc", metavar="CSV", help="print a summary of rocprofv3 --pmc CSV output")
+    ap.add_argument("--sweep", action="store_true",
+                    help="parameter sweep on the workload instead of the benchmark line: padding x AlgFAC cycles x "
+                         "relaxation order, plus the V-cycle in both orders (one JSON line)")
+    ap.add_argument("--sweep-eta", default="1,2,3")
+    ap.add_argument("--sweep-nfac", default="1,2,4,10")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run 3 elementwise copies of 256 MiB (known HBM traffic, to scale PMC counters)")
     args = ap.parse_args()
@@ -217,6 +277,8 @@ def main():
     from paper_1906_10575_amd import amgdd
 
     cfg = args.config
+    if args.sweep:
+        return sweep(torch, amgdd, cfg, args)
     prec = PRIMARY[cfg]
     rtol = RTOL[cfg]
     adjoint = cfg in ("cfg4", "cfg5")

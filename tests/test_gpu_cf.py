@@ -147,3 +147,24 @@ def test_cf_batched_and_mixed():
     for i, pp in enumerate(probs):
         assert np.linalg.norm(pp.b - pp.A @ xg[off[i]:off[i + 1]]) <= 1e-8 * np.linalg.norm(pp.b)
     say(f"  mixed CF batch: {info.iters} iterations")
+
+
+@pytest.mark.parametrize("relax", ["l1", "cf"])
+@pytest.mark.parametrize("eta,n_fac", [(3, 4), (3, 10), (1, 10)])
+def test_sweep_parameters_match_oracle(relax, eta, n_fac):
+    # the corners of the padding / AlgFAC-cycle sweep, on a small 3D problem
+    p = make_problem((18, 18, 18), (3, 3, 2), eta=eta, n_fac=n_fac, k=np.exp(grf((18, 18, 18), 1.0, 8.0, 6)))
+    say("sweep corner", relax, "eta", eta, "n_fac", n_fac, p.n)
+    H = amg.setup(p.A)
+    comps = composite.build_all(H, p.part, p.nparts, eta)
+    s = amgdd.Solver(p.A, p.part, p.nparts, padding=eta, n_fac=n_fac, relax=relax)
+    b = _t(p.b)
+    x = torch.zeros_like(b)
+    xo = np.zeros(p.n)
+    coarse = cycles.CoarseSolver(H.A[H.L])
+    for k in range(3):
+        x, info, st = s.solve(b, x, rtol=0, maxit=1)
+        xo = cycles.amgdd_iteration(H, comps, p.b, xo, n_fac, coarse, relax=relax)
+        err = _rel(_np(x), xo)
+        assert err <= 1e-12, (k, err)
+    say(f"  last rel err {err:.3e}")
