@@ -61,23 +61,34 @@ struct ProblemHost {
 //   sptr[r / (64/G)] + 64*(k / G) + (r % (64/G))*G + k % G;
 // a slice has (sptr[s+1]-sptr[s]) / 64 steps; rows shorter than the slice are
 // padded with value 0 and a column of the same grid.
+//
+// Compressed column indices (used when every slice fits): per slice two int32
+// bases b0 = base[2s], b1 = base[2s+1] and one 16-bit word per entry,
+//   column = (c16 & 0x8000 ? b1 : b0) + (c16 & 0x7fff),
+// i.e. each slice's columns lie in at most two windows of 32768 (a grid's
+// real rows and its ghost rows sit in different regions of the level).  col
+// is then emptied.
 struct Sell {
   int nrows = 0;
   int lg = 0;
   std::vector<int> sptr;
   std::vector<int> col;
   std::vector<double> val;
+  std::vector<uint16_t> col16;
+  std::vector<int> base;
   long long entries() const { return sptr.empty() ? 0 : sptr.back(); }
+  bool compressed() const { return !col16.empty(); }
 };
 
 // Block-diagonal batched layout of one level, over every composite grid
 // (and, for the G* members, over every problem's global level).
-//   composite rows: [normal-grid real rows | normal-grid ghost rows | coarse-grid rows]
+//   composite rows: [normal-grid real rows | gap to a multiple of 64 | normal-grid ghost rows | coarse-grid rows]
 //   (with CF ordering, each grid's real rows are C rows then F rows)
 //   "normal" grids are those whose problem has L > l; "coarse" grids have L == l.
 //   global rows:    [normal problems | coarse problems]
 struct BatchLevel {
   int NRn = 0, NBn = 0, NB = 0;
+  int NRa = 0;                     // first ghost row: NRn rounded up to 64 (rows between belong to no grid)
   int lg = 0, glg = 0;             // lanes per row (log2) of composite / global rows of this level
   Sell A;                          // rows [0, NBn)
   Sell P;                          // rows [0, NBn) -> level l+1 composite rows
@@ -115,6 +126,8 @@ struct Setup {
   // depend on row order, so results are the same; the half-sweeps then read
   // contiguous row ranges)
   bool cf = false;
+  // 16-bit column indices for every matrix whose slices allow them
+  bool compress = true;
   std::vector<ProblemHost> probs;
   std::vector<CompGrid> grids;
   std::vector<BatchLevel> lv;      // 0..maxL

@@ -21,6 +21,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -57,12 +58,14 @@ struct DSell {
   int *sptr = nullptr;
   int *col = nullptr;
   void *val = nullptr;  // double or float
+  unsigned short *col16 = nullptr;  // 16-bit columns (then col is null)
+  int *base = nullptr;              // two bases per slice
   int nrows = 0;
   int lg = 0;           // lanes per row (log2)
   long long entries = 0;
   template <typename T>
   dev::SellD<T> as() const {
-    return dev::SellD<T>{sptr, col, (const T *)val, lg};
+    return dev::SellD<T>{sptr, col, (const T *)val, lg, col16, base};
   }
 };
 
@@ -206,7 +209,12 @@ struct amgdd_ctx {
     d.entries = s.entries();
     amgdd_status st = upload(&d.sptr, s.sptr.data(), s.sptr.size());
     if (st) return st;
-    if ((st = upload(&d.col, s.col.data(), s.col.size()))) return st;
+    if (s.compressed()) {
+      if ((st = upload(&d.col16, (const unsigned short *)s.col16.data(), s.col16.size()))) return st;
+      if ((st = upload(&d.base, s.base.data(), s.base.size()))) return st;
+    } else if ((st = upload(&d.col, s.col.data(), s.col.size()))) {
+      return st;
+    }
     return upload_vals(&d.val, s.val, as_float);
   }
 
@@ -236,6 +244,10 @@ struct amgdd_ctx {
 namespace {
 
 inline int nblocks(long long n) { return (int)((n + dev::BLOCK - 1) / dev::BLOCK); }
+
+// Algorithmic bytes of one stored matrix entry: its value (w bytes) and its
+// column index (2 bytes when the layout holds 16-bit columns, else 4).
+inline double ent(const DSell &M, double w) { return w + (M.col16 ? 2.0 : 4.0); }
 
 // ---------------------------------------------------------------- upload
 
@@ -422,10 +434,10 @@ template <typename T>
 void enqueue_residual(amgdd_ctx *h, hipStream_t s, bool vc) {
   DLevel &D0 = h->L[0];
   if (vc)
-    PLAUNCH(h, "resid_v", 0, D0.nnzGA * 12.0 + h->N0 * 40.0, (dev::k_resid<double, true>), h->nblk, dev::BLOCK, 0, s, D0.GA.as<double>(), h->b, h->x, D0.vf, h->partial,
+    PLAUNCH(h, "resid_v", 0, D0.nnzGA * ent(D0.GA, 8.0) + h->N0 * 40.0, (dev::k_resid<double, true>), h->nblk, dev::BLOCK, 0, s, D0.GA.as<double>(), h->b, h->x, D0.vf, h->partial,
            h->blk_row0, h->blk_row1, D0.gdinv, D0.ve[0], (const signed char *)D0.gcls);
   else
-    PLAUNCH(h, "resid", 0, D0.nnzGA * 12.0 + h->N0 * (16.0 + sizeof(T)), (dev::k_resid<T, false>), h->nblk, dev::BLOCK, 0, s, D0.GA.as<double>(), h->b, h->x, (T *)D0.rt,
+    PLAUNCH(h, "resid", 0, D0.nnzGA * ent(D0.GA, 8.0) + h->N0 * (16.0 + sizeof(T)), (dev::k_resid<T, false>), h->nblk, dev::BLOCK, 0, s, D0.GA.as<double>(), h->b, h->x, (T *)D0.rt,
            h->partial, h->blk_row0, h->blk_row1, (const double *)nullptr, (double *)nullptr, (const signed char *)nullptr);
   PLAUNCH(h, "norm", 0, h->nblk * 8.0, dev::k_norm_final, h->nprob, dev::BLOCK, 0, s, h->partial, h->prob_blk0, h->norm2);
   (void)hipMemcpyAsync(h->h_norm2, h->norm2, (size_t)h->nprob * sizeof(double), hipMemcpyDeviceToHost, s);
@@ -446,13 +458,13 @@ void enqueue_fac_down(amgdd_ctx *h, hipStream_t s, int *cur, int l, int first) {
       PLAUNCH(h, "relax0", 0, nrc * 4.0 * w + (B.NBn - nrc) * w + (cf ? B.NRn : 0), dev::k_relax_zero<T>, nblocks(B.NBn), dev::BLOCK, 0, s, B.NRn, B.NBn, (const T *)B.f,
              (const T *)B.dinv, uout, (T *)B.t, (const signed char *)B.cls);
     else
-      PLAUNCH(h, "relax_pre", 0, nzc * (w + 4.0) + nrc * 4.0 * w + B.NBn * 2.0 * w + (cf ? B.NRn : 0), dev::k_relax<T>, nblocks((long long)B.NBn << B.lg), dev::BLOCK, 0, s, B.A.as<T>(), B.NRn, B.NBn, (const T *)B.f,
+      PLAUNCH(h, "relax_pre", 0, nzc * ent(B.A, w) + nrc * 4.0 * w + B.NBn * 2.0 * w + (cf ? B.NRn : 0), dev::k_relax<T>, nblocks((long long)B.NBn << B.lg), dev::BLOCK, 0, s, B.A.as<T>(), B.NRn, B.NBn, (const T *)B.f,
              (const T *)B.dinv, (const T *)uin, uout, (T *)B.t, 1, (const signed char *)B.cls, 1);
   } else {
     DLevel &Bp = h->L[l - 1];
-    PLAUNCH(h, "down", l, B.nnzR_n * (w + 4.0) + Bp.NBn * w + B.NBn * 2.0 * w + (first ? 0.0 : B.nnzA_r * (w + 4.0) + B.NBn * w) + B.NRn * (first ? 4.0 : 5.0) * w + (cf ? B.NRn : 0), dev::k_down<T>, nblocks((long long)B.NBn << B.lg), dev::BLOCK, 0, s, B.R.as<T>(), B.A.as<T>(), B.NRn, B.NBn,
+    PLAUNCH(h, "down", l, B.nnzR_n * ent(B.R, w) + Bp.NBn * w + B.NBn * 2.0 * w + (first ? 0.0 : B.nnzA_r * ent(B.A, w) + B.NBn * w) + B.NRn * (first ? 4.0 : 5.0) * w + (cf ? B.NRn : 0), dev::k_down<T>, nblocks((long long)B.NBn << B.lg), dev::BLOCK, 0, s, B.R.as<T>(), B.A.as<T>(), B.NRn, B.NBn,
            (const T *)Bp.sw, (T *)B.sw, (T *)B.f, (const T *)B.dinv, (const T *)uin, uout, (T *)B.t, first, (const signed char *)B.cls);
-    PLAUNCH(h, "coarse", l, (B.nnzR - B.nnzR_n) * (w + 4.0) + (B.NB - B.NBn) * 3.0 * w, dev::k_coarse<T>, B.ncg, dev::BLOCK, 2 * B.cg_maxn * sizeof(double), s, B.R.as<T>(), 1,
+    PLAUNCH(h, "coarse", l, (B.nnzR - B.nnzR_n) * ent(B.R, w) + (B.NB - B.NBn) * 3.0 * w, dev::k_coarse<T>, B.ncg, dev::BLOCK, 2 * B.cg_maxn * sizeof(double), s, B.R.as<T>(), 1,
            (const T *)Bp.sw, (T *)B.f, (const T *)uin, uout, h->dense_A, h->dense_inv, B.cg_row0, B.cg_n,
            B.cg_dense, 0, first, uin);
   }
@@ -462,12 +474,12 @@ void enqueue_fac_down(amgdd_ctx *h, hipStream_t s, int *cur, int l, int first) {
     // this level keep their solve, copied along)
     const int nrf = B.NRn - B.NRc;
     T *ui = (T *)B.u[cur[l]], *uo = (T *)B.u[cur[l] ^ 1];
-    PLAUNCH(h, "relax_f", l, (B.nnzA_r - B.nnzA_c) * (w + 4.0) + nrf * 4.0 * w + B.NB * 2.0 * w + B.NRn, dev::k_relax<T>, nblocks((long long)B.NB << B.lg), dev::BLOCK, 0, s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
+    PLAUNCH(h, "relax_f", l, (B.nnzA_r - B.nnzA_c) * ent(B.A, w) + nrf * 4.0 * w + B.NB * 2.0 * w + B.NRn, dev::k_relax<T>, nblocks((long long)B.NB << B.lg), dev::BLOCK, 0, s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
             (const T *)B.dinv, (const T *)ui, uo, (T *)B.t, 1, (const signed char *)B.cls, -1);
     cur[l] ^= 1;
   }
   if (B.NBn > 0 && l < maxL)
-    PLAUNCH(h, "w", l, B.nnzA * (w + 4.0) + B.NBn * (l > 0 ? 3.0 : 2.0) * w, dev::k_w<T>, nblocks((long long)B.NBn << B.lg), dev::BLOCK, 0, s, B.A.as<T>(), B.NBn, (T *)B.sw, (const T *)B.t, l > 0);
+    PLAUNCH(h, "w", l, B.nnzA * ent(B.A, w) + B.NBn * (l > 0 ? 3.0 : 2.0) * w, dev::k_w<T>, nblocks((long long)B.NBn << B.lg), dev::BLOCK, 0, s, B.A.as<T>(), B.NBn, (T *)B.sw, (const T *)B.t, l > 0);
 }
 
 template <typename T>
@@ -476,17 +488,17 @@ void enqueue_fac_up(amgdd_ctx *h, hipStream_t s, int *cur, int l) {
   DLevel &B = h->L[l];
   if (B.NBn == 0) return;
   DLevel &Bc = h->L[l + 1];
-  PLAUNCH(h, "interp", l, B.nnzP * (w + 4.0) + B.NBn * 2.0 * w + Bc.NB * w, dev::k_interp<T>, nblocks((long long)B.NBn << B.lg), dev::BLOCK, 0, s, B.P.as<T>(), B.NBn, (T *)B.u[cur[l]],
+  PLAUNCH(h, "interp", l, B.nnzP * ent(B.P, w) + B.NBn * 2.0 * w + Bc.NB * w, dev::k_interp<T>, nblocks((long long)B.NBn << B.lg), dev::BLOCK, 0, s, B.P.as<T>(), B.NBn, (T *)B.u[cur[l]],
          (const T *)Bc.u[cur[l + 1]]);
   if (B.cls) {
     const int nrf = B.NRn - B.NRc;
-    PLAUNCH(h, "relax_post_f", l, (B.nnzA_r - B.nnzA_c) * (w + 4.0) + nrf * 3.0 * w + B.NRc * w + B.NB * 2.0 * w + B.NRn, dev::k_relax<T>, nblocks((long long)B.NB << B.lg), dev::BLOCK, 0, s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
+    PLAUNCH(h, "relax_post_f", l, (B.nnzA_r - B.nnzA_c) * ent(B.A, w) + nrf * 3.0 * w + B.NRc * w + B.NB * 2.0 * w + B.NRn, dev::k_relax<T>, nblocks((long long)B.NB << B.lg), dev::BLOCK, 0, s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
             (const T *)B.dinv, (const T *)B.u[cur[l]], (T *)B.u[cur[l] ^ 1], (T *)B.t, 0, (const signed char *)B.cls, -1);
     cur[l] ^= 1;
-    PLAUNCH(h, "relax_post_c", l, B.nnzA_c * (w + 4.0) + B.NRc * 4.0 * w + B.NB * 2.0 * w + B.NRn, dev::k_relax<T>, nblocks((long long)B.NB << B.lg), dev::BLOCK, 0, s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
+    PLAUNCH(h, "relax_post_c", l, B.nnzA_c * ent(B.A, w) + B.NRc * 4.0 * w + B.NB * 2.0 * w + B.NRn, dev::k_relax<T>, nblocks((long long)B.NB << B.lg), dev::BLOCK, 0, s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
             (const T *)B.dinv, (const T *)B.u[cur[l]], (T *)B.u[cur[l] ^ 1], (T *)B.t, 1, (const signed char *)B.cls, 1);
   } else {
-    PLAUNCH(h, "relax_post", l, B.nnzA_r * (w + 4.0) + B.NRn * 3.0 * w + B.NB * 2.0 * w, dev::k_relax<T>, nblocks((long long)B.NB << B.lg), dev::BLOCK, 0, s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
+    PLAUNCH(h, "relax_post", l, B.nnzA_r * ent(B.A, w) + B.NRn * 3.0 * w + B.NB * 2.0 * w, dev::k_relax<T>, nblocks((long long)B.NB << B.lg), dev::BLOCK, 0, s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
            (const T *)B.dinv, (const T *)B.u[cur[l]], (T *)B.u[cur[l] ^ 1], (T *)B.t, 0, (const signed char *)nullptr, 1);
   }
   cur[l] ^= 1;
@@ -500,14 +512,14 @@ double tail_bytes(amgdd_ctx *h, int lt, int first) {
   const int maxL = (int)h->L.size() - 1;
   for (int l = lt; l <= maxL; ++l) {
     DLevel &B = h->L[l];
-    if (l == 0) b += first ? B.NRn * 4.0 * w + (B.NBn - B.NRn) * w : B.nnzA_r * (w + 4.0) + B.NRn * 4.0 * w + B.NBn * 2.0 * w;
-    else b += B.nnzR * (w + 4.0) + h->L[l - 1].NBn * w + B.NBn * 2.0 * w + (first ? 0.0 : B.nnzA_r * (w + 4.0) + B.NBn * w) + B.NRn * (first ? 4.0 : 5.0) * w;
+    if (l == 0) b += first ? B.NRn * 4.0 * w + (B.NBn - B.NRn) * w : B.nnzA_r * ent(B.A, w) + B.NRn * 4.0 * w + B.NBn * 2.0 * w;
+    else b += B.nnzR * ent(B.R, w) + h->L[l - 1].NBn * w + B.NBn * 2.0 * w + (first ? 0.0 : B.nnzA_r * ent(B.A, w) + B.NBn * w) + B.NRn * (first ? 4.0 : 5.0) * w;
     if (l < maxL) {
-      b += B.nnzA * (w + 4.0) + B.NBn * (l > 0 ? 3.0 : 2.0) * w;
-      b += B.nnzP * (w + 4.0) + B.NBn * 2.0 * w + h->L[l + 1].NB * w;
-      b += B.nnzA_r * (w + 4.0) + B.NRn * 3.0 * w + B.NB * 2.0 * w;
+      b += B.nnzA * ent(B.A, w) + B.NBn * (l > 0 ? 3.0 : 2.0) * w;
+      b += B.nnzP * ent(B.P, w) + B.NBn * 2.0 * w + h->L[l + 1].NB * w;
+      b += B.nnzA_r * ent(B.A, w) + B.NRn * 3.0 * w + B.NB * 2.0 * w;
       // CF order: the extra half-sweeps re-read and re-write the vectors
-      if (B.cls) b += 2.0 * (B.NBn * 2.0 * w + B.NRn) + (B.nnzA_r - B.nnzA_c) * (w + 4.0);
+      if (B.cls) b += 2.0 * (B.NBn * 2.0 * w + B.NRn) + (B.nnzA_r - B.nnzA_c) * ent(B.A, w);
     }
   }
   return b;
@@ -552,7 +564,7 @@ void enqueue_dd_core(amgdd_ctx *h, hipStream_t s, double *x, bool assign) {
   const int maxL = (int)h->L.size() - 1;
   for (int l = 1; l <= maxL; ++l) {
     DLevel &B = h->L[l];
-    PLAUNCH(h, "restrict", l, B.nnzGR * (sizeof(T) + 4.0) + (h->L[l - 1].GN + B.GN) * (double)sizeof(T), dev::k_spmv<T>, nblocks((long long)B.GN << B.glg), dev::BLOCK, 0, s, B.GRt.as<T>(), B.GN, (const T *)h->L[l - 1].rt, (T *)B.rt);
+    PLAUNCH(h, "restrict", l, B.nnzGR * ent(B.GRt, sizeof(T)) + (h->L[l - 1].GN + B.GN) * (double)sizeof(T), dev::k_spmv<T>, nblocks((long long)B.GN << B.glg), dev::BLOCK, 0, s, B.GRt.as<T>(), B.GN, (const T *)h->L[l - 1].rt, (T *)B.rt);
   }
   PLAUNCH(h, "gather", 0, h->f_total * 4.0 + h->S.composite_real_rows * 2.0 * sizeof(T), dev::k_gather<T>, nblocks(h->f_total), dev::BLOCK, 0, s, (int)h->f_total, h->gather_src,
          (const T *)h->r_arena, (T *)h->f_arena);
@@ -584,7 +596,7 @@ void enqueue_v_relax(amgdd_ctx *h, hipStream_t s, int *cur, int l, int want, con
   DLevel &B = h->L[l];
   const double nz = want == 1 ? (double)B.nnzGA_c : (double)(B.nnzGA_n - B.nnzGA_c);
   const double nr = want == 1 ? B.GNc : B.GNn - B.GNc;
-  PLAUNCH(h, name, l, nz * 12.0 + nr * 16.0 + B.GN * 16.0 + B.GNn, dev::k_relax<double>, nblocks((long long)B.GN << B.glg), dev::BLOCK, 0, s, B.GA.as<double>(), B.GNn, B.GN, B.vf, B.gdinv,
+  PLAUNCH(h, name, l, nz * ent(B.GA, 8.0) + nr * 16.0 + B.GN * 16.0 + B.GNn, dev::k_relax<double>, nblocks((long long)B.GN << B.glg), dev::BLOCK, 0, s, B.GA.as<double>(), B.GNn, B.GN, B.vf, B.gdinv,
           B.ve[cur[l]], B.ve[cur[l] ^ 1], (double *)nullptr, 2, (const signed char *)B.gcls, want);
   cur[l] ^= 1;
 }
@@ -597,14 +609,14 @@ void enqueue_v_down(amgdd_ctx *h, hipStream_t s, int *cur, int lv, bool hyb) {
     DLevel &B = h->L[l];
     DLevel &Bc = h->L[l + 1];
     if (B.GNn == 0) continue;
-    PLAUNCH(h, "vresid", l, B.nnzGA_n * 12.0 + B.GN * 8.0 + B.GNn * 16.0, dev::k_vresid<double>, nblocks((long long)B.GNn << B.glg), dev::BLOCK, 0, s, B.GA.as<double>(), B.GNn, B.vf, B.ve[cur[l]], B.vq);
+    PLAUNCH(h, "vresid", l, B.nnzGA_n * ent(B.GA, 8.0) + B.GN * 8.0 + B.GNn * 16.0, dev::k_vresid<double>, nblocks((long long)B.GNn << B.glg), dev::BLOCK, 0, s, B.GA.as<double>(), B.GNn, B.vf, B.ve[cur[l]], B.vq);
     if (hyb && l + 1 == lv)
-      PLAUNCH(h, "hrestrict", l + 1, Bc.nnzGR_n * 12.0 + B.GNn * 8.0 + Bc.GNn * (double)sizeof(T), (dev::k_spmv<double, T>), nblocks((long long)Bc.GNn << Bc.glg), dev::BLOCK, 0, s, Bc.GRd.as<double>(), Bc.GNn,
+      PLAUNCH(h, "hrestrict", l + 1, Bc.nnzGR_n * ent(Bc.GRd, 8.0) + B.GNn * 8.0 + Bc.GNn * (double)sizeof(T), (dev::k_spmv<double, T>), nblocks((long long)Bc.GNn << Bc.glg), dev::BLOCK, 0, s, Bc.GRd.as<double>(), Bc.GNn,
               (const double *)B.vq, (T *)h->inner->L[0].rt);
     else
-      PLAUNCH(h, "vdown", l + 1, Bc.nnzGR_n * 12.0 + B.GNn * 8.0 + Bc.GNn * 24.0 + (cf ? Bc.GNn : 0), dev::k_vdown<double>, nblocks((long long)Bc.GNn << Bc.glg), dev::BLOCK, 0, s, Bc.GRd.as<double>(), Bc.GNn, B.vq, Bc.vf,
+      PLAUNCH(h, "vdown", l + 1, Bc.nnzGR_n * ent(Bc.GRd, 8.0) + B.GNn * 8.0 + Bc.GNn * 24.0 + (cf ? Bc.GNn : 0), dev::k_vdown<double>, nblocks((long long)Bc.GNn << Bc.glg), dev::BLOCK, 0, s, Bc.GRd.as<double>(), Bc.GNn, B.vq, Bc.vf,
              Bc.gdinv, Bc.ve[cur[l + 1]], (const signed char *)Bc.gcls);
-    PLAUNCH(h, "vcoarse", l + 1, (Bc.nnzGR - Bc.nnzGR_n) * 12.0 + (Bc.GN - Bc.GNn) * 16.0, dev::k_coarse<double>, Bc.ngc, dev::BLOCK, 2 * Bc.gc_maxn * sizeof(double), s, Bc.GRd.as<double>(), 1, B.vq,
+    PLAUNCH(h, "vcoarse", l + 1, (Bc.nnzGR - Bc.nnzGR_n) * ent(Bc.GRd, 8.0) + (Bc.GN - Bc.GNn) * 16.0, dev::k_coarse<double>, Bc.ngc, dev::BLOCK, 2 * Bc.gc_maxn * sizeof(double), s, Bc.GRd.as<double>(), 1, B.vq,
            Bc.vf, Bc.ve[cur[l + 1]], Bc.ve[cur[l + 1]], h->dense_A, h->dense_inv, Bc.gc_row0, Bc.gc_n, Bc.gc_dense, 1,
            1, (double *)nullptr);
     if (cf && !(hyb && l + 1 == lv) && Bc.GNn > 0) enqueue_v_relax(h, s, cur, l + 1, -1, "vrelax_f");
@@ -618,7 +630,7 @@ void enqueue_v_up(amgdd_ctx *h, hipStream_t s, int *cur, int lv) {
     DLevel &B = h->L[l];
     DLevel &Bc = h->L[l + 1];
     if (B.GNn == 0) continue;
-    PLAUNCH(h, "vinterp", l, B.nnzGP * 12.0 + B.GNn * 16.0 + Bc.GN * 8.0, dev::k_interp<double>, nblocks((long long)B.GNn << B.glg), dev::BLOCK, 0, s, B.GP.as<double>(), B.GNn, B.ve[cur[l]],
+    PLAUNCH(h, "vinterp", l, B.nnzGP * ent(B.GP, 8.0) + B.GNn * 16.0 + Bc.GN * 8.0, dev::k_interp<double>, nblocks((long long)B.GNn << B.glg), dev::BLOCK, 0, s, B.GP.as<double>(), B.GNn, B.ve[cur[l]],
            Bc.ve[cur[l + 1]]);
     const bool cf = B.gcls != nullptr;
     if (cf) enqueue_v_relax(h, s, cur, l, -1, "vrelax_fu");
@@ -626,12 +638,12 @@ void enqueue_v_up(amgdd_ctx *h, hipStream_t s, int *cur, int lv) {
       if (cf) {
         enqueue_v_relax(h, s, cur, l, 1, "vrelax_cu");
       } else {
-        PLAUNCH(h, "vrelax", l, B.nnzGA_n * 12.0 + B.GNn * 16.0 + B.GN * 16.0, dev::k_relax<double>, nblocks((long long)B.GN << B.glg), dev::BLOCK, 0, s, B.GA.as<double>(), B.GNn, B.GN, B.vf, B.gdinv,
+        PLAUNCH(h, "vrelax", l, B.nnzGA_n * ent(B.GA, 8.0) + B.GNn * 16.0 + B.GN * 16.0, dev::k_relax<double>, nblocks((long long)B.GN << B.glg), dev::BLOCK, 0, s, B.GA.as<double>(), B.GNn, B.GN, B.vf, B.gdinv,
                B.ve[cur[l]], B.ve[cur[l] ^ 1], (double *)nullptr, 2, (const signed char *)nullptr, 1);
         cur[l] ^= 1;
       }
     } else {
-      PLAUNCH(h, "vfinal", 0, (cf ? B.nnzGA_c : B.nnzGA_n) * 12.0 + B.GNn * 40.0 + (cf ? B.GNn : 0), dev::k_vfinal, nblocks(B.GNn), dev::BLOCK, 0, s, B.GA.as<double>(), B.GNn, B.vf, B.gdinv, B.ve[cur[0]],
+      PLAUNCH(h, "vfinal", 0, (cf ? B.nnzGA_c : B.nnzGA_n) * ent(B.GA, 8.0) + B.GNn * 40.0 + (cf ? B.GNn : 0), dev::k_vfinal, nblocks(B.GNn), dev::BLOCK, 0, s, B.GA.as<double>(), B.GNn, B.vf, B.gdinv, B.ve[cur[0]],
              h->x, (const signed char *)B.gcls);
     }
   }
@@ -871,6 +883,8 @@ amgdd_status make_handle(const std::vector<ProblemInput> &in, const amgdd_params
     return fail(ST_EINVAL, "relax_order must be 0 (natural) or 1 (CF)");
   }
   h->S.cf = p.relax_order == 1;
+  // debugging / measurement: keep int32 column indices everywhere
+  h->S.compress = std::getenv("AMGDD_INDEX32") == nullptr;
   std::string err;
   Setup inner_S;
   int st = p.hybrid_level > 0 ? build_setup_hybrid(in, p.theta, p.max_coarse, p.max_levels, p.hybrid_level, h->S, inner_S,

@@ -1,7 +1,8 @@
 // CDNA4 (gfx950) kernels of the AMG-DD solve phase.
 //
 // Every matrix is a block-diagonal batch over all composite grids (or over
-// all problems for the global hierarchy) stored as *grouped sliced ELL*: each
+// all problems for the global hierarchy) stored as *grouped sliced ELL* (with
+// 16-bit column indices where each slice's columns fit two 32K windows): each
 // row is served by G = 2^lg lanes (G = 1 on levels with short rows, up to 16
 // on coarse levels whose Galerkin rows hold ~100 entries); one 64-lane
 // wavefront owns one slice of 64/G rows, and step k of the slice stores, for
@@ -45,12 +46,17 @@ namespace dev {
 constexpr int BLOCK = 256;
 constexpr int NXCD = 8;
 
+// Column indices are int32 (col) or, when every slice allows it, 16-bit
+// (col16) relative to one of two per-slice bases:
+//   column = (c16 & 0x8000 ? base[2s+1] : base[2s]) + (c16 & 0x7fff).
 template <typename T>
 struct SellD {
   const int *sptr;
   const int *col;
   const T *val;
   int lg;  // lanes per row G = 1 << lg
+  const unsigned short *col16;
+  const int *base;
 };
 
 // Workgroups are dispatched round-robin over the 8 XCDs; remap so that each
@@ -77,13 +83,33 @@ __device__ __forceinline__ V sell_dot(const SellD<T> &M, int r, int sub, const V
   const int beg = M.sptr[s];
   const int w = (M.sptr[s + 1] - beg) >> 6;
   const int off = beg + ((r & ((64 >> lg) - 1)) << lg) + sub;
-  const int *__restrict__ c = M.col + off;
   const T *__restrict__ v = M.val + off;
   // The matrix streams are read once per pass: non-temporal loads keep them
   // from evicting the gathered vector from L2 / MALL.  Four entries in flight
   // per lane; the sum stays in storage order.
   V acc = V(0);
   int k = 0;
+  if (M.col16) {
+    const unsigned short *__restrict__ c = M.col16 + off;
+    const int b0 = M.base[2 * s], b1 = M.base[2 * s + 1];
+    auto dec = [&](unsigned short q) { return ((q & 0x8000) ? b1 : b0) + (int)(q & 0x7fff); };
+    for (; k + 4 <= w; k += 4) {
+      const int c0 = dec(__builtin_nontemporal_load(c + 64 * k)), c1 = dec(__builtin_nontemporal_load(c + 64 * (k + 1)));
+      const int c2 = dec(__builtin_nontemporal_load(c + 64 * (k + 2))), c3 = dec(__builtin_nontemporal_load(c + 64 * (k + 3)));
+      const V v0 = (V)__builtin_nontemporal_load(v + 64 * k), v1 = (V)__builtin_nontemporal_load(v + 64 * (k + 1));
+      const V v2 = (V)__builtin_nontemporal_load(v + 64 * (k + 2)), v3 = (V)__builtin_nontemporal_load(v + 64 * (k + 3));
+      const V x0 = x[c0], x1 = x[c1], x2 = x[c2], x3 = x[c3];
+      acc = fma(v0, x0, acc);
+      acc = fma(v1, x1, acc);
+      acc = fma(v2, x2, acc);
+      acc = fma(v3, x3, acc);
+    }
+    for (; k < w; ++k)
+      acc = fma((V)__builtin_nontemporal_load(v + 64 * k), x[dec(__builtin_nontemporal_load(c + 64 * k))], acc);
+    for (int o = (1 << lg) >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    return acc;
+  }
+  const int *__restrict__ c = M.col + off;
   for (; k + 4 <= w; k += 4) {
     const int c0 = __builtin_nontemporal_load(c + 64 * k), c1 = __builtin_nontemporal_load(c + 64 * (k + 1));
     const int c2 = __builtin_nontemporal_load(c + 64 * (k + 2)), c3 = __builtin_nontemporal_load(c + 64 * (k + 3));

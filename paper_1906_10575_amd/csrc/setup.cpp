@@ -215,8 +215,11 @@ bool sell_block_diagonal(const Sell &S, const std::vector<int> &row_owner, const
       for (int lane = 0; lane < 64; ++lane) {
         const int r = (int)sl * rs + (lane >> S.lg);
         if (r >= S.nrows) break;
-        for (int k = 0; k < w; ++k)
-          if (col_owner[S.col[(size_t)base + 64 * k + lane]] != row_owner[r]) { ok = false; return; }
+        for (int k = 0; k < w; ++k) {
+          const size_t a = (size_t)base + 64 * k + lane;
+          // rows of no grid (alignment gaps) hold zeros only
+          if (row_owner[r] < 0 ? S.val[a] != 0.0 : col_owner[S.col[a]] != row_owner[r]) { ok = false; return; }
+        }
       }
     }
   }, 256);
@@ -295,6 +298,94 @@ struct SellBuilder {
     return std::move(S);
   }
 };
+
+// 16-bit column compression of a checked block-diagonal layout (see Sell).
+// Per slice, the columns of its nonzero entries are split at their largest gap
+// into two windows of at most 32768 columns (one window of 65536 when they
+// span no more).  Zero-valued entries (padding, explicit symbolic zeros)
+// contribute nothing and may take any column of their row's own grid /
+// problem: one outside the windows is moved to a column of the same owner
+// inside them; rows past the last row take the first window's base.  Returns
+// false (layout left as is) when some slice does not fit.
+bool compress_columns(Sell &S, const std::vector<int> &row_owner, const std::vector<int> &col_owner) {
+  const int rs = 64 >> S.lg, G = 1 << S.lg;
+  const int ns = (int)S.sptr.size() - 1;
+  if (ns <= 0) return false;
+  std::vector<uint16_t> c16(S.col.size());
+  std::vector<int> base(2 * (size_t)ns);
+  std::atomic<bool> ok{true};
+  parallel_for(ns, [&](long long b, long long e, int) {
+    std::vector<int> cs, owners;
+    for (long long s = b; s < e && ok.load(std::memory_order_relaxed); ++s) {
+      const int e0 = S.sptr[s], e1 = S.sptr[s + 1];
+      const int r0 = (int)s * rs;
+      auto row_of = [&](int a) { return r0 + ((a - e0) & 63) / G; };
+      cs.clear();
+      owners.clear();
+      for (int a = e0; a < e1; ++a) {
+        const int r = row_of(a);
+        if (S.val[a] != 0.0 && r < S.nrows) {
+          cs.push_back(S.col[a]);
+          if (std::find(owners.begin(), owners.end(), row_owner[r]) == owners.end()) owners.push_back(row_owner[r]);
+        }
+      }
+      // an owner whose rows in this slice hold zeros only keeps one of its
+      // own columns in the windows
+      for (int a = e0; a < e1; ++a) {
+        const int r = row_of(a);
+        if (r < S.nrows && row_owner[r] >= 0 && std::find(owners.begin(), owners.end(), row_owner[r]) == owners.end()) {
+          owners.push_back(row_owner[r]);
+          cs.push_back(S.col[a]);
+        }
+      }
+      std::sort(cs.begin(), cs.end());
+      cs.erase(std::unique(cs.begin(), cs.end()), cs.end());
+      int b0 = cs.empty() ? 0 : cs.front(), b1 = b0 + 32768;
+      if (!cs.empty() && cs.back() - cs.front() > 65535) {
+        size_t gi = 0;
+        int gap = -1;
+        for (size_t k = 1; k < cs.size(); ++k)
+          if (cs[k] - cs[k - 1] > gap) { gap = cs[k] - cs[k - 1]; gi = k; }
+        b1 = cs[gi];
+        if (cs[gi - 1] - b0 > 32767 || cs.back() - b1 > 32767) { ok = false; return; }
+      }
+      auto enc = [&](int c, uint16_t &out) {
+        if (c >= b0 && c - b0 <= 32767) { out = (uint16_t)(c - b0); return true; }
+        if (c >= b1 && c - b1 <= 32767) { out = (uint16_t)(0x8000 | (c - b1)); return true; }
+        return false;
+      };
+      for (int a = e0; a < e1; ++a) {
+        const int r = row_of(a);
+        if (r >= S.nrows || (row_owner[r] < 0 && S.val[a] == 0.0)) { S.col[a] = b0; c16[a] = 0; continue; }
+        if (!enc(S.col[a], c16[a])) {
+          if (S.val[a] != 0.0) { ok = false; return; }
+          // a zero entry outside the windows: any in-window column of the same owner
+          bool moved = false;
+          for (int c : cs)
+            if (col_owner[c] == row_owner[r]) { S.col[a] = c; enc(c, c16[a]); moved = true; break; }
+          for (int a2 = e0; a2 < e1 && !moved; ++a2) {
+            uint16_t q;
+            if (row_of(a2) < S.nrows && col_owner[S.col[a2]] == row_owner[r] && enc(S.col[a2], q)) {
+              S.col[a] = S.col[a2];
+              c16[a] = q;
+              moved = true;
+            }
+          }
+          if (!moved) { ok = false; return; }
+        }
+        const int dec = ((c16[a] & 0x8000) ? b1 : b0) + (c16[a] & 0x7fff);
+        if (dec != S.col[a]) { ok = false; return; }
+      }
+      base[2 * s] = b0;
+      base[2 * s + 1] = b1;
+    }
+  }, 64);
+  if (!ok) return false;
+  S.col16 = std::move(c16);
+  S.base = std::move(base);
+  std::vector<int>().swap(S.col);
+  return true;
+}
 
 // Lanes per row for rows averaging `avg` entries: one lane up to 20 entries,
 // otherwise the smallest power of two G <= 16 with at most ~12 entries per lane.
@@ -855,7 +946,10 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
       else { coff[l][g] = c; c += lv->nbar(); }
     }
     B.NRn = r;
-    B.NBn = r + gh;
+    // ghost rows start on a 64-row boundary: no slice mixes real and ghost rows
+    // (rows [NRn, NRa) belong to no grid and hold no entries)
+    B.NRa = (r + 63) / 64 * 64;
+    B.NBn = B.NRa + gh;
     B.NB = B.NBn + c;
     int gn = 0, gc = 0;
     for (int q = 0; q < nprob; ++q) {
@@ -890,7 +984,7 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
     const CompLevel &lv = S.grids[g].lv[l];
     if (roff[l][g] >= 0) {
       if (i < lv.nreal) return roff[l][g] + (S.cf ? rpos[l][g][i] : i);
-      return S.lv[l].NRn + goff[l][g] + (i - lv.nreal);
+      return S.lv[l].NRa + goff[l][g] + (i - lv.nreal);
     }
     return S.lv[l].NBn + coff[l][g] + i;
   };
@@ -1159,6 +1253,24 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
       if (l > 0) ok = ok && sell_block_diagonal(B.R, cown[l], cown[l - 1]) && sell_block_diagonal(B.GR, gown[l], gown[l - 1]);
       if (!ok) { err = "internal: batched layout is not block-diagonal on level " + std::to_string(l); return ST_EINVAL; }
     }
+    // 16-bit column indices where every slice fits (checked by decoding)
+    if (S.compress) {
+      std::vector<char> done(6 * (maxL + 1), 0);
+      for (int k = 0; k < 6 * (maxL + 1); ++k) {
+        const int l = k / 6, m = k % 6;
+        BatchLevel &B = S.lv[l];
+        if (m == 0) done[k] = compress_columns(B.A, cown[l], cown[l]);
+        if (m == 1 && l < maxL) done[k] = compress_columns(B.P, cown[l], cown[l + 1]);
+        if (m == 2 && l > 0) done[k] = compress_columns(B.R, cown[l], cown[l - 1]);
+        if (m == 3) done[k] = compress_columns(B.GA, gown[l], gown[l]);
+        if (m == 4 && l < maxL) done[k] = compress_columns(B.GP, gown[l], gown[l + 1]);
+        if (m == 5 && l > 0) done[k] = compress_columns(B.GR, gown[l], gown[l - 1]);
+      }
+      if (verbose())
+        for (int l = 0; l <= maxL; ++l)
+          std::fprintf(stderr, "[amgdd setup] level %d 16-bit columns A %d P %d R %d GA %d GP %d GR %d\n", l, done[6 * l],
+                       done[6 * l + 1], done[6 * l + 2], done[6 * l + 3], done[6 * l + 4], done[6 * l + 5]);
+    }
   }
   // fine-vector offsets (every problem is normal on level 0, so problem order)
   S.prob_off.assign(nprob + 1, 0);
@@ -1200,7 +1312,7 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
       if (l < L) {
         S.gl_rbeg[k] = roff[l][g];
         S.gl_nreal[k] = lv.nreal;
-        S.gl_gbeg[k] = S.lv[l].NRn + goff[l][g];
+        S.gl_gbeg[k] = S.lv[l].NRa + goff[l][g];
         S.gl_nghost[k] = lv.nbar() - lv.nreal;
       } else {
         S.gl_rbeg[k] = S.lv[l].NBn + coff[l][g];
@@ -1254,6 +1366,7 @@ int build_setup_hybrid(const std::vector<ProblemInput> &in, double theta, int ma
     const bool cf = outer.cf;
     inner = Setup();
     inner.cf = cf;
+    inner.compress = outer.compress;
     inner.theta = theta;
     inner.max_coarse = max_coarse;
     inner.max_levels = max_levels;
