@@ -46,6 +46,10 @@ namespace dev {
 constexpr int BLOCK = 256;
 constexpr int NXCD = 8;
 
+#ifndef AMGDD_UNROLL
+#define AMGDD_UNROLL 4
+#endif
+
 // Column indices are int32 (col) or, when every slice allows it, 16-bit
 // (col16) relative to one of two per-slice bases:
 //   column = (c16 & 0x8000 ? base[2s+1] : base[2s]) + (c16 & 0x7fff).
@@ -85,44 +89,48 @@ __device__ __forceinline__ V sell_dot(const SellD<T> &M, int r, int sub, const V
   const int off = beg + ((r & ((64 >> lg) - 1)) << lg) + sub;
   const T *__restrict__ v = M.val + off;
   // The matrix streams are read once per pass: non-temporal loads keep them
-  // from evicting the gathered vector from L2 / MALL.  Four entries in flight
-  // per lane; the sum stays in storage order.
+  // from evicting the gathered vector from L2 / MALL.
   V acc = V(0);
   int k = 0;
+  // U entries in flight per lane: all index and value loads of a group are
+  // issued before its gathers; the sum stays in storage order.
+  constexpr int U = AMGDD_UNROLL;
   if (M.col16) {
     const unsigned short *__restrict__ c = M.col16 + off;
     const int b0 = M.base[2 * s], b1 = M.base[2 * s + 1];
     auto dec = [&](unsigned short q) { return ((q & 0x8000) ? b1 : b0) + (int)(q & 0x7fff); };
-    for (; k + 4 <= w; k += 4) {
-      const int c0 = dec(__builtin_nontemporal_load(c + 64 * k)), c1 = dec(__builtin_nontemporal_load(c + 64 * (k + 1)));
-      const int c2 = dec(__builtin_nontemporal_load(c + 64 * (k + 2))), c3 = dec(__builtin_nontemporal_load(c + 64 * (k + 3)));
-      const V v0 = (V)__builtin_nontemporal_load(v + 64 * k), v1 = (V)__builtin_nontemporal_load(v + 64 * (k + 1));
-      const V v2 = (V)__builtin_nontemporal_load(v + 64 * (k + 2)), v3 = (V)__builtin_nontemporal_load(v + 64 * (k + 3));
-      const V x0 = x[c0], x1 = x[c1], x2 = x[c2], x3 = x[c3];
-      acc = fma(v0, x0, acc);
-      acc = fma(v1, x1, acc);
-      acc = fma(v2, x2, acc);
-      acc = fma(v3, x3, acc);
+    for (; k + U <= w; k += U) {
+      int cc[U];
+      V vv[U], xx[U];
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        cc[j] = dec(__builtin_nontemporal_load(c + 64 * (k + j)));
+        vv[j] = (V)__builtin_nontemporal_load(v + 64 * (k + j));
+      }
+#pragma unroll
+      for (int j = 0; j < U; ++j) xx[j] = x[cc[j]];
+#pragma unroll
+      for (int j = 0; j < U; ++j) acc = fma(vv[j], xx[j], acc);
     }
     for (; k < w; ++k)
       acc = fma((V)__builtin_nontemporal_load(v + 64 * k), x[dec(__builtin_nontemporal_load(c + 64 * k))], acc);
-    for (int o = (1 << lg) >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-    return acc;
+  } else {
+    const int *__restrict__ c = M.col + off;
+    for (; k + U <= w; k += U) {
+      int cc[U];
+      V vv[U], xx[U];
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        cc[j] = __builtin_nontemporal_load(c + 64 * (k + j));
+        vv[j] = (V)__builtin_nontemporal_load(v + 64 * (k + j));
+      }
+#pragma unroll
+      for (int j = 0; j < U; ++j) xx[j] = x[cc[j]];
+#pragma unroll
+      for (int j = 0; j < U; ++j) acc = fma(vv[j], xx[j], acc);
+    }
+    for (; k < w; ++k) acc = fma((V)__builtin_nontemporal_load(v + 64 * k), x[__builtin_nontemporal_load(c + 64 * k)], acc);
   }
-  const int *__restrict__ c = M.col + off;
-  for (; k + 4 <= w; k += 4) {
-    const int c0 = __builtin_nontemporal_load(c + 64 * k), c1 = __builtin_nontemporal_load(c + 64 * (k + 1));
-    const int c2 = __builtin_nontemporal_load(c + 64 * (k + 2)), c3 = __builtin_nontemporal_load(c + 64 * (k + 3));
-    const V v0 = (V)__builtin_nontemporal_load(v + 64 * k), v1 = (V)__builtin_nontemporal_load(v + 64 * (k + 1));
-    const V v2 = (V)__builtin_nontemporal_load(v + 64 * (k + 2)), v3 = (V)__builtin_nontemporal_load(v + 64 * (k + 3));
-    const V x0 = x[c0], x1 = x[c1], x2 = x[c2], x3 = x[c3];
-    acc = fma(v0, x0, acc);
-    acc = fma(v1, x1, acc);
-    acc = fma(v2, x2, acc);
-    acc = fma(v3, x3, acc);
-  }
-  for (; k < w; ++k)
-    acc = fma((V)__builtin_nontemporal_load(v + 64 * k), x[__builtin_nontemporal_load(c + 64 * k)], acc);
   for (int o = (1 << lg) >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
   return acc;
 }
