@@ -43,6 +43,8 @@ WORKLOADS = {
             "forward AMG-DD to 1e-10 plus adjoint AMG-DD to 1e-10 and face gradient",
     "cfg5": "256 independent 2D 5-point diffusion problems, sides U{64..512}, k log-normal sigma 1, Px,Py U{2..8}, "
             "padding U{1..3}; one batched handle; forward AMG-DD to 1e-8 plus adjoint AMG-DD to 1e-8",
+    "p2": "2D rotated anisotropic diffusion (theta 3pi/16, eps 1e-3), bilinear elements, 1024^2 interior nodes "
+          "(1,048,576 DOF), 4x4 subdomains of 256^2, padding 1, 2 AlgFAC cycles, FP64, AMG-DD solve to 1e-8",
 }
 
 
@@ -107,8 +109,8 @@ def cpu_baseline(seconds=12.0):
                       f"iterations in {dt:.1f} s (setup excluded)"}
 
 
-PRIMARY = {"cfg2": "fp64", "cfg3": "mixed", "cfg4": "fp64", "cfg5": "mixed"}
-RTOL = {"cfg2": 1e-8, "cfg3": 1e-8, "cfg4": 1e-10, "cfg5": 1e-8}
+PRIMARY = {"cfg2": "fp64", "cfg3": "mixed", "cfg4": "fp64", "cfg5": "mixed", "p2": "fp64"}
+RTOL = {"cfg2": 1e-8, "cfg3": 1e-8, "cfg4": 1e-10, "cfg5": 1e-8, "p2": 1e-8}
 
 
 def make_solver(amgdd, p, precision, sched=(-2, 0), hybrid_level=0):

@@ -10,7 +10,8 @@ the GPU path consume what it returns.
 The paper's workloads (Section 6) are finite-element discretisations of
 -div(K grad u) = f on regular meshes partitioned by METIS; these generators
 stand in for them with 5-point (2D) and 7-point (3D) stencils on block
-partitions.
+partitions, and (Problem 2, the rotated anisotropic case) with bilinear
+finite elements on a regular square mesh of the unit square.
 
 Conventions
 -----------
@@ -44,6 +45,9 @@ __all__ = [
     "make_problem",
     "config",
     "batch_config",
+    "anisotropic_tensor",
+    "q1_stiffness",
+    "anisotropic_problem",
     "CONFIG_NAMES",
 ]
 
@@ -229,7 +233,81 @@ def make_problem(
     )
 
 
-CONFIG_NAMES = ("cfg1", "cfg2", "cfg3", "cfg4", "cfg5")
+def anisotropic_tensor(theta: float, eps: float) -> np.ndarray:
+    """K = Q^T D Q with Q the rotation [[cos, sin], [-sin, cos]] by theta and
+    D = diag(1, eps) (Problem 2 of the paper's experiments)."""
+    c, s = np.cos(theta), np.sin(theta)
+    Q = np.array([[c, s], [-s, c]])
+    return Q.T @ np.diag([1.0, eps]) @ Q
+
+
+def q1_stiffness(dims: Sequence[int], K: np.ndarray) -> sparse.csr_matrix:
+    """Bilinear (Q1) finite-element stiffness matrix of -div(K grad u) for a
+    constant 2x2 tensor K on the unit square, meshed with (nx+1) x (ny+1)
+    rectangles; homogeneous Dirichlet nodes eliminated, so the unknowns are
+    the nx x ny interior nodes, numbered x fastest.  Element matrices by 2x2
+    Gauss quadrature (exact for these integrands)."""
+    nx, ny = (int(d) for d in dims)
+    hx, hy = 1.0 / (nx + 1), 1.0 / (ny + 1)
+    # reference nodes (0,0), (1,0), (1,1), (0,1)
+    corners = [(0, 0), (1, 0), (1, 1), (0, 1)]
+
+    def grad(a, xi, et):
+        cx, cy = corners[a]
+        gx = (1.0 if cx else -1.0) * (et if cy else 1.0 - et)
+        gy = (1.0 if cy else -1.0) * (xi if cx else 1.0 - xi)
+        return np.array([gx / hx, gy / hy])
+
+    g = [0.5 - 0.5 / np.sqrt(3.0), 0.5 + 0.5 / np.sqrt(3.0)]
+    Ke = np.zeros((4, 4))
+    for xi in g:
+        for et in g:
+            G = [grad(a, xi, et) for a in range(4)]
+            for a in range(4):
+                for b in range(4):
+                    Ke[a, b] += 0.25 * hx * hy * (G[a] @ K @ G[b])
+    Ke = 0.5 * (Ke + Ke.T)  # exactly symmetric (the two products round differently)
+    # elements (ex, ey), ex in 0..nx, ey in 0..ny; mesh node (ix, iy), interior
+    # when 1 <= ix <= nx and 1 <= iy <= ny, unknown index (ix-1) + nx (iy-1)
+    ex, ey = np.meshgrid(np.arange(nx + 1), np.arange(ny + 1), indexing="xy")
+    ex, ey = ex.ravel(), ey.ravel()
+    rows, cols, vals = [], [], []
+    for a in range(4):
+        ax, ay = corners[a]
+        ia, ja = ex + ax, ey + ay
+        ina = (ia >= 1) & (ia <= nx) & (ja >= 1) & (ja <= ny)
+        for b in range(4):
+            bx, by = corners[b]
+            ib, jb = ex + bx, ey + by
+            m = ina & (ib >= 1) & (ib <= nx) & (jb >= 1) & (jb <= ny)
+            rows.append((ia[m] - 1) + nx * (ja[m] - 1))
+            cols.append((ib[m] - 1) + nx * (jb[m] - 1))
+            vals.append(np.full(int(m.sum()), Ke[a, b]))
+    n = nx * ny
+    A = sparse.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n)).tocsr()
+    A.sum_duplicates()
+    A.sort_indices()
+    A.indices = A.indices.astype(np.int32)
+    A.indptr = A.indptr.astype(np.int32)
+    return A
+
+
+def anisotropic_problem(dims: Sequence[int], parts: Sequence[int], theta: float = 3 * np.pi / 16, eps: float = 1e-3,
+                        eta: int = 1, n_fac: int = 2, rhs_seed: int = 0, name: str = "") -> Problem:
+    """Problem 2 stand-in: 2D rotated anisotropic diffusion, K = Q^T D Q
+    (theta = 3 pi / 16, eps = 1e-3 by default), Q1 elements on the unit
+    square, block partition, b ~ U[-1, 1]."""
+    dims = tuple(int(d) for d in dims)
+    A = q1_stiffness(dims, anisotropic_tensor(theta, eps))
+    n = A.shape[0]
+    empty = np.zeros(0, dtype=np.int64)
+    return Problem(name=name or "aniso" + "x".join(map(str, dims)), dims=dims, A=A, b=uniform_rhs(n, rhs_seed),
+                   part=block_partition(dims, parts), nparts=int(np.prod(parts)), eta=int(eta), n_fac=int(n_fac),
+                   faces=Faces(empty, empty, empty), c=np.zeros(0),
+                   extra={"theta": float(theta), "eps": float(eps)})
+
+
+CONFIG_NAMES = ("cfg1", "cfg2", "cfg3", "cfg4", "cfg5", "p2")
 
 
 def config(name: str, scale: Optional[int] = None) -> Problem:
@@ -242,6 +320,9 @@ def config(name: str, scale: Optional[int] = None) -> Problem:
     cfg4  3D 7-point diffusion, 96^3, k = exp(GRF sigma 0.5, l = 8, seed 2),
           f ~ U[0,1] (seed 3), 3^3 subdomains of 32^3, padding 1, 2 FAC cycles;
           extra['u_target'] ~ U[0,1] (seed 4)
+    p2    2D rotated anisotropic diffusion (theta = 3 pi/16, eps = 1e-3), Q1
+          elements, 1024^2 interior nodes, 4x4 subdomains of 256^2, padding 1,
+          2 FAC cycles
 
     `scale` replaces the grid side while keeping the subdomain count (reduced
     instances for tests)."""
@@ -264,6 +345,9 @@ def config(name: str, scale: Optional[int] = None) -> Problem:
         p = make_problem(dims, parts, eta=1, n_fac=2, k=k, rhs_seed=3, rhs_range=(0.0, 1.0), name="cfg4")
         p.extra["u_target"] = uniform_rhs(p.n, 4, 0.0, 1.0)
         return p
+    if name == "p2":
+        s = scale or 1024
+        return anisotropic_problem((s, s), (4, 4), eta=1, n_fac=2, rhs_seed=0, name="p2")
     raise KeyError(name)
 
 

@@ -42,6 +42,7 @@ CASES = [
     ("3d_16_eta1", lambda: make_problem((16, 16, 16), (2, 2, 2), eta=1)),
     ("3d_12_var_eta2", lambda: make_problem((12, 12, 12), (2, 3, 2), eta=2, k=np.exp(grf((12, 12, 12), 1.0, 8.0, 1)))),
     ("cfg4_16", lambda: config("cfg4", scale=16)),
+    ("p2_48_aniso", lambda: config("p2", scale=48)),
 ]
 
 

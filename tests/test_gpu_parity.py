@@ -43,8 +43,10 @@ CASES = {
     "3d_20_var_eta2": lambda: make_problem((20, 18, 20), (2, 2, 3), eta=2, n_fac=2,
                                            k=np.exp(grf((20, 18, 20), 1.0, 8.0, 1))),
     "3d_30_ragged_4x4x4": lambda: make_problem((30, 30, 30), (4, 4, 4), eta=1, n_fac=2),
+    "p2_aniso_72": lambda: config("p2", scale=72),
 }
-ITERS = {"cfg1": 10, "2d_var_eta2_nfac3": 5, "3d_16_eta1": 6, "3d_20_var_eta2": 4, "3d_30_ragged_4x4x4": 4}
+ITERS = {"cfg1": 10, "2d_var_eta2_nfac3": 5, "3d_16_eta1": 6, "3d_20_var_eta2": 4, "3d_30_ragged_4x4x4": 4,
+         "p2_aniso_72": 5}
 
 
 @pytest.fixture(scope="module")
