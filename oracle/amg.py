@@ -21,6 +21,28 @@ host library; the readings used here are:
 * stop at <= max_coarse points, when a level produces no C-point or no
   reduction, or at max_levels levels
 
+The paper's own experiments use the host library's "best practices"
+components (Section 6): HMIS coarsening and extended+i interpolation.  They
+are here as options (coarsen="hmis", interp="ext+i"), written from their
+published definitions (De Sterck, Yang, Heys 2006; De Sterck, Falgout,
+Nolting, Yang 2008):
+
+* PMIS: measure lambda_i = |S^T_i| + r_i with r_i uniform in [0, 1); points
+  that influence nobody are F; repeatedly every undecided point whose measure
+  exceeds that of each undecided strong neighbour (either direction; equal
+  measures: smaller index wins) becomes C and the undecided points that
+  strongly depend on it become F.
+* HMIS: one RS first pass inside each subdomain (strong connections between
+  points of the same subdomain only); its C-points with no strong connection
+  to another subdomain form PMIS's first independent set (they are C and
+  their dependents F before the first PMIS round).  Subdomains of a coarse
+  level are inherited along the C-points.
+* r_i of point i on level l: the 53 high bits of SplitMix64(2^32 l + i)
+  divided by 2^53 (Steele, Lea, Flood 2014: add 0x9E3779B97F4A7C15, then
+  z ^= z >> 30, z *= 0xBF58476D1CE4E5B9, z ^= z >> 27, z *= 0x94D049BB133111EB,
+  z ^= z >> 31, all mod 2^64).
+* extended+i interpolation: see ext_i_interpolation.
+
 Every floating-point row sum is accumulated sequentially in ascending column
 order (the order a reader would write by hand).
 """
@@ -241,17 +263,183 @@ class Hierarchy:
         return self.A[-1].toarray()
 
 
-def setup(A0, theta: float = 0.25, max_coarse: int = 16, max_levels: int = 25) -> Hierarchy:
-    """Build the AMG hierarchy {A_l, P_l, R_l} (Section 2)."""
+MASK64 = (1 << 64) - 1
+
+
+def splitmix64(x: int) -> int:
+    """SplitMix64 output for counter x (all arithmetic mod 2^64)."""
+    z = (x + 0x9E3779B97F4A7C15) & MASK64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+    return z ^ (z >> 31)
+
+
+def pmis_random(level: int, n: int) -> np.ndarray:
+    """r_i in [0, 1) for the n points of `level` (see the module header)."""
+    return np.array([(splitmix64((level << 32) + i) >> 11) * 2.0 ** -53 for i in range(n)], dtype=np.float64)
+
+
+def pmis(S: sparse.csr_matrix, rand: np.ndarray, c_init=None) -> np.ndarray:
+    """PMIS C/F splitting (De Sterck, Yang, Heys 2006), optionally starting
+    from a given independent set c_init (boolean mask) of C-points.
+    Returns int8: +1 C, -1 F."""
+    n = S.shape[0]
+    S = _csr(S)
+    ST = _csr(S.T)
+    cnt = np.diff(ST.indptr)
+    lam = cnt.astype(np.float64) + rand
+    st = np.zeros(n, dtype=np.int8)
+    if c_init is not None:
+        st[np.asarray(c_init, dtype=bool)] = C_PT
+    st[(st == U_PT) & (cnt == 0)] = F_PT
+
+    def mark_dependents(cs):
+        for i in cs:
+            for j in ST.indices[ST.indptr[i]:ST.indptr[i + 1]]:
+                if st[j] == U_PT:
+                    st[j] = F_PT
+
+    if c_init is not None:
+        mark_dependents(np.nonzero(np.asarray(c_init, dtype=bool))[0])
+    while (st == U_PT).any():
+        und = np.nonzero(st == U_PT)[0]
+        new_c = []
+        for i in und:
+            nb = np.concatenate([S.indices[S.indptr[i]:S.indptr[i + 1]], ST.indices[ST.indptr[i]:ST.indptr[i + 1]]])
+            win = True
+            for j in nb:
+                if st[j] == U_PT and j != i and (lam[j] > lam[i] or (lam[j] == lam[i] and j < i)):
+                    win = False
+                    break
+            if win:
+                new_c.append(i)
+        for i in new_c:
+            st[i] = C_PT
+        mark_dependents(new_c)
+    return st
+
+
+def hmis(S: sparse.csr_matrix, part: np.ndarray, rand: np.ndarray) -> np.ndarray:
+    """HMIS: RS first pass inside each subdomain, then PMIS from its interior
+    C-points (see the module header)."""
+    S = _csr(S)
+    part = np.asarray(part)
+    r = row_ids(S)
+    same = part[r] == part[S.indices]
+    S_loc = sparse.csr_matrix((S.data[same], (r[same], S.indices[same])), shape=S.shape)
+    cf_loc = rs_first_pass(S_loc)
+    cross = ~same
+    bnd = np.zeros(S.shape[0], dtype=bool)
+    bnd[r[cross]] = True
+    bnd[S.indices[cross]] = True
+    return pmis(S, rand, (cf_loc == C_PT) & ~bnd)
+
+
+def ext_i_interpolation(A: sparse.csr_matrix, S: sparse.csr_matrix, cf: np.ndarray) -> sparse.csr_matrix:
+    """Extended+i interpolation (De Sterck, Falgout, Nolting, Yang 2008), no
+    truncation.  For an F-point i with strong C-neighbours C_i, strong
+    F-neighbours F_i and weak neighbours W_i (every other off-diagonal entry):
+
+        Chat_i = C_i united with the strong C-neighbours of every k in F_i
+        abar_kl = a_kl if a_kl a_kk < 0, else 0
+        d_k = sum over l in Chat_i + {i} of abar_kl              (k in F_i)
+        w_ij = -num_ij / at_ii,  j in Chat_i,
+        num_ij = a_ij + sum_{k in F_i} a_ik abar_kj / d_k
+        at_ii  = a_ii + sum_{n in W_i \ Chat_i} a_in + sum_{k in F_i} a_ik abar_ki / d_k
+
+    (a_ij = 0 when j is no neighbour of i).  A k with d_k = 0 is lumped like
+    a weak neighbour: a_ik goes into at_ii.  Every sum runs in ascending index
+    order: num_ij adds the k terms to a_ij in ascending k; at_ii adds the W_i
+    terms to a_ii, then the k terms.  C-points: injection.  F-points with an
+    empty Chat_i: empty row.  Coarse ids in increasing fine index."""
+    A = _csr(A)
+    S = _csr(S)
+    n = A.shape[0]
+    is_c = cf == C_PT
+    cidx = np.cumsum(is_c) - 1
+    nc = int(is_c.sum())
+    Ap, Aj, Av = A.indptr, A.indices, A.data
+    Sp, Sj = S.indptr, S.indices
+
+    def row(i):
+        return {int(j): float(v) for j, v in zip(Aj[Ap[i]:Ap[i + 1]], Av[Ap[i]:Ap[i + 1]])}
+
+    rows, cols, vals = [], [], []
+    for i in range(n):
+        if is_c[i]:
+            rows.append(i)
+            cols.append(int(cidx[i]))
+            vals.append(1.0)
+            continue
+        Si = set(int(j) for j in Sj[Sp[i]:Sp[i + 1]])
+        Ci = sorted(j for j in Si if is_c[j])
+        Fi = sorted(k for k in Si if not is_c[k])
+        chat = set(Ci)
+        for k in Fi:
+            chat.update(int(l) for l in Sj[Sp[k]:Sp[k + 1]] if is_c[l])
+        chat = sorted(chat)
+        if not chat:
+            continue
+        ai = row(i)
+        at = ai[i]
+        cset = set(chat)
+        for jn in sorted(ai):
+            if jn != i and jn not in Si and jn not in cset:
+                at += ai[jn]
+        num = {j: ai.get(j, 0.0) for j in chat}
+        for k in Fi:
+            ak = row(k)
+            akk = ak[k]
+            d = 0.0
+            for l in sorted(ak):
+                if (l in cset or l == i) and ak[l] * akk < 0:
+                    d += ak[l]
+            if d == 0.0:
+                at += ai[k]
+                continue
+            for j in chat:
+                abar = ak.get(j, 0.0)
+                if abar * akk < 0:
+                    num[j] += ai[k] * abar / d
+            abar_ki = ak.get(i, 0.0)
+            if abar_ki * akk < 0:
+                at += ai[k] * abar_ki / d
+        for j in chat:
+            rows.append(i)
+            cols.append(int(cidx[j]))
+            vals.append(-(num[j] / at))
+    P = sparse.csr_matrix((np.array(vals), (np.array(rows, dtype=np.int64), np.array(cols, dtype=np.int64))),
+                          shape=(n, nc))
+    P.sort_indices()
+    return P
+
+
+def setup(A0, theta: float = 0.25, max_coarse: int = 16, max_levels: int = 25, coarsen: str = "rs",
+          interp: str = "direct", part=None) -> Hierarchy:
+    """Build the AMG hierarchy {A_l, P_l, R_l} (Section 2).  coarsen="hmis"
+    needs `part`, the subdomain of every fine point."""
     A = _csr(A0).astype(np.float64)
     As, Ps, Rs, cfs, Ss = [A], [], [], [], []
+    pl = None if part is None else np.asarray(part)
     while A.shape[0] > max_coarse and len(As) < max_levels:
         S = strength(A, theta)
-        cf = rs_first_pass(S)
+        if coarsen == "rs":
+            cf = rs_first_pass(S)
+        elif coarsen == "hmis":
+            cf = hmis(S, pl, pmis_random(len(As) - 1, A.shape[0]))
+        else:
+            raise ValueError(coarsen)
         nc = int((cf == C_PT).sum())
         if nc == 0 or nc == A.shape[0]:
             break
-        P = direct_interpolation(A, S, cf)
+        if interp == "direct":
+            P = direct_interpolation(A, S, cf)
+        elif interp == "ext+i":
+            P = ext_i_interpolation(A, S, cf)
+        else:
+            raise ValueError(interp)
+        if pl is not None:
+            pl = pl[cf == C_PT]
         Ac = galerkin(A, P)
         Ss.append(S)
         cfs.append(cf)
