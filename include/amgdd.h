@@ -93,6 +93,17 @@ typedef struct {
                        over its F-points, the second seeing the first's update,
                        F-points first on the upsweep.  Applies to AlgFAC, the
                        V-cycle and the hybrid cycle alike. */
+  int coarsen;      /* 0 = classical RS first pass (default); 1 = HMIS, the
+                       coarsening of the paper's experiments (Section 6): one
+                       RS first pass inside each subdomain, then PMIS (De
+                       Sterck, Yang, Heys 2006) from its C-points that have no
+                       strong connection to another subdomain; PMIS ties broken
+                       by r_i = (SplitMix64(2^32 level + i) >> 11) / 2^53;
+                       coarse-level subdomains inherited along the C-points */
+  int interp;       /* 0 = direct interpolation (default); 1 = extended+i
+                       interpolation (De Sterck, Falgout, Nolting, Yang 2008) */
+  int interp_max;   /* extended+i rows keep their interp_max largest entries,
+                       rescaled to the row's sum; 0 = no truncation; default 4 */
 } amgdd_params;
 
 typedef struct {

@@ -41,7 +41,8 @@ Nolting, Yang 2008):
   divided by 2^53 (Steele, Lea, Flood 2014: add 0x9E3779B97F4A7C15, then
   z ^= z >> 30, z *= 0xBF58476D1CE4E5B9, z ^= z >> 27, z *= 0x94D049BB133111EB,
   z ^= z >> 31, all mod 2^64).
-* extended+i interpolation: see ext_i_interpolation.
+* extended+i interpolation: see ext_i_interpolation; rows truncated to at
+  most 4 entries (the host library's default) by truncate_row.
 
 Every floating-point row sum is accumulated sequentially in ascending column
 order (the order a reader would write by hand).
@@ -335,9 +336,30 @@ def hmis(S: sparse.csr_matrix, part: np.ndarray, rand: np.ndarray) -> np.ndarray
     return pmis(S, rand, (cf_loc == C_PT) & ~bnd)
 
 
-def ext_i_interpolation(A: sparse.csr_matrix, S: sparse.csr_matrix, cf: np.ndarray) -> sparse.csr_matrix:
-    """Extended+i interpolation (De Sterck, Falgout, Nolting, Yang 2008), no
-    truncation.  For an F-point i with strong C-neighbours C_i, strong
+def truncate_row(cols, vals, pmax):
+    """Interpolation truncation: keep the pmax entries of largest magnitude
+    (smaller column first on ties) and scale them by (sum of all entries) /
+    (sum of the kept entries), both summed in ascending column order, so the
+    row sum is preserved.  pmax = 0 or a row of at most pmax entries: as is."""
+    if pmax <= 0 or len(vals) <= pmax:
+        return list(cols), list(vals)
+    order = sorted(range(len(vals)), key=lambda q: (-abs(vals[q]), cols[q]))
+    keep = sorted(order[:pmax], key=lambda q: cols[q])
+    total = 0.0
+    for v in vals:
+        total += v
+    kept = 0.0
+    for q in keep:
+        kept += vals[q]
+    if kept == 0.0:
+        return [cols[q] for q in keep], [vals[q] for q in keep]
+    f = total / kept
+    return [cols[q] for q in keep], [vals[q] * f for q in keep]
+
+
+def ext_i_interpolation(A: sparse.csr_matrix, S: sparse.csr_matrix, cf: np.ndarray, pmax: int = 0) -> sparse.csr_matrix:
+    """Extended+i interpolation (De Sterck, Falgout, Nolting, Yang 2008),
+    rows truncated to pmax entries by truncate_row (0: no truncation).  For an F-point i with strong C-neighbours C_i, strong
     F-neighbours F_i and weak neighbours W_i (every other off-diagonal entry):
 
         Chat_i = C_i united with the strong C-neighbours of every k in F_i
@@ -404,10 +426,10 @@ def ext_i_interpolation(A: sparse.csr_matrix, S: sparse.csr_matrix, cf: np.ndarr
             abar_ki = ak.get(i, 0.0)
             if abar_ki * akk < 0:
                 at += ai[k] * abar_ki / d
-        for j in chat:
-            rows.append(i)
-            cols.append(int(cidx[j]))
-            vals.append(-(num[j] / at))
+        cj, wv = truncate_row([int(cidx[j]) for j in chat], [-(num[j] / at) for j in chat], pmax)
+        rows.extend([i] * len(cj))
+        cols.extend(cj)
+        vals.extend(wv)
     P = sparse.csr_matrix((np.array(vals), (np.array(rows, dtype=np.int64), np.array(cols, dtype=np.int64))),
                           shape=(n, nc))
     P.sort_indices()
@@ -415,9 +437,10 @@ def ext_i_interpolation(A: sparse.csr_matrix, S: sparse.csr_matrix, cf: np.ndarr
 
 
 def setup(A0, theta: float = 0.25, max_coarse: int = 16, max_levels: int = 25, coarsen: str = "rs",
-          interp: str = "direct", part=None) -> Hierarchy:
+          interp: str = "direct", part=None, pmax: int = 4) -> Hierarchy:
     """Build the AMG hierarchy {A_l, P_l, R_l} (Section 2).  coarsen="hmis"
-    needs `part`, the subdomain of every fine point."""
+    needs `part`, the subdomain of every fine point; pmax truncates
+    extended+i rows (the host library's default of 4 entries)."""
     A = _csr(A0).astype(np.float64)
     As, Ps, Rs, cfs, Ss = [A], [], [], [], []
     pl = None if part is None else np.asarray(part)
@@ -435,7 +458,7 @@ def setup(A0, theta: float = 0.25, max_coarse: int = 16, max_levels: int = 25, c
         if interp == "direct":
             P = direct_interpolation(A, S, cf)
         elif interp == "ext+i":
-            P = ext_i_interpolation(A, S, cf)
+            P = ext_i_interpolation(A, S, cf, pmax)
         else:
             raise ValueError(interp)
         if pl is not None:

@@ -34,7 +34,8 @@ class Params(C.Structure):
     _fields_ = [("theta", C.c_double), ("max_coarse", C.c_int), ("max_levels", C.c_int), ("padding", C.c_int),
                 ("n_fac", C.c_int), ("precision", C.c_int), ("device", C.c_int), ("use_graph", C.c_int),
                 ("tail_level", C.c_int), ("tail_block", C.c_int), ("hybrid_level", C.c_int),
-                ("relax_order", C.c_int)]
+                ("relax_order", C.c_int), ("coarsen", C.c_int), ("interp", C.c_int),
+                ("interp_max", C.c_int)]
 
 
 class Info(C.Structure):
@@ -155,11 +156,12 @@ class Solver:
     subdomain ids, nparts: int(s), padding: int(s).  device=-1 gives a
     host-only handle (setup and introspection, no solve).  hybrid_level=L~ > 0
     makes solve() run hybrid AMG-DD V-cycles with AMG-DD on level L~;
-    relax="cf" selects CF-ordered l1-Jacobi."""
+    relax="cf" selects CF-ordered l1-Jacobi; coarsen="hmis" and
+    interp="ext+i" the paper's best-practice AMG components."""
 
     def __init__(self, A, part, nparts, padding=1, n_fac=2, precision="fp64", device=0, theta=0.25,
                  max_coarse=16, max_levels=25, use_graph=True, stream=None, tail_level=-2, tail_block=0,
-                 hybrid_level=0, relax="l1"):
+                 hybrid_level=0, relax="l1", coarsen="rs", interp="direct", interp_max=4):
         lib = load()
         batch = isinstance(A, (list, tuple))
         As = list(A) if batch else [A]
@@ -180,6 +182,11 @@ class Solver:
         if relax not in ("l1", "cf"):
             raise ValueError(f"relax must be 'l1' or 'cf', not {relax!r}")
         prm.relax_order = 1 if relax == "cf" else 0
+        if coarsen not in ("rs", "hmis") or interp not in ("direct", "ext+i"):
+            raise ValueError(f"coarsen must be 'rs' or 'hmis' and interp 'direct' or 'ext+i', not {coarsen!r}, {interp!r}")
+        prm.coarsen = 1 if coarsen == "hmis" else 0
+        prm.interp = 1 if interp == "ext+i" else 0
+        prm.interp_max = interp_max
         if stream is None and device >= 0:
             torch = _torch()
             stream = torch.cuda.current_stream(device).cuda_stream

@@ -128,6 +128,10 @@ struct Setup {
   bool cf = false;
   // 16-bit column indices for every matrix whose slices allow them
   bool compress = true;
+  // AMG components: coarsen 0 = RS first pass, 1 = HMIS; interp 0 = direct,
+  // 1 = extended+i
+  int coarsen = 0, interp = 0;
+  int interp_max = 4;  // extended+i: at most this many entries per row (0: no truncation)
   std::vector<ProblemHost> probs;
   std::vector<CompGrid> grids;
   std::vector<BatchLevel> lv;      // 0..maxL
@@ -178,6 +182,11 @@ int build_setup_hybrid(const std::vector<ProblemInput> &in, double theta, int ma
                        std::string &err);
 
 // Individual steps, exposed for the driver's introspection.
+uint64_t splitmix64(uint64_t x);
+std::vector<double> pmis_random(int level, int n);
+std::vector<int8_t> pmis(const Csr &S, const std::vector<double> &rand, const std::vector<char> *c_init);
+std::vector<int8_t> hmis(const Csr &S, const std::vector<int> &part, const std::vector<double> &rand);
+Csr ext_i_interpolation(const Csr &A, const Csr &S, const std::vector<int8_t> &cf, int pmax);
 Csr strength(const Csr &A, double theta);
 std::vector<int8_t> rs_first_pass(const Csr &S);
 Csr direct_interpolation(const Csr &A, const Csr &S, const std::vector<int8_t> &cf);

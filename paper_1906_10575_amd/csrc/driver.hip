@@ -882,6 +882,21 @@ amgdd_status make_handle(const std::vector<ProblemInput> &in, const amgdd_params
     delete h;
     return fail(ST_EINVAL, "relax_order must be 0 (natural) or 1 (CF)");
   }
+  if (p.coarsen != 0 && p.coarsen != 1) {
+    delete h;
+    return fail(ST_EINVAL, "coarsen must be 0 (RS) or 1 (HMIS)");
+  }
+  if (p.interp != 0 && p.interp != 1) {
+    delete h;
+    return fail(ST_EINVAL, "interp must be 0 (direct) or 1 (extended+i)");
+  }
+  if (p.interp_max < 0) {
+    delete h;
+    return fail(ST_EINVAL, "interp_max must be >= 0");
+  }
+  h->S.coarsen = p.coarsen;
+  h->S.interp = p.interp;
+  h->S.interp_max = p.interp_max;
   h->S.cf = p.relax_order == 1;
   // debugging / measurement: keep int32 column indices everywhere
   h->S.compress = std::getenv("AMGDD_INDEX32") == nullptr;
@@ -980,6 +995,9 @@ void amgdd_params_default(amgdd_params *prm) {
   prm->tail_block = 0;
   prm->hybrid_level = 0;
   prm->relax_order = 0;
+  prm->coarsen = 0;
+  prm->interp = 0;
+  prm->interp_max = 4;
 }
 
 amgdd_status amgdd_setup_composite(int n, const int *rowptr, const int *colind, const double *val, const int *part,

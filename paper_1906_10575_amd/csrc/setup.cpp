@@ -533,6 +533,231 @@ Csr direct_interpolation(const Csr &A, const Csr &S, const std::vector<int8_t> &
   return P;
 }
 
+// ---- "best practices" components (PMIS / HMIS coarsening, extended+i
+// interpolation) from their published definitions: De Sterck, Yang, Heys
+// (2006) and De Sterck, Falgout, Nolting, Yang (2008).
+
+// SplitMix64 (Steele, Lea, Flood 2014), all arithmetic mod 2^64.
+uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Tie-break values of PMIS on `level`: r_i = (SplitMix64(2^32 level + i) >> 11) / 2^53.
+std::vector<double> pmis_random(int level, int n) {
+  std::vector<double> r(n);
+  for (int i = 0; i < n; ++i)
+    r[i] = (double)(splitmix64(((uint64_t)level << 32) + (uint64_t)i) >> 11) * 0x1.0p-53;
+  return r;
+}
+
+// PMIS: lambda_i = |S^T_i| + r_i; points influencing nobody are F; each round
+// every undecided point whose lambda exceeds that of all its undecided strong
+// neighbours (either direction; equal lambda: smaller index wins) becomes C,
+// and the undecided points strongly depending on a new C-point become F.
+// c_init (optional): C-points fixed before the first round (their dependents F).
+std::vector<int8_t> pmis(const Csr &S, const std::vector<double> &rand, const std::vector<char> *c_init) {
+  const int n = S.nrows;
+  Csr T = pattern_transpose(S);
+  std::vector<double> lam(n);
+  std::vector<int8_t> st(n, 0);
+  for (int i = 0; i < n; ++i) lam[i] = (double)(T.ptr[i + 1] - T.ptr[i]) + rand[i];
+  if (c_init)
+    for (int i = 0; i < n; ++i)
+      if ((*c_init)[i]) st[i] = 1;
+  for (int i = 0; i < n; ++i)
+    if (st[i] == 0 && T.ptr[i + 1] == T.ptr[i]) st[i] = -1;
+  auto mark = [&](const std::vector<int> &cs) {
+    for (int i : cs)
+      for (int jj = T.ptr[i]; jj < T.ptr[i + 1]; ++jj)
+        if (st[T.col[jj]] == 0) st[T.col[jj]] = -1;
+  };
+  if (c_init) {
+    std::vector<int> c0;
+    for (int i = 0; i < n; ++i)
+      if ((*c_init)[i]) c0.push_back(i);
+    mark(c0);
+  }
+  std::vector<int> und, nc;
+  for (;;) {
+    und.clear();
+    for (int i = 0; i < n; ++i)
+      if (st[i] == 0) und.push_back(i);
+    if (und.empty()) break;
+    nc.clear();
+    for (int i : und) {
+      bool win = true;
+      auto beats = [&](int j) { return st[j] == 0 && j != i && (lam[j] > lam[i] || (lam[j] == lam[i] && j < i)); };
+      for (int jj = S.ptr[i]; jj < S.ptr[i + 1] && win; ++jj)
+        if (beats(S.col[jj])) win = false;
+      for (int jj = T.ptr[i]; jj < T.ptr[i + 1] && win; ++jj)
+        if (beats(T.col[jj])) win = false;
+      if (win) nc.push_back(i);
+    }
+    for (int i : nc) st[i] = 1;
+    mark(nc);
+  }
+  return st;
+}
+
+// HMIS: one RS first pass inside every subdomain (strong connections between
+// points of the same subdomain only); its C-points without a strong connection
+// to another subdomain start PMIS.
+std::vector<int8_t> hmis(const Csr &S, const std::vector<int> &part, const std::vector<double> &rand) {
+  const int n = S.nrows;
+  Csr L;
+  L.nrows = L.ncols = n;
+  L.ptr.assign(n + 1, 0);
+  std::vector<char> bnd(n, 0);
+  for (int i = 0; i < n; ++i) {
+    for (int jj = S.ptr[i]; jj < S.ptr[i + 1]; ++jj) {
+      const int j = S.col[jj];
+      if (part[j] == part[i]) L.col.push_back(j);
+      else bnd[i] = bnd[j] = 1;
+    }
+    L.ptr[i + 1] = (int)L.col.size();
+  }
+  std::vector<int8_t> cf = rs_first_pass(L);
+  std::vector<char> c0(n, 0);
+  for (int i = 0; i < n; ++i) c0[i] = cf[i] == 1 && !bnd[i];
+  return pmis(S, rand, &c0);
+}
+
+// Extended+i interpolation, no truncation.  F-point i: strong C-neighbours
+// C_i, strong F-neighbours F_i, weak neighbours W_i (all other off-diagonal
+// entries); Chat_i = C_i plus the strong C-neighbours of every k in F_i;
+// abar_kl = a_kl when a_kl a_kk < 0, else 0; d_k = sum of abar_kl over
+// l in Chat_i + {i};
+//   w_ij = -num_ij / at_ii,  num_ij = a_ij + sum_k a_ik abar_kj / d_k,
+//   at_ii = a_ii + sum_{n in W_i \ Chat_i} a_in + sum_k a_ik abar_ki / d_k,
+// a k with d_k = 0 lumped into at_ii like a weak neighbour.  Sums in ascending
+// index order (W terms, then k terms, into at_ii).  C-points inject; F-points
+// with empty Chat_i get an empty row.
+// Truncation of one interpolation row: keep the pmax entries of largest
+// magnitude (smaller column first on ties), scaled by (sum of all entries) /
+// (sum of the kept ones), both summed in ascending column order; pmax <= 0 or
+// a row of at most pmax entries is left as is.
+void truncate_row(std::vector<int> &cols, std::vector<double> &vals, int pmax) {
+  const int m = (int)vals.size();
+  if (pmax <= 0 || m <= pmax) return;
+  std::vector<int> order(m);
+  for (int q = 0; q < m; ++q) order[q] = q;
+  std::sort(order.begin(), order.end(), [&](int a, int b) {
+    const double fa = std::fabs(vals[a]), fb = std::fabs(vals[b]);
+    return fa != fb ? fa > fb : cols[a] < cols[b];
+  });
+  std::vector<int> keep(order.begin(), order.begin() + pmax);
+  std::sort(keep.begin(), keep.end(), [&](int a, int b) { return cols[a] < cols[b]; });
+  double total = 0.0, kept = 0.0;
+  for (double v : vals) total += v;
+  for (int q : keep) kept += vals[q];
+  std::vector<int> c2;
+  std::vector<double> v2;
+  for (int q : keep) {
+    c2.push_back(cols[q]);
+    v2.push_back(kept == 0.0 ? vals[q] : vals[q] * (total / kept));
+  }
+  cols.swap(c2);
+  vals.swap(v2);
+}
+
+Csr ext_i_interpolation(const Csr &A, const Csr &S, const std::vector<int8_t> &cf, int pmax) {
+  const int n = A.nrows;
+  std::vector<int> cidx(n, -1);
+  int nc = 0;
+  for (int i = 0; i < n; ++i)
+    if (cf[i] == 1) cidx[i] = nc++;
+  Csr P;
+  P.nrows = n;
+  P.ncols = nc;
+  P.ptr.assign(n + 1, 0);
+  std::vector<int> mark_s(n, -1), mark_c(n, -1), posk(n, -1), posi(n, -1);
+  std::vector<double> vk(n, 0.0), vi(n, 0.0), num;
+  std::vector<int> chat, Fi;
+  for (int i = 0; i < n; ++i) {
+    if (cf[i] == 1) {
+      P.col.push_back(cidx[i]);
+      P.val.push_back(1.0);
+      P.ptr[i + 1] = (int)P.col.size();
+      continue;
+    }
+    chat.clear();
+    Fi.clear();
+    for (int jj = S.ptr[i]; jj < S.ptr[i + 1]; ++jj) {
+      const int j = S.col[jj];
+      mark_s[j] = i;
+      if (cf[j] == 1) {
+        if (mark_c[j] != i) { mark_c[j] = i; chat.push_back(j); }
+      } else {
+        Fi.push_back(j);
+      }
+    }
+    for (int k : Fi)
+      for (int jj = S.ptr[k]; jj < S.ptr[k + 1]; ++jj) {
+        const int l = S.col[jj];
+        if (cf[l] == 1 && mark_c[l] != i) { mark_c[l] = i; chat.push_back(l); }
+      }
+    if (chat.empty()) {
+      P.ptr[i + 1] = (int)P.col.size();
+      continue;
+    }
+    std::sort(chat.begin(), chat.end());
+    std::sort(Fi.begin(), Fi.end());
+    // row i scattered
+    double aii = 0.0;
+    for (int jj = A.ptr[i]; jj < A.ptr[i + 1]; ++jj) {
+      posi[A.col[jj]] = i;
+      vi[A.col[jj]] = A.val[jj];
+      if (A.col[jj] == i) aii = A.val[jj];
+    }
+    double at = aii;
+    for (int jj = A.ptr[i]; jj < A.ptr[i + 1]; ++jj) {
+      const int c = A.col[jj];
+      if (c != i && mark_s[c] != i && mark_c[c] != i) at += A.val[jj];
+    }
+    num.assign(chat.size(), 0.0);
+    for (size_t q = 0; q < chat.size(); ++q) num[q] = posi[chat[q]] == i ? vi[chat[q]] : 0.0;
+    for (int k : Fi) {
+      double akk = 0.0;
+      for (int jj = A.ptr[k]; jj < A.ptr[k + 1]; ++jj) {
+        posk[A.col[jj]] = k;
+        vk[A.col[jj]] = A.val[jj];
+        if (A.col[jj] == k) akk = A.val[jj];
+      }
+      double d = 0.0;
+      for (int jj = A.ptr[k]; jj < A.ptr[k + 1]; ++jj) {
+        const int l = A.col[jj];
+        if ((mark_c[l] == i || l == i) && A.val[jj] * akk < 0) d += A.val[jj];
+      }
+      const double aik = vi[k];
+      if (d == 0.0) {
+        at += aik;
+        continue;
+      }
+      for (size_t q = 0; q < chat.size(); ++q) {
+        const int j = chat[q];
+        const double abar = posk[j] == k ? vk[j] : 0.0;
+        if (abar * akk < 0) num[q] += aik * abar / d;
+      }
+      const double abar_ki = posk[i] == k ? vk[i] : 0.0;
+      if (abar_ki * akk < 0) at += aik * abar_ki / d;
+    }
+    std::vector<int> rc(chat.size());
+    std::vector<double> rv(chat.size());
+    for (size_t q = 0; q < chat.size(); ++q) {
+      rc[q] = cidx[chat[q]];
+      rv[q] = -(num[q] / at);
+    }
+    truncate_row(rc, rv, pmax);
+    P.col.insert(P.col.end(), rc.begin(), rc.end());
+    P.val.insert(P.val.end(), rv.begin(), rv.end());
+    P.ptr[i + 1] = (int)P.col.size();
+  }
+  return P;
+}
+
 Csr transpose(const Csr &A) {
   Csr T;
   T.nrows = A.ncols;
@@ -647,22 +872,31 @@ int validate(const ProblemInput &in, int max_coarse, std::string &err) {
   return ST_OK;
 }
 
-int build_hierarchy(ProblemHost &P, double theta, int max_coarse, int max_levels, std::string &err) {
+int build_hierarchy(ProblemHost &P, double theta, int max_coarse, int max_levels, int coarsen, int interp, int pmax,
+                    std::string &err) {
   Hierarchy &H = P.H;
   H.A.push_back(P.A0);
+  std::vector<int> part = P.part;  // subdomains of the current level (HMIS)
   while (H.A.back().nrows > max_coarse && (int)H.A.size() < max_levels) {
     const Csr &A = H.A.back();
     double th = now_s();
     Csr S = strength(A, theta);
     vlog("hier: strength", th);
     th = now_s();
-    std::vector<int8_t> cf = rs_first_pass(S);
-    vlog("hier: rs", th);
+    std::vector<int8_t> cf = coarsen == 1 ? hmis(S, part, pmis_random((int)H.A.size() - 1, A.nrows)) : rs_first_pass(S);
+    vlog("hier: coarsening", th);
     th = now_s();
     int nc = 0;
     for (auto c : cf) nc += c == 1;
     if (nc == 0 || nc == A.nrows) break;
-    Csr Pm = direct_interpolation(A, S, cf);
+    Csr Pm = interp == 1 ? ext_i_interpolation(A, S, cf, pmax) : direct_interpolation(A, S, cf);
+    {
+      std::vector<int> next;
+      next.reserve(nc);
+      for (int i = 0; i < A.nrows; ++i)
+        if (cf[i] == 1) next.push_back(part[i]);
+      part = std::move(next);
+    }
     vlog("hier: interp", th);
     th = now_s();
     Csr R = transpose(Pm);
@@ -856,7 +1090,7 @@ int setup_hierarchies(const std::vector<ProblemInput> &in, double theta, int max
   }
   // problems are independent: build the hierarchies in parallel when batched
   parallel_items(nprob, [&](int q, int) {
-    status[q] = build_hierarchy(S.probs[q], theta, max_coarse, max_levels, errs[q]);
+    status[q] = build_hierarchy(S.probs[q], theta, max_coarse, max_levels, S.coarsen, S.interp, S.interp_max, errs[q]);
   });
   for (int q = 0; q < nprob; ++q)
     if (status[q]) { err = "problem " + std::to_string(q) + ": " + errs[q]; return status[q]; }
@@ -1366,6 +1600,9 @@ int build_setup_hybrid(const std::vector<ProblemInput> &in, double theta, int ma
     const bool cf = outer.cf;
     inner = Setup();
     inner.cf = cf;
+    inner.coarsen = outer.coarsen;
+    inner.interp = outer.interp;
+    inner.interp_max = outer.interp_max;
     inner.compress = outer.compress;
     inner.theta = theta;
     inner.max_coarse = max_coarse;

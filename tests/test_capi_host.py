@@ -220,3 +220,36 @@ def test_cf_handle_setup_and_parameter_check():
         _host(p, relax="gs")
     prm = amgdd.default_params()
     assert prm.relax_order == 0
+
+
+BP_CASES = [
+    ("2d_var", lambda: make_problem((40, 36), (3, 2), eta=2, k=np.exp(grf((40, 36), 1.0, 8.0, 3)))),
+    ("3d_12_var", lambda: make_problem((12, 12, 12), (2, 3, 2), eta=1, k=np.exp(grf((12, 12, 12), 1.0, 8.0, 1)))),
+    ("p2_40", lambda: config("p2", scale=40)),
+]
+
+
+@pytest.mark.parametrize("coarsen,interp", [("hmis", "ext+i"), ("hmis", "direct"), ("rs", "ext+i")])
+@pytest.mark.parametrize("name,make", BP_CASES)
+def test_best_practice_setup_bit_exact_with_oracle(name, make, coarsen, interp):
+    # HMIS (with its SplitMix64 tie-breaks) and extended+i: identical C/F
+    # splittings, bitwise identical P and coarse operators, same composite sets
+    p = make()
+    s = _host(p, coarsen=coarsen, interp=interp)
+    H = amg.setup(p.A, coarsen=coarsen, interp=interp, part=p.part)
+    n, z = s.levels(0)
+    assert n.tolist() == [A.shape[0] for A in H.A]
+    for l in range(H.L):
+        assert np.array_equal(s.cf(0, l), H.cf[l]), f"C/F level {l}"
+        P = s.operator(0, l, 1)
+        assert np.array_equal(P.indptr, H.P[l].indptr) and np.array_equal(P.indices, H.P[l].indices)
+        np.testing.assert_array_equal(P.data, H.P[l].data)
+        A = s.operator(0, l + 1, 0)
+        assert np.array_equal(A.indices, H.A[l + 1].indices)
+        np.testing.assert_array_equal(A.data, H.A[l + 1].data)
+    comps = composite.build_all(H, p.part, p.nparts, p.eta)
+    for q, cg in enumerate(comps):
+        for l, lv in enumerate(cg.levels):
+            g, nr, om = s.composite(0, q, l)
+            assert nr == lv.n_real and np.array_equal(g, lv.gid)
+            assert om == lv.omissions

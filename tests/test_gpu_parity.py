@@ -328,3 +328,32 @@ def test_every_schedule_gives_identical_iterates(name, oracle_cache):
     st_ = s.stats()
     say("  autotuned:", st_["tail_level"], st_["tail_block"], f"{st_['autotune_s']:.3f} s")
     assert np.array_equal(_np(x), ref)
+
+
+@pytest.mark.parametrize("name", ["3d_20_var_eta2", "p2_aniso_72", "2d_var_eta2_nfac3"])
+@pytest.mark.parametrize("relax", ["l1", "cf"])
+def test_best_practice_hierarchy_iterates(name, relax):
+    # HMIS coarsening + truncated extended+i interpolation: AMG-DD and V-cycle
+    # iterates against the oracle on the same hierarchy
+    p = CASES[name]()
+    say("hmis/ext+i iterates", name, relax)
+    H = amg.setup(p.A, coarsen="hmis", interp="ext+i", part=p.part)
+    comps = composite.build_all(H, p.part, p.nparts, p.eta)
+    s = amgdd.Solver(p.A, p.part, p.nparts, padding=p.eta, n_fac=p.n_fac, coarsen="hmis", interp="ext+i", relax=relax)
+    b = _t(p.b)
+    coarse = cycles.CoarseSolver(H.A[H.L])
+    x = torch.zeros_like(b)
+    xo = np.zeros(p.n)
+    for k in range(3):
+        x, info, st = s.solve(b, x, rtol=0, maxit=1)
+        xo = cycles.amgdd_iteration(H, comps, p.b, xo, p.n_fac, coarse, relax=relax)
+        err = _rel(_np(x), xo)
+        assert err <= 1e-12, (k, err)
+    xv, _, _ = s.vsolve(b, rtol=0, maxit=3)
+    e = np.zeros(p.n)
+    for _ in range(3):
+        e = cycles.vcycle(H, e, p.b, coarse=coarse, relax=relax)
+    assert _rel(_np(xv), e) <= 1e-12
+    x, info, st = s.solve(b, rtol=1e-8, maxit=200)
+    assert st == amgdd.OK
+    say(f"  converged in {info.iters} iterations, last iterate err {err:.2e}")

@@ -127,3 +127,32 @@ def test_best_practice_hierarchies_solve(coarsen, interp):
     # Galerkin coarse operators of ext+i / HMIS hierarchies stay symmetric
     for A in H.A:
         assert abs(A - A.T).max() <= 1e-12 * abs(A).max()
+
+
+def test_truncation_keeps_largest_and_row_sum():
+    # |w| order 0.4 (7), 0.3 (9), 0.2 (11), 0.1 (3) kept; the dropped -0.05
+    # and 0.05 cancel, so the kept sum already equals the row sum 1
+    cols, vals = amg.truncate_row([3, 5, 7, 9, 11, 13], [0.1, -0.05, 0.4, 0.3, 0.2, 0.05], 4)
+    assert cols == [3, 7, 9, 11]
+    np.testing.assert_allclose(vals, [0.1, 0.4, 0.3, 0.2], rtol=1e-14)
+    # dropping 0.2 of a row summing to 1: kept entries scale by 1 / 0.8
+    c1, v1 = amg.truncate_row([0, 1, 2], [0.5, 0.3, 0.2], 2)
+    assert c1 == [0, 1]
+    np.testing.assert_allclose(v1, [0.625, 0.375], rtol=1e-15)
+    # ties: the smaller column stays
+    c2, v2 = amg.truncate_row([1, 2, 3], [0.5, 0.25, 0.25], 2)
+    assert c2 == [1, 2]
+    np.testing.assert_allclose(v2, [2 / 3, 1 / 3], rtol=1e-15)
+    # short rows are untouched
+    assert amg.truncate_row([4, 8], [0.7, 0.3], 4) == ([4, 8], [0.7, 0.3])
+
+
+def test_truncated_ext_i_rows_and_constants():
+    A = make_problem((12, 12, 12), (2, 2, 2)).A
+    S = amg.strength(A)
+    cf = amg.pmis(S, amg.pmis_random(0, A.shape[0]))
+    P0 = amg.ext_i_interpolation(A, S, cf)
+    P4 = amg.ext_i_interpolation(A, S, cf, pmax=4)
+    assert np.diff(P0.indptr).max() > 4 and np.diff(P4.indptr).max() <= 4
+    np.testing.assert_allclose(np.asarray(P4.sum(axis=1)).ravel(), np.asarray(P0.sum(axis=1)).ravel(),
+                               rtol=1e-13, atol=1e-15)
