@@ -113,13 +113,16 @@ PRIMARY = {"cfg2": "fp64", "cfg3": "mixed", "cfg4": "fp64", "cfg5": "mixed", "p2
 RTOL = {"cfg2": 1e-8, "cfg3": 1e-8, "cfg4": 1e-10, "cfg5": 1e-8, "p2": 1e-8}
 
 
+AMG_OPTS = {}  # relax / coarsen / interp from the command line
+
+
 def make_solver(amgdd, p, precision, sched=(-2, 0), hybrid_level=0):
     if isinstance(p, list):
         return amgdd.Solver([q.A for q in p], [q.part for q in p], [q.nparts for q in p],
                             padding=[q.eta for q in p], n_fac=2, precision=precision, tail_level=sched[0],
-                            tail_block=sched[1], hybrid_level=hybrid_level)
+                            tail_block=sched[1], hybrid_level=hybrid_level, **AMG_OPTS)
     return amgdd.Solver(p.A, p.part, p.nparts, padding=p.eta, n_fac=p.n_fac, precision=precision,
-                        tail_level=sched[0], tail_block=sched[1], hybrid_level=hybrid_level)
+                        tail_level=sched[0], tail_block=sched[1], hybrid_level=hybrid_level, **AMG_OPTS)
 
 
 def summarize_rocpd(db):
@@ -217,7 +220,8 @@ def sweep(torch, amgdd, cfg, args):
             p = dataclasses.replace(p0, eta=eta)
             for nfac in [int(v) for v in args.sweep_nfac.split(",")]:
                 t0 = time.perf_counter()
-                s = amgdd.Solver(p.A, p.part, p.nparts, padding=eta, n_fac=nfac, relax=relax)
+                s = amgdd.Solver(p.A, p.part, p.nparts, padding=eta, n_fac=nfac, relax=relax,
+                                 coarsen=AMG_OPTS["coarsen"], interp=AMG_OPTS["interp"])
                 setup_s = time.perf_counter() - t0
                 ov = s.stats()["composite_overhead"]
                 dt, x, info, st = timed(lambda: s.solve(b, torch.zeros_like(b), rtol=rtol, maxit=300))
@@ -230,7 +234,8 @@ def sweep(torch, amgdd, cfg, args):
                 log(f"sweep {rec}")
                 s.close()
             if eta == 1:
-                s = amgdd.Solver(p.A, p.part, p.nparts, padding=eta, n_fac=1, relax=relax)
+                s = amgdd.Solver(p.A, p.part, p.nparts, padding=eta, n_fac=1, relax=relax,
+                                 coarsen=AMG_OPTS["coarsen"], interp=AMG_OPTS["interp"])
                 dt, x, info, st = timed(lambda: s.vsolve(b, torch.zeros_like(b), rtol=rtol, maxit=400))
                 rec = {"solver": "vcycle", "relax": relax, "iters": info.iters, "rho": round(info.rho_asym, 4),
                        "time_to_tol_ms": round(dt * 1e3, 3), "ms_per_iter": round(dt * 1e3 / max(info.iters, 1), 4),
@@ -257,6 +262,9 @@ def main():
                     help="transition levels of the hybrid AMG-DD cycles timed beside the primary solve")
     ap.add_argument("--summarize-rocpd", metavar="DB", help="print a summary of a rocprofv3 kernel-trace database")
     ap.add_argument("--summarize-pmc", metavar="CSV", help="print a summary of rocprofv3 --pmc CSV output")
+    ap.add_argument("--relax", default="l1", choices=["l1", "cf"], help="l1-Jacobi order (natural / CF)")
+    ap.add_argument("--coarsen", default="rs", choices=["rs", "hmis"])
+    ap.add_argument("--interp", default="direct", choices=["direct", "ext+i"])
     ap.add_argument("--sweep", action="store_true",
                     help="parameter sweep on the workload instead of the benchmark line: padding x AlgFAC cycles x "
                          "relaxation order, plus the V-cycle in both orders (one JSON line)")
@@ -279,6 +287,7 @@ def main():
     from paper_1906_10575_amd import amgdd
 
     cfg = args.config
+    AMG_OPTS.update(relax=args.relax, coarsen=args.coarsen, interp=args.interp)
     if args.sweep:
         return sweep(torch, amgdd, cfg, args)
     prec = PRIMARY[cfg]
@@ -338,7 +347,8 @@ def main():
         "dtype": "f64" if prec == "fp64" else "f32 inner / f64 outer",
         "data": "synthetic",
         "config": {"workload": f"{cfg}: {WORKLOADS[cfg]}", "dof": n, "grids": st["n_grids"],
-                   "precision": prec, "rtol": rtol},
+                   "precision": prec, "rtol": rtol, "relax": args.relax, "coarsen": args.coarsen,
+                   "interp": args.interp},
         "iters_per_step": its,
         "time_to_tol_ms": round(ms_per_step, 4),
         "final_relres_fp64": relres,
