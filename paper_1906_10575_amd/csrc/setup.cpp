@@ -389,10 +389,16 @@ bool compress_columns(Sell &S, const std::vector<int> &row_owner, const std::vec
 
 // Lanes per row for rows averaging `avg` entries: one lane up to 20 entries,
 // otherwise the smallest power of two G <= 16 with at most ~12 entries per lane.
+#ifndef AMGDD_LANE_ONE
+#define AMGDD_LANE_ONE 20.0
+#endif
+#ifndef AMGDD_LANE_TARGET
+#define AMGDD_LANE_TARGET 12.0
+#endif
 int lanes_log2(double avg) {
-  if (avg <= 20.0) return 0;
+  if (avg <= AMGDD_LANE_ONE) return 0;
   int lg = 1;
-  while (lg < 4 && avg / (1 << lg) > 12.0) ++lg;
+  while (lg < 4 && avg / (1 << lg) > AMGDD_LANE_TARGET) ++lg;
   return lg;
 }
 
