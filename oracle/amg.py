@@ -359,15 +359,16 @@ def truncate_row(cols, vals, pmax):
 
 def ext_i_interpolation(A: sparse.csr_matrix, S: sparse.csr_matrix, cf: np.ndarray, pmax: int = 0) -> sparse.csr_matrix:
     """Extended+i interpolation (De Sterck, Falgout, Nolting, Yang 2008),
-    rows truncated to pmax entries by truncate_row (0: no truncation).  For an F-point i with strong C-neighbours C_i, strong
-    F-neighbours F_i and weak neighbours W_i (every other off-diagonal entry):
+    rows truncated to pmax entries by truncate_row (0: no truncation).  For
+    an F-point i with strong C-neighbours C_i, strong F-neighbours F_i and
+    weak neighbours W_i (every other off-diagonal entry):
 
         Chat_i = C_i united with the strong C-neighbours of every k in F_i
         abar_kl = a_kl if a_kl a_kk < 0, else 0
         d_k = sum over l in Chat_i + {i} of abar_kl              (k in F_i)
         w_ij = -num_ij / at_ii,  j in Chat_i,
         num_ij = a_ij + sum_{k in F_i} a_ik abar_kj / d_k
-        at_ii  = a_ii + sum_{n in W_i \ Chat_i} a_in + sum_{k in F_i} a_ik abar_ki / d_k
+        at_ii  = a_ii + sum_{n in W_i, not in Chat_i} a_in + sum_{k in F_i} a_ik abar_ki / d_k
 
     (a_ij = 0 when j is no neighbour of i).  A k with d_k = 0 is lumped like
     a weak neighbour: a_ik goes into at_ii.  Every sum runs in ascending index
