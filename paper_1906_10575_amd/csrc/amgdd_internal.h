@@ -90,6 +90,7 @@ struct BatchLevel {
   int NRn = 0, NBn = 0, NB = 0;
   int NRa = 0;                     // first ghost row: NRn rounded up to 64 (rows between belong to no grid)
   int lg = 0, glg = 0;             // lanes per row (log2) of composite / global rows of this level
+  int plg = 0, gplg = 0;           // lanes per row (log2) of composite / global P rows
   Sell A;                          // rows [0, NBn)
   Sell P;                          // rows [0, NBn) -> level l+1 composite rows
   Sell R;                          // R_{l-1}: rows [0, NB) -> level l-1 composite rows

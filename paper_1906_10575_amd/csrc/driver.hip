@@ -488,7 +488,7 @@ void enqueue_fac_up(amgdd_ctx *h, hipStream_t s, int *cur, int l) {
   DLevel &B = h->L[l];
   if (B.NBn == 0) return;
   DLevel &Bc = h->L[l + 1];
-  PLAUNCH(h, "interp", l, B.nnzP * ent(B.P, w) + B.NBn * 2.0 * w + Bc.NB * w, dev::k_interp<T>, nblocks((long long)B.NBn << B.lg), dev::BLOCK, 0, s, B.P.as<T>(), B.NBn, (T *)B.u[cur[l]],
+  PLAUNCH(h, "interp", l, B.nnzP * ent(B.P, w) + B.NBn * 2.0 * w + Bc.NB * w, dev::k_interp<T>, nblocks((long long)B.NBn << B.P.lg), dev::BLOCK, 0, s, B.P.as<T>(), B.NBn, (T *)B.u[cur[l]],
          (const T *)Bc.u[cur[l + 1]]);
   if (B.cls) {
     const int nrf = B.NRn - B.NRc;
@@ -630,7 +630,7 @@ void enqueue_v_up(amgdd_ctx *h, hipStream_t s, int *cur, int lv) {
     DLevel &B = h->L[l];
     DLevel &Bc = h->L[l + 1];
     if (B.GNn == 0) continue;
-    PLAUNCH(h, "vinterp", l, B.nnzGP * ent(B.GP, 8.0) + B.GNn * 16.0 + Bc.GN * 8.0, dev::k_interp<double>, nblocks((long long)B.GNn << B.glg), dev::BLOCK, 0, s, B.GP.as<double>(), B.GNn, B.ve[cur[l]],
+    PLAUNCH(h, "vinterp", l, B.nnzGP * ent(B.GP, 8.0) + B.GNn * 16.0 + Bc.GN * 8.0, dev::k_interp<double>, nblocks((long long)B.GNn << B.GP.lg), dev::BLOCK, 0, s, B.GP.as<double>(), B.GNn, B.ve[cur[l]],
            Bc.ve[cur[l + 1]]);
     const bool cf = B.gcls != nullptr;
     if (cf) enqueue_v_relax(h, s, cur, l, -1, "vrelax_fu");

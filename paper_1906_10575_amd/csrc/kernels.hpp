@@ -417,7 +417,8 @@ __global__ __launch_bounds__(BLOCK) void k_interp(SellD<T> P, int nb, T *__restr
 
 // ---------------------------------------------------------------- per-grid schedule
 
-// Pointers of one batched composite level (A, P, R share the lane grouping).
+// Pointers of one batched composite level (A and R share the lane grouping;
+// P has its own).
 template <typename T>
 struct LevelDev {
   SellD<T> A, P, R;
@@ -573,10 +574,14 @@ __global__ __launch_bounds__(1024) void k_fac_tail(const LevelDev<T> *__restrict
       const int lg = B.A.lg, sub = tid & ((1 << lg) - 1), j0 = tid >> lg, js = nt >> lg;
       const T *uc = lv[l + 1].u0;
       T *ucur = B.cls ? B.u0 : B.u1;
-      for (int j = j0; j < nb; j += js) {
-        const int i = grid_row(d, j);
-        const T v = sell_dot<T, T, false>(B.P, i, sub, uc);
-        if (sub == 0) ucur[i] += v;
+      {
+        // interpolation rows have their own lane count
+        const int pg = B.P.lg, psub = tid & ((1 << pg) - 1);
+        for (int j = tid >> pg; j < nb; j += nt >> pg) {
+          const int i = grid_row(d, j);
+          const T v = sell_dot<T, T, false>(B.P, i, psub, uc);
+          if (psub == 0) ucur[i] += v;
+        }
       }
       __syncthreads();
       if (B.cls) {

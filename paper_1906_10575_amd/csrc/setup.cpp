@@ -1236,18 +1236,26 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
   // lanes per row of every level, from the mean row length of A_l (of the
   // restriction rows on a level that only holds coarsest grids); the fine
   // global level keeps one lane per row
+  // Interpolation rows (a few entries) get their own lane count.
   for (int l = 0; l <= maxL; ++l) {
-    long long nzA = 0, nzR = 0;
+    long long nzA = 0, nzR = 0, nzP = 0;
     for (int g = 0; g < ng; ++g) {
-      if (roff[l][g] >= 0) nzA += S.grids[g].lv[l].A.nnz();
+      if (roff[l][g] >= 0) {
+        nzA += S.grids[g].lv[l].A.nnz();
+        nzP += S.grids[g].lv[l].P.nnz();
+      }
       if (l > 0 && (roff[l][g] >= 0 || coff[l][g] >= 0)) nzR += S.grids[g].lv[l - 1].P.nnz();
     }
     BatchLevel &B = S.lv[l];
     B.lg = B.NBn > 0 ? lanes_log2((double)nzA / B.NBn) : (B.NB > 0 ? lanes_log2((double)nzR / B.NB) : 0);
-    long long nzG = 0;
-    for (int q = 0; q < nprob; ++q)
+    B.plg = B.NBn > 0 ? lanes_log2((double)nzP / B.NBn) : 0;
+    long long nzG = 0, nzGP = 0;
+    for (int q = 0; q < nprob; ++q) {
       if (l <= S.probs[q].H.L()) nzG += S.probs[q].H.A[l].nnz();
+      if (l < S.probs[q].H.L()) nzGP += S.probs[q].H.P[l].nnz();
+    }
     B.glg = (l == 0 || B.GN == 0) ? 0 : lanes_log2((double)nzG / B.GN);
+    B.gplg = B.GNn > 0 ? lanes_log2((double)nzGP / B.GNn) : 0;
   }
   for (int l = 0; l <= maxL; ++l) {
     BatchLevel &B = S.lv[l];
@@ -1266,7 +1274,7 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
     // ---- composite A and P rows of normal grids, dinv, gather sources
     SellBuilder bA, bP;
     bA.init(B.NBn, B.lg);
-    bP.init(B.NBn, B.lg);
+    bP.init(B.NBn, B.plg);
     B.dinv.assign(B.NRn, 0.0);
     B.gsrc.assign(B.NB, -1);
     parallel_items(ng, [&](int g, int) {
@@ -1360,7 +1368,7 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
     // ---- global level l over problems
     SellBuilder bGA, bGP;
     bGA.init(B.GN, B.glg);
-    bGP.init(B.GNn, B.glg);
+    bGP.init(B.GNn, B.gplg);
     B.gdinv.assign(B.GNn, 0.0);
     B.prob_row0.assign(nprob, -1);
     for (int q = 0; q < nprob; ++q) {
