@@ -80,8 +80,16 @@ __device__ __forceinline__ int xcd_block() {
 
 __device__ __forceinline__ int thread_id() { return xcd_block() * BLOCK + (int)threadIdx.x; }
 
+// Sum over the G = 2^lg lanes of each row group (xor butterfly, fixed order).
+template <typename V>
+__device__ __forceinline__ V group_sum(V acc, int lg) {
+  for (int o = (1 << lg) >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  return acc;
+}
+
 // Row r of a grouped sliced-ELL matrix times x; `sub` is the calling lane's
-// position in the row's group.  Every lane of the group returns the full sum.
+// position in the row's group.  The group's first lane (sub == 0) returns the
+// full sum.
 // ALIGNED: the wavefront lies in one slice (threads assigned 64-aligned), so
 // the slice bounds are wave-uniform scalars.
 template <typename T, typename V, bool ALIGNED = true>
@@ -169,8 +177,7 @@ __device__ __forceinline__ V sell_dot(const SellD<T> &M, int r, int sub, const V
     }
     for (; k < w; ++k) acc = fma((V)__builtin_nontemporal_load(v + 64 * k), x[__builtin_nontemporal_load(c + 64 * k)], acc);
   }
-  for (int o = (1 << lg) >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-  return acc;
+  return group_sum(acc, lg);
 }
 
 __device__ __forceinline__ bool relaxes(const signed char *__restrict__ cls, int want, int i) {
