@@ -145,6 +145,7 @@ struct amgdd_ctx {
   hipStream_t cap_stream = nullptr;  // private stream used for graph capture
   std::vector<void *> allocs;
   long long dev_bytes = 0;
+  long long max_bytes = 0;  // > 0: device-memory cap (AMGDD_TEST_MAX_BYTES, failure-path tests)
   std::vector<DLevel> L;
   // outer vectors
   double *b = nullptr, *x = nullptr;
@@ -185,6 +186,8 @@ struct amgdd_ctx {
   amgdd_status alloc(void **p, size_t bytes) {
     *p = nullptr;
     if (bytes == 0) return AMGDD_OK;
+    if (max_bytes > 0 && dev_bytes + (long long)bytes > max_bytes)
+      return fail(ST_ENOMEM, "device memory cap reached (" + std::to_string(max_bytes) + " bytes)");
     hipError_t e = hipMalloc(p, bytes);
     if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? ST_ENOMEM : ST_EDEVICE, std::string("hipMalloc: ") + hipGetErrorString(e));
     allocs.push_back(*p);
@@ -952,8 +955,11 @@ amgdd_status make_handle(const std::vector<ProblemInput> &in, const amgdd_params
       return fail(ST_EDEVICE, "no HIP device " + std::to_string(p.device));
     }
     (void)hipSetDevice(p.device);
+    long long cap = 0;
+    if (const char *e2 = std::getenv("AMGDD_TEST_MAX_BYTES")) cap = std::atoll(e2);
     for (amgdd_ctx *c : {h, h->inner}) {
       if (!c) continue;
+      c->max_bytes = cap;
       c->device = p.device;
       c->stream = (hipStream_t)stream;
       if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess ||

@@ -1,0 +1,79 @@
+// Host-only driver of the setup code for sanitizer builds: assembles 2D and
+// 3D Laplacians with block partitions and runs every setup variant (RS /
+// HMIS, direct / extended+i, natural / CF row order, hybrid levels, batches).
+// Exit status 0 when every setup returns OK and its layout checks pass.
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../paper_1906_10575_amd/csrc/amgdd_internal.h"
+
+using namespace amgdd;
+
+struct Prob {
+  int n = 0;
+  std::vector<int> ptr, col, part;
+  std::vector<double> val;
+};
+
+static Prob laplace(int nx, int ny, int nz, int px, int py, int pz) {
+  Prob P;
+  P.n = nx * ny * nz;
+  P.ptr.push_back(0);
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        const int i = x + nx * (y + ny * z);
+        std::vector<std::pair<int, double>> row;
+        if (z > 0) row.push_back({i - nx * ny, -1.0});
+        if (y > 0) row.push_back({i - nx, -1.0});
+        if (x > 0) row.push_back({i - 1, -1.0});
+        row.push_back({i, nz > 1 ? 6.0 : 4.0});
+        if (x < nx - 1) row.push_back({i + 1, -1.0});
+        if (y < ny - 1) row.push_back({i + nx, -1.0});
+        if (z < nz - 1) row.push_back({i + nx * ny, -1.0});
+        for (auto &e : row) {
+          P.col.push_back(e.first);
+          P.val.push_back(e.second);
+        }
+        P.ptr.push_back((int)P.col.size());
+        P.part.push_back((x * px) / nx + px * ((y * py) / ny + py * ((z * pz) / nz)));
+      }
+  return P;
+}
+
+int main() {
+  std::vector<Prob> probs = {laplace(40, 36, 1, 3, 2, 1), laplace(14, 12, 10, 2, 2, 2), laplace(9, 9, 1, 3, 3, 1)};
+  const int nparts[] = {6, 8, 9};
+  int fails = 0, runs = 0;
+  for (int coarsen = 0; coarsen < 2; ++coarsen)
+    for (int interp = 0; interp < 2; ++interp)
+      for (int cf = 0; cf < 2; ++cf)
+        for (int hybrid = 0; hybrid < 3; ++hybrid) {
+          std::vector<ProblemInput> in;
+          for (size_t q = 0; q < probs.size(); ++q)
+            in.push_back(ProblemInput{probs[q].n, probs[q].ptr.data(), probs[q].col.data(), probs[q].val.data(),
+                                      probs[q].part.data(), nparts[q], 1 + (int)q % 2});
+          Setup S, I;
+          S.coarsen = coarsen;
+          S.interp = interp;
+          S.cf = cf;
+          std::string err;
+          int st;
+          if (hybrid == 0) {
+            st = build_setup(in, 0.25, 16, 25, S, err);
+          } else {
+            std::vector<int> inner_of;
+            std::vector<std::vector<int>> pm;
+            st = build_setup_hybrid(in, 0.25, 16, 25, hybrid, S, I, inner_of, pm, err);
+          }
+          ++runs;
+          if (st) {
+            ++fails;
+            std::fprintf(stderr, "setup coarsen %d interp %d cf %d hybrid %d: status %d %s\n", coarsen, interp, cf,
+                         hybrid, st, err.c_str());
+          }
+        }
+  std::printf("%d setups, %d failed\n", runs, fails);
+  return fails ? 1 : 0;
+}

@@ -357,3 +357,30 @@ def test_best_practice_hierarchy_iterates(name, relax):
     x, info, st = s.solve(b, rtol=1e-8, maxit=200)
     assert st == amgdd.OK
     say(f"  converged in {info.iters} iterations, last iterate err {err:.2e}")
+
+
+def test_mixed_iterates_track_the_float32_emulation():
+    # the oracle's float32 emulation (FP32 operators, restriction chain and
+    # AlgFAC; FP64 residual, patch and coarsest solve) deviates from FP64 by
+    # d_k after k iterations; the device's mixed iterates must sit within a
+    # few d_k of the emulation (a residual or coarse solve in FP32 would not:
+    # its error stops shrinking with the corrections)
+    p = CASES["3d_20_var_eta2"]()
+    say("mixed vs float32 emulation", p.n)
+    H = amg.setup(p.A)
+    comps = composite.build_all(H, p.part, p.nparts, p.eta)
+    co = cycles.CoarseSolver(H.A[H.L])
+    s = amgdd.Solver(p.A, p.part, p.nparts, padding=p.eta, n_fac=p.n_fac, precision="mixed")
+    b = _t(p.b)
+    x = torch.zeros_like(b)
+    x64 = np.zeros(p.n)
+    x32 = np.zeros(p.n)
+    for k in range(5):
+        x, info, st = s.solve(b, x, rtol=0, maxit=1)
+        x64 = cycles.amgdd_iteration(H, comps, p.b, x64, p.n_fac, co)
+        x32 = cycles.amgdd_iteration(H, comps, p.b, x32, p.n_fac, co, dtype=np.float32)
+        d = np.linalg.norm(x32 - x64)
+        e = np.linalg.norm(_np(x) - x32)
+        say(f"  iter {k + 1}: emulation vs FP64 {d / np.linalg.norm(x64):.2e}, device vs emulation "
+            f"{e / np.linalg.norm(x64):.2e}")
+        assert e <= 4.0 * d + 1e-13 * np.linalg.norm(x64), (k, e, d)
