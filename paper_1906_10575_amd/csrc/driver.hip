@@ -17,6 +17,7 @@
 // into the same graph.
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <chrono>
 #include <cmath>
@@ -53,6 +54,27 @@ amgdd_status fail(int st, const std::string &msg) {
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
+
+// Named ranges for timeline tools (rocprofv3 --marker-trace) when the
+// environment sets AMGDD_TRACE=1: setup, upload, autotuning, graph capture,
+// every solve and every outer iteration.
+bool tracing() {
+  static const bool on = [] {
+    const char *e = std::getenv("AMGDD_TRACE");
+    return e && e[0] == '1';
+  }();
+  return on;
+}
+struct TraceRange {
+  bool on;
+  explicit TraceRange(const char *name) : on(tracing()) {
+    if (on) roctxRangePush(name);
+  }
+  TraceRange(const std::string &name) : TraceRange(name.c_str()) {}
+  ~TraceRange() {
+    if (on) roctxRangePop();
+  }
+};
 
 struct DSell {
   int *sptr = nullptr;
@@ -681,6 +703,7 @@ void enqueue_hybrid(amgdd_ctx *h, hipStream_t s) {
 }
 
 amgdd_status capture(amgdd_ctx *h, bool dd, hipGraph_t *gr, hipGraphExec_t *ex) {
+  TraceRange tr(dd ? "amgdd: capture AMG-DD iteration" : "amgdd: capture V-cycle");
   HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
   if (dd && h->inner) {
     enqueue_hybrid(h, h->cap_stream);
@@ -700,6 +723,7 @@ amgdd_status capture(amgdd_ctx *h, bool dd, hipGraph_t *gr, hipGraphExec_t *ex) 
 // the fastest.  Every candidate computes identical results, so the choice only
 // affects time.  The iterate is restored afterwards.
 amgdd_status autotune(amgdd_ctx *h) {
+  TraceRange tr("amgdd: autotune");
   const double t0 = now_s();
   const int nlev = (int)h->L.size();
   hipStream_t s = h->stream;
@@ -752,6 +776,7 @@ enum SolveKind { SOLVE_DD = 0, SOLVE_V = 1 };
 
 amgdd_status run_solve(amgdd_ctx *h, SolveKind kind, const double *b_dev, double *x_dev, double rtol, int maxit,
                        amgdd_info *info) {
+  TraceRange tr(kind == SOLVE_V ? "amgdd: V-cycle solve" : "amgdd: AMG-DD solve");
   if (!h) return fail(ST_EINVAL, "null handle");
   if (h->host_only) return fail(ST_EDEVICE, "host-only handle (device = -1): no device solve");
   if (!b_dev || !x_dev) return fail(ST_EINVAL, "null device vector");
@@ -822,6 +847,7 @@ amgdd_status run_solve(amgdd_ctx *h, SolveKind kind, const double *b_dev, double
   amgdd_status result = AMGDD_OK;
   if (!finite()) result = fail(ST_EBREAKDOWN, "non-finite initial residual");
   while (result == AMGDD_OK && !converged() && it < maxit) {
+    TraceRange ti(tracing() ? "amgdd: iteration " + std::to_string(it + 1) : std::string());
     HIP_TRY(enqueue_iter(s));
     HIP_TRY(hipStreamSynchronize(s));
     ++it;
@@ -854,6 +880,7 @@ amgdd_status run_solve(amgdd_ctx *h, SolveKind kind, const double *b_dev, double
 }
 
 amgdd_status make_handle(const std::vector<ProblemInput> &in, const amgdd_params *prm, void *stream, amgdd_handle *out) {
+  TraceRange tr("amgdd: setup");
   if (!out) return fail(ST_EINVAL, "null output handle");
   *out = nullptr;
   double t0 = now_s();
@@ -905,9 +932,13 @@ amgdd_status make_handle(const std::vector<ProblemInput> &in, const amgdd_params
   h->S.compress = std::getenv("AMGDD_INDEX32") == nullptr;
   std::string err;
   Setup inner_S;
-  int st = p.hybrid_level > 0 ? build_setup_hybrid(in, p.theta, p.max_coarse, p.max_levels, p.hybrid_level, h->S, inner_S,
-                                                   h->inner_of, h->part_map, err)
-                              : build_setup(in, p.theta, p.max_coarse, p.max_levels, h->S, err);
+  int st;
+  {
+    TraceRange trh("amgdd: host setup (hierarchy, composite grids, layouts)");
+    st = p.hybrid_level > 0 ? build_setup_hybrid(in, p.theta, p.max_coarse, p.max_levels, p.hybrid_level, h->S, inner_S,
+                                                 h->inner_of, h->part_map, err)
+                            : build_setup(in, p.theta, p.max_coarse, p.max_levels, h->S, err);
+  }
   if (st) {
     delete h;
     return fail(st, err);
@@ -967,6 +998,7 @@ amgdd_status make_handle(const std::vector<ProblemInput> &in, const amgdd_params
         delete h;
         return fail(ST_EDEVICE, "stream/event creation failed");
       }
+      TraceRange tru("amgdd: upload");
       amgdd_status us = upload_all(c);
       if (us) {
         std::string msg = g_last_error;

@@ -63,3 +63,27 @@ def test_allocation_cap_gives_enomem_and_recovers(monkeypatch):
     x2, _, st3 = s.solve(b, rtol=1e-8, maxit=100)
     assert st3 == amgdd.OK and torch.equal(x, x2)
     s.close()
+
+
+def test_trace_ranges_do_not_change_results(tmp_path):
+    # AMGDD_TRACE=1 wraps setup, autotuning, capture, solves and iterations
+    # in roctx ranges; a child process solves with tracing on and must give
+    # the same iterate as this one with tracing off
+    import subprocess
+    p = make_problem((16, 16, 16), (2, 2, 2), eta=1, n_fac=2)
+    s = amgdd.Solver(p.A, p.part, p.nparts, padding=1, n_fac=2)
+    x, _, _ = s.solve(torch.as_tensor(p.b, device="cuda:0"), rtol=0, maxit=4)
+    out = tmp_path / "x.npy"
+    code = (
+        "import numpy as np, torch\n"
+        "from paper_1906_10575_amd import amgdd\n"
+        "from synth import make_problem\n"
+        "p = make_problem((16, 16, 16), (2, 2, 2), eta=1, n_fac=2)\n"
+        "s = amgdd.Solver(p.A, p.part, p.nparts, padding=1, n_fac=2)\n"
+        "x, _, _ = s.solve(torch.as_tensor(p.b, device='cuda:0'), rtol=0, maxit=4)\n"
+        f"np.save({str(out)!r}, x.cpu().numpy())\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, AMGDD_TRACE="1", PYTHONPATH=root)
+    r = subprocess.run([sys.executable, "-c", code], env=env, cwd=root, capture_output=True, text=True, timeout=240)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert np.array_equal(np.load(out), x.cpu().numpy())
