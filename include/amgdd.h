@@ -244,7 +244,8 @@ amgdd_status amgdd_get_history(amgdd_handle h, int prob, double *hist, int cap, 
  * internal state, launching kernel by kernel (no graph) with a HIP event pair
  * around every launch on the handle's stream.  Sites are aggregated by
  * (kernel name, level): launches = launches per iteration, ms = device time
- * per iteration, bytes = algorithmic bytes per iteration (stored nonzeros,
+ * per iteration (median over the reps, so one stalled launch does not move
+ * it), bytes = algorithmic bytes per iteration (stored nonzeros,
  * each vector entry touched once).  Fills up to cap entries of out, sets *n to
  * the number of sites. */
 typedef struct {

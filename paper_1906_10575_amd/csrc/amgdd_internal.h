@@ -68,9 +68,17 @@ struct ProblemHost {
 // i.e. each slice's columns lie in at most two windows of 32768 (a grid's
 // real rows and its ghost rows sit in different regions of the level).  col
 // is then emptied.
+// Paired sliced-ELL layout (see the device mat-vec for the address map): a
+// matrix whose rows are served by at most 2^AMGDD_PAIR_MAXLG lanes loads two
+// consecutive entries of a row per lane and step; -1 never pairs.
+#ifndef AMGDD_PAIR_MAXLG
+#define AMGDD_PAIR_MAXLG 4
+#endif
+
 struct Sell {
   int nrows = 0;
   int lg = 0;
+  int vlg = 0;  // 1: paired steps (two entries per lane and load step)
   std::vector<int> sptr;
   std::vector<int> col;
   std::vector<double> val;

@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 #include <rocprofiler-sdk-roctx/roctx.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -84,10 +85,11 @@ struct DSell {
   int *base = nullptr;              // two bases per slice
   int nrows = 0;
   int lg = 0;           // lanes per row (log2)
+  int vlg = 0;          // 1: paired layout
   long long entries = 0;
   template <typename T>
   dev::SellD<T> as() const {
-    return dev::SellD<T>{sptr, col, (const T *)val, lg, col16, base};
+    return dev::SellD<T>{sptr, col, (const T *)val, lg, col16, base, vlg};
   }
 };
 
@@ -130,10 +132,12 @@ struct Prof {
     double bytes;
     hipEvent_t e0, e1;
     int grid, block;
+    int rep;
   };
   std::vector<Site> sites;
   std::vector<hipEvent_t> pool;
   size_t used = 0;
+  int rep = 0;  // iteration being recorded
   hipEvent_t get() {
     if (used == pool.size()) {
       hipEvent_t e;
@@ -143,7 +147,7 @@ struct Prof {
     return pool[used++];
   }
   int begin(const char *name, int level, double bytes, hipStream_t s, int grid, int block) {
-    Site st{name, level, bytes, get(), get(), grid, block};
+    Site st{name, level, bytes, get(), get(), grid, block, rep};
     (void)hipEventRecord(st.e0, s);
     sites.push_back(st);
     return (int)sites.size() - 1;
@@ -231,6 +235,7 @@ struct amgdd_ctx {
   amgdd_status upload_sell(DSell &d, const Sell &s, bool as_float) {
     d.nrows = s.nrows;
     d.lg = s.lg;
+    d.vlg = s.vlg;
     d.entries = s.entries();
     amgdd_status st = upload(&d.sptr, s.sptr.data(), s.sptr.size());
     if (st) return st;
@@ -1253,6 +1258,7 @@ amgdd_status amgdd_profile(amgdd_handle h, int kind, int reps, amgdd_kernel_time
   h->prof = &prof;
   if (h->inner) h->inner->prof = &prof;
   for (int r = 0; r < reps; ++r) {
+    prof.rep = r;
     if (kind == 1) enqueue_v_iteration(h, s);
     else if (hybrid) enqueue_hybrid(h, s);
     else if (h->mixed()) enqueue_dd_iteration<float>(h, s);
@@ -1265,7 +1271,8 @@ amgdd_status amgdd_profile(amgdd_handle h, int kind, int reps, amgdd_kernel_time
   struct Agg {
     std::string name;
     int level, launches;
-    double ms, bytes;
+    std::vector<double> ms;  // per rep
+    double bytes;
     int grid, block;
   };
   std::vector<Agg> agg;
@@ -1276,20 +1283,25 @@ amgdd_status amgdd_profile(amgdd_handle h, int kind, int reps, amgdd_kernel_time
     for (auto &x : agg)
       if (x.name == site.name && x.level == site.level) a = &x;
     if (!a) {
-      agg.push_back(Agg{site.name, site.level, 0, 0.0, 0.0, site.grid, site.block});
+      agg.push_back(Agg{site.name, site.level, 0, std::vector<double>(reps, 0.0), 0.0, site.grid, site.block});
       a = &agg.back();
     }
     a->launches++;
-    a->ms += ms;
+    a->ms[site.rep] += ms;
     a->bytes += site.bytes;
   }
+  auto median = [](std::vector<double> v) {
+    std::sort(v.begin(), v.end());
+    const size_t m = v.size() / 2;
+    return v.size() % 2 ? v[m] : 0.5 * (v[m - 1] + v[m]);
+  };
   *n = (int)agg.size();
   for (int i = 0; i < (int)agg.size() && out && i < cap; ++i) {
     std::memset(&out[i], 0, sizeof(out[i]));
     std::strncpy(out[i].name, agg[i].name.c_str(), sizeof(out[i].name) - 1);
     out[i].level = agg[i].level;
     out[i].launches = agg[i].launches / reps;
-    out[i].ms = agg[i].ms / reps;
+    out[i].ms = median(agg[i].ms);
     out[i].bytes = agg[i].bytes / reps;
     out[i].workgroups = agg[i].grid;
     out[i].block = agg[i].block;

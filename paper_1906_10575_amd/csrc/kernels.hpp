@@ -9,8 +9,11 @@
 // every row r of the slice and every lane j of its group, entry k*G + j of row
 // r at
 //     sptr[slice] + 64*k + (r mod 64/G)*G + j
-// so every load instruction of a wavefront is one contiguous 256-byte (index)
-// / 512-byte (FP64) segment.  Each lane accumulates its entries in order; the
+// so every load instruction of a wavefront is one contiguous 128-byte (16-bit
+// index) / 512-byte (FP64) segment.  Paired matrices (see sell_dot2) store two
+// consecutive entries of a row per lane and step instead, halving the index
+// and value load instructions per entry (the slices keep the same size: an
+// odd last step stays unpaired).  Each lane accumulates its entries in order; the
 // G partial sums are combined by an xor-shuffle tree (fixed order, so results
 // do not depend on the launch schedule).  Padding entries carry value 0 and a
 // column of the row's own grid.
@@ -66,6 +69,7 @@ struct SellD {
   int lg;  // lanes per row G = 1 << lg
   const unsigned short *col16;
   const int *base;
+  int vlg;  // 1: paired steps (see sell_dot2)
 };
 
 // Workgroups are dispatched round-robin over the 8 XCDs; remap so that each
@@ -87,6 +91,104 @@ __device__ __forceinline__ V group_sum(V acc, int lg) {
   return acc;
 }
 
+// Paired layout: a slice of 64u entries (u unpaired steps of 64 lanes) holds
+// floor(u/2) paired steps first, then one unpaired step when u is odd.  Paired
+// step k stores, for lane p = (r mod 64/G)*G + j, entries 2(kG + j) and
+// 2(kG + j) + 1 of row r at sptr[slice] + 128k + 2p + {0, 1}: one 16-byte
+// (FP64) / 8-byte (FP32) value load and one 32-bit index load per lane and
+// step.  The unpaired step stores entry 2G floor(u/2) + j at
+// sptr[slice] + 128 floor(u/2) + p.  Each lane accumulates in storage order.
+template <typename T, typename V>
+__device__ __forceinline__ V sell_dot2(const SellD<T> &M, int s, int beg, int r, int sub, const V *__restrict__ x) {
+  typedef T T2 __attribute__((ext_vector_type(2)));
+  typedef unsigned short C2 __attribute__((ext_vector_type(2)));
+  typedef int I2 __attribute__((ext_vector_type(2)));
+  const int lg = M.lg;
+  const int u = (M.sptr[s + 1] - beg) >> 6, w = u >> 1;
+  const int p = ((r & ((64 >> lg) - 1)) << lg) + sub;
+  const T2 *__restrict__ v = (const T2 *)(M.val + beg + 2 * p);
+  const int tail = beg + 128 * w + p;
+  constexpr int U = AMGDD_UNROLL / 2 > 0 ? AMGDD_UNROLL / 2 : 1;
+  V acc = V(0);
+  int k = 0;
+  if (M.col16) {
+    const C2 *__restrict__ c = (const C2 *)(M.col16 + beg + 2 * p);
+    const int b0 = M.base[2 * s], b1 = M.base[2 * s + 1];
+    auto dec = [&](unsigned short q) { return ((q & 0x8000) ? b1 : b0) + (int)(q & 0x7fff); };
+    if (k + U <= w) {
+      C2 cn[U];
+      T2 vn[U];
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        cn[j] = __builtin_nontemporal_load(c + 64 * (k + j));
+        vn[j] = __builtin_nontemporal_load(v + 64 * (k + j));
+      }
+      for (; k + U <= w; k += U) {
+        int cc[2 * U];
+        V vv[2 * U], xx[2 * U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+          cc[2 * j] = dec(cn[j].x);
+          cc[2 * j + 1] = dec(cn[j].y);
+          vv[2 * j] = (V)vn[j].x;
+          vv[2 * j + 1] = (V)vn[j].y;
+        }
+#pragma unroll
+        for (int j = 0; j < 2 * U; ++j) xx[j] = x[cc[j]];
+        if (k + 2 * U <= w) {
+#pragma unroll
+          for (int j = 0; j < U; ++j) {
+            cn[j] = __builtin_nontemporal_load(c + 64 * (k + U + j));
+            vn[j] = __builtin_nontemporal_load(v + 64 * (k + U + j));
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 2 * U; ++j) acc = fma(vv[j], xx[j], acc);
+      }
+    }
+    for (; k < w; ++k) {
+      const C2 cq = __builtin_nontemporal_load(c + 64 * k);
+      const T2 vq = __builtin_nontemporal_load(v + 64 * k);
+      const V x0 = x[dec(cq.x)], x1 = x[dec(cq.y)];
+      acc = fma((V)vq.x, x0, acc);
+      acc = fma((V)vq.y, x1, acc);
+    }
+    if (u & 1)
+      acc = fma((V)__builtin_nontemporal_load(M.val + tail), x[dec(__builtin_nontemporal_load(M.col16 + tail))], acc);
+  } else {
+    const I2 *__restrict__ c = (const I2 *)(M.col + beg + 2 * p);
+    for (; k + U <= w; k += U) {
+      I2 cq[U];
+      T2 vq[U];
+      V xx[2 * U];
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        cq[j] = __builtin_nontemporal_load(c + 64 * (k + j));
+        vq[j] = __builtin_nontemporal_load(v + 64 * (k + j));
+      }
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        xx[2 * j] = x[cq[j].x];
+        xx[2 * j + 1] = x[cq[j].y];
+      }
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        acc = fma((V)vq[j].x, xx[2 * j], acc);
+        acc = fma((V)vq[j].y, xx[2 * j + 1], acc);
+      }
+    }
+    for (; k < w; ++k) {
+      const I2 cq = __builtin_nontemporal_load(c + 64 * k);
+      const T2 vq = __builtin_nontemporal_load(v + 64 * k);
+      const V x0 = x[cq.x], x1 = x[cq.y];
+      acc = fma((V)vq.x, x0, acc);
+      acc = fma((V)vq.y, x1, acc);
+    }
+    if (u & 1) acc = fma((V)__builtin_nontemporal_load(M.val + tail), x[__builtin_nontemporal_load(M.col + tail)], acc);
+  }
+  return group_sum(acc, lg);
+}
+
 // Row r of a grouped sliced-ELL matrix times x; `sub` is the calling lane's
 // position in the row's group.  The group's first lane (sub == 0) returns the
 // full sum.
@@ -98,6 +200,7 @@ __device__ __forceinline__ V sell_dot(const SellD<T> &M, int r, int sub, const V
   int s = r >> (6 - lg);
   if (ALIGNED) s = __builtin_amdgcn_readfirstlane(s);
   const int beg = M.sptr[s];
+  if (M.vlg) return sell_dot2<T, V>(M, s, beg, r, sub, x);
   const int w = (M.sptr[s + 1] - beg) >> 6;
   const int off = beg + ((r & ((64 >> lg) - 1)) << lg) + sub;
   const T *__restrict__ v = M.val + off;

@@ -202,6 +202,15 @@ bool sell_in_bounds(const Sell &S, int nrows, int ncols) {
   return ok;
 }
 
+// Row (within its slice) of the entry stored at position `pos` of a slice of
+// `size` entries.  Unpaired: 64-entry steps of 64/G rows x G lanes.  Paired:
+// the first 128 * (size / 128) entries are 128-entry steps of 64 lanes x 2
+// entries, followed by at most one unpaired 64-entry step.
+inline int sell_slice_row(const Sell &S, int size, int pos) {
+  if (S.vlg && pos < ((size >> 7) << 7)) return (pos & 127) >> (S.lg + 1);
+  return (pos & 63) >> S.lg;
+}
+
 // Block-diagonal check: every stored entry of row r (padding included) must
 // point at a column owned by the same composite grid / problem as r.  The
 // per-grid schedule runs grids concurrently, so any cross-grid load would race.
@@ -211,15 +220,13 @@ bool sell_block_diagonal(const Sell &S, const std::vector<int> &row_owner, const
   std::atomic<bool> ok(true);
   parallel_for(ns, [&](long long b, long long e, int) {
     for (long long sl = b; sl < e && ok; ++sl) {
-      const int base = S.sptr[sl], w = (S.sptr[sl + 1] - base) >> 6;
-      for (int lane = 0; lane < 64; ++lane) {
-        const int r = (int)sl * rs + (lane >> S.lg);
-        if (r >= S.nrows) break;
-        for (int k = 0; k < w; ++k) {
-          const size_t a = (size_t)base + 64 * k + lane;
-          // rows of no grid (alignment gaps) hold zeros only
-          if (row_owner[r] < 0 ? S.val[a] != 0.0 : col_owner[S.col[a]] != row_owner[r]) { ok = false; return; }
-        }
+      const int base = S.sptr[sl], size = S.sptr[sl + 1] - base;
+      for (int pos = 0; pos < size; ++pos) {
+        const int r = (int)sl * rs + sell_slice_row(S, size, pos);
+        if (r >= S.nrows) continue;
+        const size_t a = (size_t)base + pos;
+        // rows of no grid (alignment gaps) hold zeros only
+        if (row_owner[r] < 0 ? S.val[a] != 0.0 : col_owner[S.col[a]] != row_owner[r]) { ok = false; return; }
       }
     }
   }, 256);
@@ -236,6 +243,7 @@ struct SellBuilder {
   void init(int nrows, int lg) {
     S.nrows = nrows;
     S.lg = lg;
+    S.vlg = lg <= AMGDD_PAIR_MAXLG ? 1 : 0;
     rs = 64 >> lg;
     len.assign(nrows, 0);
   }
@@ -267,9 +275,17 @@ struct SellBuilder {
           S.val[at(r, k)] = 0.0;
         }
   }
+  // entry k of row r (see sell_slice_row for the step structure)
   inline size_t at(int r, int k) const {
-    const int lg = S.lg;
-    return (size_t)S.sptr[r / rs] + 64 * (size_t)(k >> lg) + ((size_t)(r % rs) << lg) + (k & ((1 << lg) - 1));
+    const int lg = S.lg, s = r / rs;
+    const size_t b = (size_t)S.sptr[s];
+    if (S.vlg) {
+      const int np = (S.sptr[s + 1] - S.sptr[s]) >> 7, gv = lg + 1;
+      const int kp = np << gv;  // entries of the row held in paired steps
+      if (k < kp) return b + ((size_t)(k >> gv) << 7) + ((size_t)(r % rs) << gv) + (k & ((1 << gv) - 1));
+      return b + ((size_t)np << 7) + ((size_t)(r % rs) << lg) + (k - kp);
+    }
+    return b + 64 * (size_t)(k >> lg) + ((size_t)(r % rs) << lg) + (k & ((1 << lg) - 1));
   }
   inline void put(int r, int k, int c, double v) {
     const size_t a = at(r, k);
@@ -308,7 +324,7 @@ struct SellBuilder {
 // inside them; rows past the last row take the first window's base.  Returns
 // false (layout left as is) when some slice does not fit.
 bool compress_columns(Sell &S, const std::vector<int> &row_owner, const std::vector<int> &col_owner) {
-  const int rs = 64 >> S.lg, G = 1 << S.lg;
+  const int rs = 64 >> S.lg;
   const int ns = (int)S.sptr.size() - 1;
   if (ns <= 0) return false;
   std::vector<uint16_t> c16(S.col.size());
@@ -319,7 +335,7 @@ bool compress_columns(Sell &S, const std::vector<int> &row_owner, const std::vec
     for (long long s = b; s < e && ok.load(std::memory_order_relaxed); ++s) {
       const int e0 = S.sptr[s], e1 = S.sptr[s + 1];
       const int r0 = (int)s * rs;
-      auto row_of = [&](int a) { return r0 + ((a - e0) & 63) / G; };
+      auto row_of = [&](int a) { return r0 + sell_slice_row(S, e1 - e0, a - e0); };
       cs.clear();
       owners.clear();
       for (int a = e0; a < e1; ++a) {
