@@ -404,17 +404,21 @@ bool compress_columns(Sell &S, const std::vector<int> &row_owner, const std::vec
 }
 
 // Lanes per row for rows averaging `avg` entries: one lane up to 20 entries,
-// otherwise the smallest power of two G <= 16 with at most ~12 entries per lane.
+// otherwise the smallest power of two G <= 16 with at most `target` entries
+// per lane (16 on composite levels, 12 on the global levels of the V-cycle).
 #ifndef AMGDD_LANE_ONE
 #define AMGDD_LANE_ONE 20.0
 #endif
 #ifndef AMGDD_LANE_TARGET
-#define AMGDD_LANE_TARGET 12.0
+#define AMGDD_LANE_TARGET 16.0
 #endif
-int lanes_log2(double avg) {
+#ifndef AMGDD_GLANE_TARGET
+#define AMGDD_GLANE_TARGET 12.0
+#endif
+int lanes_log2(double avg, double target = AMGDD_LANE_TARGET) {
   if (avg <= AMGDD_LANE_ONE) return 0;
   int lg = 1;
-  while (lg < 4 && avg / (1 << lg) > AMGDD_LANE_TARGET) ++lg;
+  while (lg < 4 && avg / (1 << lg) > target) ++lg;
   return lg;
 }
 
@@ -1270,8 +1274,8 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
       if (l <= S.probs[q].H.L()) nzG += S.probs[q].H.A[l].nnz();
       if (l < S.probs[q].H.L()) nzGP += S.probs[q].H.P[l].nnz();
     }
-    B.glg = (l == 0 || B.GN == 0) ? 0 : lanes_log2((double)nzG / B.GN);
-    B.gplg = B.GNn > 0 ? lanes_log2((double)nzGP / B.GNn) : 0;
+    B.glg = (l == 0 || B.GN == 0) ? 0 : lanes_log2((double)nzG / B.GN, AMGDD_GLANE_TARGET);
+    B.gplg = B.GNn > 0 ? lanes_log2((double)nzGP / B.GNn, AMGDD_GLANE_TARGET) : 0;
   }
   for (int l = 0; l <= maxL; ++l) {
     BatchLevel &B = S.lv[l];
