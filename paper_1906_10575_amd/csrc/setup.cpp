@@ -409,6 +409,9 @@ bool compress_columns(Sell &S, const std::vector<int> &row_owner, const std::vec
 #ifndef AMGDD_LANE_ONE
 #define AMGDD_LANE_ONE 20.0
 #endif
+#ifndef AMGDD_SORT_WINDOW
+#define AMGDD_SORT_WINDOW 128
+#endif
 #ifndef AMGDD_LANE_TARGET
 #define AMGDD_LANE_TARGET 16.0
 #endif
@@ -1222,29 +1225,65 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
     B.GN = gn + gc;
     if ((long long)B.NB >= std::numeric_limits<int>::max() / 2) throw std::length_error("level too large");
   }
-  // CF ordering: position of every real row within its grid's real range,
-  // C-points first (each class in local order)
-  std::vector<std::vector<std::vector<int>>> rpos(maxL + 1);
-  if (S.cf) {
-    for (int l = 0; l <= maxL; ++l) rpos[l].resize(ng);
+  // Row order within each grid's real and ghost ranges.  Real rows: CF
+  // ordering puts C-points first (each class in local order).  With
+  // AMGDD_SORT_WINDOW > 0, rows are then sorted by decreasing length within
+  // consecutive windows of that many rows (never across the C/F boundary),
+  // so sliced-ELL slices hold rows of similar length; ghost rows likewise.
+  // Jacobi sweeps and mat-vecs do not depend on row order.
+  const int sortw = AMGDD_SORT_WINDOW;
+  std::vector<std::vector<std::vector<int>>> rpos(maxL + 1), gpos(maxL + 1);
+  if (S.cf || sortw > 0) {
+    for (int l = 0; l <= maxL; ++l) {
+      rpos[l].resize(ng);
+      gpos[l].resize(ng);
+    }
     parallel_items(ng, [&](int g, int) {
       const Hierarchy &H = S.probs[S.grids[g].prob].H;
       for (int l = 0; l < H.L(); ++l) {
         const CompLevel &lv = S.grids[g].lv[l];
+        auto len = [&](int i) { return lv.A.ptr[i + 1] - lv.A.ptr[i]; };
+        // windows of `ord` positions [b, e) sorted by decreasing row length
+        auto sort_windows = [&](std::vector<int> &ord, int b, int e) {
+          if (sortw <= 0) return;
+          for (int w = b; w < e; w += sortw)
+            std::stable_sort(ord.begin() + w, ord.begin() + std::min(e, w + sortw),
+                             [&](int x, int y) { return len(x) > len(y); });
+        };
+        std::vector<int> ord;
+        ord.reserve(lv.nreal);
+        int nc = lv.nreal;
+        if (S.cf) {
+          for (int pass = 0; pass < 2; ++pass) {
+            for (int i = 0; i < lv.nreal; ++i)
+              if ((H.cf[l][lv.gid[i]] == 1) == (pass == 0)) ord.push_back(i);
+            if (pass == 0) nc = (int)ord.size();
+          }
+        } else {
+          for (int i = 0; i < lv.nreal; ++i) ord.push_back(i);
+        }
+        sort_windows(ord, 0, nc);
+        sort_windows(ord, nc, lv.nreal);
         std::vector<int> &pos = rpos[l][g];
         pos.resize(lv.nreal);
-        int k = 0;
-        for (int pass = 0; pass < 2; ++pass)
-          for (int i = 0; i < lv.nreal; ++i)
-            if ((H.cf[l][lv.gid[i]] == 1) == (pass == 0)) pos[i] = k++;
+        for (int k = 0; k < lv.nreal; ++k) pos[ord[k]] = k;
+        if (sortw > 0) {
+          const int ngh = lv.nbar() - lv.nreal;
+          std::vector<int> go(ngh);
+          for (int k = 0; k < ngh; ++k) go[k] = lv.nreal + k;
+          sort_windows(go, 0, ngh);
+          std::vector<int> &gp = gpos[l][g];
+          gp.resize(ngh);
+          for (int k = 0; k < ngh; ++k) gp[go[k] - lv.nreal] = k;
+        }
       }
     });
   }
   auto bidx = [&](int g, int l, int i) -> int {
     const CompLevel &lv = S.grids[g].lv[l];
     if (roff[l][g] >= 0) {
-      if (i < lv.nreal) return roff[l][g] + (S.cf ? rpos[l][g][i] : i);
-      return S.lv[l].NRa + goff[l][g] + (i - lv.nreal);
+      if (i < lv.nreal) return roff[l][g] + (rpos[l].empty() ? i : rpos[l][g][i]);
+      return S.lv[l].NRa + goff[l][g] + (gpos[l].empty() || gpos[l][g].empty() ? i - lv.nreal : gpos[l][g][i - lv.nreal]);
     }
     return S.lv[l].NBn + coff[l][g] + i;
   };
