@@ -1226,12 +1226,20 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
     if ((long long)B.NB >= std::numeric_limits<int>::max() / 2) throw std::length_error("level too large");
   }
   // Row order within each grid's real and ghost ranges.  Real rows: CF
-  // ordering puts C-points first (each class in local order).  With
+  // ordering puts C-points first (each class in local order).  On levels
+  // with grouped rows (mean composite row length above one lane's share) and
   // AMGDD_SORT_WINDOW > 0, rows are then sorted by decreasing length within
   // consecutive windows of that many rows (never across the C/F boundary),
   // so sliced-ELL slices hold rows of similar length; ghost rows likewise.
   // Jacobi sweeps and mat-vecs do not depend on row order.
   const int sortw = AMGDD_SORT_WINDOW;
+  std::vector<char> sort_lv(maxL + 1, 0);
+  for (int l = 0; l <= maxL && sortw > 0; ++l) {
+    long long nz = 0;
+    for (int g = 0; g < ng; ++g)
+      if (roff[l][g] >= 0) nz += S.grids[g].lv[l].A.nnz();
+    sort_lv[l] = S.lv[l].NBn > 0 && (double)nz / S.lv[l].NBn > AMGDD_LANE_ONE;
+  }
   std::vector<std::vector<std::vector<int>>> rpos(maxL + 1), gpos(maxL + 1);
   if (S.cf || sortw > 0) {
     for (int l = 0; l <= maxL; ++l) {
@@ -1245,7 +1253,7 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
         auto len = [&](int i) { return lv.A.ptr[i + 1] - lv.A.ptr[i]; };
         // windows of `ord` positions [b, e) sorted by decreasing row length
         auto sort_windows = [&](std::vector<int> &ord, int b, int e) {
-          if (sortw <= 0) return;
+          if (sortw <= 0 || !sort_lv[l]) return;
           for (int w = b; w < e; w += sortw)
             std::stable_sort(ord.begin() + w, ord.begin() + std::min(e, w + sortw),
                              [&](int x, int y) { return len(x) > len(y); });
@@ -1267,7 +1275,7 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
         std::vector<int> &pos = rpos[l][g];
         pos.resize(lv.nreal);
         for (int k = 0; k < lv.nreal; ++k) pos[ord[k]] = k;
-        if (sortw > 0) {
+        if (sortw > 0 && sort_lv[l]) {
           const int ngh = lv.nbar() - lv.nreal;
           std::vector<int> go(ngh);
           for (int k = 0; k < ngh; ++k) go[k] = lv.nreal + k;
