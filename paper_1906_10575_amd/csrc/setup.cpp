@@ -1649,6 +1649,9 @@ int guarded(std::string &err, F &&f) {
   } catch (const std::length_error &e) {
     err = std::string("layout too large: ") + e.what();
     return ST_EUNSUP;
+  } catch (const std::logic_error &e) {
+    err = std::string("internal: ") + e.what();
+    return ST_EINVAL;
   }
 }
 
