@@ -68,13 +68,6 @@ struct ProblemHost {
 // i.e. each slice's columns lie in at most two windows of 32768 (a grid's
 // real rows and its ghost rows sit in different regions of the level).  col
 // is then emptied.
-// Paired sliced-ELL layout (see the device mat-vec for the address map): a
-// matrix whose rows are served by at most 2^AMGDD_PAIR_MAXLG lanes loads two
-// consecutive entries of a row per lane and step; -1 never pairs.
-#ifndef AMGDD_PAIR_MAXLG
-#define AMGDD_PAIR_MAXLG 4
-#endif
-
 struct Sell {
   int nrows = 0;
   int lg = 0;
@@ -137,6 +130,12 @@ struct Setup {
   bool cf = false;
   // 16-bit column indices for every matrix whose slices allow them
   bool compress = true;
+  // paired sliced-ELL steps: each lane loads two consecutive entries of its
+  // row per step (the device mat-vec gives the address map); false: one
+  bool pair = true;
+  // on levels with grouped rows, each grid's real and ghost rows are sorted
+  // by decreasing length within windows of this many rows (0: local order)
+  int sort_window = 128;
   // AMG components: coarsen 0 = RS first pass, 1 = HMIS; interp 0 = direct,
   // 1 = extended+i
   int coarsen = 0, interp = 0;

@@ -933,8 +933,12 @@ amgdd_status make_handle(const std::vector<ProblemInput> &in, const amgdd_params
   h->S.interp = p.interp;
   h->S.interp_max = p.interp_max;
   h->S.cf = p.relax_order == 1;
-  // debugging / measurement: keep int32 column indices everywhere
+  // measurement / testing: int32 column indices everywhere, one entry per
+  // lane and step, rows in local order (every one gives the same results;
+  // only the unpaired layout changes the summation order of grouped rows)
   h->S.compress = std::getenv("AMGDD_INDEX32") == nullptr;
+  h->S.pair = std::getenv("AMGDD_UNPAIRED") == nullptr;
+  if (const char *e = std::getenv("AMGDD_SORT_WINDOW")) h->S.sort_window = std::max(0, std::atoi(e));
   std::string err;
   Setup inner_S;
   int st;

@@ -240,10 +240,10 @@ struct SellBuilder {
   Sell S;
   std::vector<int> len;
   int rs = 64;  // rows per slice
-  void init(int nrows, int lg) {
+  void init(int nrows, int lg, bool pair) {
     S.nrows = nrows;
     S.lg = lg;
-    S.vlg = lg <= AMGDD_PAIR_MAXLG ? 1 : 0;
+    S.vlg = pair ? 1 : 0;
     rs = 64 >> lg;
     len.assign(nrows, 0);
   }
@@ -408,9 +408,6 @@ bool compress_columns(Sell &S, const std::vector<int> &row_owner, const std::vec
 // per lane (16 on composite levels, 12 on the global levels of the V-cycle).
 #ifndef AMGDD_LANE_ONE
 #define AMGDD_LANE_ONE 20.0
-#endif
-#ifndef AMGDD_SORT_WINDOW
-#define AMGDD_SORT_WINDOW 128
 #endif
 #ifndef AMGDD_LANE_TARGET
 #define AMGDD_LANE_TARGET 16.0
@@ -1228,11 +1225,11 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
   // Row order within each grid's real and ghost ranges.  Real rows: CF
   // ordering puts C-points first (each class in local order).  On levels
   // with grouped rows (mean composite row length above one lane's share) and
-  // AMGDD_SORT_WINDOW > 0, rows are then sorted by decreasing length within
+  // a sort window > 0, rows are then sorted by decreasing length within
   // consecutive windows of that many rows (never across the C/F boundary),
   // so sliced-ELL slices hold rows of similar length; ghost rows likewise.
   // Jacobi sweeps and mat-vecs do not depend on row order.
-  const int sortw = AMGDD_SORT_WINDOW;
+  const int sortw = S.sort_window;
   std::vector<char> sort_lv(maxL + 1, 0);
   for (int l = 0; l <= maxL && sortw > 0; ++l) {
     long long nz = 0;
@@ -1340,8 +1337,8 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
     const int nn = (int)normal.size();
     // ---- composite A and P rows of normal grids, dinv, gather sources
     SellBuilder bA, bP;
-    bA.init(B.NBn, B.lg);
-    bP.init(B.NBn, B.plg);
+    bA.init(B.NBn, B.lg, S.pair);
+    bP.init(B.NBn, B.plg, S.pair);
     B.dinv.assign(B.NRn, 0.0);
     B.gsrc.assign(B.NB, -1);
     parallel_items(ng, [&](int g, int) {
@@ -1399,7 +1396,7 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
     if (l < maxL) {
       BatchLevel &Bn = S.lv[l + 1];
       SellBuilder bR;
-      bR.init(Bn.NB, Bn.lg);
+      bR.init(Bn.NB, Bn.lg, S.pair);
       std::vector<Csr> Rl(nn);
       parallel_items(nn, [&](int k, int) {
         int g = normal[k];
@@ -1434,8 +1431,8 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
     tp = now_s();
     // ---- global level l over problems
     SellBuilder bGA, bGP;
-    bGA.init(B.GN, B.glg);
-    bGP.init(B.GNn, B.gplg);
+    bGA.init(B.GN, B.glg, S.pair);
+    bGP.init(B.GNn, B.gplg, S.pair);
     B.gdinv.assign(B.GNn, 0.0);
     B.prob_row0.assign(nprob, -1);
     for (int q = 0; q < nprob; ++q) {
@@ -1506,7 +1503,7 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
       // R_l = P_l^T is stored in the hierarchy; rows = level l+1
       BatchLevel &Bn = S.lv[l + 1];
       SellBuilder bGR;
-      bGR.init(Bn.GN, Bn.glg);
+      bGR.init(Bn.GN, Bn.glg, S.pair);
       parallel_items(nprob, [&](int q, int) {
         const Hierarchy &H = S.probs[q].H;
         if (l >= H.L()) return;
@@ -1688,6 +1685,8 @@ int build_setup_hybrid(const std::vector<ProblemInput> &in, double theta, int ma
     inner.interp = outer.interp;
     inner.interp_max = outer.interp_max;
     inner.compress = outer.compress;
+    inner.pair = outer.pair;
+    inner.sort_window = outer.sort_window;
     inner.theta = theta;
     inner.max_coarse = max_coarse;
     inner.max_levels = max_levels;

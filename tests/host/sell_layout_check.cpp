@@ -40,8 +40,7 @@ static int check(int nrows, int lg, int vlg, int maxlen, unsigned seed) {
   std::mt19937 rng(seed);
   const int G = 1 << lg;
   SellBuilder b;
-  b.init(nrows, lg);
-  b.S.vlg = vlg;
+  b.init(nrows, lg, vlg != 0);
   std::vector<std::vector<std::pair<int, double>>> rows(nrows);
   for (int r = 0; r < nrows; ++r) {
     const int len = (rng() % 7 == 0) ? 0 : (int)(rng() % (maxlen + 1));

@@ -1,6 +1,7 @@
 // Host-only driver of the setup code for sanitizer builds: assembles 2D and
 // 3D Laplacians with block partitions and runs every setup variant (RS /
-// HMIS, direct / extended+i, natural / CF row order, hybrid levels, batches).
+// HMIS, direct / extended+i, natural / CF row order, hybrid levels, batches;
+// paired / unpaired steps, sorted / local row order, 16-bit / int32 indices).
 // Exit status 0 when every setup returns OK and its layout checks pass.
 #include <cstdio>
 #include <string>
@@ -58,6 +59,12 @@ int main() {
           S.coarsen = coarsen;
           S.interp = interp;
           S.cf = cf;
+          // the other layouts (unpaired steps, local row order, int32
+          // indices) on a rotating subset of the variants
+          const int k = runs % 4;
+          S.pair = k != 1;
+          S.sort_window = k == 2 ? 0 : 128;
+          S.compress = k != 3;
           std::string err;
           int st;
           if (hybrid == 0) {
