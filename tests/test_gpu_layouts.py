@@ -1,14 +1,17 @@
 """GPU: the sliced-ELL layout options through the C ABI — 16-bit or int32
 column indices (AMGDD_INDEX32), rows of grouped levels sorted by length or
-kept in local order (AMGDD_SORT_WINDOW=0), paired or unpaired load steps
+kept in local order (AMGDD_SORT_WINDOW), paired or unpaired load steps
 (AMGDD_UNPAIRED).
 
-Index width and row order change neither the entries of a row nor the order
-in which each lane adds them (padding adds exact zeros), so every iterate is
-bitwise identical, for AMG-DD, the V-cycle and the hybrid cycle, in FP64 and
-in mixed precision.  Unpaired steps give the lanes of a grouped row other
-subsets of its entries, so their iterates are held to the oracle bar
-instead (1e-12 relative, FP64)."""
+Index width changes neither the entries of a row nor the order in which each
+lane adds them (padding adds exact zeros), so iterates are bitwise identical
+for AMG-DD, the V-cycle and the hybrid cycle, in FP64 and mixed precision.
+With unpaired steps lane j of a row with G lanes adds entries j, j + G, ...
+wherever the row sits, so row order is bitwise neutral too.  With paired
+steps a slice of u steps holds floor(u/2) paired steps and an unpaired one
+when u is odd, and u is set by the slice's longest row: which lane adds which
+entry of a grouped row then depends on its neighbours, so row order and
+pairing are held to the oracle bar (1e-12 relative, FP64)."""
 
 import sys
 
@@ -63,41 +66,53 @@ def _run(p, monkeypatch, env, precision="fp64", hybrid=0, iters=4):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_index_width_and_row_order_are_bitwise_neutral(name, precision, monkeypatch):
+def test_index_width_is_bitwise_neutral(name, precision, monkeypatch):
     p = CASES[name]()
-    say("layout neutrality", name, precision, p.n)
-    ref = _run(p, monkeypatch, {}, precision)
-    for env in ({"AMGDD_INDEX32": "1"}, {"AMGDD_SORT_WINDOW": "0"}, {"AMGDD_SORT_WINDOW": "32"},
-                {"AMGDD_INDEX32": "1", "AMGDD_SORT_WINDOW": "0"}):
-        got = _run(p, monkeypatch, env, precision)
-        say("  ", env)
-        assert np.array_equal(got[0], ref[0]), env
-        assert np.array_equal(got[1], ref[1]), env
+    say("index width", name, precision, p.n)
+    for base in ({}, {"AMGDD_UNPAIRED": "1", "AMGDD_SORT_WINDOW": "0"}):
+        ref = _run(p, monkeypatch, base, precision)
+        got = _run(p, monkeypatch, dict(base, AMGDD_INDEX32="1"), precision)
+        say("  ", base)
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), base
 
 
-def test_hybrid_cycle_is_bitwise_neutral_to_row_order_and_index_width(monkeypatch):
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_row_order_is_bitwise_neutral_with_unpaired_steps(name, precision, monkeypatch):
+    p = CASES[name]()
+    say("row order, unpaired steps", name, precision, p.n)
+    ref = _run(p, monkeypatch, {"AMGDD_UNPAIRED": "1", "AMGDD_SORT_WINDOW": "0"}, precision)
+    for w in ("32", "128"):
+        got = _run(p, monkeypatch, {"AMGDD_UNPAIRED": "1", "AMGDD_SORT_WINDOW": w}, precision)
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), w
+
+
+def test_hybrid_cycle_is_bitwise_neutral_to_index_width_and_unpaired_row_order(monkeypatch):
     p = CASES["3d_30_ragged_4x4x4"]()
     say("hybrid layout neutrality", p.n)
     ref = _run(p, monkeypatch, {}, hybrid=2)
-    for env in ({"AMGDD_INDEX32": "1"}, {"AMGDD_SORT_WINDOW": "0"}):
-        got = _run(p, monkeypatch, env, hybrid=2)
-        assert np.array_equal(got[0], ref[0]), env
+    got = _run(p, monkeypatch, {"AMGDD_INDEX32": "1"}, hybrid=2)
+    assert np.array_equal(got[0], ref[0])
+    ref = _run(p, monkeypatch, {"AMGDD_UNPAIRED": "1"}, hybrid=2)
+    got = _run(p, monkeypatch, {"AMGDD_UNPAIRED": "1", "AMGDD_SORT_WINDOW": "0"}, hybrid=2)
+    assert np.array_equal(got[0], ref[0])
 
 
 @pytest.mark.parametrize("name", list(CASES))
-def test_unpaired_steps_match_the_oracle(name, monkeypatch):
+def test_every_layout_matches_the_oracle(name, monkeypatch):
     p = CASES[name]()
-    say("unpaired steps vs oracle", name, p.n)
+    say("layouts vs oracle", name, p.n)
     H = amg.setup(p.A)
     comps = composite.build_all(H, p.part, p.nparts, p.eta)
     coarse = cycles.CoarseSolver(H.A[H.L])
-    for env in ({"AMGDD_UNPAIRED": "1"}, {"AMGDD_UNPAIRED": "1", "AMGDD_INDEX32": "1"}):
+    xo = np.zeros(p.n)
+    xvo = np.zeros(p.n)
+    for _ in range(3):
+        xo = cycles.amgdd_iteration(H, comps, p.b, xo, p.n_fac, coarse)
+        xvo = cycles.vcycle(H, xvo, p.b, coarse=coarse)
+    for env in ({}, {"AMGDD_SORT_WINDOW": "0"}, {"AMGDD_SORT_WINDOW": "32"}, {"AMGDD_UNPAIRED": "1"},
+                {"AMGDD_UNPAIRED": "1", "AMGDD_INDEX32": "1"}):
         x, xv = _run(p, monkeypatch, env, iters=3)
-        xo = np.zeros(p.n)
-        xvo = np.zeros(p.n)
-        for _ in range(3):
-            xo = cycles.amgdd_iteration(H, comps, p.b, xo, p.n_fac, coarse)
-            xvo = cycles.vcycle(H, xvo, p.b, coarse=coarse)
         err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
         errv = np.linalg.norm(xv - xvo) / np.linalg.norm(xvo)
         say("  ", env, f"amgdd {err:.2e} vcycle {errv:.2e}")
