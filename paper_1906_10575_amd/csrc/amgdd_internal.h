@@ -71,7 +71,7 @@ struct ProblemHost {
 struct Sell {
   int nrows = 0;
   int lg = 0;
-  int vlg = 0;  // 1: paired steps (two entries per lane and load step)
+  int vlg = 0;  // log2 entries per lane in the widest load steps (0, 1 or 2)
   std::vector<int> sptr;
   std::vector<int> col;
   std::vector<double> val;
@@ -130,9 +130,12 @@ struct Setup {
   bool cf = false;
   // 16-bit column indices for every matrix whose slices allow them
   bool compress = true;
-  // paired sliced-ELL steps: each lane loads two consecutive entries of its
-  // row per step (the device mat-vec gives the address map); false: one
-  bool pair = true;
+  // log2 of the entries of its row each lane loads per sliced-ELL step in
+  // the widest steps (the device mat-vec gives the address map): 0 one,
+  // 1 two (paired), 2 four; for the global operators and for the composite
+  // operators (four when those are stored in FP32: one 16-byte value load)
+  int step_log2 = 1;
+  int comp_step_log2 = 1;
   // on levels with grouped rows, each grid's real and ghost rows are sorted
   // by decreasing length within windows of this many rows (0: local order)
   int sort_window = 128;

@@ -85,7 +85,7 @@ struct DSell {
   int *base = nullptr;              // two bases per slice
   int nrows = 0;
   int lg = 0;           // lanes per row (log2)
-  int vlg = 0;          // 1: paired layout
+  int vlg = 0;          // log2 entries per lane in the widest steps
   long long entries = 0;
   template <typename T>
   dev::SellD<T> as() const {
@@ -933,11 +933,13 @@ amgdd_status make_handle(const std::vector<ProblemInput> &in, const amgdd_params
   h->S.interp = p.interp;
   h->S.interp_max = p.interp_max;
   h->S.cf = p.relax_order == 1;
-  // measurement / testing: int32 column indices everywhere, one entry per
-  // lane and step, rows in local order (every one gives the same results;
-  // only the unpaired layout changes the summation order of grouped rows)
+  // measurement / testing: int32 column indices everywhere, one or four
+  // entries per lane and step everywhere, the row-sorting window
   h->S.compress = std::getenv("AMGDD_INDEX32") == nullptr;
-  h->S.pair = std::getenv("AMGDD_UNPAIRED") == nullptr;
+  // composite operators stored in FP32 load four entries per lane and step
+  if (p.precision == AMGDD_MIXED) h->S.comp_step_log2 = 2;
+  if (std::getenv("AMGDD_QUAD")) h->S.step_log2 = h->S.comp_step_log2 = 2;
+  if (std::getenv("AMGDD_UNPAIRED")) h->S.step_log2 = h->S.comp_step_log2 = 0;
   if (const char *e = std::getenv("AMGDD_SORT_WINDOW")) h->S.sort_window = std::max(0, std::atoi(e));
   std::string err;
   Setup inner_S;

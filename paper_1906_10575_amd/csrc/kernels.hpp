@@ -10,10 +10,10 @@
 // r at
 //     sptr[slice] + 64*k + (r mod 64/G)*G + j
 // so every load instruction of a wavefront is one contiguous 128-byte (16-bit
-// index) / 512-byte (FP64) segment.  Paired matrices (see sell_dot2) store two
-// consecutive entries of a row per lane and step instead, halving the index
-// and value load instructions per entry (the slices keep the same size: an
-// odd last step stays unpaired).  Each lane accumulates its entries in order; the
+// index) / 512-byte (FP64) segment.  Wide-step matrices (see sell_dotw) store
+// two or four consecutive entries of a row per lane and step instead, cutting
+// the index and value load instructions per entry (the slices keep the same
+// size: the last steps narrow down to what is left).  Each lane accumulates its entries in order; the
 // G partial sums are combined by an xor-shuffle tree (fixed order, so results
 // do not depend on the launch schedule).  Padding entries carry value 0 and a
 // column of the row's own grid.
@@ -69,7 +69,7 @@ struct SellD {
   int lg;  // lanes per row G = 1 << lg
   const unsigned short *col16;
   const int *base;
-  int vlg;  // 1: paired steps (see sell_dot2)
+  int vlg;  // log2 entries per lane in the widest steps (see sell_dotw)
 };
 
 // Workgroups are dispatched round-robin over the 8 XCDs; remap so that each
@@ -91,50 +91,60 @@ __device__ __forceinline__ V group_sum(V acc, int lg) {
   return acc;
 }
 
-// Paired layout: a slice of 64u entries (u unpaired steps of 64 lanes) holds
-// floor(u/2) paired steps first, then one unpaired step when u is odd.  Paired
-// step k stores, for lane p = (r mod 64/G)*G + j, entries 2(kG + j) and
-// 2(kG + j) + 1 of row r at sptr[slice] + 128k + 2p + {0, 1}: one 16-byte
-// (FP64) / 8-byte (FP32) value load and one 32-bit index load per lane and
-// step.  The unpaired step stores entry 2G floor(u/2) + j at
-// sptr[slice] + 128 floor(u/2) + p.  Each lane accumulates in storage order.
-template <typename T, typename V>
-__device__ __forceinline__ V sell_dot2(const SellD<T> &M, int s, int beg, int r, int sub, const V *__restrict__ x) {
+// Wide load steps: a slice of 64u entries (u unpaired steps of 64 lanes)
+// whose widest steps carry W = 2^VL entries per lane holds floor(u/W) steps
+// of 64W entries first, then one step of 64 * 2^v entries for each narrower
+// width 2^v whose bit is set in u (v = VL-1 .. 0), so slices keep the size
+// of the unpaired layout.  A step of width 2^v stores, for lane
+// p = (r mod 64/G)*G + j, 2^v consecutive entries of row r at offset p 2^v
+// (the first step of the widest region holds entries 0 .. W-1 of lane j's
+// share, i.e. entries jW .. jW + W-1 of the row): one W-wide value load
+// (16 bytes for two FP64 or four FP32 values) and one W-wide load of 16-bit
+// indices per lane and step.  Each lane accumulates in storage order.
+template <typename T, typename V, int VL>
+__device__ __forceinline__ V sell_dotw(const SellD<T> &M, int s, int beg, int r, int sub, const V *__restrict__ x) {
+  constexpr int W = 1 << VL;
+  typedef T TW __attribute__((ext_vector_type(W)));
   typedef T T2 __attribute__((ext_vector_type(2)));
+  typedef unsigned short CW __attribute__((ext_vector_type(W)));
   typedef unsigned short C2 __attribute__((ext_vector_type(2)));
+  typedef int IW __attribute__((ext_vector_type(W)));
   typedef int I2 __attribute__((ext_vector_type(2)));
   const int lg = M.lg;
-  const int u = (M.sptr[s + 1] - beg) >> 6, w = u >> 1;
+  const int u = (M.sptr[s + 1] - beg) >> 6, w = u >> VL;
   const int p = ((r & ((64 >> lg) - 1)) << lg) + sub;
-  const T2 *__restrict__ v = (const T2 *)(M.val + beg + 2 * p);
-  const int tail = beg + 128 * w + p;
-  constexpr int U = AMGDD_UNROLL / 2 > 0 ? AMGDD_UNROLL / 2 : 1;
+  const TW *__restrict__ v = (const TW *)(M.val + beg + W * p);
+  // narrower steps after the widest region
+  const int off2 = beg + (w << (6 + VL));                          // width 2 (VL == 2 only)
+  const int has2 = VL == 2 ? (u >> 1) & 1 : 0;
+  const int off1 = off2 + (has2 << 7);                             // width 1
+  constexpr int U = AMGDD_UNROLL / W > 0 ? AMGDD_UNROLL / W : 1;  // steps in flight
   V acc = V(0);
   int k = 0;
   if (M.col16) {
-    const C2 *__restrict__ c = (const C2 *)(M.col16 + beg + 2 * p);
+    const CW *__restrict__ c = (const CW *)(M.col16 + beg + W * p);
     const int b0 = M.base[2 * s], b1 = M.base[2 * s + 1];
     auto dec = [&](unsigned short q) { return ((q & 0x8000) ? b1 : b0) + (int)(q & 0x7fff); };
     if (k + U <= w) {
-      C2 cn[U];
-      T2 vn[U];
+      CW cn[U];
+      TW vn[U];
 #pragma unroll
       for (int j = 0; j < U; ++j) {
         cn[j] = __builtin_nontemporal_load(c + 64 * (k + j));
         vn[j] = __builtin_nontemporal_load(v + 64 * (k + j));
       }
       for (; k + U <= w; k += U) {
-        int cc[2 * U];
-        V vv[2 * U], xx[2 * U];
+        int cc[W * U];
+        V vv[W * U], xx[W * U];
 #pragma unroll
-        for (int j = 0; j < U; ++j) {
-          cc[2 * j] = dec(cn[j].x);
-          cc[2 * j + 1] = dec(cn[j].y);
-          vv[2 * j] = (V)vn[j].x;
-          vv[2 * j + 1] = (V)vn[j].y;
-        }
+        for (int j = 0; j < U; ++j)
 #pragma unroll
-        for (int j = 0; j < 2 * U; ++j) xx[j] = x[cc[j]];
+          for (int e = 0; e < W; ++e) {
+            cc[W * j + e] = dec(cn[j][e]);
+            vv[W * j + e] = (V)vn[j][e];
+          }
+#pragma unroll
+        for (int j = 0; j < W * U; ++j) xx[j] = x[cc[j]];
         if (k + 2 * U <= w) {
 #pragma unroll
           for (int j = 0; j < U; ++j) {
@@ -143,48 +153,64 @@ __device__ __forceinline__ V sell_dot2(const SellD<T> &M, int s, int beg, int r,
           }
         }
 #pragma unroll
-        for (int j = 0; j < 2 * U; ++j) acc = fma(vv[j], xx[j], acc);
+        for (int j = 0; j < W * U; ++j) acc = fma(vv[j], xx[j], acc);
       }
     }
     for (; k < w; ++k) {
-      const C2 cq = __builtin_nontemporal_load(c + 64 * k);
-      const T2 vq = __builtin_nontemporal_load(v + 64 * k);
+      const CW cq = __builtin_nontemporal_load(c + 64 * k);
+      const TW vq = __builtin_nontemporal_load(v + 64 * k);
+      V xx[W];
+#pragma unroll
+      for (int e = 0; e < W; ++e) xx[e] = x[dec(cq[e])];
+#pragma unroll
+      for (int e = 0; e < W; ++e) acc = fma((V)vq[e], xx[e], acc);
+    }
+    if (has2) {
+      const C2 cq = __builtin_nontemporal_load((const C2 *)(M.col16 + off2 + 2 * p));
+      const T2 vq = __builtin_nontemporal_load((const T2 *)(M.val + off2 + 2 * p));
       const V x0 = x[dec(cq.x)], x1 = x[dec(cq.y)];
       acc = fma((V)vq.x, x0, acc);
       acc = fma((V)vq.y, x1, acc);
     }
     if (u & 1)
-      acc = fma((V)__builtin_nontemporal_load(M.val + tail), x[dec(__builtin_nontemporal_load(M.col16 + tail))], acc);
+      acc = fma((V)__builtin_nontemporal_load(M.val + off1 + p), x[dec(__builtin_nontemporal_load(M.col16 + off1 + p))], acc);
   } else {
-    const I2 *__restrict__ c = (const I2 *)(M.col + beg + 2 * p);
+    const IW *__restrict__ c = (const IW *)(M.col + beg + W * p);
     for (; k + U <= w; k += U) {
-      I2 cq[U];
-      T2 vq[U];
-      V xx[2 * U];
+      IW cq[U];
+      TW vq[U];
+      V xx[W * U];
 #pragma unroll
       for (int j = 0; j < U; ++j) {
         cq[j] = __builtin_nontemporal_load(c + 64 * (k + j));
         vq[j] = __builtin_nontemporal_load(v + 64 * (k + j));
       }
 #pragma unroll
-      for (int j = 0; j < U; ++j) {
-        xx[2 * j] = x[cq[j].x];
-        xx[2 * j + 1] = x[cq[j].y];
-      }
+      for (int j = 0; j < U; ++j)
 #pragma unroll
-      for (int j = 0; j < U; ++j) {
-        acc = fma((V)vq[j].x, xx[2 * j], acc);
-        acc = fma((V)vq[j].y, xx[2 * j + 1], acc);
-      }
+        for (int e = 0; e < W; ++e) xx[W * j + e] = x[cq[j][e]];
+#pragma unroll
+      for (int j = 0; j < U; ++j)
+#pragma unroll
+        for (int e = 0; e < W; ++e) acc = fma((V)vq[j][e], xx[W * j + e], acc);
     }
     for (; k < w; ++k) {
-      const I2 cq = __builtin_nontemporal_load(c + 64 * k);
-      const T2 vq = __builtin_nontemporal_load(v + 64 * k);
+      const IW cq = __builtin_nontemporal_load(c + 64 * k);
+      const TW vq = __builtin_nontemporal_load(v + 64 * k);
+      V xx[W];
+#pragma unroll
+      for (int e = 0; e < W; ++e) xx[e] = x[cq[e]];
+#pragma unroll
+      for (int e = 0; e < W; ++e) acc = fma((V)vq[e], xx[e], acc);
+    }
+    if (has2) {
+      const I2 cq = __builtin_nontemporal_load((const I2 *)(M.col + off2 + 2 * p));
+      const T2 vq = __builtin_nontemporal_load((const T2 *)(M.val + off2 + 2 * p));
       const V x0 = x[cq.x], x1 = x[cq.y];
       acc = fma((V)vq.x, x0, acc);
       acc = fma((V)vq.y, x1, acc);
     }
-    if (u & 1) acc = fma((V)__builtin_nontemporal_load(M.val + tail), x[__builtin_nontemporal_load(M.col + tail)], acc);
+    if (u & 1) acc = fma((V)__builtin_nontemporal_load(M.val + off1 + p), x[__builtin_nontemporal_load(M.col + off1 + p)], acc);
   }
   return group_sum(acc, lg);
 }
@@ -200,7 +226,8 @@ __device__ __forceinline__ V sell_dot(const SellD<T> &M, int r, int sub, const V
   int s = r >> (6 - lg);
   if (ALIGNED) s = __builtin_amdgcn_readfirstlane(s);
   const int beg = M.sptr[s];
-  if (M.vlg) return sell_dot2<T, V>(M, s, beg, r, sub, x);
+  if (M.vlg == 1) return sell_dotw<T, V, 1>(M, s, beg, r, sub, x);
+  if (M.vlg == 2) return sell_dotw<T, V, 2>(M, s, beg, r, sub, x);
   const int w = (M.sptr[s + 1] - beg) >> 6;
   const int off = beg + ((r & ((64 >> lg) - 1)) << lg) + sub;
   const T *__restrict__ v = M.val + off;

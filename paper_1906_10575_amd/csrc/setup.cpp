@@ -202,13 +202,24 @@ bool sell_in_bounds(const Sell &S, int nrows, int ncols) {
   return ok;
 }
 
-// Row (within its slice) of the entry stored at position `pos` of a slice of
-// `size` entries.  Unpaired: 64-entry steps of 64/G rows x G lanes.  Paired:
-// the first 128 * (size / 128) entries are 128-entry steps of 64 lanes x 2
-// entries, followed by at most one unpaired 64-entry step.
+// Step structure of a slice of `size` = 64u entries with widest steps of
+// V = 2^vlg entries per lane: floor(u/V) steps of 64V entries, then at most
+// one step of each narrower width (64 * 2^v entries for v = vlg-1 .. 0, when
+// bit v of u is set), so slice sizes equal those of the unpaired layout.
+// Step of width 2^v holds, for lane p = (r mod 64/G) G + j, the 2^v
+// consecutive entries of row r at offset p 2^v within the step.
+inline int sell_region_steps(int u, int vlg, int v) { return v == vlg ? (u >> v) : ((u >> v) & 1); }
+
+// Row (within its slice) of the entry stored at position `pos` of the slice.
 inline int sell_slice_row(const Sell &S, int size, int pos) {
-  if (S.vlg && pos < ((size >> 7) << 7)) return (pos & 127) >> (S.lg + 1);
-  return (pos & 63) >> S.lg;
+  const int u = size >> 6;
+  int base = 0;
+  for (int v = S.vlg; v > 0; --v) {
+    const int span = sell_region_steps(u, S.vlg, v) << (6 + v);
+    if (pos < base + span) return ((pos - base) & ((64 << v) - 1)) >> (S.lg + v);
+    base += span;
+  }
+  return ((pos - base) & 63) >> S.lg;
 }
 
 // Block-diagonal check: every stored entry of row r (padding included) must
@@ -240,10 +251,10 @@ struct SellBuilder {
   Sell S;
   std::vector<int> len;
   int rs = 64;  // rows per slice
-  void init(int nrows, int lg, bool pair) {
+  void init(int nrows, int lg, int step_log2) {
     S.nrows = nrows;
     S.lg = lg;
-    S.vlg = pair ? 1 : 0;
+    S.vlg = step_log2;
     rs = 64 >> lg;
     len.assign(nrows, 0);
   }
@@ -275,17 +286,19 @@ struct SellBuilder {
           S.val[at(r, k)] = 0.0;
         }
   }
-  // entry k of row r (see sell_slice_row for the step structure)
+  // entry k of row r (see sell_region_steps for the step structure)
   inline size_t at(int r, int k) const {
-    const int lg = S.lg, s = r / rs;
-    const size_t b = (size_t)S.sptr[s];
-    if (S.vlg) {
-      const int np = (S.sptr[s + 1] - S.sptr[s]) >> 7, gv = lg + 1;
-      const int kp = np << gv;  // entries of the row held in paired steps
-      if (k < kp) return b + ((size_t)(k >> gv) << 7) + ((size_t)(r % rs) << gv) + (k & ((1 << gv) - 1));
-      return b + ((size_t)np << 7) + ((size_t)(r % rs) << lg) + (k - kp);
+    const int lg = S.lg, s = r / rs, u = (S.sptr[s + 1] - S.sptr[s]) >> 6;
+    size_t b = (size_t)S.sptr[s];
+    for (int v = S.vlg; v >= 0; --v) {
+      const int steps = sell_region_steps(u, S.vlg, v), gv = lg + v;
+      const int per_row = steps << gv;  // entries of the row in this region
+      if (k < per_row || v == 0)
+        return b + ((size_t)(k >> gv) << (6 + v)) + ((size_t)(r % rs) << gv) + (k & ((1 << gv) - 1));
+      k -= per_row;
+      b += (size_t)steps << (6 + v);
     }
-    return b + 64 * (size_t)(k >> lg) + ((size_t)(r % rs) << lg) + (k & ((1 << lg) - 1));
+    return b;
   }
   inline void put(int r, int k, int c, double v) {
     const size_t a = at(r, k);
@@ -1337,8 +1350,8 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
     const int nn = (int)normal.size();
     // ---- composite A and P rows of normal grids, dinv, gather sources
     SellBuilder bA, bP;
-    bA.init(B.NBn, B.lg, S.pair);
-    bP.init(B.NBn, B.plg, S.pair);
+    bA.init(B.NBn, B.lg, S.comp_step_log2);
+    bP.init(B.NBn, B.plg, S.comp_step_log2);
     B.dinv.assign(B.NRn, 0.0);
     B.gsrc.assign(B.NB, -1);
     parallel_items(ng, [&](int g, int) {
@@ -1396,7 +1409,7 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
     if (l < maxL) {
       BatchLevel &Bn = S.lv[l + 1];
       SellBuilder bR;
-      bR.init(Bn.NB, Bn.lg, S.pair);
+      bR.init(Bn.NB, Bn.lg, S.comp_step_log2);
       std::vector<Csr> Rl(nn);
       parallel_items(nn, [&](int k, int) {
         int g = normal[k];
@@ -1431,8 +1444,8 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
     tp = now_s();
     // ---- global level l over problems
     SellBuilder bGA, bGP;
-    bGA.init(B.GN, B.glg, S.pair);
-    bGP.init(B.GNn, B.gplg, S.pair);
+    bGA.init(B.GN, B.glg, S.step_log2);
+    bGP.init(B.GNn, B.gplg, S.step_log2);
     B.gdinv.assign(B.GNn, 0.0);
     B.prob_row0.assign(nprob, -1);
     for (int q = 0; q < nprob; ++q) {
@@ -1503,7 +1516,7 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
       // R_l = P_l^T is stored in the hierarchy; rows = level l+1
       BatchLevel &Bn = S.lv[l + 1];
       SellBuilder bGR;
-      bGR.init(Bn.GN, Bn.glg, S.pair);
+      bGR.init(Bn.GN, Bn.glg, S.step_log2);
       parallel_items(nprob, [&](int q, int) {
         const Hierarchy &H = S.probs[q].H;
         if (l >= H.L()) return;
@@ -1685,7 +1698,8 @@ int build_setup_hybrid(const std::vector<ProblemInput> &in, double theta, int ma
     inner.interp = outer.interp;
     inner.interp_max = outer.interp_max;
     inner.compress = outer.compress;
-    inner.pair = outer.pair;
+    inner.step_log2 = outer.step_log2;
+    inner.comp_step_log2 = outer.comp_step_log2;
     inner.sort_window = outer.sort_window;
     inner.theta = theta;
     inner.max_coarse = max_coarse;

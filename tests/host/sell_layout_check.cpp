@@ -1,7 +1,8 @@
-// Host check of the grouped sliced-ELL packing (unpaired and paired steps)
+// Host check of the grouped sliced-ELL packing (one, two or four entries per
+// lane and step)
 // against an independent walk of the addresses the device mat-vec reads.
 // Random row lengths (empty rows, ragged slices, a partial last slice) for
-// every lane count G = 1..16, both step kinds.  For each row, the entries
+// every lane count G = 1..16, every step width.  For each row, the entries
 // reached by the walk of its G lanes, in the order each lane accumulates
 // them, must be the row's entries in storage order followed by padding
 // (value 0, the row's last column); every stored position must be reached
@@ -16,31 +17,46 @@
 using namespace amgdd;
 
 // Positions lane `sub` of row r reads, in its accumulation order, following
-// the device address map: unpaired steps at sptr + 64k + p; paired steps at
-// sptr + 128k + 2p + {0, 1} for the first floor(u/2) steps, then one
-// unpaired step at sptr + 128 floor(u/2) + p when u is odd
-// (p = (r mod 64/G) G + sub, u = slice size / 64).
+// the device address map: with widest steps of W = 2^vlg entries per lane, a
+// slice of u = size/64 unpaired-step equivalents holds floor(u/W) steps at
+// sptr + 64W k + W p + {0..W-1}, then one step of width 2^v at the next
+// 64 * 2^v entries for every bit v < vlg set in u, narrowest last
+// (p = (r mod 64/G) G + sub).
 static std::vector<size_t> lane_walk(const Sell &S, int r, int sub) {
-  const int rs = 64 >> S.lg, s = r / rs, beg = S.sptr[s], u = (S.sptr[s + 1] - beg) / 64;
+  const int rs = 64 >> S.lg, s = r / rs, u = (S.sptr[s + 1] - S.sptr[s]) / 64;
   const int p = (r % rs) * (1 << S.lg) + sub;
   std::vector<size_t> out;
-  if (!S.vlg) {
-    for (int k = 0; k < u; ++k) out.push_back((size_t)beg + 64 * k + p);
-    return out;
+  size_t base = S.sptr[s];
+  for (int v = S.vlg; v >= 0; --v) {
+    const int steps = v == S.vlg ? u >> v : (u >> v) & 1, W = 1 << v;
+    for (int k = 0; k < steps; ++k)
+      for (int e = 0; e < W; ++e) out.push_back(base + 64 * W * k + W * p + e);
+    base += (size_t)64 * W * steps;
   }
-  for (int k = 0; k < u / 2; ++k) {
-    out.push_back((size_t)beg + 128 * k + 2 * p);
-    out.push_back((size_t)beg + 128 * k + 2 * p + 1);
-  }
-  if (u % 2) out.push_back((size_t)beg + 128 * (u / 2) + p);
   return out;
+}
+
+// Entries of its row lane j adds, in order: region by region (widest first),
+// step k of width W holds entries K + (k G + j) W + {0..W-1}, where K counts
+// the row's entries in the earlier regions.
+static std::vector<int> lane_entries(const Sell &S, int r, int j) {
+  const int rs = 64 >> S.lg, s = r / rs, u = (S.sptr[s + 1] - S.sptr[s]) / 64, G = 1 << S.lg;
+  std::vector<int> ks;
+  int K = 0;
+  for (int v = S.vlg; v >= 0; --v) {
+    const int steps = v == S.vlg ? u >> v : (u >> v) & 1, W = 1 << v;
+    for (int k = 0; k < steps; ++k)
+      for (int e = 0; e < W; ++e) ks.push_back(K + (k * G + j) * W + e);
+    K += steps * G * W;
+  }
+  return ks;
 }
 
 static int check(int nrows, int lg, int vlg, int maxlen, unsigned seed) {
   std::mt19937 rng(seed);
   const int G = 1 << lg;
   SellBuilder b;
-  b.init(nrows, lg, vlg != 0);
+  b.init(nrows, lg, vlg);
   std::vector<std::vector<std::pair<int, double>>> rows(nrows);
   for (int r = 0; r < nrows; ++r) {
     const int len = (rng() % 7 == 0) ? 0 : (int)(rng() % (maxlen + 1));
@@ -81,20 +97,10 @@ static int check(int nrows, int lg, int vlg, int maxlen, unsigned seed) {
         return 5;
       }
     }
-    // lane j accumulates entries kG + j (unpaired steps), or 2(mG + j),
-    // 2(mG + j) + 1 for paired steps m, then 2G floor(u/2) + j
+    // lane j adds the entries the layout assigns it, in storage order
     for (int j = 0; j < G; ++j) {
-      std::vector<int> ks;
-      if (!S.vlg) {
-        for (int k = 0; k < per_lane; ++k) ks.push_back(k * G + j);
-      } else {
-        const int np = per_lane / 2;
-        for (int m = 0; m < np; ++m) {
-          ks.push_back(2 * (m * G + j));
-          ks.push_back(2 * (m * G + j) + 1);
-        }
-        if (per_lane % 2) ks.push_back(2 * G * np + j);
-      }
+      const std::vector<int> ks = lane_entries(S, r, j);
+      if ((int)ks.size() != per_lane) return 6;
       for (int q = 0; q < per_lane; ++q)
         if (b.at(r, ks[q]) != walks[j][q]) return 6;
     }
@@ -126,7 +132,7 @@ int main() {
   int fails = 0, runs = 0;
   const int sizes[] = {1, 63, 64, 65, 200, 1000};
   for (int lg = 0; lg <= 4; ++lg)
-    for (int vlg = 0; vlg <= 1; ++vlg)
+    for (int vlg = 0; vlg <= 2; ++vlg)
       for (int n : sizes)
         for (int maxlen : {1, 3, 7, 20, 70}) {
           const int rc = check(n, lg, vlg, maxlen, 1000u * lg + 100u * vlg + (unsigned)n + 7u * maxlen);

@@ -1,7 +1,8 @@
 // Host-only driver of the setup code for sanitizer builds: assembles 2D and
 // 3D Laplacians with block partitions and runs every setup variant (RS /
 // HMIS, direct / extended+i, natural / CF row order, hybrid levels, batches;
-// paired / unpaired steps, sorted / local row order, 16-bit / int32 indices).
+// one / two / four entries per lane and step, sorted / local row order,
+// 16-bit / int32 indices).
 // Exit status 0 when every setup returns OK and its layout checks pass.
 #include <cstdio>
 #include <string>
@@ -62,7 +63,8 @@ int main() {
           // the other layouts (unpaired steps, local row order, int32
           // indices) on a rotating subset of the variants
           const int k = runs % 4;
-          S.pair = k != 1;
+          S.step_log2 = k == 1 ? 0 : (k == 2 ? 2 : 1);
+          S.comp_step_log2 = k == 3 ? 2 : S.step_log2;
           S.sort_window = k == 2 ? 0 : 128;
           S.compress = k != 3;
           std::string err;

@@ -28,7 +28,7 @@ def test_setup_under_asan_ubsan(tmp_path):
 
 @pytest.mark.skipif(shutil.which("g++") is None, reason="g++ not available")
 def test_sliced_ell_packing_matches_the_device_walk(tmp_path):
-    """Unpaired and paired sliced-ELL packing, every lane count, ragged and
+    """Sliced-ELL packing with one, two or four entries per lane and step, every lane count, ragged and
     empty rows: the addresses each lane of the device mat-vec reads give the
     row's entries in the documented accumulation order (under ASan/UBSan)."""
     exe = tmp_path / "sell_layout_check"
@@ -38,4 +38,4 @@ def test_sliced_ell_packing_matches_the_device_walk(tmp_path):
     subprocess.run(cmd, check=True, capture_output=True, timeout=600)
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=600, env=dict(os.environ, AMGDD_THREADS="4"))
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
-    assert "300 layouts, 0 failed" in r.stdout
+    assert "450 layouts, 0 failed" in r.stdout
