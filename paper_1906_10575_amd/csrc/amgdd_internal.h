@@ -125,7 +125,8 @@ struct Setup {
   int max_coarse = 16, max_levels = 25;
   // CF-ordered relaxation: class arrays are filled and each grid's real rows
   // of a level are stored C-points first (Jacobi within a class does not
-  // depend on row order, so results are the same; the half-sweeps then read
+  // depend on row order, so results agree up to the rounding of grouped rows,
+  // whose lanes' shares follow their slice; the half-sweeps then read
   // contiguous row ranges)
   bool cf = false;
   // 16-bit column indices for every matrix whose slices allow them

@@ -1241,7 +1241,9 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
   // a sort window > 0, rows are then sorted by decreasing length within
   // consecutive windows of that many rows (never across the C/F boundary),
   // so sliced-ELL slices hold rows of similar length; ghost rows likewise.
-  // Jacobi sweeps and mat-vecs do not depend on row order.
+  // Jacobi sweeps and mat-vecs do not depend on row order (up to the
+  // rounding of grouped rows: with wide steps, which lane adds which entry
+  // depends on the step count of the row's slice).
   const int sortw = S.sort_window;
   std::vector<char> sort_lv(maxL + 1, 0);
   for (int l = 0; l <= maxL && sortw > 0; ++l) {
