@@ -11,7 +11,7 @@ solve time.  The V(1,1) cycle on the same hierarchy, the hybrid AMG-DD
 V-cycle (AMG-DD on a transition level, Algorithm 3) and the mixed-precision
 form are timed beside it and reported as extra fields.
 
-Prints one JSON line.  --gpus must be 1 (this build runs on one GPU).
+Prints one JSON line.  --gpus must be 1 (the solver runs on one device).
 """
 
 from __future__ import annotations
@@ -280,7 +280,7 @@ def main():
         print(summarize_pmc(args.summarize_pmc))
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
+        print(f"bench.py: the solver runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -52,7 +52,7 @@ typedef enum {
   AMGDD_EDEVICE = 3,      /* HIP error, or a device call on a host-only handle */
   AMGDD_ENOCONV = 4,      /* maxit reached above rtol; x holds the last iterate */
   AMGDD_EBREAKDOWN = 5,   /* non-finite residual norm */
-  AMGDD_EUNSUPPORTED = 6  /* valid input outside what this build supports */
+  AMGDD_EUNSUPPORTED = 6  /* valid input outside what the library supports */
 } amgdd_status;
 
 typedef enum { AMGDD_FP64 = 0, AMGDD_MIXED = 1 } amgdd_precision;

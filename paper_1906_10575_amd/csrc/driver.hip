@@ -1079,7 +1079,7 @@ amgdd_status amgv_solve(amgdd_handle h, const double *b_dev, double *x_dev, doub
 amgdd_status amgdd_solve_adjoint(amgdd_handle h, const double *g_dev, double *lambda_dev, double rtol, int maxit,
                                  amgdd_info *info) {
   if (!h) return fail(ST_EINVAL, "null handle");
-  if (!h->symmetric) return fail(ST_EUNSUP, "adjoint of a non-symmetric operator is not supported by this build");
+  if (!h->symmetric) return fail(ST_EUNSUP, "adjoint solves need a symmetric operator (A^T = A is used)");
   return run_solve(h, SOLVE_DD, g_dev, lambda_dev, rtol, maxit, info);
 }
 

@@ -1,0 +1,71 @@
+"""Host checks of bench.py's measurement plumbing: the one-GPU guard, the
+roofline arithmetic, the rocprofv3 counter summary, and the committed HBM
+traffic records (current for the kernel source, scaled consistently, close
+to the algorithmic bytes)."""
+
+import glob
+import hashlib
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in r.stderr and not r.stdout.strip()
+
+
+def test_roofline_takes_the_largest_site_per_launch():
+    prof = [dict(name="w", level=1, launches=2, ms=0.10, bytes=2 * 300e6, workgroups=7, block=256),
+            dict(name="down", level=1, launches=2, ms=0.16, bytes=2 * 400e6, workgroups=7, block=256),
+            dict(name="interp", level=0, launches=1, ms=0.05, bytes=100e6, workgroups=9, block=256)]
+    dom, roof = bench.roofline(prof)
+    assert dom["name"] == "down"
+    assert roof["ms_per_launch"] == pytest.approx(0.08)
+    assert roof["bytes_per_launch"] == pytest.approx(400e6)
+    assert roof["achieved"] == pytest.approx(400e6 / 0.08e-3 / 1e9, rel=1e-3)
+    assert roof["frac"] == pytest.approx(roof["achieved"] / roof["peak"], abs=1e-4)
+    assert roof["bound"] == "hbm" and roof["unit"] == "GB/s" and roof["peak"] == 8000.0
+
+
+def test_pmc_summary_averages_per_kernel_and_launch_size(tmp_path):
+    csv = tmp_path / "run_counter_collection.csv"
+    csv.write_text("Kernel_Name,Grid_Size,Workgroup_Size,Counter_Name,Counter_Value\n"
+                   "void amgdd::dev::k_relax<double>(x),1856256,256,FETCH_SIZE,100\n"
+                   "void amgdd::dev::k_relax<double>(x),1856256,256,FETCH_SIZE,300\n"
+                   "void amgdd::dev::k_w<double>(x),2560,256,FETCH_SIZE,7\n")
+    out = bench.summarize_pmc(str(csv))
+    line = [l for l in out.splitlines() if l.startswith("k_relax<double>")][0]
+    assert line.split()[1] == "7251" and line.split()[-2] == "2" and float(line.split()[-1]) == 200.0
+
+
+def _records():
+    return sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json")))
+
+
+def test_traffic_records_are_current_and_consistent():
+    recs = _records()
+    assert recs, "no traffic record in profiles/"
+    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_1906_10575_amd", "csrc", "kernels.hpp"), "rb").read()).hexdigest()
+    for path in recs:
+        r = json.load(open(path))
+        assert r["kernels_sha256"] == sha, f"{os.path.basename(path)} was measured on other kernels"
+        cal = r["calibration"]
+        assert cal["fetch_factor"] == pytest.approx(cal["fetch_size_kib"] / cal["expected_kib"], abs=1e-4)
+        assert cal["write_factor"] == pytest.approx(cal["write_size_kib"] / cal["expected_kib"], abs=1e-4)
+        t = (r["fetch_size_kib"] / cal["fetch_factor"] + r["write_size_kib"] / cal["write_factor"]) * 1024
+        assert r["traffic_bytes"] == pytest.approx(t, rel=1e-3)
+        assert 0.95 <= r["traffic_bytes"] / r["algorithmic_bytes"] <= 1.25
+        # bench.py finds the record for its launch site
+        dom = dict(name=r["site"], level=r["level"], workgroups=r["workgroups"])
+        assert bench.measured_traffic(dom) == r["traffic_bytes"]
