@@ -330,6 +330,31 @@ def test_every_schedule_gives_identical_iterates(name, oracle_cache):
     assert np.array_equal(_np(x), ref)
 
 
+@pytest.mark.parametrize("name", ["3d_20_var_eta2", "3d_30_ragged_4x4x4"])
+def test_mixed_every_schedule_gives_identical_iterates(name, oracle_cache):
+    """Mixed precision (FP32 composite operators with four entries per lane
+    and step): every launch schedule gives bitwise identical iterates, and
+    they stay within the float32 error scale of the FP64 oracle."""
+    p, H, comps = _oracle(name, oracle_cache)
+    b = _t(p.b)
+    nlev = H.L + 1
+    xo = np.zeros(p.n)
+    coarse = cycles.CoarseSolver(H.A[H.L])
+    for _ in range(3):
+        xo = cycles.amgdd_iteration(H, comps, p.b, xo, p.n_fac, coarse)
+    ref = None
+    for lt, bs in [(-1, 256), (0, 512), (1, 1024), (nlev // 2, 256)]:
+        say("mixed schedule", name, lt, bs)
+        s = amgdd.Solver(p.A, p.part, p.nparts, padding=p.eta, n_fac=p.n_fac, precision="mixed", tail_level=lt,
+                         tail_block=bs)
+        x, info, st = s.solve(b, rtol=0, maxit=3)
+        xn = _np(x)
+        if ref is None:
+            ref = xn
+        assert np.array_equal(xn, ref), (lt, bs)
+        assert _rel(xn, xo) <= 1e-5
+
+
 @pytest.mark.parametrize("name", ["3d_20_var_eta2", "p2_aniso_72", "2d_var_eta2_nfac3"])
 @pytest.mark.parametrize("relax", ["l1", "cf"])
 def test_best_practice_hierarchy_iterates(name, relax):
