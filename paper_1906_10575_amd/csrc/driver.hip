@@ -169,6 +169,13 @@ struct amgdd_ctx {
   int device = 0;
   hipStream_t stream = nullptr;      // caller's stream
   hipStream_t cap_stream = nullptr;  // private stream used for graph capture
+  // second branch of an AMG-DD iteration (restriction chain and coarse
+  // right-hand sides, beside the first cycle's level-0 passes); off when
+  // AMGDD_SERIAL is set
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  bool overlap = true;
+  long long f_off1 = 0;  // composite right-hand sides of level 0: arena entries [0, f_off1)
   std::vector<void *> allocs;
   long long dev_bytes = 0;
   long long max_bytes = 0;  // > 0: device-memory cap (AMGDD_TEST_MAX_BYTES, failure-path tests)
@@ -265,8 +272,11 @@ struct amgdd_ctx {
       for (void *p : allocs) (void)hipFree(p);
       if (h_norm2) (void)hipHostFree(h_norm2);
       if (cap_stream) (void)hipStreamDestroy(cap_stream);
+      if (side) (void)hipStreamDestroy(side);
       if (ev0) (void)hipEventDestroy(ev0);
       if (ev1) (void)hipEventDestroy(ev1);
+      if (ev_fork) (void)hipEventDestroy(ev_fork);
+      if (ev_join) (void)hipEventDestroy(ev_join);
     }
   }
 };
@@ -298,6 +308,7 @@ amgdd_status upload_all(amgdd_ctx *h) {
     roff[l + 1] = roff[l] + S.lv[l].GN;
   }
   h->f_total = foff[nl];
+  h->f_off1 = nl > 1 ? foff[1] : foff[nl];
   if ((st = h->alloc(&h->f_arena, foff[nl] * tsz))) return st;
   if (!S.grids.empty())
     if ((st = h->alloc(&h->r_arena, roff[nl] * tsz))) return st;
@@ -570,7 +581,8 @@ void enqueue_tail(amgdd_ctx *h, hipStream_t s, int lt, int ncycles, int first) {
 // the cut is level 0).  At the start and end of each cycle every level's u is
 // in buffer 0 (cur[l] == 0).
 template <typename T>
-void enqueue_fac(amgdd_ctx *h, hipStream_t s, int *cur) {
+// skip0: the first cycle's level-0 down passes are already enqueued.
+void enqueue_fac(amgdd_ctx *h, hipStream_t s, int *cur, bool skip0 = false) {
   const int maxL = (int)h->L.size() - 1;
   const int nfac = h->prm.n_fac;
   const int lt = h->sched_level < 0 ? maxL + 1 : h->sched_level;
@@ -580,7 +592,7 @@ void enqueue_fac(amgdd_ctx *h, hipStream_t s, int *cur) {
   }
   for (int c = 0; c < nfac; ++c) {
     const int first = c == 0;
-    for (int l = 0; l < std::min(lt, maxL + 1); ++l) enqueue_fac_down<T>(h, s, cur, l, first);
+    for (int l = first && skip0 ? 1 : 0; l < std::min(lt, maxL + 1); ++l) enqueue_fac_down<T>(h, s, cur, l, first);
     if (lt <= maxL) enqueue_tail<T>(h, s, lt, 1, first);
     for (int l = std::min(lt, maxL) - 1; l >= 0; --l) enqueue_fac_up<T>(h, s, cur, l);
   }
@@ -592,14 +604,39 @@ void enqueue_fac(amgdd_ctx *h, hipStream_t s, int *cur) {
 template <typename T>
 void enqueue_dd_core(amgdd_ctx *h, hipStream_t s, double *x, bool assign) {
   const int maxL = (int)h->L.size() - 1;
+  const int lt = h->sched_level < 0 ? maxL + 1 : h->sched_level;
+  std::vector<int> cur(maxL + 1, 0);
+  // Two branches when the first cycle starts with level-synchronous level-0
+  // passes: those need only the level-0 right-hand sides, so the restriction
+  // chain and the coarser right-hand sides run beside them on the side stream
+  // and join before level 1 (a fork/join in a captured graph).  Profiling
+  // keeps one stream so every launch is timed alone.
+  const bool fork = h->side && h->overlap && !h->prof && maxL >= 1 && lt > 0;
+  hipStream_t sr = s;
+  if (fork) {
+    (void)hipEventRecord(h->ev_fork, s);
+    (void)hipStreamWaitEvent(h->side, h->ev_fork, 0);
+    sr = h->side;
+  }
   for (int l = 1; l <= maxL; ++l) {
     DLevel &B = h->L[l];
-    PLAUNCH(h, "restrict", l, B.nnzGR * ent(B.GRt, sizeof(T)) + (h->L[l - 1].GN + B.GN) * (double)sizeof(T), dev::k_spmv<T>, nblocks((long long)B.GN << B.glg), dev::BLOCK, 0, s, B.GRt.as<T>(), B.GN, (const T *)h->L[l - 1].rt, (T *)B.rt);
+    PLAUNCH(h, "restrict", l, B.nnzGR * ent(B.GRt, sizeof(T)) + (h->L[l - 1].GN + B.GN) * (double)sizeof(T), dev::k_spmv<T>, nblocks((long long)B.GN << B.glg), dev::BLOCK, 0, sr, B.GRt.as<T>(), B.GN, (const T *)h->L[l - 1].rt, (T *)B.rt);
   }
-  PLAUNCH(h, "gather", 0, h->f_total * 4.0 + h->S.composite_real_rows * 2.0 * sizeof(T), dev::k_gather<T>, nblocks(h->f_total), dev::BLOCK, 0, s, (int)h->f_total, h->gather_src,
-         (const T *)h->r_arena, (T *)h->f_arena);
-  std::vector<int> cur(maxL + 1, 0);
-  enqueue_fac<T>(h, s, cur.data());
+  if (fork) {
+    const long long n1 = h->f_total - h->f_off1;
+    PLAUNCH(h, "gather", 1, n1 * 4.0 + n1 * 2.0 * sizeof(T), dev::k_gather<T>, nblocks(n1), dev::BLOCK, 0, sr, (int)n1, h->gather_src + h->f_off1,
+           (const T *)h->r_arena, (T *)h->f_arena + h->f_off1);
+    (void)hipEventRecord(h->ev_join, sr);
+    PLAUNCH(h, "gather", 0, h->f_off1 * (4.0 + 2.0 * sizeof(T)), dev::k_gather<T>, nblocks(h->f_off1), dev::BLOCK, 0, s, (int)h->f_off1, h->gather_src,
+           (const T *)h->r_arena, (T *)h->f_arena);
+    enqueue_fac_down<T>(h, s, cur.data(), 0, 1);
+    (void)hipStreamWaitEvent(s, h->ev_join, 0);
+    enqueue_fac<T>(h, s, cur.data(), true);
+  } else {
+    PLAUNCH(h, "gather", 0, h->f_total * 4.0 + h->S.composite_real_rows * 2.0 * sizeof(T), dev::k_gather<T>, nblocks(h->f_total), dev::BLOCK, 0, s, (int)h->f_total, h->gather_src,
+           (const T *)h->r_arena, (T *)h->f_arena);
+    enqueue_fac<T>(h, s, cur.data());
+  }
   if (assign)
     PLAUNCH(h, "patch", 0, h->N0 * (12.0 + sizeof(T)), (dev::k_patch<T, true>), nblocks(h->N0), dev::BLOCK, 0, s, h->N0, x, h->owner, (const T *)h->L[0].u[cur[0]]);
   else
@@ -1004,7 +1041,11 @@ amgdd_status make_handle(const std::vector<ProblemInput> &in, const amgdd_params
       c->max_bytes = cap;
       c->device = p.device;
       c->stream = (hipStream_t)stream;
+      c->overlap = std::getenv("AMGDD_SERIAL") == nullptr;
       if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess ||
+          hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+          hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
           hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
         delete h;
         return fail(ST_EDEVICE, "stream/event creation failed");

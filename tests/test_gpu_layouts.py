@@ -27,7 +27,7 @@ torch = pytest.importorskip("torch")
 amgdd = pytest.importorskip("paper_1906_10575_amd.amgdd")
 
 DEV = "cuda:0"
-ENV = ("AMGDD_INDEX32", "AMGDD_SORT_WINDOW", "AMGDD_UNPAIRED")
+ENV = ("AMGDD_INDEX32", "AMGDD_SORT_WINDOW", "AMGDD_UNPAIRED", "AMGDD_QUAD", "AMGDD_SERIAL")
 
 CASES = {
     "3d_20_var_eta2": lambda: make_problem((20, 18, 20), (2, 2, 3), eta=2, n_fac=2,
@@ -117,3 +117,22 @@ def test_every_layout_matches_the_oracle(name, monkeypatch):
         errv = np.linalg.norm(xv - xvo) / np.linalg.norm(xvo)
         say("  ", env, f"amgdd {err:.2e} vcycle {errv:.2e}")
         assert err <= 1e-12 and errv <= 1e-12, (env, err, errv)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_side_stream_branch_is_bitwise_neutral(precision, monkeypatch):
+    """The restriction chain and coarse right-hand sides run on a second
+    stream beside the first cycle's level-0 passes (joined before level 1);
+    AMGDD_SERIAL keeps one stream.  Same kernels on the same data: the
+    iterates are bitwise identical, with and without graph capture."""
+    p = CASES["3d_30_ragged_4x4x4"]()
+    say("side-stream branch", precision, p.n)
+    ref = _run(p, monkeypatch, {"AMGDD_SERIAL": "1"}, precision)
+    got = _run(p, monkeypatch, {}, precision)
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+    for k in ENV:
+        monkeypatch.delenv(k, raising=False)
+    s = amgdd.Solver(p.A, p.part, p.nparts, padding=p.eta, n_fac=p.n_fac, precision=precision, use_graph=False)
+    x, info, st = s.solve(_t(p.b), rtol=0, maxit=4)
+    assert np.array_equal(x.cpu().numpy(), ref[0])
+    s.close()
