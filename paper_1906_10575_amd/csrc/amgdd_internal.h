@@ -140,6 +140,9 @@ struct Setup {
   // on levels with grouped rows, each grid's real and ghost rows are sorted
   // by decreasing length within windows of this many rows (0: local order)
   int sort_window = 128;
+  // grouped composite rows: lanes per row = smallest power of two with at
+  // most this many entries per lane (rows of up to 20 entries keep one lane)
+  double comp_lane_target = 16.0;
   // AMG components: coarsen 0 = RS first pass, 1 = HMIS; interp 0 = direct,
   // 1 = extended+i
   int coarsen = 0, interp = 0;

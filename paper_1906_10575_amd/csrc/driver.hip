@@ -978,6 +978,7 @@ amgdd_status make_handle(const std::vector<ProblemInput> &in, const amgdd_params
   if (std::getenv("AMGDD_QUAD")) h->S.step_log2 = h->S.comp_step_log2 = 2;
   if (std::getenv("AMGDD_UNPAIRED")) h->S.step_log2 = h->S.comp_step_log2 = 0;
   if (const char *e = std::getenv("AMGDD_SORT_WINDOW")) h->S.sort_window = std::max(0, std::atoi(e));
+  if (const char *e = std::getenv("AMGDD_LANE_TARGET")) h->S.comp_lane_target = std::max(1.0, std::atof(e));
   std::string err;
   Setup inner_S;
   int st;

@@ -1326,8 +1326,9 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
       if (l > 0 && (roff[l][g] >= 0 || coff[l][g] >= 0)) nzR += S.grids[g].lv[l - 1].P.nnz();
     }
     BatchLevel &B = S.lv[l];
-    B.lg = B.NBn > 0 ? lanes_log2((double)nzA / B.NBn) : (B.NB > 0 ? lanes_log2((double)nzR / B.NB) : 0);
-    B.plg = B.NBn > 0 ? lanes_log2((double)nzP / B.NBn) : 0;
+    const double tgt = S.comp_lane_target;
+    B.lg = B.NBn > 0 ? lanes_log2((double)nzA / B.NBn, tgt) : (B.NB > 0 ? lanes_log2((double)nzR / B.NB, tgt) : 0);
+    B.plg = B.NBn > 0 ? lanes_log2((double)nzP / B.NBn, tgt) : 0;
     long long nzG = 0, nzGP = 0;
     for (int q = 0; q < nprob; ++q) {
       if (l <= S.probs[q].H.L()) nzG += S.probs[q].H.A[l].nnz();
@@ -1703,6 +1704,7 @@ int build_setup_hybrid(const std::vector<ProblemInput> &in, double theta, int ma
     inner.step_log2 = outer.step_log2;
     inner.comp_step_log2 = outer.comp_step_log2;
     inner.sort_window = outer.sort_window;
+    inner.comp_lane_target = outer.comp_lane_target;
     inner.theta = theta;
     inner.max_coarse = max_coarse;
     inner.max_levels = max_levels;
