@@ -418,17 +418,15 @@ bool compress_columns(Sell &S, const std::vector<int> &row_owner, const std::vec
 
 // Lanes per row for rows averaging `avg` entries: one lane up to 20 entries,
 // otherwise the smallest power of two G <= 16 with at most `target` entries
-// per lane (16 on composite levels, 12 on the global levels of the V-cycle).
+// per lane (Setup::comp_lane_target on composite levels, 12 on the global
+// levels of the V-cycle).
 #ifndef AMGDD_LANE_ONE
 #define AMGDD_LANE_ONE 20.0
-#endif
-#ifndef AMGDD_LANE_TARGET
-#define AMGDD_LANE_TARGET 16.0
 #endif
 #ifndef AMGDD_GLANE_TARGET
 #define AMGDD_GLANE_TARGET 12.0
 #endif
-int lanes_log2(double avg, double target = AMGDD_LANE_TARGET) {
+int lanes_log2(double avg, double target) {
   if (avg <= AMGDD_LANE_ONE) return 0;
   int lg = 1;
   while (lg < 4 && avg / (1 << lg) > target) ++lg;
