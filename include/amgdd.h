@@ -35,6 +35,22 @@
  *   - A handle is used by one host thread at a time.
  *   - Batched handles (amgdd_setup_composite_batch) see device vectors as the
  *     concatenation of the problems' vectors in setup order.
+ *
+ * Environment variables read when a handle is created (measurement and
+ * testing; none changes the method):
+ *   AMGDD_TRACE=1         roctx ranges around setup, upload, autotuning,
+ *                         capture, solves and iterations
+ *   AMGDD_THREADS=n       host threads of the setup (default: all)
+ *   AMGDD_INDEX32         int32 column indices everywhere
+ *   AMGDD_UNPAIRED        one entry per lane and load step everywhere
+ *   AMGDD_QUAD            four entries per lane and load step everywhere
+ *   AMGDD_SORT_WINDOW=n   row-sorting window on grouped levels (0: local order)
+ *   AMGDD_LANE_TARGET=x   entries per lane that set the lanes per composite row
+ *   AMGDD_SERIAL          one stream per iteration (no side-stream branch)
+ *   AMGDD_TEST_MAX_BYTES=n  device-memory cap (failure-path tests)
+ * Index width, the side-stream branch and the launch schedule leave results
+ * bitwise unchanged; step width, row order and lanes per row change only the
+ * rounding of rows served by several lanes.
  */
 #ifndef AMGDD_H
 #define AMGDD_H
