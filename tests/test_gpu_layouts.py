@@ -1,7 +1,8 @@
 """GPU: the sliced-ELL layout options through the C ABI — 16-bit or int32
 column indices (AMGDD_INDEX32), rows of grouped levels sorted by length or
-kept in local order (AMGDD_SORT_WINDOW), paired or unpaired load steps
-(AMGDD_UNPAIRED).
+kept in local order (AMGDD_SORT_WINDOW), one, two or four entries per lane
+and load step (AMGDD_UNPAIRED, default, AMGDD_QUAD), lanes per composite row
+(AMGDD_LANE_TARGET), one or two streams per iteration (AMGDD_SERIAL).
 
 Index width changes neither the entries of a row nor the order in which each
 lane adds them (padding adds exact zeros), so iterates are bitwise identical
@@ -27,7 +28,7 @@ torch = pytest.importorskip("torch")
 amgdd = pytest.importorskip("paper_1906_10575_amd.amgdd")
 
 DEV = "cuda:0"
-ENV = ("AMGDD_INDEX32", "AMGDD_SORT_WINDOW", "AMGDD_UNPAIRED", "AMGDD_QUAD", "AMGDD_SERIAL")
+ENV = ("AMGDD_INDEX32", "AMGDD_SORT_WINDOW", "AMGDD_UNPAIRED", "AMGDD_QUAD", "AMGDD_SERIAL", "AMGDD_LANE_TARGET")
 
 CASES = {
     "3d_20_var_eta2": lambda: make_problem((20, 18, 20), (2, 2, 3), eta=2, n_fac=2,
@@ -111,7 +112,8 @@ def test_every_layout_matches_the_oracle(name, monkeypatch):
         xo = cycles.amgdd_iteration(H, comps, p.b, xo, p.n_fac, coarse)
         xvo = cycles.vcycle(H, xvo, p.b, coarse=coarse)
     for env in ({}, {"AMGDD_SORT_WINDOW": "0"}, {"AMGDD_SORT_WINDOW": "32"}, {"AMGDD_UNPAIRED": "1"},
-                {"AMGDD_UNPAIRED": "1", "AMGDD_INDEX32": "1"}):
+                {"AMGDD_UNPAIRED": "1", "AMGDD_INDEX32": "1"}, {"AMGDD_QUAD": "1"}, {"AMGDD_QUAD": "1", "AMGDD_INDEX32": "1"},
+                {"AMGDD_LANE_TARGET": "6"}, {"AMGDD_LANE_TARGET": "40"}):
         x, xv = _run(p, monkeypatch, env, iters=3)
         err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
         errv = np.linalg.norm(xv - xvo) / np.linalg.norm(xvo)
