@@ -108,15 +108,16 @@ def test_cf_hybrid_iterates_match_oracle(name, lt, cache):
         assert err <= 1e-12, (k, err)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("name", ["3d_20_var_eta2", "2d_var_eta2_nfac3"])
-def test_cf_every_schedule_and_graph_identical(name, cache):
+def test_cf_every_schedule_and_graph_identical(name, precision, cache):
     p, H, comps = _oracle(name, cache)
-    say("cf schedules", name)
+    say("cf schedules", name, precision)
     b = _t(p.b)
     ref = None
     for use_graph, tl, tb in [(True, -2, 0), (False, -1, 256), (True, 0, 256), (True, 1, 512), (True, 2, 1024)]:
         s = amgdd.Solver(p.A, p.part, p.nparts, padding=p.eta, n_fac=p.n_fac, relax="cf", use_graph=use_graph,
-                         tail_level=tl, tail_block=tb)
+                         tail_level=tl, tail_block=tb, precision=precision)
         x, info, st = s.solve(b, rtol=0, maxit=4)
         if ref is None:
             ref = x
