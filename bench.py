@@ -270,6 +270,10 @@ def main():
                          "relaxation order, plus the V-cycle in both orders (one JSON line)")
     ap.add_argument("--sweep-eta", default="1,2,3")
     ap.add_argument("--sweep-nfac", default="1,2,4,10")
+    ap.add_argument("--sites", action="store_true",
+                    help="also print every launch site of one iteration (device time, algorithmic bytes, rate)")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default=None,
+                    help="override the workload's primary precision (the JSON line then reports that one)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run 3 elementwise copies of 256 MiB (known HBM traffic, to scale PMC counters)")
     args = ap.parse_args()
@@ -290,7 +294,7 @@ def main():
     AMG_OPTS.update(relax=args.relax, coarsen=args.coarsen, interp=args.interp)
     if args.sweep:
         return sweep(torch, amgdd, cfg, args)
-    prec = PRIMARY[cfg]
+    prec = args.precision or PRIMARY[cfg]
     rtol = RTOL[cfg]
     adjoint = cfg in ("cfg4", "cfg5")
     p = build_problem(cfg)
@@ -330,6 +334,12 @@ def main():
     prof = s.profile(kind=0, reps=3)
     dom, roof = roofline(prof)
     iter_ms = sum(r_["ms"] for r_ in prof)
+    if args.sites:
+        log(f"{'site':14s} {'lvl':>3s} {'n':>2s} {'ms/iter':>8s} {'MB/iter':>9s} {'GB/s':>7s} {'wg':>6s}")
+        for r_ in sorted(prof, key=lambda r_: (r_["level"], r_["name"])):
+            gbs = r_["bytes"] / (r_["ms"] * 1e-3) / 1e9 if r_["ms"] > 0 else 0.0
+            log(f"{r_['name']:14s} {r_['level']:3d} {r_['launches']:2d} {r_['ms']:8.4f} {r_['bytes'] / 1e6:9.1f} "
+                f"{gbs:7.0f} {r_['workgroups']:6d}")
     log(f"dominant launch {roof['kernel']}: {roof['ms_per_launch']:.4f} ms, {roof['achieved']:.0f} GB/s "
         f"({100 * roof['frac']:.1f}% of HBM peak); kernel time per iteration {iter_ms:.3f} ms")
 
