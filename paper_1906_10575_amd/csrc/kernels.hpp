@@ -49,10 +49,8 @@ namespace dev {
 constexpr int BLOCK = 256;
 constexpr int NXCD = 8;
 
-// entries of its row each lane has in flight in the mat-vec (three paired
-// FP64 steps; one four-wide FP32 step)
 #ifndef AMGDD_UNROLL
-#define AMGDD_UNROLL 6
+#define AMGDD_UNROLL 4
 #endif
 // 16-bit-index mat-vecs issue the next group's index / value loads before the
 // current group's gathers (measured: 1-3% faster on every workload)
