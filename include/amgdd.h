@@ -120,6 +120,13 @@ typedef struct {
                        interpolation (De Sterck, Falgout, Nolting, Yang 2008) */
   int interp_max;   /* extended+i rows keep their interp_max largest entries,
                        rescaled to the row's sum; 0 = no truncation; default 4 */
+  int n_padding_levels;          /* length of padding_per_level; 0 (default) = none */
+  const int *padding_per_level;  /* eta_l of Section 3 per level: level l < n_padding_levels
+                                    is grown by padding_per_level[l] (>= 0), deeper levels by
+                                    `padding`; the coarsest level is stored whole whatever
+                                    its entry says.  Borrowed for the setup call only; NULL
+                                    when n_padding_levels = 0.  Levels are counted from the
+                                    fine level also on a hybrid handle. */
 } amgdd_params;
 
 typedef struct {
@@ -179,9 +186,10 @@ amgdd_status amgdd_setup_composite(int n, const int *rowptr, const int *colind, 
 /*
  * Batched form: nprob independent problems with their own matrices,
  * partitions and paddings, all composite grids of all problems in one
- * batched layout.  Fields of prm[0] other than padding (theta, max_coarse,
- * max_levels, n_fac, precision, device, use_graph) apply to the whole batch;
- * padding is taken per problem from prm[i].
+ * batched layout.  Fields of prm[0] other than the padding fields (theta,
+ * max_coarse, max_levels, n_fac, precision, device, use_graph, ...) apply to
+ * the whole batch; padding, n_padding_levels and padding_per_level are taken
+ * per problem from prm[i].
  */
 amgdd_status amgdd_setup_composite_batch(int nprob, const int *n, const int *const *rowptr,
                                          const int *const *colind, const double *const *val,

@@ -35,7 +35,8 @@ class Params(C.Structure):
                 ("n_fac", C.c_int), ("precision", C.c_int), ("device", C.c_int), ("use_graph", C.c_int),
                 ("tail_level", C.c_int), ("tail_block", C.c_int), ("hybrid_level", C.c_int),
                 ("relax_order", C.c_int), ("coarsen", C.c_int), ("interp", C.c_int),
-                ("interp_max", C.c_int)]
+                ("interp_max", C.c_int), ("n_padding_levels", C.c_int),
+                ("padding_per_level", C.POINTER(C.c_int))]
 
 
 class Info(C.Structure):
@@ -142,10 +143,16 @@ def _torch():
     return torch
 
 
-def _dev_ptr(t, name):
+def _dev_ptr(t, name, n=None, dtype=None):
+    """Raw device pointer of a contiguous tensor on the HIP device, after
+    checking its dtype (float64 unless given) and, when n is given, that it
+    holds exactly n elements: the library reads and writes that many."""
     torch = _torch()
-    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
-        raise TypeError(f"{name} must be a contiguous float64 tensor on the HIP device")
+    dtype = dtype or torch.float64
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor on the HIP device")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, the handle needs exactly {n}")
     return C.c_void_p(t.data_ptr())
 
 
@@ -161,13 +168,25 @@ class Solver:
 
     def __init__(self, A, part, nparts, padding=1, n_fac=2, precision="fp64", device=0, theta=0.25,
                  max_coarse=16, max_levels=25, use_graph=True, stream=None, tail_level=-2, tail_block=0,
-                 hybrid_level=0, relax="l1", coarsen="rs", interp="direct", interp_max=4):
+                 hybrid_level=0, relax="l1", coarsen="rs", interp="direct", interp_max=4,
+                 padding_per_level=None):
         lib = load()
         batch = isinstance(A, (list, tuple))
         As = list(A) if batch else [A]
         parts = list(part) if batch else [part]
         nps = list(nparts) if batch else [nparts]
         pads = list(padding) if isinstance(padding, (list, tuple)) else [padding] * len(As)
+        # per-level padding: one sequence (single problem) or one sequence or
+        # None per problem (batch)
+        if padding_per_level is None:
+            ppl = [None] * len(As)
+        elif batch:
+            ppl = list(padding_per_level)
+        else:
+            ppl = [padding_per_level]
+        if len(ppl) != len(As):
+            raise ValueError("padding_per_level needs one entry per problem")
+        ppl = [None if v is None else np.ascontiguousarray(v, dtype=np.int32) for v in ppl]
         prm = default_params()
         prm.theta = theta
         prm.max_coarse = max_coarse
@@ -196,8 +215,13 @@ class Solver:
         pts = [np.ascontiguousarray(p, dtype=np.int32) for p in parts]
         self.sizes = [int(a.shape[0]) for a in As]
         self.offsets = np.concatenate([[0], np.cumsum(self.sizes)]).astype(np.int64)
+        def set_levels(pr, v):
+            pr.n_padding_levels = 0 if v is None else int(v.size)
+            pr.padding_per_level = None if v is None else _iptr(v)
+
         if not batch:
             prm.padding = pads[0]
+            set_levels(prm, ppl[0])
             st = lib.amgdd_setup_composite(self.sizes[0], _iptr(arrs[0][0]), _iptr(arrs[0][1]), _dptr(arrs[0][2]),
                                            _iptr(pts[0]), int(nps[0]), C.byref(prm), C.c_void_p(stream), C.byref(h))
         else:
@@ -206,6 +230,7 @@ class Solver:
             for i in range(n):
                 prms[i] = prm
                 prms[i].padding = int(pads[i])
+                set_levels(prms[i], ppl[i])
             ns = np.array(self.sizes, dtype=np.int32)
             rp = (_IP * n)(*[_iptr(a[0]) for a in arrs])
             ci = (_IP * n)(*[_iptr(a[1]) for a in arrs])
@@ -223,10 +248,11 @@ class Solver:
     # ---------------------------------------------------------------- solves
     def _solve(self, fn, b, x, rtol, maxit):
         torch = _torch()
+        bp = _dev_ptr(b, "b", self.n)
         if x is None:
             x = torch.zeros_like(b)
         info = Info()
-        st = fn(self._h, _dev_ptr(b, "b"), _dev_ptr(x, "x"), float(rtol), int(maxit), C.byref(info))
+        st = fn(self._h, bp, _dev_ptr(x, "x", self.n), float(rtol), int(maxit), C.byref(info))
         if st not in (OK, ENOCONV):
             _check(st)
         return x, info, st
@@ -243,12 +269,22 @@ class Solver:
         return self._solve(load().amgdd_solve_adjoint, g, lam, rtol, maxit)
 
     def face_gradient(self, u, lam, face_i, face_j):
+        """dL/dc per face; face_i in [0, n), face_j in [-1, n) (-1: boundary
+        face), both of the same length.  Index ranges are checked on the host
+        before anything is launched."""
         torch = _torch()
-        fi = face_i.to(device=u.device, dtype=torch.int32).contiguous()
-        fj = face_j.to(device=u.device, dtype=torch.int32).contiguous()
+        fi_h = np.asarray(face_i.cpu() if isinstance(face_i, torch.Tensor) else face_i).ravel()
+        fj_h = np.asarray(face_j.cpu() if isinstance(face_j, torch.Tensor) else face_j).ravel()
+        if fi_h.size != fj_h.size:
+            raise ValueError("face_i and face_j must have the same length")
+        if fi_h.size and (fi_h.min() < 0 or fi_h.max() >= self.n or fj_h.min() < -1 or fj_h.max() >= self.n):
+            raise ValueError(f"face indices out of range: need 0 <= face_i < {self.n} and -1 <= face_j < {self.n}")
+        up, lp = _dev_ptr(u, "u", self.n), _dev_ptr(lam, "lam", self.n)
+        fi = torch.as_tensor(fi_h.astype(np.int32), device=u.device)
+        fj = torch.as_tensor(fj_h.astype(np.int32), device=u.device)
         out = torch.empty(fi.numel(), dtype=torch.float64, device=u.device)
-        _check(load().amgdd_face_gradient(self._h, _dev_ptr(u, "u"), _dev_ptr(lam, "lam"), C.c_void_p(fi.data_ptr()),
-                                          C.c_void_p(fj.data_ptr()), int(fi.numel()), C.c_void_p(out.data_ptr())))
+        _check(load().amgdd_face_gradient(self._h, up, lp, C.c_void_p(fi.data_ptr()), C.c_void_p(fj.data_ptr()),
+                                          int(fi.numel()), C.c_void_p(out.data_ptr())))
         return out
 
     # ---------------------------------------------------------- introspection

@@ -19,7 +19,7 @@ import numpy as np
 import torch
 from scipy import sparse
 
-from .amgdd import Solver
+from .amgdd import OK, AmgddError, Solver
 
 
 @dataclass
@@ -62,6 +62,10 @@ class _DiffusionSolve(torch.autograd.Function):
         solver = Solver(A, prob.part, prob.nparts, padding=prob.padding, n_fac=prob.n_fac, precision=prob.precision,
                         device=dev.index or 0)
         u, info, st = solver.solve(f.detach().double().contiguous(), rtol=prob.rtol, maxit=prob.maxit)
+        if st != OK:
+            # an unconverged forward solve would give a wrong u and wrong gradients
+            raise AmgddError(st, f"forward AMG-DD solve stopped at relative residual {info.relres:.3e} "
+                                 f"after {info.iters} iterations (rtol {prob.rtol}, maxit {prob.maxit})")
         ctx.solver = solver
         ctx.prob = prob
         ctx.forward_info = info
@@ -73,6 +77,10 @@ class _DiffusionSolve(torch.autograd.Function):
         (u,) = ctx.saved_tensors
         prob = ctx.prob
         lam, info, st = ctx.solver.solve_adjoint(gu.detach().double().contiguous(), rtol=prob.rtol, maxit=prob.maxit)
+        if st != OK:
+            raise AmgddError(st, f"adjoint AMG-DD solve stopped at relative residual {info.relres:.3e} "
+                                 f"after {info.iters} iterations (rtol {prob.rtol}, maxit {prob.maxit})")
+        ctx.adjoint_info = info
         fi = torch.as_tensor(np.asarray(prob.face_i, dtype=np.int32), device=u.device)
         fj = torch.as_tensor(np.asarray(prob.face_j, dtype=np.int32), device=u.device)
         dc = ctx.solver.face_gradient(u, lam, fi, fj)

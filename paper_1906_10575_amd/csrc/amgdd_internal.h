@@ -49,6 +49,8 @@ struct CompGrid {
 
 struct ProblemHost {
   int n = 0, nparts = 0, eta = 1;
+  std::vector<int> etas;            // per-level padding override (levels < etas.size())
+  int eta_of(int l) const { return l < (int)etas.size() ? etas[l] : eta; }
   Csr A0;
   std::vector<int> part;
   Hierarchy H;
@@ -178,6 +180,8 @@ struct ProblemInput {
   const int *part;
   int nparts;
   int eta;
+  const int *etas;  // per-level padding (levels < n_etas), may be null
+  int n_etas;
 };
 
 // Host setup: hierarchy, composite grids and batched layouts.  Returns a

@@ -1089,6 +1089,8 @@ void amgdd_params_default(amgdd_params *prm) {
   prm->coarsen = 0;
   prm->interp = 0;
   prm->interp_max = 4;
+  prm->n_padding_levels = 0;
+  prm->padding_per_level = nullptr;
 }
 
 amgdd_status amgdd_setup_composite(int n, const int *rowptr, const int *colind, const double *val, const int *part,
@@ -1096,7 +1098,7 @@ amgdd_status amgdd_setup_composite(int n, const int *rowptr, const int *colind, 
   amgdd_params p;
   amgdd_params_default(&p);
   if (prm) p = *prm;
-  std::vector<ProblemInput> in{ProblemInput{n, rowptr, colind, val, part, nparts, p.padding}};
+  std::vector<ProblemInput> in{ProblemInput{n, rowptr, colind, val, part, nparts, p.padding, p.padding_per_level, p.n_padding_levels}};
   return make_handle(in, &p, hip_stream, out);
 }
 
@@ -1106,7 +1108,9 @@ amgdd_status amgdd_setup_composite_batch(int nprob, const int *n, const int *con
   if (nprob <= 0 || !n || !rowptr || !colind || !val || !part || !nparts || !prm)
     return fail(ST_EINVAL, "null batch argument");
   std::vector<ProblemInput> in;
-  for (int q = 0; q < nprob; ++q) in.push_back(ProblemInput{n[q], rowptr[q], colind[q], val[q], part[q], nparts[q], prm[q].padding});
+  for (int q = 0; q < nprob; ++q)
+    in.push_back(ProblemInput{n[q], rowptr[q], colind[q], val[q], part[q], nparts[q], prm[q].padding,
+                              prm[q].padding_per_level, prm[q].n_padding_levels});
   return make_handle(in, &prm[0], hip_stream, out);
 }
 

@@ -881,6 +881,9 @@ int validate(const ProblemInput &in, int max_coarse, std::string &err) {
   if (in.n <= 0 || !in.rowptr || !in.colind || !in.val || !in.part) { err = "null array or n <= 0"; return ST_EINVAL; }
   if (in.nparts <= 0 || in.nparts > in.n) { err = "nparts out of range"; return ST_EINVAL; }
   if (in.eta < 0) { err = "negative padding"; return ST_EINVAL; }
+  if (in.n_etas < 0 || in.n_etas > 1024 || (in.n_etas > 0 && !in.etas)) { err = "bad per-level padding array"; return ST_EINVAL; }
+  for (int l = 0; l < in.n_etas; ++l)
+    if (in.etas[l] < 0) { err = "negative padding on level " + std::to_string(l); return ST_EINVAL; }
   if (in.rowptr[0] != 0) { err = "rowptr[0] != 0"; return ST_EINVAL; }
   for (int i = 0; i < in.n; ++i) {
     int a = in.rowptr[i], b = in.rowptr[i + 1];
@@ -999,7 +1002,8 @@ void build_sets(const ProblemHost &P, const std::vector<Csr> &G, const std::vect
       D = seeds;
       for (int s : seeds) sc.a.mark[s] = e;
       sc.front = seeds;
-      for (int r = 0; r < P.eta && !sc.front.empty(); ++r) {
+      const int eta = P.eta_of(l);
+      for (int r = 0; r < eta && !sc.front.empty(); ++r) {
         sc.nxt.clear();
         for (int v : sc.front)
           for (int jj = G[l].ptr[v]; jj < G[l].ptr[v + 1]; ++jj) {
@@ -1115,6 +1119,7 @@ int setup_hierarchies(const std::vector<ProblemInput> &in, double theta, int max
     P.n = in[q].n;
     P.nparts = in[q].nparts;
     P.eta = in[q].eta;
+    if (in[q].n_etas > 0) P.etas.assign(in[q].etas, in[q].etas + in[q].n_etas);
     P.A0.nrows = P.A0.ncols = P.n;
     P.A0.ptr.assign(in[q].rowptr, in[q].rowptr + P.n + 1);
     long long nnz = P.A0.ptr[P.n];
@@ -1733,6 +1738,7 @@ int build_setup_hybrid(const std::vector<ProblemInput> &in, double theta, int ma
       P.n = O.H.A[lt].nrows;
       P.nparts = np;
       P.eta = O.eta;
+      if ((int)O.etas.size() > lt) P.etas.assign(O.etas.begin() + lt, O.etas.end());
       P.part = std::move(part);
       P.symmetric = O.symmetric;
       P.H.A.assign(O.H.A.begin() + lt, O.H.A.end());

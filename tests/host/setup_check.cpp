@@ -47,6 +47,7 @@ static Prob laplace(int nx, int ny, int nz, int px, int py, int pz) {
 int main() {
   std::vector<Prob> probs = {laplace(40, 36, 1, 3, 2, 1), laplace(14, 12, 10, 2, 2, 2), laplace(9, 9, 1, 3, 3, 1)};
   const int nparts[] = {6, 8, 9};
+  static const int per_level_eta[] = {2, 0, 1};
   int fails = 0, runs = 0;
   for (int coarsen = 0; coarsen < 2; ++coarsen)
     for (int interp = 0; interp < 2; ++interp)
@@ -55,7 +56,8 @@ int main() {
           std::vector<ProblemInput> in;
           for (size_t q = 0; q < probs.size(); ++q)
             in.push_back(ProblemInput{probs[q].n, probs[q].ptr.data(), probs[q].col.data(), probs[q].val.data(),
-                                      probs[q].part.data(), nparts[q], 1 + (int)q % 2});
+                                      probs[q].part.data(), nparts[q], 1 + (int)q % 2,
+                                      q == 2 ? per_level_eta : nullptr, q == 2 ? 3 : 0});
           Setup S, I;
           S.coarsen = coarsen;
           S.interp = interp;

@@ -253,3 +253,92 @@ def test_best_practice_setup_bit_exact_with_oracle(name, make, coarsen, interp):
             g, nr, om = s.composite(0, q, l)
             assert nr == lv.n_real and np.array_equal(g, lv.gid)
             assert om == lv.omissions
+
+
+# ---------------------------------------------------------------- per-level padding
+
+def _mask(n, gids):
+    m = np.zeros(n, dtype=bool)
+    m[gids] = True
+    return m
+
+
+def test_per_level_padding_matches_hand_derived_chain():
+    import json
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "composite_chain33.json")))
+    p = make_problem((33,), (2,), eta=1)
+    for case in g["cases"]:
+        s = amgdd.Solver(p.A, p.part, 2, padding=1, padding_per_level=case["padding"], max_coarse=4, device=-1)
+        n, _ = s.levels(0)
+        assert n.tolist() == g["levels"]
+        for q in range(2):
+            for l in range(len(n)):
+                gids, nr, om = s.composite(0, q, l)
+                a, b = case["sets"][str(q)]["D"][l]
+                ab, bb = case["sets"][str(q)]["Dbar"][l]
+                assert gids[:nr].tolist() == list(range(a, b + 1)), (case["padding"], q, l)
+                assert sorted(gids.tolist()) == list(range(ab, bb + 1)), (case["padding"], q, l)
+                assert om == 0
+
+
+def test_per_level_padding_matches_closed_form_and_oracle():
+    from tests.test_oracle_composite_levels import closed_form_sets, xline_operator, xline_part
+    A = xline_operator()
+    part = xline_part()
+    etas = [1, 2, 0, 3]
+    s = amgdd.Solver(A, part, 4, padding=5, padding_per_level=etas, device=-1)
+    H = amg.setup(A)
+    n, _ = s.levels(0)
+    for q in range(4):
+        Dc, Dbc = closed_form_sets(part, q, etas, H.L + 1)
+        D, Db = composite.composite_sets(H, part, q, etas + [0])
+        for l in range(H.L + 1):
+            gids, nr, om = s.composite(0, q, l)
+            assert np.array_equal(_mask(n[l], gids[:nr]), Dc[l]) and np.array_equal(_mask(n[l], gids), Dbc[l])
+            assert np.array_equal(D[l], Dc[l])
+    # a shorter list: deeper levels take `padding`
+    p = make_problem((20, 18, 20), (2, 2, 3), eta=2, k=np.exp(grf((20, 18, 20), 1.0, 8.0, 1)))
+    s = amgdd.Solver(p.A, p.part, p.nparts, padding=2, padding_per_level=[1, 3], device=-1)
+    H = amg.setup(p.A)
+    etas = [1, 3] + [2] * (H.L - 1)
+    for q in range(p.nparts):
+        D, Db = composite.composite_sets(H, p.part, q, etas)
+        for l in range(H.L + 1):
+            gids, nr, om = s.composite(0, q, l)
+            assert np.array_equal(_mask(H.A[l].shape[0], gids[:nr]), D[l]), (q, l)
+            assert np.array_equal(_mask(H.A[l].shape[0], gids), Db[l]), (q, l)
+
+
+def test_per_level_padding_in_a_batch_and_errors():
+    p1 = make_problem((33,), (2,), eta=1)
+    p2 = make_problem((24, 24), (2, 2), eta=1)
+    s = amgdd.Solver([p1.A, p2.A], [p1.part, p2.part], [2, 4], padding=[1, 1], padding_per_level=[[2, 0, 1], None],
+                     max_coarse=4, device=-1)
+    gids, nr, om = s.composite(0, 1, 1)
+    assert gids[:nr].tolist() == list(range(7, 16))        # hand-derived chain, eta (2, 0, 1)
+    ref = amgdd.Solver(p2.A, p2.part, 4, padding=1, max_coarse=4, device=-1)
+    for q in range(4):
+        assert np.array_equal(s.composite(1, q, 1)[0], ref.composite(0, q, 1)[0])
+    with pytest.raises(amgdd.AmgddError) as e:
+        amgdd.Solver(p1.A, p1.part, 2, padding_per_level=[1, -1], device=-1)
+    assert e.value.status == amgdd.EINVAL
+    with pytest.raises(ValueError):
+        amgdd.Solver([p1.A, p2.A], [p1.part, p2.part], [2, 4], padding_per_level=[[1]], device=-1)
+
+
+# ---------------------------------------------------------------- binding argument checks
+
+def test_binding_rejects_bad_vectors_and_face_indices():
+    torch = pytest.importorskip("torch")
+    p = make_problem((24, 24), (2, 2), eta=1)
+    s = _host(p)
+    with pytest.raises(TypeError):
+        s.solve(torch.zeros(p.n, dtype=torch.float64))             # host tensor
+    with pytest.raises(TypeError):
+        s.solve(np.zeros(p.n))
+    with pytest.raises(ValueError):
+        s.face_gradient(None, None, np.array([0, p.n]), np.array([1, -1]))   # face_i past the end
+    with pytest.raises(ValueError):
+        s.face_gradient(None, None, np.array([0, 1]), np.array([-2, 3]))     # face_j below -1
+    with pytest.raises(ValueError):
+        s.face_gradient(None, None, np.array([0, 1]), np.array([2]))         # length mismatch
