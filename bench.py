@@ -1,15 +1,18 @@
 #!/usr/bin/env python3
 """Benchmark of the AMG-DD solve phase on one MI355X.
 
-Workload (default): 3D 7-point Laplacian on 128^3 (2,097,152 unknowns),
-4x4x4 = 64 subdomains of 32^3, padding 1, 2 AlgFAC V(1,1) cycles per AMG-DD
-iteration, FP64, b ~ U[-1, 1] (seed 0), x0 = 0.  One step = one AMG-DD solve
-to 1e-8 relative residual (fine residual, restriction chain, composite
-right-hand sides, batched AlgFAC on all 64 composite grids, patch), with all
-inputs resident in HBM.  value = DOF*cycles/s = N_0 * outer iterations /
-solve time.  The V(1,1) cycle on the same hierarchy, the hybrid AMG-DD
-V-cycle (AMG-DD on a transition level, Algorithm 3) and the mixed-precision
-form are timed beside it and reported as extra fields.
+Workload (default): 3D 7-point variable-coefficient diffusion on 192^3
+(7,077,888 unknowns), k = exp(g) with g a seeded Gaussian random field
+(sigma 1, correlation length 8 cells), harmonic-mean faces; 8x8x8 = 512
+subdomains of 24^3, padding 2, 2 AlgFAC V(1,1) cycles per AMG-DD iteration,
+FP64, b ~ U[-1, 1] (seed 0), x0 = 0.  One step = one AMG-DD solve to 1e-8
+relative residual (fine residual, restriction chain, composite right-hand
+sides, batched AlgFAC on all 512 composite grids, patch), with all inputs
+resident in HBM.  value = DOF*cycles/s = N_0 * outer iterations / solve time.
+Beside it: the mixed-precision form (its time to 1e-8 and its distance from
+the FP64 iterates, iteration by iteration), the V(1,1) cycle on the same
+hierarchy, the hybrid AMG-DD V-cycle (Algorithm 3), and the oracle on the
+host's cores on a bounded sample of the same workload.
 
 Prints one JSON line.  --gpus must be 1 (the solver runs on one device).
 """
@@ -38,7 +41,8 @@ WORKLOADS = {
     "cfg2": "3D 7-point Laplacian 128^3 (2,097,152 DOF), 4x4x4 subdomains of 32^3, padding 1, 2 AlgFAC V(1,1) "
             "cycles per AMG-DD iteration, FP64, AMG-DD solve to 1e-8 from x0 = 0",
     "cfg3": "3D 7-point diffusion 192^3 (7,077,888 DOF), k = exp(GRF sigma 1, l 8), harmonic faces, 8x8x8 "
-            "subdomains of 24^3, padding 2, 2 AlgFAC cycles, AMG-DD solve to 1e-8 from x0 = 0",
+            "subdomains of 24^3, padding 2, 2 AlgFAC V(1,1) cycles per AMG-DD iteration, AMG-DD solve to 1e-8 "
+            "from x0 = 0",
     "cfg4": "3D 7-point diffusion 96^3 (884,736 DOF), k = exp(GRF sigma 0.5), 3x3x3 subdomains of 32^3, padding 1, "
             "forward AMG-DD to 1e-10 plus adjoint AMG-DD to 1e-10 and face gradient",
     "cfg5": "256 independent 2D 5-point diffusion problems, sides U{64..512}, k log-normal sigma 1, Px,Py U{2..8}, "
@@ -83,33 +87,72 @@ def roofline(prof):
                  "block": dom.get("block"), "bytes_per_launch": per_launch_bytes, "ms_per_launch": per_launch_ms}
 
 
-def cpu_baseline(seconds=12.0):
-    """The oracle (plain serial FP64 NumPy/SciPy) timed on the host: AMG-DD
-    iterations on a 64^3 Laplacian with 2^3 subdomains of 32^3 (cfg2's
-    subdomain size, padding and cycle count at 1/8 of its subdomains), BLAS
-    limited to one thread; DOF*cycles/s = N_0 * iterations / time."""
+def host_cores():
+    """CPU threads this process may use (the box's share: at most 16) and a
+    description of the host."""
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    share = min(aff, 16)
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return share, {"nproc": os.cpu_count(), "affinity": aff, "model": model}
+
+
+def cpu_baseline(seconds=10.0):
+    """The oracle (plain FP64 NumPy/SciPy, written from the paper) timed on the
+    host on a bounded sample of the 192^3 workload: the 72^3 corner of the
+    same coefficient field (GRF sigma 1, l 8, seed 1; harmonic faces;
+    Dirichlet at the cut), 3^3 of its 24^3 subdomains, padding 2, 2 AlgFAC
+    cycles, b ~ U[-1, 1] (seed 0).  Setup (hierarchy, composite grids) is
+    not timed.  Two runs: one core (BLAS limited to one thread, subdomains in
+    turn) and all of the host's cores (the AlgFAC phase of every iteration
+    spread over worker processes, one subdomain per task; residual,
+    restriction and patch stay serial).  DOF*cycles/s = N_0 * iterations /
+    time."""
     from threadpoolctl import threadpool_limits
 
     from oracle import amg, composite, cycles
-    from synth import make_problem
-    p = make_problem((64, 64, 64), (2, 2, 2), eta=1, n_fac=2)
+    from oracle.parallel import SubdomainPool
+    from synth import grf, make_problem
+    t0 = time.perf_counter()
+    k = np.exp(grf((192,) * 3, 1.0, 8.0, 1))[:72, :72, :72]
+    p = make_problem((72,) * 3, (3,) * 3, eta=2, n_fac=2, k=k)
     H = amg.setup(p.A)
     comps = composite.build_all(H, p.part, p.nparts, p.eta)
     co = cycles.CoarseSolver(H.A[H.L])
-    with threadpool_limits(1):
+    setup_s = time.perf_counter() - t0
+    share, host = host_cores()
+
+    def timed(step):
         x = np.zeros(p.n)
         it = 0
-        t0 = time.perf_counter()
-        while time.perf_counter() - t0 < seconds or it < 3:
-            x = cycles.amgdd_iteration(H, comps, p.b, x, 2, co)
+        t1 = time.perf_counter()
+        while time.perf_counter() - t1 < seconds or it < 3:
+            x = step(x)
             it += 1
-        dt = time.perf_counter() - t0
-    return {"value": round(p.n * it / dt, 1), "unit": "DOF*cycles/s", "cores": 1, "kind": "oracle",
-            "sample": f"64^3 Laplacian, 2^3 subdomains of 32^3, padding 1, 2 AlgFAC cycles: {it} AMG-DD "
-                      f"iterations in {dt:.1f} s (setup excluded)"}
+        return it, time.perf_counter() - t1
+
+    with threadpool_limits(1):
+        it1, dt1 = timed(lambda x: cycles.amgdd_iteration(H, comps, p.b, x, 2, co))
+        workers = min(share, p.nparts)
+        with SubdomainPool(H, comps, 2, workers, coarse=co) as pool:
+            itn, dtn = timed(lambda x: pool.iteration(p.b, x))
+    sample = (f"72^3 corner of the 192^3 workload's coefficient field, 3^3 subdomains of 24^3, padding 2, "
+              f"2 AlgFAC cycles ({p.n} DOF); solve phase only (setup {setup_s:.0f} s untimed)")
+    return {"value": round(p.n * itn / dtn, 1), "unit": "DOF*cycles/s", "cores": workers, "kind": "oracle",
+            "sample": sample + f": {itn} AMG-DD iterations in {dtn:.1f} s on {workers} worker processes",
+            "one_core": {"value": round(p.n * it1 / dt1, 1), "cores": 1,
+                         "run": f"{it1} AMG-DD iterations in {dt1:.1f} s"},
+            "host": host}
 
 
-PRIMARY = {"cfg2": "fp64", "cfg3": "mixed", "cfg4": "fp64", "cfg5": "mixed", "p2": "fp64"}
+PRIMARY = {"cfg2": "fp64", "cfg3": "fp64", "cfg4": "fp64", "cfg5": "mixed", "p2": "fp64"}
+HYBRID_LEVELS = {"cfg2": "1,2,3", "cfg3": "2,3", "p2": "1,2,3"}
 RTOL = {"cfg2": 1e-8, "cfg3": 1e-8, "cfg4": 1e-10, "cfg5": 1e-8, "p2": 1e-8}
 
 
@@ -173,22 +216,44 @@ def residual_rel(p, x):
     return float(np.linalg.norm(p.b - p.A @ x) / np.linalg.norm(p.b))
 
 
-def run_steps(torch, s, b, steps, rtol, adjoint):
+def run_steps(torch, s, b, steps, rtol, adjoint, per_step=None):
     """K steps from x = 0; a step is one AMG-DD solve (plus, for the adjoint
     workloads, one adjoint AMG-DD solve with right-hand side u), bracketed by
-    device synchronisation.  Returns (seconds, iterations per step, x)."""
+    device synchronisation (every solve returns with its stream drained, so
+    per-step host times are exact).  Returns (seconds, iterations per step, x)
+    and appends each step's seconds to per_step."""
     iters = []
+    zeros = [torch.zeros_like(b) for _ in range(2 * steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        x, info, st = s.solve(b, torch.zeros_like(b), rtol=rtol, maxit=300)
+    for k in range(steps):
+        ts = time.perf_counter()
+        x, info, st = s.solve(b, zeros[2 * k], rtol=rtol, maxit=300)
         it = info.iters
         if adjoint:
-            lam, info2, st2 = s.solve_adjoint(x, torch.zeros_like(b), rtol=rtol, maxit=300)
+            lam, info2, st2 = s.solve_adjoint(x, zeros[2 * k + 1], rtol=rtol, maxit=300)
             it += info2.iters
         iters.append(it)
+        if per_step is not None:
+            per_step.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     return time.perf_counter() - t0, iters, x
+
+
+def mixed_vs_fp64(torch, s64, smx, b, iters, rtol):
+    """Distance of the mixed-precision iterates from the FP64 ones, iteration
+    by iteration from x0 = 0 (||x_mixed - x_fp64|| / ||x_fp64||), and of the
+    two solutions at the tolerance."""
+    x64 = torch.zeros_like(b)
+    xm = torch.zeros_like(b)
+    per_iter = []
+    for _ in range(iters):
+        x64, _, _ = s64.solve(b, x64, rtol=0, maxit=1)
+        xm, _, _ = smx.solve(b, xm, rtol=0, maxit=1)
+        per_iter.append(float(torch.linalg.norm(xm - x64) / torch.linalg.norm(x64)))
+    x64, _, _ = s64.solve(b, torch.zeros_like(b), rtol=rtol, maxit=300)
+    xm, _, _ = smx.solve(b, torch.zeros_like(b), rtol=rtol, maxit=300)
+    return per_iter, float(torch.linalg.norm(xm - x64) / torch.linalg.norm(x64))
 
 
 def sweep(torch, amgdd, cfg, args):
@@ -253,12 +318,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="cfg2", choices=sorted(WORKLOADS))
+    ap.add_argument("--config", default="cfg3", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--tail-level", type=int, default=-2, help="fixed AlgFAC schedule cut level (-2: autotune)")
     ap.add_argument("--tail-block", type=int, default=0, help="fixed persistent workgroup size (0: autotune)")
-    ap.add_argument("--hybrid-levels", default="1,2,3",
+    ap.add_argument("--hybrid-levels", default=None,
                     help="transition levels of the hybrid AMG-DD cycles timed beside the primary solve")
     ap.add_argument("--summarize-rocpd", metavar="DB", help="print a summary of a rocprofv3 kernel-trace database")
     ap.add_argument("--summarize-pmc", metavar="CSV", help="print a summary of rocprofv3 --pmc CSV output")
@@ -276,6 +341,7 @@ def main():
                     help="override the workload's primary precision (the JSON line then reports that one)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run 3 elementwise copies of 256 MiB (known HBM traffic, to scale PMC counters)")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="seconds per CPU-baseline run")
     args = ap.parse_args()
     if args.summarize_rocpd:
         print(summarize_rocpd(args.summarize_rocpd))
@@ -284,7 +350,8 @@ def main():
         print(summarize_pmc(args.summarize_pmc))
         return
     if args.gpus != 1:
-        print(f"bench.py: the solver runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
+        print(f"bench.py: the solver runs on one GPU (the multi-GPU exchange is a design only); --gpus {args.gpus} "
+              f"is not supported", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -313,13 +380,16 @@ def main():
     st = s.stats()
     log(f"warmup done; schedule: cut level {st['tail_level']}, workgroup {st['tail_block']} "
         f"(autotune {st['autotune_s']:.2f} s)")
-    dt, iters, x = run_steps(torch, s, b, args.steps, rtol, adjoint)
+    per_step = []
+    dt, iters, x = run_steps(torch, s, b, args.steps, rtol, adjoint, per_step)
     its = int(np.median(iters))
     ms_per_step = dt / args.steps * 1e3
     value = n * sum(iters) / dt
     relres = residual_rel(p, x.cpu().numpy())
-    log(f"AMG-DD: {its} iterations per step, {ms_per_step:.2f} ms per step, {value:.3e} DOF*cycles/s, "
-        f"final relres (FP64, host) {relres:.2e}")
+    step_ms = {"mean": round(ms_per_step, 4), "median": round(float(np.median(per_step)) * 1e3, 4),
+               "min": round(float(np.min(per_step)) * 1e3, 4), "max": round(float(np.max(per_step)) * 1e3, 4)}
+    log(f"AMG-DD: {its} iterations per step, {ms_per_step:.2f} ms per step (median {step_ms['median']:.2f}, "
+        f"min {step_ms['min']:.2f}), {value:.3e} DOF*cycles/s, final relres (FP64, host) {relres:.2e}")
 
     if args.calibrate_copy:
         # y = x + 1 over 2^25 doubles: 256 MiB read, 256 MiB written per launch
@@ -342,6 +412,7 @@ def main():
                 f"{gbs:7.0f} {r_['workgroups']:6d}")
     log(f"dominant launch {roof['kernel']}: {roof['ms_per_launch']:.4f} ms, {roof['achieved']:.0f} GB/s "
         f"({100 * roof['frac']:.1f}% of HBM peak); kernel time per iteration {iter_ms:.3f} ms")
+    iter_bytes = sum(r_["bytes"] for r_ in prof)
 
     out = {
         "metric": "DOF*cycles/s and time to 1e-8 rel. residual, FP64 vs mixed; % of HBM roofline",
@@ -361,12 +432,15 @@ def main():
                    "interp": args.interp},
         "iters_per_step": its,
         "time_to_tol_ms": round(ms_per_step, 4),
+        "step_ms": step_ms,
         "final_relres_fp64": relres,
         "roofline": roof,
         "kernel_ms_per_iteration": round(iter_ms, 4),
+        "iteration_alg_gbs": round(iter_bytes / (iter_ms * 1e-3) / 1e9, 1),
         "profile_top": sorted(({k: (round(v, 5) if isinstance(v, float) else v) for k, v in r_.items()}
                                for r_ in prof), key=lambda r_: -r_["ms"])[:8],
-        "schedule": {"tail_level": st["tail_level"], "tail_block": st["tail_block"]},
+        "schedule": {"tail_level": st["tail_level"], "tail_block": st["tail_block"],
+                     "autotune_s": round(st["autotune_s"], 3)},
         "setup_s": round(setup_s, 2),
         "composite_overhead": round(st["composite_overhead"], 4),
     }
@@ -374,31 +448,59 @@ def main():
         k = max(3, args.steps // 2)
         if not isinstance(p, list) and not adjoint:
             s.vsolve(b, torch.zeros_like(b), rtol=rtol, maxit=400)
+            vstep = []
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             itv = []
             for _ in range(k):
+                ts = time.perf_counter()
                 xv, infov, _ = s.vsolve(b, torch.zeros_like(b), rtol=rtol, maxit=400)
+                vstep.append(time.perf_counter() - ts)
                 itv.append(infov.iters)
             torch.cuda.synchronize()
             dtv = time.perf_counter() - t0
             out["vcycle"] = {"iters": int(np.median(itv)), "time_to_tol_ms": round(dtv / k * 1e3, 4),
+                             "step_ms_median": round(float(np.median(vstep)) * 1e3, 4),
+                             "step_ms_min": round(float(np.min(vstep)) * 1e3, 4),
                              "dof_cycles_per_s": round(n * sum(itv) / dtv, 1)}
             log(f"V(1,1): {out['vcycle']}")
         other = "mixed" if prec == "fp64" else "fp64"
+        so = make_solver(amgdd, p, other)
+        run_steps(torch, so, b, 1, rtol, adjoint)
+        ostep = []
+        dto, ito, xo = run_steps(torch, so, b, k, rtol, adjoint, ostep)
+        out[other] = {"iters_per_step": int(np.median(ito)), "time_to_tol_ms": round(dto / k * 1e3, 4),
+                      "step_ms_median": round(float(np.median(ostep)) * 1e3, 4),
+                      "step_ms_min": round(float(np.min(ostep)) * 1e3, 4),
+                      "dof_cycles_per_s": round(n * sum(ito) / dto, 1),
+                      "final_relres_fp64": residual_rel(p, xo.cpu().numpy())}
+        if not adjoint:
+            # error of the reduced-precision iterates against the FP64 ones
+            s64, smx = (s, so) if prec == "fp64" else (so, s)
+            per_iter, at_tol = mixed_vs_fp64(torch, s64, smx, b, its, rtol)
+            out["mixed_error"] = {"what": "||x_mixed - x_fp64|| / ||x_fp64|| after each iteration from x0 = 0, "
+                                          "and of the two solutions at the tolerance",
+                                  "per_iter": [float(f"{e:.3e}") for e in per_iter],
+                                  "at_tol": float(f"{at_tol:.3e}")}
+            log(f"mixed vs FP64: {out['mixed_error']}")
+        log(f"{other}: {out[other]}")
+        del so
         del s
         torch.cuda.empty_cache()
-        if not isinstance(p, list) and not adjoint and args.hybrid_levels:
+        hl = args.hybrid_levels if args.hybrid_levels is not None else HYBRID_LEVELS.get(cfg, "")
+        if not isinstance(p, list) and not adjoint and hl:
             # hybrid AMG-DD V-cycles (Algorithm 3), same precision and tolerance
             out["hybrid"] = []
-            for lt in [int(v) for v in args.hybrid_levels.split(",") if v.strip()]:
+            for lt in [int(v) for v in hl.split(",") if v.strip()]:
                 t0 = time.perf_counter()
                 sh = make_solver(amgdd, p, prec, hybrid_level=lt)
                 hsetup = time.perf_counter() - t0
                 run_steps(torch, sh, b, 1, rtol, False)
-                dth, ith, xh = run_steps(torch, sh, b, k, rtol, False)
+                hstep = []
+                dth, ith, xh = run_steps(torch, sh, b, k, rtol, False, hstep)
                 sth = sh.stats()
                 rec = {"level": lt, "iters": int(np.median(ith)), "time_to_tol_ms": round(dth / k * 1e3, 4),
+                       "step_ms_median": round(float(np.median(hstep)) * 1e3, 4),
                        "dof_cycles_per_s": round(n * sum(ith) / dth, 1), "grids": sth["n_grids"],
                        "composite_overhead": round(sth["composite_overhead"], 4), "setup_s": round(hsetup, 2),
                        "device_gib": round(sth["device_bytes"] / 2**30, 3),
@@ -407,16 +509,8 @@ def main():
                 log(f"hybrid L~={lt}: {rec}")
                 del sh
                 torch.cuda.empty_cache()
-        so = make_solver(amgdd, p, other)
-        run_steps(torch, so, b, 1, rtol, adjoint)
-        dto, ito, xo = run_steps(torch, so, b, k, rtol, adjoint)
-        out[other] = {"iters_per_step": int(np.median(ito)), "time_to_tol_ms": round(dto / k * 1e3, 4),
-                      "dof_cycles_per_s": round(n * sum(ito) / dto, 1),
-                      "final_relres_fp64": residual_rel(p, xo.cpu().numpy())}
-        log(f"{other}: {out[other]}")
-        del so
-    if not args.no_cpu_baseline and cfg == "cfg2":
-        out["cpu_baseline"] = cpu_baseline()
+    if not args.no_cpu_baseline and cfg == "cfg3":
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
         log(f"cpu baseline: {out['cpu_baseline']}")
     print(json.dumps(out), flush=True)
 

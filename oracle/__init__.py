@@ -13,9 +13,10 @@ Modules
   cycles     V-cycle (Algorithm 1), AlgFAC (Algorithm 4), masked full-grid
              cycle (Section 4 guiding principle), AMG-DD (Algorithm 2)
   adjoint    dense adjoint and face gradients (derivative of a linear solve)
+  parallel   the AMG-DD iteration with its subdomain loop in worker processes
 
 Parity status: every function is pinned by tests under tests/ (dense solves,
 closed-form composite sizes, special-case reductions, invariants) except the
 float32 emulation of the mixed-precision form, whose parity is unpinned.
 """
-from . import amg, composite, cycles, adjoint  # noqa: F401
+from . import amg, composite, cycles, adjoint, parallel  # noqa: F401

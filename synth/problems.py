@@ -48,6 +48,7 @@ __all__ = [
     "anisotropic_tensor",
     "q1_stiffness",
     "anisotropic_problem",
+    "isolated_column_problem",
     "CONFIG_NAMES",
 ]
 
@@ -231,6 +232,37 @@ def make_problem(
         c=c,
         k=None if k is None else kk,
     )
+
+
+def isolated_column_problem(dims: Sequence[int] = (40, 40), parts: Sequence[int] = (2, 2), col: Optional[int] = None,
+                            eta: int = 1, n_fac: int = 2, rhs_seed: int = 0, name: str = "") -> Problem:
+    """2D 5-point operator (diagonal 4, couplings -1) in which every point of
+    one grid column x = col couples to its four neighbours with +0.25 instead
+    (symmetric, strictly diagonally dominant, so SPD).  Those points have no
+    negative coupling at all, so no strength-of-connection rule links them to
+    anything: they become F-points with empty interpolation rows, and the
+    grids to their left and right fall apart on every coarse level.  A
+    subdomain whose padding reaches across the column then has ghost points
+    whose interpolation columns lie outside its coarse composite grid: the
+    omitted entries of Section 4.2 (its Figure 4 draws such a point)."""
+    dims = tuple(int(d) for d in dims)
+    nx, ny = dims
+    col = nx // 2 - 1 if col is None else int(col)
+    n = nx * ny
+    idx = np.arange(n).reshape(ny, nx)
+    xs = np.tile(np.arange(nx), ny)
+    rows, cols, vals = [np.arange(n)], [np.arange(n)], [np.full(n, 4.0)]
+    for a_, b_ in ((idx[:, :-1].ravel(), idx[:, 1:].ravel()), (idx[:-1, :].ravel(), idx[1:, :].ravel())):
+        c = np.where((xs[a_] == col) | (xs[b_] == col), 0.25, -1.0)
+        rows += [a_, b_]
+        cols += [b_, a_]
+        vals += [c, c]
+    A = sparse.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n))
+    A.sort_indices()
+    empty = np.zeros(0, dtype=np.int64)
+    return Problem(name=name or f"isolated_column{nx}x{ny}", dims=dims, A=A, b=uniform_rhs(n, rhs_seed),
+                   part=block_partition(dims, parts), nparts=int(np.prod(parts)), eta=int(eta), n_fac=int(n_fac),
+                   faces=Faces(empty, empty, empty), c=np.zeros(0), extra={"column": col})
 
 
 def anisotropic_tensor(theta: float, eps: float) -> np.ndarray:

@@ -69,3 +69,12 @@ def test_traffic_records_are_current_and_consistent():
         # bench.py finds the record for its launch site
         dom = dict(name=r["site"], level=r["level"], workgroups=r["workgroups"])
         assert bench.measured_traffic(dom) == r["traffic_bytes"]
+
+
+def test_cpu_baseline_times_the_oracle_on_the_sample():
+    rec = bench.cpu_baseline(seconds=0.5)
+    assert rec["kind"] == "oracle" and rec["unit"] == "DOF*cycles/s"
+    assert rec["value"] > 0 and rec["one_core"]["value"] > 0 and rec["one_core"]["cores"] == 1
+    share, host = bench.host_cores()
+    assert rec["cores"] == min(share, 27) and host["affinity"] >= 1
+    assert "72^3" in rec["sample"]

@@ -35,8 +35,7 @@ def _np(t):
     return t.detach().cpu().numpy()
 
 
-def _rel(a, b):
-    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+from tests.parity import rel_2, rel_inf as _rel  # noqa: E402  (element-wise bar)
 
 
 CASES = {

@@ -1,0 +1,173 @@
+"""GPU parity on the method's degenerate and edge cases, element by element
+against the oracle (max-entry bar 1e-12, tests/parity.py):
+
+* one subdomain: the composite grid is the whole hierarchy, so one AMG-DD
+  iteration is n_fac V(1,1) cycles (Section 4's guiding principle with
+  nothing masked);
+* padding 0 (composite grids are the subdomains' C-point trees plus ghosts);
+* padding at least the graph diameter: every level whole again, = V-cycles;
+* dropped interpolation columns (Section 4.2): an operator with a column of
+  isolated points, whose ghost rows interpolate from coarse points outside
+  the composite grid; the library must drop exactly the oracle's entries and
+  reproduce its AlgFAC iterates;
+* per-level padding eta_l;
+* the binding's argument checks on device tensors and the autograd error
+  path for an unconverged solve."""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import amg, composite, cycles
+from synth import grf, isolated_column_problem, make_problem
+from tests.parity import rel_2, rel_inf
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+amgdd = pytest.importorskip("paper_1906_10575_amd.amgdd")
+
+DEV = "cuda:0"
+
+
+def say(*a):
+    print("[gpu-test]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _t(x):
+    return torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64), device=DEV)
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _iterate(p, s, H, comps, iters, eta_list=None, tol=1e-12):
+    b = _t(p.b)
+    x = torch.zeros_like(b)
+    xo = np.zeros(p.n)
+    co = cycles.CoarseSolver(H.A[H.L])
+    for k in range(iters):
+        x, info, st = s.solve(b, x, rtol=0, maxit=1)
+        assert st == amgdd.OK and info.iters == 1
+        xo = cycles.amgdd_iteration(H, comps, p.b, xo, p.n_fac, co)
+        err = rel_inf(_np(x), xo)
+        say(f"  iter {k + 1}: max-entry rel err {err:.2e}, 2-norm {rel_2(_np(x), xo):.2e}")
+        assert err <= tol, (k, err)
+    return _np(x), xo
+
+
+@pytest.mark.parametrize("dims,nfac", [((24, 20, 18), 2), ((50, 46), 3)])
+def test_one_subdomain_is_nfac_vcycles(dims, nfac):
+    p = make_problem(dims, (1,) * len(dims), eta=1, n_fac=nfac)
+    say("one subdomain", dims, "n_fac", nfac)
+    H = amg.setup(p.A)
+    comps = composite.build_all(H, p.part, 1, 1)
+    for l, lev in enumerate(comps[0].levels):
+        assert lev.n_real == H.A[l].shape[0] and lev.n_bar == lev.n_real
+    s = amgdd.Solver(p.A, p.part, 1, padding=1, n_fac=nfac)
+    x, xo = _iterate(p, s, H, comps, 3)
+    # the same three iterations as 3 * n_fac V-cycles (oracle and device)
+    co = cycles.CoarseSolver(H.A[H.L])
+    xv = np.zeros(p.n)
+    for _ in range(3 * nfac):
+        xv = cycles.vcycle(H, xv, p.b, coarse=co)
+    assert rel_inf(xo, xv) <= 1e-12
+    xd, _, _ = s.vsolve(_t(p.b), rtol=0, maxit=3 * nfac)
+    assert rel_inf(x, _np(xd)) <= 1e-12
+
+
+def test_padding_zero():
+    p = make_problem((20, 18, 20), (2, 2, 3), eta=0, n_fac=2, k=np.exp(grf((20, 18, 20), 1.0, 8.0, 1)))
+    say("padding 0", p.n)
+    H = amg.setup(p.A)
+    comps = composite.build_all(H, p.part, p.nparts, 0)
+    s = amgdd.Solver(p.A, p.part, p.nparts, padding=0, n_fac=2)
+    for q in range(p.nparts):
+        gids, nr, om = s.composite(0, q, 0)
+        assert np.array_equal(gids, comps[q].levels[0].gid) and nr == comps[q].levels[0].n_real
+        assert nr == int((p.part == q).sum())
+    _iterate(p, s, H, comps, 4)
+
+
+def test_padding_beyond_diameter_is_vcycles():
+    dims = (16, 16, 16)
+    p = make_problem(dims, (2, 2, 2), eta=64, n_fac=2)   # graph diameter 45
+    say("padding 64 >= diameter", p.n)
+    H = amg.setup(p.A)
+    comps = composite.build_all(H, p.part, p.nparts, 64)
+    s = amgdd.Solver(p.A, p.part, p.nparts, padding=64, n_fac=2)
+    for q in range(p.nparts):
+        for l in range(H.L + 1):
+            gids, nr, om = s.composite(0, q, l)
+            assert nr == H.A[l].shape[0] == gids.size
+    x, xo = _iterate(p, s, H, comps, 3)
+    co = cycles.CoarseSolver(H.A[H.L])
+    xv = np.zeros(p.n)
+    for _ in range(6):
+        xv = cycles.vcycle(H, xv, p.b, coarse=co)
+    assert rel_inf(xo, xv) <= 1e-12 and rel_inf(x, xv) <= 1e-12
+
+
+@pytest.mark.parametrize("parts,eta", [((2, 2), 1), ((4, 2), 2)])
+def test_dropped_interpolation_columns(parts, eta):
+    p = isolated_column_problem((40, 40), parts, eta=eta)
+    say("omissions", parts, eta)
+    H = amg.setup(p.A)
+    comps = composite.build_all(H, p.part, p.nparts, eta)
+    om_o = [[lev.omissions for lev in cg.levels] for cg in comps]
+    s = amgdd.Solver(p.A, p.part, p.nparts, padding=eta, n_fac=2)
+    om_d = [[s.composite(0, q, l)[2] for l in range(H.L + 1)] for q in range(p.nparts)]
+    say("  omissions per grid and level", om_d)
+    assert om_d == om_o and sum(map(sum, om_o)) > 0
+    assert s.stats()["omissions"] == sum(map(sum, om_o))
+    _iterate(p, s, H, comps, 4)
+    x, info, st = s.solve(_t(p.b), rtol=1e-8, maxit=100)
+    assert st == amgdd.OK
+    assert np.linalg.norm(p.b - p.A @ _np(x)) <= 1e-8 * np.linalg.norm(p.b)
+
+
+@pytest.mark.parametrize("etas", [[2, 1, 0, 2], [0, 3]])
+def test_per_level_padding_iterates(etas):
+    dims = (20, 18, 20)
+    p = make_problem(dims, (2, 2, 3), eta=1, n_fac=2, k=np.exp(grf(dims, 1.0, 8.0, 1)))
+    say("per-level padding", etas)
+    H = amg.setup(p.A)
+    full = (list(etas) + [p.eta] * (H.L + 1))[: H.L + 1]
+    comps = composite.build_all(H, p.part, p.nparts, full)
+    s = amgdd.Solver(p.A, p.part, p.nparts, padding=p.eta, n_fac=2, padding_per_level=etas)
+    _iterate(p, s, H, comps, 3)
+
+
+def test_binding_checks_on_device_tensors():
+    p = make_problem((16, 16), (2, 2), eta=1)
+    say("binding argument checks")
+    s = amgdd.Solver(p.A, p.part, p.nparts)
+    with pytest.raises(ValueError):
+        s.solve(torch.zeros(p.n - 1, dtype=torch.float64, device=DEV))
+    with pytest.raises(ValueError):
+        s.solve(_t(p.b), torch.zeros(p.n + 5, dtype=torch.float64, device=DEV))
+    with pytest.raises(TypeError):
+        s.solve(torch.zeros(p.n, dtype=torch.float32, device=DEV))
+    u = torch.zeros(p.n, dtype=torch.float64, device=DEV)
+    with pytest.raises(ValueError):
+        s.face_gradient(u, u, torch.tensor([0, p.n]), torch.tensor([1, -1]))
+    with pytest.raises(ValueError):
+        s.face_gradient(u[:-1], u, torch.tensor([0]), torch.tensor([1]))
+    # empty face list is fine
+    assert s.face_gradient(u, u, torch.tensor([], dtype=torch.int32), torch.tensor([], dtype=torch.int32)).numel() == 0
+
+
+def test_autograd_raises_on_unconverged_solves():
+    from paper_1906_10575_amd.autograd import FaceProblem, diffusion_solve
+    p = make_problem((12, 12, 12), (2, 2, 2), eta=1)
+    say("autograd unconverged")
+    fi = np.concatenate([p.faces.inner_i, p.faces.bnd_i])
+    fj = np.concatenate([p.faces.inner_j, -np.ones(p.faces.bnd_i.size, dtype=np.int64)])
+    prob = FaceProblem(p.n, fi, fj, p.part, p.nparts, rtol=1e-10, maxit=1)
+    c = _t(p.c).requires_grad_(True)
+    with pytest.raises(amgdd.AmgddError) as e:
+        diffusion_solve(c, _t(p.b), prob)
+    assert e.value.status == amgdd.ENOCONV

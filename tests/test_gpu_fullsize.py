@@ -4,7 +4,8 @@ configuration bench.py times (graph replay, default schedule).
 
 * sampled outputs: the first two AMG-DD iterates and V(1,1) iterates at 2000
   seeded points and the residual norms, against values written by
-  tests/golden/make_cfg2_samples.py from the oracle alone (1e-12 relative);
+  tests/golden/make_cfg2_samples.py from the oracle alone (every sampled entry
+  within 1e-12 of the largest sampled magnitude);
 * properties at any size: the solve reaches 1e-8 with the residual recomputed
   in FP64 on the host, a second solve is bitwise identical, and every
   subdomain's level-0 composite sets have the closed-form L1-ball sizes."""
@@ -16,6 +17,7 @@ import numpy as np
 import pytest
 
 from synth import config
+from tests.parity import rel_2, rel_inf
 
 pytestmark = pytest.mark.gpu
 
@@ -47,8 +49,9 @@ def test_cfg2_sampled_iterates_match_oracle(cfg2):
             x, info, st = fn(b, x, rtol=0, maxit=1)
             ref = np.array(g[f"{kind}_x{k}"])
             got = x.cpu().numpy()[idx]
-            err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
-            print(f"[gpu-test] {kind} iterate {k}: sampled rel err {err:.2e}", flush=True)
+            err = rel_inf(got, ref)
+            print(f"[gpu-test] {kind} iterate {k}: sampled max-entry rel err {err:.2e}, 2-norm "
+                  f"{rel_2(got, ref):.2e}", flush=True)
             assert err <= 1e-12
             hist = s.history(0)
             np.testing.assert_allclose(hist[-1], g[f"{kind}_hist"][k], rtol=1e-10)
@@ -95,8 +98,8 @@ def test_cfg2_hybrid_sampled_iterates_and_solve():
         for k in (1, 2):
             x, info, st = s.solve(b, x, rtol=0, maxit=1)
             ref = np.array(g[f"hybrid_x{k}"])
-            err = np.linalg.norm(x.cpu().numpy()[idx] - ref) / np.linalg.norm(ref)
-            print(f"[gpu-test] hybrid iterate {k}: sampled rel err {err:.2e}", flush=True)
+            err = rel_inf(x.cpu().numpy()[idx], ref)
+            print(f"[gpu-test] hybrid iterate {k}: sampled max-entry rel err {err:.2e}", flush=True)
             assert err <= 1e-12
             np.testing.assert_allclose(s.history(0)[-1], g["hybrid_hist"][k], rtol=1e-10)
     x, info, st = s.solve(b, rtol=1e-8, maxit=200)
