@@ -104,6 +104,18 @@ def host_cores():
 
 
 def cpu_baseline(seconds=10.0):
+    """The oracle timed on the host (see _cpu_baseline_run), in a child
+    process of its own: the worker processes it forks then never inherit a
+    process that holds a GPU context or BLAS thread pools in use."""
+    import subprocess
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only", "--cpu-seconds",
+                        str(seconds)], capture_output=True, text=True, timeout=3600)
+    if r.returncode != 0:
+        raise RuntimeError(f"CPU baseline run failed (exit {r.returncode}): {r.stderr[-2000:]}")
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def _cpu_baseline_run(seconds=10.0):
     """The oracle (plain FP64 NumPy/SciPy, written from the paper) timed on the
     host on a bounded sample of the 192^3 workload: the 72^3 corner of the
     same coefficient field (GRF sigma 1, l 8, seed 1; harmonic faces;
@@ -342,7 +354,12 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run 3 elementwise copies of 256 MiB (known HBM traffic, to scale PMC counters)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="seconds per CPU-baseline run")
+    ap.add_argument("--cpu-baseline-only", action="store_true",
+                    help="only time the oracle on the host (one JSON line; no GPU is touched)")
     args = ap.parse_args()
+    if args.cpu_baseline_only:
+        print(json.dumps(_cpu_baseline_run(args.cpu_seconds)), flush=True)
+        return
     if args.summarize_rocpd:
         print(summarize_rocpd(args.summarize_rocpd))
         return

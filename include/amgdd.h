@@ -48,6 +48,11 @@
  *   AMGDD_LANE_TARGET=x   entries per lane that set the lanes per composite row
  *   AMGDD_SERIAL          one stream per iteration (no side-stream branch)
  *   AMGDD_TEST_MAX_BYTES=n  device-memory cap (failure-path tests)
+ * and when a handle's schedule is tuned:
+ *   AMGDD_TUNE_CACHE=path schedule cache file (JSON, one entry per line,
+ *                         keyed by a hash of the layout, device and library
+ *                         build); default $HOME/.cache/amgdd/schedules.json,
+ *                         "off" = no file (the in-process cache remains)
  * Index width, the side-stream branch and the launch schedule leave results
  * bitwise unchanged; step width, row order and lanes per row change only the
  * rounding of rows served by several lanes.
@@ -86,8 +91,10 @@ typedef struct {
   int tail_level;   /* AlgFAC schedule: levels >= tail_level run in one persistent
                        launch per cycle with one workgroup per composite grid,
                        levels above it level-synchronously over all grids.
-                       -2 = chosen by the autotuner at the first solve (default),
-                       -1 = level-synchronous everywhere, >= 0 fixed */
+                       -2 = chosen by the autotuner at the first solve (default;
+                       the choice is cached per layout and device, see
+                       AMGDD_TUNE_CACHE), -1 = level-synchronous everywhere,
+                       >= 0 fixed */
   int tail_block;   /* workgroup size of the persistent launch: 256, 512 or 1024;
                        0 = chosen by the autotuner (default) */
   int hybrid_level; /* 0 = AMG-DD on the fine level (default).  L~ >= 1 = hybrid
@@ -163,6 +170,8 @@ typedef struct {
                                the level-L~ problems' grids (levels >= L~), and
                                composite_overhead = (nnz of A_l, l < L~, plus
                                composite_real_nnz) / global_nnz */
+  int schedule_cached;      /* 1 = the schedule came from the schedule cache
+                               (no tuning runs), 0 = tuned or fixed */
 } amgdd_stats;
 
 void amgdd_params_default(amgdd_params *prm);
@@ -212,10 +221,21 @@ amgdd_status amgv_solve(amgdd_handle h, const double *b_dev, double *x_dev, doub
                         amgdd_info *info);
 
 /*
- * Adjoint solve A^T lambda = g with the same hierarchy and composite grids.
- * Supported when every A_0 given at setup is symmetric (checked at setup):
- * then A^T = A and the forward operators are the transposed ones.  Returns
- * EUNSUPPORTED for a non-symmetric handle.  lambda_dev is in/out like x_dev.
+ * Adjoint solve A^T lambda = g by AMG-DD iterations (hybrid cycles on a
+ * hybrid handle) with the same hierarchy: the same C/F splittings, P_l,
+ * R_l = P_l^T and composite grids.  Because A_{l+1} = R_l A_l P_l (Section 2),
+ * A_{l+1}^T = R_l A_l^T P_l, so these form a Galerkin hierarchy for A^T whose
+ * operators are the transposes A_l^T:
+ *   - symmetric A_0 (checked bitwise at setup): A^T = A, the forward
+ *     operators are used as they are;
+ *   - otherwise the transposed composite operators (rows of A_l^T on every
+ *     composite grid, l1-Jacobi diagonals sum_j |a_ji|, coarsest inverse of
+ *     A_L^T) are built on the host and uploaded at the first adjoint call of
+ *     the handle (host time and device memory comparable to the forward
+ *     setup's composite part; reported in amgdd_stats.device_bytes), and
+ *     kept until amgdd_destroy.
+ * g_dev, lambda_dev: device FP64 of length sum N_0; lambda is in/out like
+ * x_dev of amgdd_solve, with the same stopping rule and statuses.
  */
 amgdd_status amgdd_solve_adjoint(amgdd_handle h, const double *g_dev, double *lambda_dev, double rtol,
                                  int maxit, amgdd_info *info);

@@ -1,7 +1,10 @@
 """Differentiable AMG-DD solve of a face-coefficient diffusion operator.
 
-A(c) = sum_f c_f E_f with E_f = (e_i - e_j)(e_i - e_j)^T for an interior face
-(i, j) and e_i e_i^T for a boundary face of cell i.  Forward: assemble A(c) on
+A(c) = sum_f c_f E_f + B with E_f = (e_i - e_j)(e_i - e_j)^T for an interior
+face (i, j) and e_i e_i^T for a boundary face of cell i, and B an optional
+fixed operator independent of c (for example upwind convection, which makes
+A non-symmetric; the library then solves the adjoint with the transposed
+composite operators).  Forward: assemble A(c) on
 the host, build the hierarchy and composite grids (host setup in the
 library), solve A u = f by AMG-DD on the device.  Backward (adjoint): solve
 A^T lambda = dL/du by AMG-DD with the same hierarchy, then dL/df = lambda and
@@ -14,6 +17,7 @@ whatever differentiable map the caller uses for c(k).
 from __future__ import annotations
 
 from dataclasses import dataclass
+from typing import Optional
 
 import numpy as np
 import torch
@@ -37,6 +41,7 @@ class FaceProblem:
     precision: str = "fp64"
     rtol: float = 1e-10
     maxit: int = 200
+    fixed: Optional[sparse.csr_matrix] = None  # B: added to sum_f c_f E_f, independent of c
 
     def assemble(self, c: np.ndarray) -> sparse.csr_matrix:
         fi = np.asarray(self.face_i, dtype=np.int64)
@@ -49,6 +54,8 @@ class FaceProblem:
         cols = np.concatenate([np.arange(self.n), fj[inner], fi[inner]])
         vals = np.concatenate([diag, -c[inner], -c[inner]])
         A = sparse.coo_matrix((vals, (rows, cols)), shape=(self.n, self.n)).tocsr()
+        if self.fixed is not None:
+            A = (A + self.fixed).tocsr()
         A.sum_duplicates()
         A.sort_indices()
         return A
@@ -90,3 +97,15 @@ class _DiffusionSolve(torch.autograd.Function):
 def diffusion_solve(c: torch.Tensor, f: torch.Tensor, prob: FaceProblem) -> torch.Tensor:
     """u = A(c)^{-1} f by AMG-DD, differentiable in c and f."""
     return _DiffusionSolve.apply(c, f, prob)
+
+
+def harmonic_face_coefficients(k: torch.Tensor, face_i, face_j) -> torch.Tensor:
+    """Face coefficients from cell coefficients as torch operations (so dL/dk
+    follows from dL/dc by autograd): 2 k_i k_j / (k_i + k_j) for an interior
+    face (i, j), k_i for a boundary face of cell i (face_j = -1)."""
+    fi = torch.as_tensor(np.asarray(face_i, dtype=np.int64), device=k.device)
+    fj = torch.as_tensor(np.asarray(face_j, dtype=np.int64), device=k.device)
+    inner = fj >= 0
+    ki = k[fi]
+    kj = k[torch.where(inner, fj, fi)]
+    return torch.where(inner, 2.0 * ki * kj / (ki + kj), ki)

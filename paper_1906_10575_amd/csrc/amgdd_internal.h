@@ -200,6 +200,11 @@ int build_setup_hybrid(const std::vector<ProblemInput> &in, double theta, int ma
                        Setup &outer, Setup &inner, std::vector<int> &inner_of, std::vector<std::vector<int>> &part_map,
                        std::string &err);
 
+// Hierarchy of A^T from the forward setup F (same C/F splittings, P_l, R_l
+// and composite sets; operators A_l^T and their l1 diagonals and coarsest
+// inverse), with composite grids and layouts when `composite` (F has grids).
+int build_setup_transposed(const Setup &F, bool composite, Setup &T, std::string &err);
+
 // Individual steps, exposed for the driver's introspection.
 uint64_t splitmix64(uint64_t x);
 std::vector<double> pmis_random(int level, int n);

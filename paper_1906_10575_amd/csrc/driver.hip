@@ -19,12 +19,16 @@
 #include <hip/hip_runtime.h>
 #include <rocprofiler-sdk-roctx/roctx.h>
 
+#include <sys/stat.h>
+#include <unistd.h>
+
 #include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -200,6 +204,7 @@ struct amgdd_ctx {
   std::vector<int> tail_off, tail_cnt;   // per lt
   int tail_maxn = 0;                     // largest coarsest level (shared memory of the tail)
   int sched_level = -2, sched_block = 256;
+  int sched_cached = 0;  // schedule taken from the schedule cache
   double autotune_s = 0.0;
   hipGraphExec_t g_dd = nullptr, g_v = nullptr;
   hipGraph_t gr_dd = nullptr, gr_v = nullptr;
@@ -212,6 +217,9 @@ struct amgdd_ctx {
   int hybrid_lt = 0;                       // transition level L~ (0: not hybrid)
   std::vector<int> inner_of;               // problem -> its level-L~ problem (-1: none)
   std::vector<std::vector<int>> part_map;  // subdomain -> level-L~ subdomain (-1: empty)
+  // adjoint of a non-symmetric operator: a handle of its own on the transposed
+  // hierarchy (built at the first adjoint solve)
+  amgdd_ctx *adj = nullptr;
 
   bool mixed() const { return prm.precision == AMGDD_MIXED; }
   bool cf() const { return S.cf; }
@@ -265,6 +273,7 @@ struct amgdd_ctx {
   }
 
   ~amgdd_ctx() {
+    delete adj;
     delete inner;
     if (!host_only) {
       (void)hipSetDevice(device);
@@ -760,6 +769,135 @@ amgdd_status capture(amgdd_ctx *h, bool dd, hipGraph_t *gr, hipGraphExec_t *ex) 
   return AMGDD_OK;
 }
 
+// ---------------------------------------------------------------- schedule cache
+//
+// The autotuner's choice depends only on the layout (levels, rows, stored
+// entries and lane groupings of every batched matrix, grids, precision, cycles,
+// relaxation order), on the device and on the kernels, so it is cached under a
+// 64-bit FNV-1a hash of those: in memory for the process, and in a JSON file
+// (one entry per line) that later processes read.  The file is
+// $AMGDD_TUNE_CACHE, or $HOME/.cache/amgdd/schedules.json when that is unset;
+// AMGDD_TUNE_CACHE=off disables the file.  The kernels enter the key through
+// the library's build time, so a rebuilt library tunes again.
+
+struct SchedKey {
+  uint64_t h = 1469598103934665603ull;
+  void add(const void *p, size_t n) {
+    const unsigned char *c = (const unsigned char *)p;
+    for (size_t i = 0; i < n; ++i) { h ^= c[i]; h *= 1099511628211ull; }
+  }
+  template <typename V>
+  void add(V v) { add(&v, sizeof(v)); }
+  void add_str(const char *s) { add(s, std::strlen(s)); }
+};
+
+uint64_t schedule_key(amgdd_ctx *h) {
+  SchedKey k;
+  k.add_str(__DATE__ " " __TIME__);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) {
+    k.add_str(prop.gcnArchName);
+    k.add(prop.multiProcessorCount);
+  }
+  k.add(h->prm.precision);
+  k.add(h->prm.n_fac);
+  k.add(h->prm.tail_level);
+  k.add(h->prm.tail_block);
+  k.add((int)h->S.cf);
+  k.add((int)h->S.grids.size());
+  k.add(h->tail_maxn);
+  for (const DLevel &D : h->L) {
+    k.add(D.NRn); k.add(D.NBn); k.add(D.NB); k.add(D.lg); k.add(D.ncg); k.add(D.cg_maxn);
+    for (const DSell *M : {&D.A, &D.P, &D.R}) { k.add(M->entries); k.add(M->lg); k.add(M->vlg); k.add((int)(M->col16 != nullptr)); }
+    k.add(D.nnzA); k.add(D.nnzP); k.add(D.nnzR);
+  }
+  for (int c : h->tail_cnt) k.add(c);
+  return k.h;
+}
+
+struct SchedEntry {
+  int level, block;
+  double ms;
+};
+
+std::string sched_cache_path() {
+  const char *e = std::getenv("AMGDD_TUNE_CACHE");
+  if (e && std::strcmp(e, "off") == 0) return std::string();
+  if (e && e[0]) return e;
+  const char *home = std::getenv("HOME");
+  if (!home || !home[0]) return std::string();
+  return std::string(home) + "/.cache/amgdd/schedules.json";
+}
+
+// Entries of the cache file (lines of the form  "key": [level, block, ms],).
+std::vector<std::pair<uint64_t, SchedEntry>> read_sched_file(const std::string &path) {
+  std::vector<std::pair<uint64_t, SchedEntry>> out;
+  FILE *f = path.empty() ? nullptr : std::fopen(path.c_str(), "r");
+  if (!f) return out;
+  char line[512];
+  while (std::fgets(line, sizeof line, f)) {
+    unsigned long long key;
+    SchedEntry e;
+    if (std::sscanf(line, " \"%16llx\": [%d, %d, %lf]", &key, &e.level, &e.block, &e.ms) == 4)
+      out.push_back({(uint64_t)key, e});
+  }
+  std::fclose(f);
+  return out;
+}
+
+// Adds or replaces one entry; written to a temporary file and renamed over the
+// old one, so readers never see a partial file.  Failures are silent (the
+// cache is an optimisation).
+void write_sched_file(const std::string &path, uint64_t key, const SchedEntry &e) {
+  if (path.empty()) return;
+  auto ent = read_sched_file(path);
+  bool found = false;
+  for (auto &x : ent)
+    if (x.first == key) { x.second = e; found = true; }
+  if (!found) ent.push_back({key, e});
+  const size_t slash = path.rfind('/');
+  if (slash != std::string::npos && slash > 0) {
+    // create the directory chain
+    for (size_t pos = 1; pos <= slash; ++pos)
+      if (pos == slash || path[pos] == '/') (void)mkdir(path.substr(0, pos).c_str(), 0755);
+  }
+  const std::string tmp = path + ".tmp" + std::to_string((long long)getpid());
+  FILE *f = std::fopen(tmp.c_str(), "w");
+  if (!f) return;
+  std::fprintf(f, "{\n");
+  for (size_t i = 0; i < ent.size(); ++i)
+    std::fprintf(f, "\"%016llx\": [%d, %d, %.6f]%s\n", (unsigned long long)ent[i].first, ent[i].second.level,
+                 ent[i].second.block, ent[i].second.ms, i + 1 < ent.size() ? "," : "");
+  std::fprintf(f, "}\n");
+  const bool ok = std::fclose(f) == 0;
+  if (!ok || std::rename(tmp.c_str(), path.c_str()) != 0) (void)std::remove(tmp.c_str());
+}
+
+std::mutex g_sched_mu;
+std::vector<std::pair<uint64_t, SchedEntry>> g_sched_mem;
+
+bool sched_lookup(uint64_t key, SchedEntry &e) {
+  std::lock_guard<std::mutex> lk(g_sched_mu);
+  for (auto &x : g_sched_mem)
+    if (x.first == key) { e = x.second; return true; }
+  for (auto &x : read_sched_file(sched_cache_path()))
+    if (x.first == key) {
+      e = x.second;
+      g_sched_mem.push_back(x);
+      return true;
+    }
+  return false;
+}
+
+void sched_store(uint64_t key, const SchedEntry &e) {
+  std::lock_guard<std::mutex> lk(g_sched_mu);
+  bool found = false;
+  for (auto &x : g_sched_mem)
+    if (x.first == key) { x.second = e; found = true; }
+  if (!found) g_sched_mem.push_back({key, e});
+  write_sched_file(sched_cache_path(), key, e);
+}
+
 // Project autotuner: time one graph-replayed AMG-DD iteration for every
 // schedule candidate (cut level x workgroup size) on the caller's data and keep
 // the fastest.  Every candidate computes identical results, so the choice only
@@ -768,6 +906,17 @@ amgdd_status autotune(amgdd_ctx *h) {
   TraceRange tr("amgdd: autotune");
   const double t0 = now_s();
   const int nlev = (int)h->L.size();
+  const uint64_t key = schedule_key(h);
+  {
+    SchedEntry e;
+    if (sched_lookup(key, e) && e.level >= -1 && e.level < nlev && (e.block == 256 || e.block == 512 || e.block == 1024)) {
+      h->sched_level = e.level;
+      h->sched_block = e.block;
+      h->sched_cached = 1;
+      h->autotune_s = now_s() - t0;
+      return AMGDD_OK;
+    }
+  }
   hipStream_t s = h->stream;
   std::vector<int> levels, blocks;
   if (h->prm.tail_level >= -1) levels.push_back(h->prm.tail_level >= nlev ? -1 : h->prm.tail_level);
@@ -807,9 +956,11 @@ amgdd_status autotune(amgdd_ctx *h) {
     }
   h->sched_level = best_l;
   h->sched_block = best_b;
+  h->sched_cached = 0;
   HIP_TRY(hipMemcpyAsync(h->x, xsave, (size_t)h->N0 * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
   h->drop_graphs();
+  sched_store(key, SchedEntry{best_l, best_b, best / 3.0});
   h->autotune_s = now_s() - t0;
   return AMGDD_OK;
 }
@@ -919,6 +1070,75 @@ amgdd_status run_solve(amgdd_ctx *h, SolveKind kind, const double *b_dev, double
     info->rho_asym = rho;
   }
   return result;
+}
+
+// Streams, events and device layouts of a handle and of its level-L~ handle.
+amgdd_status init_device(amgdd_ctx *h, int device, hipStream_t stream) {
+  HIP_TRY(hipSetDevice(device));
+  long long cap = 0;
+  if (const char *e2 = std::getenv("AMGDD_TEST_MAX_BYTES")) cap = std::atoll(e2);
+  for (amgdd_ctx *c : {h, h->inner}) {
+    if (!c) continue;
+    c->host_only = false;
+    c->max_bytes = cap;
+    c->device = device;
+    c->stream = stream;
+    c->overlap = std::getenv("AMGDD_SERIAL") == nullptr;
+    if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess)
+      return fail(ST_EDEVICE, "stream/event creation failed");
+    TraceRange tru("amgdd: upload");
+    amgdd_status us = upload_all(c);
+    if (us) return us;
+  }
+  return AMGDD_OK;
+}
+
+// The handle of the transposed hierarchy (A_l^T with the same P_l, R_l and
+// composite grids; see build_setup_transposed) for adjoint solves of a
+// non-symmetric operator, and of its level-L~ problems on a hybrid handle.
+amgdd_status make_adjoint(amgdd_ctx *h) {
+  TraceRange tr("amgdd: setup of the transposed hierarchy");
+  const double t0 = now_s();
+  amgdd_ctx *a = new (std::nothrow) amgdd_ctx();
+  if (!a) return fail(ST_ENOMEM, "handle allocation");
+  auto copy_cfg = [](amgdd_ctx *dst, const amgdd_ctx *src) {
+    dst->prm = src->prm;
+    dst->symmetric = src->symmetric;
+    dst->sched_level = src->prm.tail_level >= -1 && src->prm.tail_block != 0 ? src->sched_level : -2;
+    dst->sched_block = src->prm.tail_block ? src->prm.tail_block : 256;
+    dst->lbase = src->lbase;
+    dst->hybrid_lt = src->hybrid_lt;
+    dst->inner_of = src->inner_of;
+    dst->part_map = src->part_map;
+  };
+  copy_cfg(a, h);
+  std::string err;
+  int st = build_setup_transposed(h->S, !h->S.grids.empty(), a->S, err);
+  if (!st && h->inner) {
+    a->inner = new (std::nothrow) amgdd_ctx();
+    if (!a->inner) st = ST_ENOMEM, err = "handle allocation";
+    else {
+      copy_cfg(a->inner, h->inner);
+      st = build_setup_transposed(h->inner->S, true, a->inner->S, err);
+    }
+  }
+  if (st) {
+    delete a;
+    return fail(st, err);
+  }
+  amgdd_status us = init_device(a, h->device, h->stream);
+  if (us) {
+    std::string msg = g_last_error;
+    delete a;
+    return fail(us, msg);
+  }
+  a->setup_s = now_s() - t0;
+  h->adj = a;
+  return AMGDD_OK;
 }
 
 amgdd_status make_handle(const std::vector<ProblemInput> &in, const amgdd_params *prm, void *stream, amgdd_handle *out) {
@@ -1034,30 +1254,11 @@ amgdd_status make_handle(const std::vector<ProblemInput> &in, const amgdd_params
       delete h;
       return fail(ST_EDEVICE, "no HIP device " + std::to_string(p.device));
     }
-    (void)hipSetDevice(p.device);
-    long long cap = 0;
-    if (const char *e2 = std::getenv("AMGDD_TEST_MAX_BYTES")) cap = std::atoll(e2);
-    for (amgdd_ctx *c : {h, h->inner}) {
-      if (!c) continue;
-      c->max_bytes = cap;
-      c->device = p.device;
-      c->stream = (hipStream_t)stream;
-      c->overlap = std::getenv("AMGDD_SERIAL") == nullptr;
-      if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess ||
-          hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
-          hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-          hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
-          hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
-        delete h;
-        return fail(ST_EDEVICE, "stream/event creation failed");
-      }
-      TraceRange tru("amgdd: upload");
-      amgdd_status us = upload_all(c);
-      if (us) {
-        std::string msg = g_last_error;
-        delete h;
-        return fail(us, msg);
-      }
+    amgdd_status us = init_device(h, p.device, (hipStream_t)stream);
+    if (us) {
+      std::string msg = g_last_error;
+      delete h;
+      return fail(us, msg);
     }
     h->S.times.upload = now_s() - tu;
   }
@@ -1125,8 +1326,15 @@ amgdd_status amgv_solve(amgdd_handle h, const double *b_dev, double *x_dev, doub
 amgdd_status amgdd_solve_adjoint(amgdd_handle h, const double *g_dev, double *lambda_dev, double rtol, int maxit,
                                  amgdd_info *info) {
   if (!h) return fail(ST_EINVAL, "null handle");
-  if (!h->symmetric) return fail(ST_EUNSUP, "adjoint solves need a symmetric operator (A^T = A is used)");
-  return run_solve(h, SOLVE_DD, g_dev, lambda_dev, rtol, maxit, info);
+  if (h->symmetric || h->host_only) return run_solve(h, SOLVE_DD, g_dev, lambda_dev, rtol, maxit, info);
+  if (!h->adj) {
+    HIP_TRY(hipSetDevice(h->device));
+    amgdd_status st = make_adjoint(h);
+    if (st) return st;
+  }
+  amgdd_status st = run_solve(h->adj, SOLVE_DD, g_dev, lambda_dev, rtol, maxit, info);
+  h->hist = h->adj->hist;  // amgdd_get_history reports the last solve
+  return st;
 }
 
 amgdd_status amgdd_face_gradient(amgdd_handle h, const double *u_dev, const double *lambda_dev, const int *face_i_dev,
@@ -1167,10 +1375,11 @@ amgdd_status amgdd_get_stats(amgdd_handle h, amgdd_stats *st) {
   st->setup_composite_s = S.times.composite;
   st->setup_pack_s = S.times.pack;
   st->setup_upload_s = S.times.upload;
-  st->device_bytes = h->dev_bytes;
+  st->device_bytes = h->dev_bytes + (h->adj ? h->adj->dev_bytes + (h->adj->inner ? h->adj->inner->dev_bytes : 0) : 0);
   st->tail_level = h->sched_level;
   st->tail_block = h->sched_block;
   st->autotune_s = h->autotune_s;
+  st->schedule_cached = h->sched_cached;
   if (h->hybrid_lt > 0) {
     // composite figures of the level-L~ problems; levels above L~ (and whole
     // hierarchies that end at or above L~) are cycled on the global grids
@@ -1207,6 +1416,7 @@ amgdd_status amgdd_get_stats(amgdd_handle h, amgdd_stats *st) {
       st->tail_level = in->sched_level;
       st->tail_block = in->sched_block;
       st->autotune_s = in->autotune_s;
+      st->schedule_cached = in->sched_cached;
     }
     st->composite_overhead = S.global_nnz ? (double)(upper + st->composite_real_nnz) / (double)S.global_nnz : 0.0;
   }
@@ -1363,8 +1573,8 @@ amgdd_status amgdd_profile(amgdd_handle h, int kind, int reps, amgdd_kernel_time
 
 amgdd_status amgdd_set_stream(amgdd_handle h, void *hip_stream) {
   if (!h) return fail(ST_EINVAL, "null handle");
-  h->stream = (hipStream_t)hip_stream;
-  if (h->inner) h->inner->stream = h->stream;
+  for (amgdd_ctx *c : {h, h->inner, h->adj, h->adj ? h->adj->inner : nullptr})
+    if (c) c->stream = (hipStream_t)hip_stream;
   return AMGDD_OK;
 }
 

@@ -1218,7 +1218,11 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
       int L = S.probs[S.grids[g].prob].H.L();
       const CompLevel *lv = l <= L ? &S.grids[g].lv[l] : nullptr;
       if (!lv) continue;
-      if (L > l) { roff[l][g] = r; r += lv->nreal; goff[l][g] = gh; gh += lv->nbar() - lv->nreal; }
+      // a grid with no points on a level above its coarsest (possible with
+      // small paddings: D_l empty, hence every deeper level but the coarsest)
+      // keeps one empty ghost row there, so the padding entries of its rows
+      // on the neighbouring levels have a column of their own grid
+      if (L > l) { roff[l][g] = r; r += lv->nreal; goff[l][g] = gh; gh += std::max(1, lv->nbar()) - lv->nreal; }
       else { coff[l][g] = c; c += lv->nbar(); }
     }
     B.NRn = r;
@@ -1389,6 +1393,12 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
         for (int jj = lv.P.ptr[i]; jj < lv.P.ptr[i + 1]; ++jj) bP.put(row, kk++, bidx(g, l + 1, lv.P.col[jj]), lv.P.val[jj]);
         bP.pad(row, bidx(g, l + 1, 0));
       }
+      if (lv.nbar() == 0) {
+        // the empty ghost row of a grid without points on this level
+        const int row = bidx(g, l, 0);
+        bA.pad(row, row);
+        bP.pad(row, bidx(g, l + 1, 0));
+      }
     });
     B.nnzA_r = bA.nnz_rows(0, B.NRn);
     B.nnzA = bA.nnz_rows(0, B.NBn);
@@ -1435,6 +1445,7 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
           for (int jj = R.ptr[J]; jj < R.ptr[J + 1]; ++jj) bR.put(row, kk++, bidx(g, l, R.col[jj]), R.val[jj]);
           bR.pad(row, bidx(g, l, 0));
         }
+        if (R.nrows == 0) bR.pad(bidx(g, l + 1, 0), bidx(g, l, 0));
       });
       Bn.nnzR_n = bR.nnz_rows(0, Bn.NBn);
       Bn.nnzR = bR.nnz_rows(0, Bn.NB);
@@ -1573,7 +1584,7 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
     }
     for (int g = 0; g < ng; ++g)
       for (int l = 0; l <= S.probs[S.grids[g].prob].H.L(); ++l)
-        for (int i = 0; i < S.grids[g].lv[l].nbar(); ++i) cown[l][bidx(g, l, i)] = g;
+        for (int i = 0; i < std::max(1, S.grids[g].lv[l].nbar()); ++i) cown[l][bidx(g, l, i)] = g;
     for (int q = 0; q < nprob; ++q)
       for (int l = 0; l <= S.probs[q].H.L(); ++l)
         for (int i = 0; i < S.probs[q].H.A[l].nrows; ++i) gown[l][gbidx(q, l, i)] = q;
@@ -1644,7 +1655,7 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
         S.gl_rbeg[k] = roff[l][g];
         S.gl_nreal[k] = lv.nreal;
         S.gl_gbeg[k] = S.lv[l].NRa + goff[l][g];
-        S.gl_nghost[k] = lv.nbar() - lv.nreal;
+        S.gl_nghost[k] = std::max(1, lv.nbar()) - lv.nreal;
       } else {
         S.gl_rbeg[k] = S.lv[l].NBn + coff[l][g];
         S.gl_nreal[k] = lv.nbar();
@@ -1752,6 +1763,62 @@ int build_setup_hybrid(const std::vector<ProblemInput> &in, double theta, int ma
     inner.times.hierarchy = now_s() - t0;
     if (inner.probs.empty()) return (int)ST_OK;
     return setup_layouts(inner, true, err);
+  });
+}
+
+// Transposed hierarchy for the adjoint A^T lambda = g.  With R_l = P_l^T and
+// A_{l+1} = R_l A_l P_l (Section 2), A_{l+1}^T = R_l A_l^T P_l: the same C/F
+// splittings, P_l and R_l form a Galerkin hierarchy for A^T whose operators are
+// the transposes A_l^T; its l1-Jacobi diagonals are the row sums of |A_l^T|
+// and its coarsest solve uses the inverse of A_L^T.  Composite sets depend on
+// the undirected graph of A_l only, which A_l^T shares, so every composite
+// grid has the forward one's points; its local operators are rows of A_l^T.
+int build_setup_transposed(const Setup &F, bool composite, Setup &T, std::string &err) {
+  return guarded(err, [&]() {
+    double t0 = now_s();
+    T = Setup();
+    T.theta = F.theta;
+    T.max_coarse = F.max_coarse;
+    T.max_levels = F.max_levels;
+    T.cf = F.cf;
+    T.compress = F.compress;
+    T.step_log2 = F.step_log2;
+    T.comp_step_log2 = F.comp_step_log2;
+    T.sort_window = F.sort_window;
+    T.comp_lane_target = F.comp_lane_target;
+    T.coarsen = F.coarsen;
+    T.interp = F.interp;
+    T.interp_max = F.interp_max;
+    const int nprob = (int)F.probs.size();
+    T.probs.resize(nprob);
+    std::vector<int> status(nprob, ST_OK);
+    parallel_items(nprob, [&](int q, int) {
+      const ProblemHost &O = F.probs[q];
+      ProblemHost &P = T.probs[q];
+      P.n = O.n;
+      P.nparts = O.nparts;
+      P.eta = O.eta;
+      P.etas = O.etas;
+      P.part = O.part;
+      P.symmetric = O.symmetric;
+      P.A0 = transpose(O.A0);
+      Hierarchy &H = P.H;
+      H.P = O.H.P;
+      H.R = O.H.R;
+      H.cf = O.H.cf;
+      for (const Csr &A : O.H.A) H.A.push_back(transpose(A));
+      for (const Csr &A : H.A) H.l1.push_back(l1_rowsum(A));
+      const Csr &Ac = H.A.back();
+      const int nl = Ac.nrows;
+      H.Ac.assign((size_t)nl * nl, 0.0);
+      for (int i = 0; i < nl; ++i)
+        for (int jj = Ac.ptr[i]; jj < Ac.ptr[i + 1]; ++jj) H.Ac[(size_t)i * nl + Ac.col[jj]] = Ac.val[jj];
+      if (!dense_inverse(nl, H.Ac, H.Ac_inv)) status[q] = ST_EINVAL;
+    });
+    for (int q = 0; q < nprob; ++q)
+      if (status[q]) { err = "problem " + std::to_string(q) + ": singular transposed coarsest operator"; return status[q]; }
+    T.times.hierarchy = now_s() - t0;
+    return setup_layouts(T, composite, err);
   });
 }
 

@@ -49,6 +49,8 @@ __all__ = [
     "q1_stiffness",
     "anisotropic_problem",
     "isolated_column_problem",
+    "upwind_convection",
+    "convection_diffusion_problem",
     "CONFIG_NAMES",
 ]
 
@@ -232,6 +234,59 @@ def make_problem(
         c=c,
         k=None if k is None else kk,
     )
+
+
+def upwind_convection(dims: Sequence[int], velocity: Sequence[float]) -> sparse.csr_matrix:
+    """First-order upwind convection b . grad u on the cell grid (unscaled, as
+    the diffusion operator): for each axis with velocity b_a != 0, row i gets
+    +|b_a| on the diagonal and -|b_a| at its upstream neighbour (x - 1 for
+    b_a > 0, x + 1 for b_a < 0) when that neighbour is inside the grid
+    (homogeneous Dirichlet outside).  Off-diagonals are non-positive and every
+    interior row sums to zero; the matrix is not symmetric, and its pattern
+    lies inside the 5/7-point stencil."""
+    dims = tuple(int(d) for d in dims)
+    n = int(np.prod(dims))
+    idx = np.arange(n).reshape(_np_shape(dims))
+    rows, cols, vals = [np.arange(n)], [np.arange(n)], [np.zeros(n)]
+    for a, b in enumerate(velocity):
+        if b == 0.0:
+            continue
+        ax = len(dims) - 1 - a  # numpy axis of grid axis a (x is the last)
+        vals[0] = vals[0] + abs(b)
+        src = [slice(None)] * len(dims)
+        dst = [slice(None)] * len(dims)
+        if b > 0:
+            dst[ax], src[ax] = slice(1, None), slice(None, -1)
+        else:
+            dst[ax], src[ax] = slice(None, -1), slice(1, None)
+        rows.append(idx[tuple(dst)].ravel())
+        cols.append(idx[tuple(src)].ravel())
+        vals.append(np.full(rows[-1].size, -abs(b)))
+    C = sparse.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n)).tocsr()
+    C.sum_duplicates()
+    C.sort_indices()
+    return C
+
+
+def convection_diffusion_problem(dims: Sequence[int], parts: Sequence[int], velocity: Sequence[float] = (1.0, 0.5),
+                                 eta: int = 1, n_fac: int = 2, k: Optional[np.ndarray] = None, rhs_seed: int = 0,
+                                 name: str = "") -> Problem:
+    """Diffusion (face coefficients c from k, as make_problem) plus upwind
+    convection: A = A_diff(c) + C.  A non-symmetric M-matrix whose stored
+    pattern is the symmetric 5/7-point pattern of A_diff (C's entries fall on
+    it).  C does not depend on c; it is kept in extra["convection"]."""
+    p = make_problem(dims, parts, eta=eta, n_fac=n_fac, k=k, rhs_seed=rhs_seed, name=name or "convdiff")
+    C = upwind_convection(p.dims, velocity)
+    A = (p.A + C).tocsr()
+    A.sum_duplicates()
+    A.sort_indices()
+    A.indices = A.indices.astype(np.int32)
+    A.indptr = A.indptr.astype(np.int32)
+    assert A.nnz == p.A.nnz, "convection entries must fall on the diffusion pattern"
+    p.A = A
+    p.extra["convection"] = C
+    p.extra["velocity"] = tuple(float(v) for v in velocity)
+    return p
 
 
 def isolated_column_problem(dims: Sequence[int] = (40, 40), parts: Sequence[int] = (2, 2), col: Optional[int] = None,

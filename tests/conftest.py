@@ -7,5 +7,10 @@ if ROOT not in sys.path:
 
 
 def pytest_configure(config):
+    # tuned schedules of the test session go to a file of its own, not the
+    # user's cache (tests of the cache set their own path)
+    if "AMGDD_TUNE_CACHE" not in os.environ:
+        import tempfile
+        os.environ["AMGDD_TUNE_CACHE"] = os.path.join(tempfile.mkdtemp(prefix="amgdd_tune_"), "schedules.json")
     config.addinivalue_line("markers", "gpu: needs an MI355X (HIP device) and the built library")
     config.addinivalue_line("markers", "slow: larger CPU case")

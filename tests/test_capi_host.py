@@ -43,6 +43,9 @@ CASES = [
     ("3d_12_var_eta2", lambda: make_problem((12, 12, 12), (2, 3, 2), eta=2, k=np.exp(grf((12, 12, 12), 1.0, 8.0, 1)))),
     ("cfg4_16", lambda: config("cfg4", scale=16)),
     ("p2_48_aniso", lambda: config("p2", scale=48)),
+    # padding 0: two subdomains have no points on level 4 (above the coarsest)
+    ("3d_pad0_empty_levels", lambda: make_problem((20, 18, 20), (2, 2, 3), eta=0,
+                                                  k=np.exp(grf((20, 18, 20), 1.0, 8.0, 1)))),
 ]
 
 
@@ -67,6 +70,8 @@ def test_host_setup_bit_exact_with_oracle(name, make):
             g, nr, om = s.composite(0, q, l)
             assert nr == lv.n_real and np.array_equal(g, lv.gid), f"p {q} level {l}"
             assert om == lv.omissions
+    if name == "3d_pad0_empty_levels":
+        assert any(lv.n_bar == 0 for cg in comps for lv in cg.levels)
     st = s.stats()
     assert st["n_grids"] == p.nparts
     assert abs(st["composite_overhead"] - composite.composite_overhead(H, comps)) < 1e-14

@@ -111,10 +111,13 @@ def test_padding_beyond_diameter_is_vcycles():
     assert rel_inf(xo, xv) <= 1e-12 and rel_inf(x, xv) <= 1e-12
 
 
-@pytest.mark.parametrize("parts,eta", [((2, 2), 1), ((4, 2), 2)])
-def test_dropped_interpolation_columns(parts, eta):
-    p = isolated_column_problem((40, 40), parts, eta=eta)
-    say("omissions", parts, eta)
+# the isolated column sits where the padding of some subdomain reaches across
+# it on level 0 but its coarse composite grid does not (x = 19 for padding 1,
+# x = 21 for padding 2 with 4 x 2 subdomains of 10 x 20)
+@pytest.mark.parametrize("parts,eta,col", [((2, 2), 1, 19), ((4, 2), 2, 21)])
+def test_dropped_interpolation_columns(parts, eta, col):
+    p = isolated_column_problem((40, 40), parts, eta=eta, col=col)
+    say("omissions", parts, eta, col)
     H = amg.setup(p.A)
     comps = composite.build_all(H, p.part, p.nparts, eta)
     om_o = [[lev.omissions for lev in cg.levels] for cg in comps]
