@@ -18,7 +18,7 @@ struct Prob {
   std::vector<double> val;
 };
 
-static Prob laplace(int nx, int ny, int nz, int px, int py, int pz) {
+static Prob laplace(int nx, int ny, int nz, int px, int py, int pz, double upwind = 0.0) {
   Prob P;
   P.n = nx * ny * nz;
   P.ptr.push_back(0);
@@ -29,8 +29,9 @@ static Prob laplace(int nx, int ny, int nz, int px, int py, int pz) {
         std::vector<std::pair<int, double>> row;
         if (z > 0) row.push_back({i - nx * ny, -1.0});
         if (y > 0) row.push_back({i - nx, -1.0});
-        if (x > 0) row.push_back({i - 1, -1.0});
-        row.push_back({i, nz > 1 ? 6.0 : 4.0});
+        // upwind > 0: convection in +x (non-symmetric values, same pattern)
+        if (x > 0) row.push_back({i - 1, -1.0 - upwind});
+        row.push_back({i, (nz > 1 ? 6.0 : 4.0) + upwind});
         if (x < nx - 1) row.push_back({i + 1, -1.0});
         if (y < ny - 1) row.push_back({i + nx, -1.0});
         if (z < nz - 1) row.push_back({i + nx * ny, -1.0});
@@ -85,6 +86,69 @@ int main() {
                          hybrid, st, err.c_str());
           }
         }
+  // padding 0 with subdomains that have no points on some level above their
+  // coarsest (30^2 in 5 x 5, 24 x 22 x 20 in 3 x 3 x 3), every layout variant
+  {
+    std::vector<Prob> p0 = {laplace(30, 30, 1, 5, 5, 1), laplace(24, 22, 20, 3, 3, 3)};
+    const int np0[] = {25, 27};
+    for (int v = 0; v < 8; ++v) {
+      std::vector<ProblemInput> in;
+      for (size_t q = 0; q < p0.size(); ++q)
+        in.push_back(ProblemInput{p0[q].n, p0[q].ptr.data(), p0[q].col.data(), p0[q].val.data(), p0[q].part.data(),
+                                  np0[q], 0, nullptr, 0});
+      Setup S, I;
+      S.cf = v & 1;
+      S.step_log2 = (v >> 1) & 1 ? 0 : 1;
+      S.comp_step_log2 = v == 6 ? 2 : S.step_log2;
+      S.sort_window = v & 2 ? 0 : 128;
+      S.compress = v < 4;
+      std::string err;
+      int st = (v & 4) ? [&] {
+        std::vector<int> inner_of;
+        std::vector<std::vector<int>> pm;
+        return build_setup_hybrid(in, 0.25, 16, 25, 1, S, I, inner_of, pm, err);
+      }() : build_setup(in, 0.25, 16, 25, S, err);
+      ++runs;
+      if (st) {
+        ++fails;
+        std::fprintf(stderr, "padding-0 setup variant %d: status %d %s\n", v, st, err.c_str());
+      }
+    }
+  }
+  // transposed hierarchies (adjoint of a non-symmetric operator), plain and hybrid
+  {
+    std::vector<Prob> pc = {laplace(40, 36, 1, 3, 2, 1, 0.5), laplace(14, 12, 10, 2, 2, 2, 0.7)};
+    const int npc[] = {6, 8};
+    for (int v = 0; v < 4; ++v) {
+      std::vector<ProblemInput> in;
+      for (size_t q = 0; q < pc.size(); ++q)
+        in.push_back(ProblemInput{pc[q].n, pc[q].ptr.data(), pc[q].col.data(), pc[q].val.data(), pc[q].part.data(),
+                                  npc[q], 1 + (int)q % 2, nullptr, 0});
+      Setup S, I, T, TI;
+      S.cf = v & 1;
+      std::string err;
+      int st;
+      if (v < 2) {
+        st = build_setup(in, 0.25, 16, 25, S, err);
+        if (!st) st = build_setup_transposed(S, true, T, err);
+      } else {
+        std::vector<int> inner_of;
+        std::vector<std::vector<int>> pm;
+        st = build_setup_hybrid(in, 0.25, 16, 25, 2, S, I, inner_of, pm, err);
+        if (!st) st = build_setup_transposed(S, false, T, err);
+        if (!st && !I.probs.empty()) st = build_setup_transposed(I, true, TI, err);
+      }
+      ++runs;
+      if (!st && S.probs[0].symmetric) {
+        st = 1;
+        err = "non-symmetric input reported symmetric";
+      }
+      if (st) {
+        ++fails;
+        std::fprintf(stderr, "transposed setup variant %d: status %d %s\n", v, st, err.c_str());
+      }
+    }
+  }
   std::printf("%d setups, %d failed\n", runs, fails);
   return fails ? 1 : 0;
 }

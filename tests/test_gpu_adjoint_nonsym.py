@@ -153,7 +153,8 @@ def test_nonsymmetric_gradients_vs_central_differences():
         return float(np.sum((uu - ut) ** 2))
 
     A0 = prob.assemble(p.c)
-    assert abs(A0 - p.A).max() == 0
+    # same operator; the diagonal sums the face coefficients in another order
+    assert abs(A0 - p.A).max() <= 1e-14 * abs(p.A).max()
     lam_d = adjoint.dense_adjoint(A0, 2 * (np.linalg.solve(A0.toarray(), p.b) - ut))
     assert rel_inf(gf, lam_d) <= 1e-8
     h = 1e-6

@@ -1,5 +1,6 @@
 """The host setup code (coarsening, interpolation, Galerkin products,
-composite sets, batched layouts, 16-bit index compression) built with
+composite sets, batched layouts, 16-bit index compression, padding 0 with
+empty coarse levels, transposed hierarchies for the adjoint) built with
 AddressSanitizer and UndefinedBehaviorSanitizer and run over every setup
 variant by a small C++ driver (tests/host/setup_check.cpp).  CPU only."""
 
@@ -23,7 +24,7 @@ def test_setup_under_asan_ubsan(tmp_path):
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1", AMGDD_THREADS="4")
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=600, env=env)
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
-    assert "24 setups, 0 failed" in r.stdout
+    assert "36 setups, 0 failed" in r.stdout
 
 
 @pytest.mark.skipif(shutil.which("g++") is None, reason="g++ not available")
