@@ -1,6 +1,7 @@
-"""Full-size parity on the benchmark workload (3D Laplacian 128^3, 4x4x4
-subdomains of 32^3, padding 1, 2 AlgFAC cycles, FP64) in the launch
-configuration bench.py times (graph replay, default schedule).
+"""Full-size parity on the benchmark workloads in the launch configuration
+bench.py times (graph replay, autotuned schedule): 3D Laplacian 128^3 (4x4x4
+subdomains of 32^3, padding 1, 2 AlgFAC cycles, FP64) and the 192^3
+variable-k diffusion (8x8x8 subdomains of 24^3, padding 2, FP64 and mixed).
 
 * sampled outputs: the first two AMG-DD iterates and V(1,1) iterates at 2000
   seeded points and the residual norms, against values written by
@@ -110,3 +111,72 @@ def test_cfg2_hybrid_sampled_iterates_and_solve():
           f"grids {st_['n_grids']}, overhead {st_['composite_overhead']:.3f}", flush=True)
     assert rel <= 1e-8
     assert st_["n_grids"] == p.nparts
+
+
+GOLD3 = os.path.join(os.path.dirname(__file__), "golden", "cfg3_samples.json")
+
+
+@pytest.fixture(scope="module")
+def cfg3():
+    if not os.path.exists(GOLD3):
+        pytest.skip("cfg3 golden samples not generated")
+    p = config("cfg3")
+    print("[gpu-test] cfg3 setup", p.n, flush=True)
+    s = amgdd.Solver(p.A, p.part, p.nparts, padding=p.eta, n_fac=p.n_fac)
+    yield p, s, json.load(open(GOLD3))
+    s.close()
+
+
+def test_cfg3_sampled_iterates_and_history_match_oracle(cfg3):
+    """192^3 variable-k diffusion, 512 grids, padding 2, FP64, in the launch
+    configuration bench.py times (graph replay, autotuned schedule): the first
+    two AMG-DD and V(1,1) iterates at 2000 seeded points, and the whole AMG-DD
+    residual history to 1e-8 (27 iterations), against the oracle's values
+    (tests/golden/make_fullsize_samples.py)."""
+    p, s, g = cfg3
+    assert s.levels(0)[0].tolist() == g["levels"] and s.stats()["omissions"] == g["omissions"]
+    idx = np.array(g["idx"])
+    b = torch.as_tensor(p.b, device="cuda:0")
+    for kind, fn, nm in (("amgdd", s.solve, "amgdd"), ("vcycle", s.vsolve, "vcycle")):
+        x = torch.zeros_like(b)
+        for k in (1, 2):
+            x, info, st = fn(b, x, rtol=0, maxit=1)
+            ref = np.array(g[f"{nm}_x{k}"])
+            got = x.cpu().numpy()[idx]
+            err = rel_inf(got, ref)
+            print(f"[gpu-test] cfg3 {kind} iterate {k}: sampled max-entry rel err {err:.2e}, 2-norm "
+                  f"{rel_2(got, ref):.2e}", flush=True)
+            assert err <= 1e-12
+    x, info, st = s.solve(b, rtol=1e-8, maxit=100)
+    hist = s.history(0)
+    ref = np.array(g["amgdd_hist"])
+    print(f"[gpu-test] cfg3 AMG-DD: {info.iters} iterations (oracle {len(ref) - 1}), "
+          f"history max rel diff {np.abs(hist - ref).max() / ref[0] if hist.size == ref.size else -1:.2e}", flush=True)
+    assert st == amgdd.OK and hist.size == ref.size
+    np.testing.assert_allclose(hist, ref, rtol=1e-9, atol=0)
+    rel = np.linalg.norm(p.b - p.A @ x.cpu().numpy()) / np.linalg.norm(p.b)
+    assert rel <= 1e-8
+
+
+def test_cfg3_mixed_precision_against_the_float32_emulation(cfg3):
+    """Mixed form at full size: reaches 1e-8 (residual in FP64 on the host);
+    its distance from the FP64 iterates stays within 4x of the oracle's
+    float32 emulation's distance from the FP64 oracle at every iteration
+    (parity of the mixed form itself is unpinned)."""
+    p, s64, g = cfg3
+    em = g["mixed_emulation"]["err_vs_fp64"]
+    s = amgdd.Solver(p.A, p.part, p.nparts, padding=p.eta, n_fac=p.n_fac, precision="mixed")
+    b = torch.as_tensor(p.b, device="cuda:0")
+    x64 = torch.zeros_like(b)
+    xm = torch.zeros_like(b)
+    for k in range(min(8, len(em))):
+        x64, _, _ = s64.solve(b, x64, rtol=0, maxit=1)
+        xm, _, _ = s.solve(b, xm, rtol=0, maxit=1)
+        e = float(torch.linalg.norm(xm - x64) / torch.linalg.norm(x64))
+        print(f"[gpu-test] cfg3 mixed iteration {k + 1}: vs FP64 {e:.3e}, emulation {em[k]:.3e}", flush=True)
+        assert e <= 4 * em[k]
+    x, info, st = s.solve(b, rtol=1e-8, maxit=100)
+    rel = np.linalg.norm(p.b - p.A @ x.cpu().numpy()) / np.linalg.norm(p.b)
+    print(f"[gpu-test] cfg3 mixed: {info.iters} iterations, FP64 relres {rel:.2e}", flush=True)
+    assert st == amgdd.OK and rel <= 1e-8
+    s.close()
