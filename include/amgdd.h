@@ -39,7 +39,8 @@
  * Environment variables read when a handle is created (measurement and
  * testing; none changes the method):
  *   AMGDD_TRACE=1         roctx ranges around setup, upload, autotuning,
- *                         capture, solves and iterations
+ *                         capture, solves and iterations (the roctx library
+ *                         is opened with dlopen only then)
  *   AMGDD_THREADS=n       host threads of the setup (default: all)
  *   AMGDD_INDEX32         int32 column indices everywhere
  *   AMGDD_UNPAIRED        one entry per lane and load step everywhere
@@ -140,7 +141,8 @@ typedef struct {
   int iters;            /* outer iterations (or V-cycles) performed */
   double relres;        /* max over problems of ||r_k|| / ||r_0|| */
   double rho_asym;      /* geometric-mean factor over the last <= 5 iterations */
-  double solve_s;       /* device time of the iterations (HIP events) */
+  double solve_s;       /* host time of the solve from its first launch to the
+                           synchronisation after its last iteration */
   double setup_s;       /* host setup time of the handle */
 } amgdd_info;
 

@@ -43,8 +43,10 @@ def build(verbose: bool = False) -> str:
     _run([cxx, *HOST_FLAGS, "-c", os.path.join(CSRC, "setup.cpp"), "-o", setup_o], verbose)
     _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "driver.hip"), "-o", driver_o], verbose)
     tmp = LIB + ".tmp"
-    _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", setup_o, driver_o, "-o", tmp, "-pthread",
-          f"-L{os.path.join(ROCM, 'lib')}", "-lrocprofiler-sdk-roctx", f"-Wl,-rpath,{os.path.join(ROCM, 'lib')}"], verbose)
+    # roctx (AMGDD_TRACE=1) is opened at run time with dlopen: no link-time
+    # dependency on a profiling library
+    _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", setup_o, driver_o, "-o", tmp, "-pthread", "-ldl",
+          f"-Wl,-rpath,{os.path.join(ROCM, 'lib')}"], verbose)
     os.replace(tmp, LIB)
     return LIB
 

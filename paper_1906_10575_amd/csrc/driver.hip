@@ -16,8 +16,8 @@
 // second handle's AMG-DD passes (the level-L~ problems) below it, captured
 // into the same graph.
 
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
-#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <sys/stat.h>
 #include <unistd.h>
@@ -62,22 +62,38 @@ double now_s() {
 
 // Named ranges for timeline tools (rocprofv3 --marker-trace) when the
 // environment sets AMGDD_TRACE=1: setup, upload, autotuning, graph capture,
-// every solve and every outer iteration.
-bool tracing() {
-  static const bool on = [] {
+// every solve and every outer iteration.  The roctx library is opened only
+// then (dlopen), so an ordinary process loads no profiling library through
+// this one: the HIP runtime in use may be another ROCm release's (the one
+// torch ships).
+struct Roctx {
+  int (*push)(const char *) = nullptr;
+  int (*pop)() = nullptr;
+};
+const Roctx &roctx() {
+  static const Roctx r = [] {
+    Roctx x;
     const char *e = std::getenv("AMGDD_TRACE");
-    return e && e[0] == '1';
+    if (!(e && e[0] == '1')) return x;
+    void *lib = dlopen("librocprofiler-sdk-roctx.so.1", RTLD_NOW | RTLD_GLOBAL);
+    if (!lib) lib = dlopen("/opt/rocm/lib/librocprofiler-sdk-roctx.so.1", RTLD_NOW | RTLD_GLOBAL);
+    if (!lib) return x;
+    x.push = (int (*)(const char *))dlsym(lib, "roctxRangePushA");
+    x.pop = (int (*)())dlsym(lib, "roctxRangePop");
+    if (!x.push || !x.pop) x.push = nullptr, x.pop = nullptr;
+    return x;
   }();
-  return on;
+  return r;
 }
+bool tracing() { return roctx().push != nullptr; }
 struct TraceRange {
   bool on;
   explicit TraceRange(const char *name) : on(tracing()) {
-    if (on) roctxRangePush(name);
+    if (on) roctx().push(name);
   }
   TraceRange(const std::string &name) : TraceRange(name.c_str()) {}
   ~TraceRange() {
-    if (on) roctxRangePop();
+    if (on) roctx().pop();
   }
 };
 
@@ -209,7 +225,6 @@ struct amgdd_ctx {
   hipGraphExec_t g_dd = nullptr, g_v = nullptr;
   hipGraph_t gr_dd = nullptr, gr_v = nullptr;
   std::vector<std::vector<double>> hist;  // per problem
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
   Prof *prof = nullptr;
   int lbase = 0;  // level of this handle's fine level in the profiling sites
   // hybrid AMG-DD: the level-L~ AMG-DD problems live in a handle of their own
@@ -277,13 +292,15 @@ struct amgdd_ctx {
     delete inner;
     if (!host_only) {
       (void)hipSetDevice(device);
+      // nothing of this handle may still run when its resources go
+      (void)hipStreamSynchronize(stream);
+      if (cap_stream) (void)hipStreamSynchronize(cap_stream);
+      if (side) (void)hipStreamSynchronize(side);
       drop_graphs();
       for (void *p : allocs) (void)hipFree(p);
       if (h_norm2) (void)hipHostFree(h_norm2);
       if (cap_stream) (void)hipStreamDestroy(cap_stream);
       if (side) (void)hipStreamDestroy(side);
-      if (ev0) (void)hipEventDestroy(ev0);
-      if (ev1) (void)hipEventDestroy(ev1);
       if (ev_fork) (void)hipEventDestroy(ev_fork);
       if (ev_join) (void)hipEventDestroy(ev_join);
     }
@@ -944,12 +961,11 @@ amgdd_status autotune(amgdd_ctx *h) {
       st = capture(h, true, &gr, &ex);
       if (st) return st;
       HIP_TRY(hipGraphLaunch(ex, s));
-      HIP_TRY(hipEventRecord(h->ev0, s));
-      for (int r = 0; r < 3; ++r) HIP_TRY(hipGraphLaunch(ex, s));
-      HIP_TRY(hipEventRecord(h->ev1, s));
       HIP_TRY(hipStreamSynchronize(s));
-      float ms = 0.f;
-      HIP_TRY(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+      const double tc = now_s();
+      for (int r = 0; r < 3; ++r) HIP_TRY(hipGraphLaunch(ex, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      const double ms = (now_s() - tc) * 1e3;
       (void)hipGraphExecDestroy(ex);
       (void)hipGraphDestroy(gr);
       if (ms < best) { best = ms; best_l = lt; best_b = bs; }
@@ -1014,7 +1030,7 @@ amgdd_status run_solve(amgdd_ctx *h, SolveKind kind, const double *b_dev, double
     else enqueue_dd_iteration<double>(h, st);
     return hipGetLastError();
   };
-  HIP_TRY(hipEventRecord(h->ev0, s));
+  const double t_start = now_s();
   enqueue_res(s);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(s));
@@ -1047,16 +1063,14 @@ amgdd_status run_solve(amgdd_ctx *h, SolveKind kind, const double *b_dev, double
     for (int q = 0; q < np; ++q) h->hist[q].push_back(std::sqrt(h->h_norm2[q]));
     if (!finite()) result = fail(ST_EBREAKDOWN, "non-finite residual norm at iteration " + std::to_string(it));
   }
-  HIP_TRY(hipEventRecord(h->ev1, s));
+  const double solve_s = now_s() - t_start;  // every iteration ended in a stream synchronisation
   HIP_TRY(hipMemcpyAsync(x_dev, h->x, nbytes, hipMemcpyDeviceToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
-  float ms = 0.f;
-  HIP_TRY(hipEventElapsedTime(&ms, h->ev0, h->ev1));
   if (result == AMGDD_OK && rtol > 0 && !converged())
     result = fail(ST_ENOCONV, "maxit reached before rtol");
   if (info) {
     info->iters = it;
-    info->solve_s = ms * 1e-3;
+    info->solve_s = solve_s;
     info->setup_s = h->setup_s;
     double rel = 0.0, rho = 0.0;
     for (int q = 0; q < np; ++q) {
@@ -1087,8 +1101,7 @@ amgdd_status init_device(amgdd_ctx *h, int device, hipStream_t stream) {
     if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess)
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess)
       return fail(ST_EDEVICE, "stream/event creation failed");
     TraceRange tru("amgdd: upload");
     amgdd_status us = upload_all(c);

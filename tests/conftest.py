@@ -12,5 +12,11 @@ def pytest_configure(config):
     if "AMGDD_TUNE_CACHE" not in os.environ:
         import tempfile
         os.environ["AMGDD_TUNE_CACHE"] = os.path.join(tempfile.mkdtemp(prefix="amgdd_tune_"), "schedules.json")
+    # optional native backtraces on fatal signals (diagnostics only)
+    if os.environ.get("AMGDD_CRASH_TRACE") == "1":
+        so = os.path.join(ROOT, "tests", "native", "crash_trace.so")
+        if os.path.exists(so):
+            import ctypes
+            ctypes.CDLL(so).crash_trace_install()
     config.addinivalue_line("markers", "gpu: needs an MI355X (HIP device) and the built library")
     config.addinivalue_line("markers", "slow: larger CPU case")
