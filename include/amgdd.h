@@ -218,6 +218,24 @@ amgdd_status amgdd_setup_composite_batch(int nprob, const int *n, const int *con
 amgdd_status amgdd_solve(amgdd_handle h, const double *b_dev, double *x_dev, double rtol, int maxit,
                          amgdd_info *info);
 
+/*
+ * For callers that cannot allocate device memory during a solve (serving
+ * loops, harnesses that forbid hipMalloc): amgdd_solve's iterations with no
+ * device allocation in the call -- no tuning runs (a handle whose schedule is
+ * not tuned yet runs the level-synchronous schedule, which gives the same
+ * iterates), no graph capture (kernels enqueued one by one), and the residual
+ * partial sums and norms in a static device array of the library
+ * (1 MiB per device: the handle must need at most 131072 doubles, one per 256
+ * fine rows plus one per problem, i.e. about 33 million fine rows; larger
+ * handles get EUNSUPPORTED with nothing run).  Every other array it uses was
+ * allocated when the handle was set up.  Same arguments, stopping rule and
+ * statuses as amgdd_solve.  Calls that overlap on one device share the static
+ * array and race; it keeps the last call's contents, and every call writes
+ * all of it that it reads.
+ */
+amgdd_status amgdd_solve_noalloc(amgdd_handle h, const double *b_dev, double *x_dev, double rtol, int maxit,
+                                 amgdd_info *info);
+
 /* AMG V(1,1) cycles (Algorithm 1) on the same hierarchy, same conventions. */
 amgdd_status amgv_solve(amgdd_handle h, const double *b_dev, double *x_dev, double rtol, int maxit,
                         amgdd_info *info);

@@ -79,6 +79,7 @@ SIGNATURES = {
     "amgdd_setup_composite_batch": (_I, [_I, _IP, C.POINTER(_IP), C.POINTER(_IP), C.POINTER(_DP), C.POINTER(_IP),
                                          _IP, C.POINTER(Params), _P, C.POINTER(_H)]),
     "amgdd_solve": (_I, [_H, _P, _P, _D, _I, C.POINTER(Info)]),
+    "amgdd_solve_noalloc": (_I, [_H, _P, _P, _D, _I, C.POINTER(Info)]),
     "amgv_solve": (_I, [_H, _P, _P, _D, _I, C.POINTER(Info)]),
     "amgdd_solve_adjoint": (_I, [_H, _P, _P, _D, _I, C.POINTER(Info)]),
     "amgdd_face_gradient": (_I, [_H, _P, _P, _P, _P, _I, _P]),
@@ -261,6 +262,11 @@ class Solver:
     def solve(self, b, x=None, rtol=1e-8, maxit=100):
         """AMG-DD iterations; returns (x, Info, status) with status OK or ENOCONV."""
         return self._solve(load().amgdd_solve, b, x, rtol, maxit)
+
+    def solve_noalloc(self, b, x=None, rtol=1e-8, maxit=100):
+        """AMG-DD iterations with no device allocation inside the library call
+        (x must be given for that: with x=None a zero tensor is allocated here)."""
+        return self._solve(load().amgdd_solve_noalloc, b, x, rtol, maxit)
 
     def vsolve(self, b, x=None, rtol=1e-8, maxit=100):
         """AMG V(1,1) cycles on the same hierarchy."""

@@ -203,6 +203,11 @@ struct amgdd_ctx {
   // outer vectors
   double *b = nullptr, *x = nullptr;
   double *partial = nullptr, *norm2 = nullptr;
+  // residual partial sums / norms in use: the handle's own, or the library's
+  // static scratch during amgdd_solve_noalloc
+  double *rs_partial = nullptr, *rs_norm2 = nullptr;
+  double *partial_buf() const { return rs_partial ? rs_partial : partial; }
+  double *norm2_buf() const { return rs_norm2 ? rs_norm2 : norm2; }
   double *h_norm2 = nullptr;  // pinned
   int *blk_row0 = nullptr, *blk_row1 = nullptr, *prob_blk0 = nullptr;
   int nblk = 0, nprob = 0, N0 = 0;
@@ -501,13 +506,13 @@ template <typename T>
 void enqueue_residual(amgdd_ctx *h, hipStream_t s, bool vc) {
   DLevel &D0 = h->L[0];
   if (vc)
-    PLAUNCH(h, "resid_v", 0, D0.nnzGA * ent(D0.GA, 8.0) + h->N0 * 40.0, (dev::k_resid<double, true>), h->nblk, dev::BLOCK, 0, s, D0.GA.as<double>(), h->b, h->x, D0.vf, h->partial,
+    PLAUNCH(h, "resid_v", 0, D0.nnzGA * ent(D0.GA, 8.0) + h->N0 * 40.0, (dev::k_resid<double, true>), h->nblk, dev::BLOCK, 0, s, D0.GA.as<double>(), h->b, h->x, D0.vf, h->partial_buf(),
            h->blk_row0, h->blk_row1, D0.gdinv, D0.ve[0], (const signed char *)D0.gcls);
   else
     PLAUNCH(h, "resid", 0, D0.nnzGA * ent(D0.GA, 8.0) + h->N0 * (16.0 + sizeof(T)), (dev::k_resid<T, false>), h->nblk, dev::BLOCK, 0, s, D0.GA.as<double>(), h->b, h->x, (T *)D0.rt,
-           h->partial, h->blk_row0, h->blk_row1, (const double *)nullptr, (double *)nullptr, (const signed char *)nullptr);
-  PLAUNCH(h, "norm", 0, h->nblk * 8.0, dev::k_norm_final, h->nprob, dev::BLOCK, 0, s, h->partial, h->prob_blk0, h->norm2);
-  (void)hipMemcpyAsync(h->h_norm2, h->norm2, (size_t)h->nprob * sizeof(double), hipMemcpyDeviceToHost, s);
+           h->partial_buf(), h->blk_row0, h->blk_row1, (const double *)nullptr, (double *)nullptr, (const signed char *)nullptr);
+  PLAUNCH(h, "norm", 0, h->nblk * 8.0, dev::k_norm_final, h->nprob, dev::BLOCK, 0, s, h->partial_buf(), h->prob_blk0, h->norm2_buf());
+  (void)hipMemcpyAsync(h->h_norm2, h->norm2_buf(), (size_t)h->nprob * sizeof(double), hipMemcpyDeviceToHost, s);
 }
 
 // Level-synchronous downsweep pass of level l (all grids normal at l, plus the
@@ -983,8 +988,11 @@ amgdd_status autotune(amgdd_ctx *h) {
 
 enum SolveKind { SOLVE_DD = 0, SOLVE_V = 1 };
 
+// noalloc: no tuning runs (an untuned handle runs the level-synchronous
+// schedule, which gives the same iterates), no graph capture (kernels are
+// enqueued one by one), residual scratch as set in h->rs_partial / rs_norm2.
 amgdd_status run_solve(amgdd_ctx *h, SolveKind kind, const double *b_dev, double *x_dev, double rtol, int maxit,
-                       amgdd_info *info) {
+                       amgdd_info *info, bool noalloc = false) {
   TraceRange tr(kind == SOLVE_V ? "amgdd: V-cycle solve" : "amgdd: AMG-DD solve");
   if (!h) return fail(ST_EINVAL, "null handle");
   if (h->host_only) return fail(ST_EDEVICE, "host-only handle (device = -1): no device solve");
@@ -999,14 +1007,27 @@ amgdd_status run_solve(amgdd_ctx *h, SolveKind kind, const double *b_dev, double
   const bool hybrid = kind == SOLVE_DD && h->inner;
   HIP_TRY(hipMemcpyAsync(h->b, b_dev, nbytes, hipMemcpyDeviceToDevice, s));
   HIP_TRY(hipMemcpyAsync(h->x, x_dev, nbytes, hipMemcpyDeviceToDevice, s));
+  // an untuned schedule during a no-allocation solve: level-synchronous for
+  // this call only
+  struct SchedRestore {
+    amgdd_ctx *t = nullptr;
+    ~SchedRestore() {
+      if (t) t->sched_level = -2;
+    }
+  } sched_restore;
   if (kind == SOLVE_DD) {
     amgdd_ctx *t = hybrid ? h->inner : h;
     if (t->sched_level == -2) {
-      amgdd_status st = autotune(t);
-      if (st) return st;
+      if (noalloc) {
+        t->sched_level = -1;
+        sched_restore.t = t;
+      } else {
+        amgdd_status st = autotune(t);
+        if (st) return st;
+      }
     }
   }
-  bool use_graph = h->prm.use_graph != 0;
+  bool use_graph = h->prm.use_graph != 0 && !noalloc;
   if (use_graph) {
     if (kind == SOLVE_DD && !h->g_dd) {
       amgdd_status st = capture(h, true, &h->gr_dd, &h->g_dd);
@@ -1086,9 +1107,41 @@ amgdd_status run_solve(amgdd_ctx *h, SolveKind kind, const double *b_dev, double
   return result;
 }
 
+// ---------------------------------------------------------------- no-allocation solve
+//
+// amgdd_solve_noalloc keeps the only device memory a solve needs beyond the
+// handle's own arrays -- the residual partial sums (one per 256-row block) and
+// the per-problem squared norms -- in this static array, so the call itself
+// allocates nothing.  Each device holds its own copy; its address is taken once
+// per device when a handle is first set up there.  Calls that overlap on one
+// device share the array and race.
+constexpr long long NOALLOC_SCRATCH = 1LL << 17;  // doubles (1 MiB): blocks + problems
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device (recorded once per device).
+amgdd_status resolve_scratch(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return fail(ST_EUNSUP, "device ordinal beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return AMGDD_OK;
+  void *p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p)
+    return fail(ST_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_scratch_ptr[device] = (double *)p;
+  return AMGDD_OK;
+}
+
 // Streams, events and device layouts of a handle and of its level-L~ handle.
 amgdd_status init_device(amgdd_ctx *h, int device, hipStream_t stream) {
   HIP_TRY(hipSetDevice(device));
+  {
+    amgdd_status ss = resolve_scratch(device);
+    if (ss) return ss;
+  }
   long long cap = 0;
   if (const char *e2 = std::getenv("AMGDD_TEST_MAX_BYTES")) cap = std::atoll(e2);
   for (amgdd_ctx *c : {h, h->inner}) {
@@ -1334,6 +1387,32 @@ amgdd_status amgdd_solve(amgdd_handle h, const double *b_dev, double *x_dev, dou
 
 amgdd_status amgv_solve(amgdd_handle h, const double *b_dev, double *x_dev, double rtol, int maxit, amgdd_info *info) {
   return run_solve(h, SOLVE_V, b_dev, x_dev, rtol, maxit, info);
+}
+
+amgdd_status amgdd_solve_noalloc(amgdd_handle h, const double *b_dev, double *x_dev, double rtol, int maxit,
+                                 amgdd_info *info) {
+  if (!h) return fail(ST_EINVAL, "null handle");
+  if (h->host_only) return fail(ST_EDEVICE, "host-only handle (device = -1): no device solve");
+  long long cap = NOALLOC_SCRATCH;
+  if (const char *e = std::getenv("AMGDD_TEST_NOALLOC_CAP")) cap = std::min(cap, std::atoll(e));
+  const long long need = (long long)h->nblk + h->nprob;
+  if (need > cap)
+    return fail(ST_EUNSUP, "amgdd_solve_noalloc: the handle needs " + std::to_string(need) +
+                               " doubles of residual scratch (one per 256 fine rows plus one per problem); the "
+                               "library's static scratch holds " + std::to_string(cap));
+  double *p = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (h->device >= 0 && h->device < MAX_DEVICES) p = g_scratch_ptr[h->device];
+  }
+  if (!p) return fail(ST_EDEVICE, "amgdd_solve_noalloc: no scratch address for this device");
+  struct Restore {
+    amgdd_ctx *h;
+    ~Restore() { h->rs_partial = h->rs_norm2 = nullptr; }
+  } restore{h};
+  h->rs_partial = p;
+  h->rs_norm2 = p + h->nblk;
+  return run_solve(h, SOLVE_DD, b_dev, x_dev, rtol, maxit, info, true);
 }
 
 amgdd_status amgdd_solve_adjoint(amgdd_handle h, const double *g_dev, double *lambda_dev, double rtol, int maxit,
