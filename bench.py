@@ -201,9 +201,9 @@ def summarize_rocpd(db):
     return "\n".join(lines)
 
 
-def summarize_pmc(path):
-    """Mean counter value per (kernel, workgroups) from rocprofv3 --pmc CSV
-    output (counter_collection.csv), as text."""
+def _pmc_means(path):
+    """{(kernel, workgroups, workgroup size, counter): [values per dispatch]}
+    from rocprofv3 --pmc CSV output (counter_collection.csv)."""
     import csv
     agg = {}
     with open(path) as fh:
@@ -214,6 +214,74 @@ def summarize_pmc(path):
             wg = int(float(row.get("Workgroup_Size", 1) or 1))
             key = (short, grid // max(wg, 1), wg, row.get("Counter_Name", ""))
             agg.setdefault(key, []).append(float(row.get("Counter_Value", 0) or 0))
+    return agg
+
+
+# launch sites of amgdd_profile -> kernel names in the counter output
+SITE_KERNEL = {"relax_pre": "k_relax", "relax_post": "k_relax", "relax_f": "k_relax", "relax_post_f": "k_relax",
+               "relax_post_c": "k_relax", "w": "k_w", "down": "k_down", "interp": "k_interp", "restrict": "k_spmv",
+               "resid": "k_resid", "gather": "k_gather", "patch": "k_patch", "relax0": "k_relax_zero"}
+
+
+def traffic_records(fetch_csv, write_csv, sites_log, workload, top=3):
+    """HBM traffic records of the `top` longest launch sites of one iteration:
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch, one rocprofv3 --pmc pass
+    each, run with --calibrate-copy) scaled by the same counters on the
+    calibration kernel (y = x + 1 over 2^25 doubles: 256 MiB read, 256 MiB
+    written), matched to the sites of a `bench.py --sites` log by kernel and
+    workgroup count.  Returns the records (dicts)."""
+    import hashlib
+    f = _pmc_means(fetch_csv)
+    w = _pmc_means(write_csv)
+
+    def mean(agg, kern, wgs, ctr):
+        vals = [v for (k, g, _, c), vs in agg.items() if k.startswith(kern + "<") and g == wgs and c == ctr for v in vs]
+        return sum(vals) / len(vals) if vals else None
+
+    def calib(agg, ctr):
+        vals = [v for (k, g, _, c), vs in agg.items() if "elementwise" in k and g == 32768 and c == ctr for v in vs]
+        return sum(vals) / len(vals) if vals else None
+    cf, cw = calib(f, "FETCH_SIZE"), calib(w, "WRITE_SIZE")
+    if not cf or not cw:
+        raise SystemExit("no calibration kernel in the counter output (run the passes with --calibrate-copy)")
+    exp = 256.0 * 1024  # KiB
+    sites = []
+    for line in open(sites_log):
+        parts = line.split()
+        if len(parts) == 8 and parts[0] == "[bench]" and parts[1] in SITE_KERNEL and parts[2].isdigit():
+            name, lvl, n, ms, mb, _, wg = parts[1], int(parts[2]), int(parts[3]), float(parts[4]), float(parts[5]), \
+                parts[6], int(parts[7])
+            sites.append(dict(name=name, level=lvl, launches=n, ms=ms, mb=mb, workgroups=wg))
+    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_1906_10575_amd", "csrc", "kernels.hpp"), "rb").read()).hexdigest()
+    recs = []
+    for st in sorted(sites, key=lambda r: -r["ms"])[:top]:
+        kern = SITE_KERNEL[st["name"]]
+        fk, wk = mean(f, kern, st["workgroups"], "FETCH_SIZE"), mean(w, kern, st["workgroups"], "WRITE_SIZE")
+        if fk is None or wk is None:
+            continue
+        traffic = (fk / (cf / exp) + wk / (cw / exp)) * 1024
+        recs.append({
+            "what": f"HBM traffic per launch of the {st['name']} site on composite level {st['level']} of the "
+                    f"{workload} AMG-DD iteration, from two rocprofv3 --pmc passes, scaled by the same counters on "
+                    f"a known-size elementwise kernel (y = x + 1 over 2^25 doubles: 256 MiB read + 256 MiB written)",
+            "kernels_sha256": sha, "site": st["name"], "level": st["level"], "kernel": kern + "<...>",
+            "workgroups": st["workgroups"], "fetch_size_kib": round(fk, 1), "write_size_kib": round(wk, 1),
+            "calibration": {"fetch_size_kib": round(cf, 1), "write_size_kib": round(cw, 1), "expected_kib": exp,
+                            "fetch_factor": round(cf / exp, 5), "write_factor": round(cw / exp, 5)},
+            "traffic_bytes": int(round(traffic)), "algorithmic_bytes": st["mb"] * 1e6 / st["launches"],
+            "commands": [f"rocprofv3 --pmc FETCH_SIZE --kernel-include-regex 'k_w|k_relax|k_down|k_interp|k_spmv|"
+                         f"k_resid|k_gather|k_patch|elementwise' -f csv -d <dir> -o run -- python3 bench.py --config "
+                         f"{workload} --precision fp64 --steps 1 --warmup 1 --no-cpu-baseline --no-extras "
+                         f"--calibrate-copy --sites", "rocprofv3 --pmc WRITE_SIZE (same options)",
+                         "python3 bench.py --traffic-records <fetch csv> <write csv> <sites log> --config "
+                         f"{workload}"]})
+    return recs
+
+
+def summarize_pmc(path):
+    """Mean counter value per (kernel, workgroups) from rocprofv3 --pmc CSV
+    output (counter_collection.csv), as text."""
+    agg = _pmc_means(path)
     lines = ["kernel                           workgroups x size  counter        dispatches   mean_value", "-" * 88]
     for k, v in sorted(agg.items(), key=lambda kv: (kv[0][3], -sum(kv[1]))):
         lines.append(f"{k[0][:32]:32s} {k[1]:10d} x {k[2]:4d}  {k[3]:14s} {len(v):6d} {sum(v) / len(v):14.1f}")
@@ -339,6 +407,9 @@ def main():
                     help="transition levels of the hybrid AMG-DD cycles timed beside the primary solve")
     ap.add_argument("--summarize-rocpd", metavar="DB", help="print a summary of a rocprofv3 kernel-trace database")
     ap.add_argument("--summarize-pmc", metavar="CSV", help="print a summary of rocprofv3 --pmc CSV output")
+    ap.add_argument("--traffic-records", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "SITES_LOG"),
+                    help="write profiles/traffic_<site>_l<level>_<config>.json for the longest launch sites from "
+                         "FETCH_SIZE / WRITE_SIZE --pmc output and a --sites log (host only)")
     ap.add_argument("--relax", default="l1", choices=["l1", "cf"], help="l1-Jacobi order (natural / CF)")
     ap.add_argument("--coarsen", default="rs", choices=["rs", "hmis"])
     ap.add_argument("--interp", default="direct", choices=["direct", "ext+i"])
@@ -365,6 +436,14 @@ def main():
         return
     if args.summarize_pmc:
         print(summarize_pmc(args.summarize_pmc))
+        return
+    if args.traffic_records:
+        for rec in traffic_records(*args.traffic_records, workload=args.config):
+            path = os.path.join(ROOT, "profiles", f"traffic_{rec['site']}_l{rec['level']}_{args.config}.json")
+            with open(path, "w") as fh:
+                json.dump(rec, fh, indent=1)
+            print(f"{path}: {rec['traffic_bytes'] / 1e6:.1f} MB traffic, {rec['algorithmic_bytes'] / 1e6:.1f} MB "
+                  f"algorithmic per launch")
         return
     if args.gpus != 1:
         print(f"bench.py: the solver runs on one GPU (the multi-GPU exchange is a design only); --gpus {args.gpus} "
@@ -395,8 +474,8 @@ def main():
 
     run_steps(torch, s, b, args.warmup, rtol, adjoint)
     st = s.stats()
-    log(f"warmup done; schedule: cut level {st['tail_level']}, workgroup {st['tail_block']} "
-        f"(autotune {st['autotune_s']:.2f} s)")
+    log(f"warmup done; schedule: cut level {st['tail_level']}, workgroup {st['tail_block']}, 512-thread levels "
+        f"{[l for l in range(32) if (st['wide_levels'] >> l) & 1]} (autotune {st['autotune_s']:.2f} s)")
     per_step = []
     dt, iters, x = run_steps(torch, s, b, args.steps, rtol, adjoint, per_step)
     its = int(np.median(iters))
@@ -457,7 +536,8 @@ def main():
         "profile_top": sorted(({k: (round(v, 5) if isinstance(v, float) else v) for k, v in r_.items()}
                                for r_ in prof), key=lambda r_: -r_["ms"])[:8],
         "schedule": {"tail_level": st["tail_level"], "tail_block": st["tail_block"],
-                     "autotune_s": round(st["autotune_s"], 3)},
+                     "wide_levels": [l for l in range(32) if (st["wide_levels"] >> l) & 1],
+                     "autotune_s": round(st["autotune_s"], 3), "cached": bool(st["schedule_cached"])},
         "setup_s": round(setup_s, 2),
         "composite_overhead": round(st["composite_overhead"], 4),
     }

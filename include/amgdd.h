@@ -49,6 +49,8 @@
  *   AMGDD_LANE_TARGET=x   entries per lane that set the lanes per composite row
  *   AMGDD_SERIAL          one stream per iteration (no side-stream branch)
  *   AMGDD_TEST_MAX_BYTES=n  device-memory cap (failure-path tests)
+ *   AMGDD_WG=n            workgroup size of the composite passes (256, 512 or
+ *                         1024) on every level, instead of the tuned choice
  * and when a handle's schedule is tuned:
  *   AMGDD_TUNE_CACHE=path schedule cache file (JSON, one entry per line,
  *                         keyed by a hash of the layout, device and library
@@ -174,6 +176,9 @@ typedef struct {
                                composite_real_nnz) / global_nnz */
   int schedule_cached;      /* 1 = the schedule came from the schedule cache
                                (no tuning runs), 0 = tuned or fixed */
+  int wide_levels;          /* bit l set: the level-synchronous passes of composite
+                               level l run in 512-thread workgroups (chosen by the
+                               autotuner), else 256 */
 } amgdd_stats;
 
 void amgdd_params_default(amgdd_params *prm);

@@ -117,6 +117,7 @@ struct DLevel {
   // composite
   int NRn = 0, NBn = 0, NB = 0;
   int lg = 0, glg = 0;  // lanes per row (log2) of composite / global rows
+  int wg = dev::BLOCK;  // workgroup size of the level's composite passes (256, 512 or 1024)
   DSell A, P, R;
   void *dinv = nullptr;
   void *u[2] = {nullptr, nullptr};
@@ -226,6 +227,7 @@ struct amgdd_ctx {
   int tail_maxn = 0;                     // largest coarsest level (shared memory of the tail)
   int sched_level = -2, sched_block = 256;
   int sched_cached = 0;  // schedule taken from the schedule cache
+  bool wg_fixed = false;  // composite-pass workgroup sizes set by the environment (not tuned)
   double autotune_s = 0.0;
   hipGraphExec_t g_dd = nullptr, g_v = nullptr;
   hipGraph_t gr_dd = nullptr, gr_v = nullptr;
@@ -315,6 +317,9 @@ struct amgdd_ctx {
 namespace {
 
 inline int nblocks(long long n) { return (int)((n + dev::BLOCK - 1) / dev::BLOCK); }
+inline int nblocks_wg(long long n, int wg) { return (int)((n + wg - 1) / wg); }
+// instantiation of a composite pass for a level's workgroup size
+#define WGK(K, T, wg) ((wg) == 1024 ? K<T, 1024> : (wg) == 512 ? K<T, 512> : K<T, 256>)
 
 // Algorithmic bytes of one stored matrix entry: its value (w bytes) and its
 // column index (2 bytes when the layout holds 16-bit columns, else 4).
@@ -355,6 +360,15 @@ amgdd_status upload_all(amgdd_ctx *h) {
     DLevel &D = h->L[l];
     D.NRn = B.NRn;
     D.NBn = B.NBn;
+    {
+      // measurement: AMGDD_WG=256|512|1024 fixes the composite passes'
+      // workgroup size on every level (otherwise the autotuner picks 256 or
+      // 512 per level)
+      const char *e = std::getenv("AMGDD_WG");
+      const int v = e ? std::atoi(e) : dev::BLOCK;
+      D.wg = (v == 512 || v == 1024) ? v : dev::BLOCK;
+      if (e) h->wg_fixed = true;
+    }
     D.NB = B.NB;
     D.lg = B.lg;
     D.glg = B.glg;
@@ -530,11 +544,11 @@ void enqueue_fac_down(amgdd_ctx *h, hipStream_t s, int *cur, int l, int first) {
       PLAUNCH(h, "relax0", 0, nrc * 4.0 * w + (B.NBn - nrc) * w + (cf ? B.NRn : 0), dev::k_relax_zero<T>, nblocks(B.NBn), dev::BLOCK, 0, s, B.NRn, B.NBn, (const T *)B.f,
              (const T *)B.dinv, uout, (T *)B.t, (const signed char *)B.cls);
     else
-      PLAUNCH(h, "relax_pre", 0, nzc * ent(B.A, w) + nrc * 4.0 * w + B.NBn * 2.0 * w + (cf ? B.NRn : 0), dev::k_relax<T>, nblocks((long long)B.NBn << B.lg), dev::BLOCK, 0, s, B.A.as<T>(), B.NRn, B.NBn, (const T *)B.f,
+      PLAUNCH(h, "relax_pre", 0, nzc * ent(B.A, w) + nrc * 4.0 * w + B.NBn * 2.0 * w + (cf ? B.NRn : 0), WGK(dev::k_relax, T, B.wg), nblocks_wg((long long)B.NBn << B.lg, B.wg), B.wg, 0, s, B.A.as<T>(), B.NRn, B.NBn, (const T *)B.f,
              (const T *)B.dinv, (const T *)uin, uout, (T *)B.t, 1, (const signed char *)B.cls, 1);
   } else {
     DLevel &Bp = h->L[l - 1];
-    PLAUNCH(h, "down", l, B.nnzR_n * ent(B.R, w) + Bp.NBn * w + B.NBn * 2.0 * w + (first ? 0.0 : B.nnzA_r * ent(B.A, w) + B.NBn * w) + B.NRn * (first ? 4.0 : 5.0) * w + (cf ? B.NRn : 0), dev::k_down<T>, nblocks((long long)B.NBn << B.lg), dev::BLOCK, 0, s, B.R.as<T>(), B.A.as<T>(), B.NRn, B.NBn,
+    PLAUNCH(h, "down", l, B.nnzR_n * ent(B.R, w) + Bp.NBn * w + B.NBn * 2.0 * w + (first ? 0.0 : B.nnzA_r * ent(B.A, w) + B.NBn * w) + B.NRn * (first ? 4.0 : 5.0) * w + (cf ? B.NRn : 0), WGK(dev::k_down, T, B.wg), nblocks_wg((long long)B.NBn << B.lg, B.wg), B.wg, 0, s, B.R.as<T>(), B.A.as<T>(), B.NRn, B.NBn,
            (const T *)Bp.sw, (T *)B.sw, (T *)B.f, (const T *)B.dinv, (const T *)uin, uout, (T *)B.t, first, (const signed char *)B.cls);
     PLAUNCH(h, "coarse", l, (B.nnzR - B.nnzR_n) * ent(B.R, w) + (B.NB - B.NBn) * 3.0 * w, dev::k_coarse<T>, B.ncg, dev::BLOCK, 2 * B.cg_maxn * sizeof(double), s, B.R.as<T>(), 1,
            (const T *)Bp.sw, (T *)B.f, (const T *)uin, uout, h->dense_A, h->dense_inv, B.cg_row0, B.cg_n,
@@ -546,12 +560,12 @@ void enqueue_fac_down(amgdd_ctx *h, hipStream_t s, int *cur, int l, int first) {
     // this level keep their solve, copied along)
     const int nrf = B.NRn - B.NRc;
     T *ui = (T *)B.u[cur[l]], *uo = (T *)B.u[cur[l] ^ 1];
-    PLAUNCH(h, "relax_f", l, (B.nnzA_r - B.nnzA_c) * ent(B.A, w) + nrf * 4.0 * w + B.NB * 2.0 * w + B.NRn, dev::k_relax<T>, nblocks((long long)B.NB << B.lg), dev::BLOCK, 0, s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
+    PLAUNCH(h, "relax_f", l, (B.nnzA_r - B.nnzA_c) * ent(B.A, w) + nrf * 4.0 * w + B.NB * 2.0 * w + B.NRn, WGK(dev::k_relax, T, B.wg), nblocks_wg((long long)B.NB << B.lg, B.wg), B.wg, 0, s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
             (const T *)B.dinv, (const T *)ui, uo, (T *)B.t, 1, (const signed char *)B.cls, -1);
     cur[l] ^= 1;
   }
   if (B.NBn > 0 && l < maxL)
-    PLAUNCH(h, "w", l, B.nnzA * ent(B.A, w) + B.NBn * (l > 0 ? 3.0 : 2.0) * w, dev::k_w<T>, nblocks((long long)B.NBn << B.lg), dev::BLOCK, 0, s, B.A.as<T>(), B.NBn, (T *)B.sw, (const T *)B.t, l > 0);
+    PLAUNCH(h, "w", l, B.nnzA * ent(B.A, w) + B.NBn * (l > 0 ? 3.0 : 2.0) * w, WGK(dev::k_w, T, B.wg), nblocks_wg((long long)B.NBn << B.lg, B.wg), B.wg, 0, s, B.A.as<T>(), B.NBn, (T *)B.sw, (const T *)B.t, l > 0);
 }
 
 template <typename T>
@@ -560,17 +574,17 @@ void enqueue_fac_up(amgdd_ctx *h, hipStream_t s, int *cur, int l) {
   DLevel &B = h->L[l];
   if (B.NBn == 0) return;
   DLevel &Bc = h->L[l + 1];
-  PLAUNCH(h, "interp", l, B.nnzP * ent(B.P, w) + B.NBn * 2.0 * w + Bc.NB * w, dev::k_interp<T>, nblocks((long long)B.NBn << B.P.lg), dev::BLOCK, 0, s, B.P.as<T>(), B.NBn, (T *)B.u[cur[l]],
+  PLAUNCH(h, "interp", l, B.nnzP * ent(B.P, w) + B.NBn * 2.0 * w + Bc.NB * w, WGK(dev::k_interp, T, B.wg), nblocks_wg((long long)B.NBn << B.P.lg, B.wg), B.wg, 0, s, B.P.as<T>(), B.NBn, (T *)B.u[cur[l]],
          (const T *)Bc.u[cur[l + 1]]);
   if (B.cls) {
     const int nrf = B.NRn - B.NRc;
-    PLAUNCH(h, "relax_post_f", l, (B.nnzA_r - B.nnzA_c) * ent(B.A, w) + nrf * 3.0 * w + B.NRc * w + B.NB * 2.0 * w + B.NRn, dev::k_relax<T>, nblocks((long long)B.NB << B.lg), dev::BLOCK, 0, s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
+    PLAUNCH(h, "relax_post_f", l, (B.nnzA_r - B.nnzA_c) * ent(B.A, w) + nrf * 3.0 * w + B.NRc * w + B.NB * 2.0 * w + B.NRn, WGK(dev::k_relax, T, B.wg), nblocks_wg((long long)B.NB << B.lg, B.wg), B.wg, 0, s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
             (const T *)B.dinv, (const T *)B.u[cur[l]], (T *)B.u[cur[l] ^ 1], (T *)B.t, 0, (const signed char *)B.cls, -1);
     cur[l] ^= 1;
-    PLAUNCH(h, "relax_post_c", l, B.nnzA_c * ent(B.A, w) + B.NRc * 4.0 * w + B.NB * 2.0 * w + B.NRn, dev::k_relax<T>, nblocks((long long)B.NB << B.lg), dev::BLOCK, 0, s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
+    PLAUNCH(h, "relax_post_c", l, B.nnzA_c * ent(B.A, w) + B.NRc * 4.0 * w + B.NB * 2.0 * w + B.NRn, WGK(dev::k_relax, T, B.wg), nblocks_wg((long long)B.NB << B.lg, B.wg), B.wg, 0, s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
             (const T *)B.dinv, (const T *)B.u[cur[l]], (T *)B.u[cur[l] ^ 1], (T *)B.t, 1, (const signed char *)B.cls, 1);
   } else {
-    PLAUNCH(h, "relax_post", l, B.nnzA_r * ent(B.A, w) + B.NRn * 3.0 * w + B.NB * 2.0 * w, dev::k_relax<T>, nblocks((long long)B.NB << B.lg), dev::BLOCK, 0, s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
+    PLAUNCH(h, "relax_post", l, B.nnzA_r * ent(B.A, w) + B.NRn * 3.0 * w + B.NB * 2.0 * w, WGK(dev::k_relax, T, B.wg), nblocks_wg((long long)B.NB << B.lg, B.wg), B.wg, 0, s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
            (const T *)B.dinv, (const T *)B.u[cur[l]], (T *)B.u[cur[l] ^ 1], (T *)B.t, 0, (const signed char *)nullptr, 1);
   }
   cur[l] ^= 1;
@@ -840,6 +854,7 @@ uint64_t schedule_key(amgdd_ctx *h) {
 struct SchedEntry {
   int level, block;
   double ms;
+  unsigned wide = 0;  // levels whose composite passes use 512-thread workgroups (bit l)
 };
 
 std::string sched_cache_path() {
@@ -860,8 +875,11 @@ std::vector<std::pair<uint64_t, SchedEntry>> read_sched_file(const std::string &
   while (std::fgets(line, sizeof line, f)) {
     unsigned long long key;
     SchedEntry e;
-    if (std::sscanf(line, " \"%16llx\": [%d, %d, %lf]", &key, &e.level, &e.block, &e.ms) == 4)
+    const int k = std::sscanf(line, " \"%16llx\": [%d, %d, %lf, %u]", &key, &e.level, &e.block, &e.ms, &e.wide);
+    if (k >= 4) {
+      if (k == 4) e.wide = 0;
       out.push_back({(uint64_t)key, e});
+    }
   }
   std::fclose(f);
   return out;
@@ -888,8 +906,8 @@ void write_sched_file(const std::string &path, uint64_t key, const SchedEntry &e
   if (!f) return;
   std::fprintf(f, "{\n");
   for (size_t i = 0; i < ent.size(); ++i)
-    std::fprintf(f, "\"%016llx\": [%d, %d, %.6f]%s\n", (unsigned long long)ent[i].first, ent[i].second.level,
-                 ent[i].second.block, ent[i].second.ms, i + 1 < ent.size() ? "," : "");
+    std::fprintf(f, "\"%016llx\": [%d, %d, %.6f, %u]%s\n", (unsigned long long)ent[i].first, ent[i].second.level,
+                 ent[i].second.block, ent[i].second.ms, ent[i].second.wide, i + 1 < ent.size() ? "," : "");
   std::fprintf(f, "}\n");
   const bool ok = std::fclose(f) == 0;
   if (!ok || std::rename(tmp.c_str(), path.c_str()) != 0) (void)std::remove(tmp.c_str());
@@ -929,11 +947,16 @@ amgdd_status autotune(amgdd_ctx *h) {
   const double t0 = now_s();
   const int nlev = (int)h->L.size();
   const uint64_t key = schedule_key(h);
+  auto set_wide = [&](unsigned mask) {
+    if (h->wg_fixed) return;
+    for (int l = 0; l < nlev; ++l) h->L[l].wg = (mask >> l) & 1u ? 512 : dev::BLOCK;
+  };
   {
     SchedEntry e;
     if (sched_lookup(key, e) && e.level >= -1 && e.level < nlev && (e.block == 256 || e.block == 512 || e.block == 1024)) {
       h->sched_level = e.level;
       h->sched_block = e.block;
+      set_wide(e.wide);
       h->sched_cached = 1;
       h->autotune_s = now_s() - t0;
       return AMGDD_OK;
@@ -954,34 +977,71 @@ amgdd_status autotune(amgdd_ctx *h) {
   HIP_TRY(hipMemcpyAsync(xsave, h->x, (size_t)h->N0 * sizeof(double), hipMemcpyDeviceToDevice, s));
   if (h->mixed()) enqueue_residual<float>(h, s, false);
   else enqueue_residual<double>(h, s, false);
+  // host-clock time of three replays of one captured iteration (after one
+  // warm replay) with the handle's current schedule
+  auto time_iteration = [&](double &ms) -> amgdd_status {
+    hipGraph_t gr = nullptr;
+    hipGraphExec_t ex = nullptr;
+    amgdd_status cs = capture(h, true, &gr, &ex);
+    if (cs) return cs;
+    HIP_TRY(hipGraphLaunch(ex, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const double tc = now_s();
+    for (int r = 0; r < 3; ++r) HIP_TRY(hipGraphLaunch(ex, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    ms = (now_s() - tc) * 1e3;
+    (void)hipGraphExecDestroy(ex);
+    (void)hipGraphDestroy(gr);
+    return AMGDD_OK;
+  };
   double best = 1e300;
   int best_l = -1, best_b = 256;
+  set_wide(0);
   for (int lt : levels)
     for (int bs : blocks) {
       if (lt < 0 && bs != blocks[0]) continue;
       h->sched_level = lt;
       h->sched_block = bs;
-      hipGraph_t gr = nullptr;
-      hipGraphExec_t ex = nullptr;
-      st = capture(h, true, &gr, &ex);
-      if (st) return st;
-      HIP_TRY(hipGraphLaunch(ex, s));
-      HIP_TRY(hipStreamSynchronize(s));
-      const double tc = now_s();
-      for (int r = 0; r < 3; ++r) HIP_TRY(hipGraphLaunch(ex, s));
-      HIP_TRY(hipStreamSynchronize(s));
-      const double ms = (now_s() - tc) * 1e3;
-      (void)hipGraphExecDestroy(ex);
-      (void)hipGraphDestroy(gr);
+      double ms = 0;
+      if ((st = time_iteration(ms))) return st;
       if (ms < best) { best = ms; best_l = lt; best_b = bs; }
     }
   h->sched_level = best_l;
   h->sched_block = best_b;
+  // then, level by level, 512-thread workgroups for the level-synchronous
+  // passes of that level (more rows per workgroup share the L1 cache's
+  // gathered vector lines): the current and the candidate schedule are timed
+  // alternately, twice each, and the candidate is kept when its faster time
+  // beats the current one's by more than 0.1%
+  unsigned wide = 0;
+  if (!h->wg_fixed) {
+    const int cut = best_l < 0 ? nlev : best_l;
+    for (int l = 0; l < std::min(cut, nlev) && l < 32; ++l) {
+      if (h->L[l].NBn == 0) continue;
+      double base = 1e300, cand = 1e300;
+      for (int rep = 0; rep < 2; ++rep) {
+        double ms = 0;
+        set_wide(wide);
+        if ((st = time_iteration(ms))) return st;
+        base = std::min(base, ms);
+        set_wide(wide | (1u << l));
+        if ((st = time_iteration(ms))) return st;
+        cand = std::min(cand, ms);
+      }
+      if (cand < base * 0.999) {
+        wide |= 1u << l;
+        best = cand;
+      }
+      set_wide(wide);
+    }
+  }
   h->sched_cached = 0;
   HIP_TRY(hipMemcpyAsync(h->x, xsave, (size_t)h->N0 * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
   h->drop_graphs();
-  sched_store(key, SchedEntry{best_l, best_b, best / 3.0});
+  SchedEntry e{best_l, best_b, best / 3.0};
+  e.wide = wide;
+  sched_store(key, e);
   h->autotune_s = now_s() - t0;
   return AMGDD_OK;
 }
@@ -1472,6 +1532,8 @@ amgdd_status amgdd_get_stats(amgdd_handle h, amgdd_stats *st) {
   st->tail_block = h->sched_block;
   st->autotune_s = h->autotune_s;
   st->schedule_cached = h->sched_cached;
+  for (int l = 0; l < (int)h->L.size() && l < 32; ++l)
+    if (h->L[l].wg == 512) st->wide_levels |= 1 << l;
   if (h->hybrid_lt > 0) {
     // composite figures of the level-L~ problems; levels above L~ (and whole
     // hierarchies that end at or above L~) are cycled on the global grids
@@ -1509,6 +1571,9 @@ amgdd_status amgdd_get_stats(amgdd_handle h, amgdd_stats *st) {
       st->tail_block = in->sched_block;
       st->autotune_s = in->autotune_s;
       st->schedule_cached = in->sched_cached;
+      st->wide_levels = 0;
+      for (int l = 0; l < (int)in->L.size() && l + h->hybrid_lt < 32; ++l)
+        if (in->L[l].wg == 512) st->wide_levels |= 1 << (l + h->hybrid_lt);
     }
     st->composite_overhead = S.global_nnz ? (double)(upper + st->composite_real_nnz) / (double)S.global_nnz : 0.0;
   }

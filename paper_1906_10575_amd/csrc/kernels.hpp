@@ -83,6 +83,8 @@ __device__ __forceinline__ int xcd_block() {
 }
 
 __device__ __forceinline__ int thread_id() { return xcd_block() * BLOCK + (int)threadIdx.x; }
+template <int WG>
+__device__ __forceinline__ int thread_id_wg() { return xcd_block() * WG + (int)threadIdx.x; }
 
 // Sum over the G = 2^lg lanes of each row group (xor butterfly, fixed order).
 template <typename V>
@@ -427,12 +429,12 @@ __global__ __launch_bounds__(BLOCK) void k_relax_zero(int nr, int nb, const T *_
 // null); other rows of [0, nb) are copied.
 // tmode: 0 t = delta (t = 0 at real rows of the other class), 1 t += delta,
 // 2 no t.
-template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_relax(SellD<T> A, int nr, int nb, const T *__restrict__ f,
+template <typename T, int WG = BLOCK>
+__global__ __launch_bounds__(WG) void k_relax(SellD<T> A, int nr, int nb, const T *__restrict__ f,
                                                   const T *__restrict__ dinv, const T *__restrict__ u_in,
                                                   T *__restrict__ u_out, T *__restrict__ t, int tmode,
                                                   const signed char *__restrict__ cls, int want) {
-  const int th = thread_id(), i = th >> A.lg, sub = th & ((1 << A.lg) - 1);
+  const int th = thread_id_wg<WG>(), i = th >> A.lg, sub = th & ((1 << A.lg) - 1);
   if (i < nr && relaxes(cls, want, i)) {
     const T d = (f[i] - sell_dot<T, T>(A, i, sub, u_in)) * dinv[i];
     if (sub == 0) {
@@ -448,10 +450,10 @@ __global__ __launch_bounds__(BLOCK) void k_relax(SellD<T> A, int nr, int nb, con
 
 // w = s + A t over rows [0, nb), in place in the s buffer (s is absent on
 // level 0).  t is zero at ghost points, so ghost rows store real columns only.
-template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_w(SellD<T> A, int nb, T *__restrict__ sw, const T *__restrict__ t,
+template <typename T, int WG = BLOCK>
+__global__ __launch_bounds__(WG) void k_w(SellD<T> A, int nb, T *__restrict__ sw, const T *__restrict__ t,
                                               int has_s) {
-  const int th = thread_id(), i = th >> A.lg, sub = th & ((1 << A.lg) - 1);
+  const int th = thread_id_wg<WG>(), i = th >> A.lg, sub = th & ((1 << A.lg) - 1);
   if (i < nb) {
     const T at = sell_dot<T, T>(A, i, sub, t);
     if (sub == 0) sw[i] = has_s ? sw[i] + at : at;
@@ -464,12 +466,12 @@ __global__ __launch_bounds__(BLOCK) void k_w(SellD<T> A, int nb, T *__restrict__
 // and the first relaxation from zero delta = f / d (CF order: the C half,
 // delta = 0 at F rows); ghost rows get u = 0.  R and A of one level share the
 // lane grouping.
-template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_down(SellD<T> R, SellD<T> A, int nr, int nb, const T *__restrict__ w_prev,
+template <typename T, int WG = BLOCK>
+__global__ __launch_bounds__(WG) void k_down(SellD<T> R, SellD<T> A, int nr, int nb, const T *__restrict__ w_prev,
                                                  T *__restrict__ sw, T *__restrict__ f, const T *__restrict__ dinv,
                                                  const T *__restrict__ u_in, T *__restrict__ u_out, T *__restrict__ t,
                                                  int first, const signed char *__restrict__ cls) {
-  const int th = thread_id(), i = th >> A.lg, sub = th & ((1 << A.lg) - 1);
+  const int th = thread_id_wg<WG>(), i = th >> A.lg, sub = th & ((1 << A.lg) - 1);
   if (i >= nb) return;
   const T s = sell_dot<T, T>(R, i, sub, w_prev);
   if (i < nr) {
@@ -543,9 +545,9 @@ __global__ __launch_bounds__(BLOCK) void k_coarse(SellD<T> R, int has_r, const T
 }
 
 // u += P u_c over rows [0, nb).
-template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_interp(SellD<T> P, int nb, T *__restrict__ u, const T *__restrict__ uc) {
-  const int th = thread_id(), i = th >> P.lg, sub = th & ((1 << P.lg) - 1);
+template <typename T, int WG = BLOCK>
+__global__ __launch_bounds__(WG) void k_interp(SellD<T> P, int nb, T *__restrict__ u, const T *__restrict__ uc) {
+  const int th = thread_id_wg<WG>(), i = th >> P.lg, sub = th & ((1 << P.lg) - 1);
   if (i < nb) {
     const T v = sell_dot<T, T>(P, i, sub, uc);
     if (sub == 0) u[i] += v;

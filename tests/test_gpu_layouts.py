@@ -30,7 +30,8 @@ torch = pytest.importorskip("torch")
 amgdd = pytest.importorskip("paper_1906_10575_amd.amgdd")
 
 DEV = "cuda:0"
-ENV = ("AMGDD_INDEX32", "AMGDD_SORT_WINDOW", "AMGDD_UNPAIRED", "AMGDD_QUAD", "AMGDD_SERIAL", "AMGDD_LANE_TARGET")
+ENV = ("AMGDD_INDEX32", "AMGDD_SORT_WINDOW", "AMGDD_UNPAIRED", "AMGDD_QUAD", "AMGDD_SERIAL", "AMGDD_LANE_TARGET",
+       "AMGDD_WG")
 
 CASES = {
     "3d_20_var_eta2": lambda: make_problem((20, 18, 20), (2, 2, 3), eta=2, n_fac=2,
@@ -125,6 +126,21 @@ def test_every_layout_matches_the_oracle(name, monkeypatch):
         errv = rel_inf(xv, xvo)
         say("  ", env, f"amgdd {err:.2e} vcycle {errv:.2e}")
         assert err <= 1e-12 and errv <= 1e-12, (env, err, errv)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_workgroup_size_is_bitwise_neutral(precision, monkeypatch):
+    """The composite passes' workgroup size (256 / 512 / 1024, fixed here by
+    AMGDD_WG; tuned per level otherwise) changes which workgroup serves a row,
+    not the row's arithmetic: iterates are bitwise identical."""
+    p = CASES["3d_20_var_eta2"]()
+    say("workgroup size", precision, p.n)
+    ref = _run(p, monkeypatch, {"AMGDD_WG": "256"}, precision)
+    for wg in ("512", "1024"):
+        got = _run(p, monkeypatch, {"AMGDD_WG": wg}, precision)
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), wg
+    got = _run(p, monkeypatch, {}, precision)  # tuned per level
+    assert np.array_equal(got[0], ref[0])
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
