@@ -475,7 +475,9 @@ def main():
     run_steps(torch, s, b, args.warmup, rtol, adjoint)
     st = s.stats()
     log(f"warmup done; schedule: cut level {st['tail_level']}, workgroup {st['tail_block']}, 512-thread levels "
-        f"{[l for l in range(32) if (st['wide_levels'] >> l) & 1]} (autotune {st['autotune_s']:.2f} s)")
+        f"{[l for l in range(32) if (st['wide_levels'] >> l) & 1]}, LDS-band levels "
+        f"{[l for l in range(32) if (st['lds_levels'] >> l) & 1]} / restriction "
+        f"{[l for l in range(32) if (st['restrict_lds_levels'] >> l) & 1]} (autotune {st['autotune_s']:.2f} s)")
     per_step = []
     dt, iters, x = run_steps(torch, s, b, args.steps, rtol, adjoint, per_step)
     its = int(np.median(iters))
@@ -537,6 +539,8 @@ def main():
                                for r_ in prof), key=lambda r_: -r_["ms"])[:8],
         "schedule": {"tail_level": st["tail_level"], "tail_block": st["tail_block"],
                      "wide_levels": [l for l in range(32) if (st["wide_levels"] >> l) & 1],
+                     "lds_levels": [l for l in range(32) if (st["lds_levels"] >> l) & 1],
+                     "restrict_lds_levels": [l for l in range(32) if (st["restrict_lds_levels"] >> l) & 1],
                      "autotune_s": round(st["autotune_s"], 3), "cached": bool(st["schedule_cached"])},
         "setup_s": round(setup_s, 2),
         "composite_overhead": round(st["composite_overhead"], 4),

@@ -51,14 +51,21 @@
  *   AMGDD_TEST_MAX_BYTES=n  device-memory cap (failure-path tests)
  *   AMGDD_WG=n            workgroup size of the composite passes (256, 512 or
  *                         1024) on every level, instead of the tuned choice
+ *   AMGDD_LDS=1|0         the operator and restriction passes of every level
+ *                         stage their tile's band of the gathered vector in
+ *                         LDS / none does, instead of the tuned choice
+ *   AMGDD_FUSED_R         restriction fused into the down pass with the
+ *                         operator's row order and lanes (no reordered P, R)
+ *   AMGDD_TIGHT_WINDOW=n  sort window of the reordered P and R (default 128)
  * and when a handle's schedule is tuned:
  *   AMGDD_TUNE_CACHE=path schedule cache file (JSON, one entry per line,
  *                         keyed by a hash of the layout, device and library
  *                         build); default $HOME/.cache/amgdd/schedules.json,
  *                         "off" = no file (the in-process cache remains)
- * Index width, the side-stream branch and the launch schedule leave results
- * bitwise unchanged; step width, row order and lanes per row change only the
- * rounding of rows served by several lanes.
+ * Index width, LDS staging, the side-stream branch and the launch schedule
+ * leave results bitwise unchanged; step width, row order, lanes per row and
+ * the fused restriction change only the rounding of rows served by several
+ * lanes.
  */
 #ifndef AMGDD_H
 #define AMGDD_H
@@ -179,6 +186,12 @@ typedef struct {
   int wide_levels;          /* bit l set: the level-synchronous passes of composite
                                level l run in 512-thread workgroups (chosen by the
                                autotuner), else 256 */
+  int lds_levels;           /* bit l set: the level-synchronous passes with the
+                               composite operator of level l run in 1024-thread
+                               workgroups that stage the gathered vector's band in
+                               LDS (chosen by the autotuner; same sums) */
+  int restrict_lds_levels;  /* bit l set: the same for the restriction pass of
+                               level l (the band of w_{l-1}) */
 } amgdd_stats;
 
 void amgdd_params_default(amgdd_params *prm);

@@ -53,7 +53,8 @@ class Stats(C.Structure):
                 ("setup_composite_s", C.c_double), ("setup_pack_s", C.c_double), ("setup_upload_s", C.c_double),
                 ("device_bytes", C.c_longlong), ("tail_level", C.c_int), ("tail_block", C.c_int),
                 ("autotune_s", C.c_double), ("composite_nnz", C.c_longlong), ("hybrid_level", C.c_int),
-                ("schedule_cached", C.c_int), ("wide_levels", C.c_int)]
+                ("schedule_cached", C.c_int), ("wide_levels", C.c_int),
+                ("lds_levels", C.c_int), ("restrict_lds_levels", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -79,6 +79,10 @@ struct Sell {
   std::vector<double> val;
   std::vector<uint16_t> col16;
   std::vector<int> base;
+  // LDS bands (composite operators; see build_bands): 8 ints per tile of 16
+  // slices, and each entry's position in its tile's band
+  std::vector<int> tiles;
+  std::vector<uint16_t> colL;
   long long entries() const { return sptr.empty() ? 0 : sptr.back(); }
   bool compressed() const { return !col16.empty(); }
 };
@@ -97,6 +101,15 @@ struct BatchLevel {
   Sell A;                          // rows [0, NBn)
   Sell P;                          // rows [0, NBn) -> level l+1 composite rows
   Sell R;                          // R_{l-1}: rows [0, NB) -> level l-1 composite rows
+  // level-synchronous passes (Setup::tight): P and R_{l-1} of the normal rows
+  // [0, NBn) again, each in a row order of its own (rows sorted by their own
+  // length in sort_window windows; position k holds row pperm[k] / rperm[k])
+  // and, for R, a lane count of its own (rlg)
+  Sell Pt, Rt;
+  std::vector<int> pperm, rperm;
+  int rlg = 0;
+  int band_max = 0;                // largest LDS band of A's tiles (values)
+  int rband_max = 0;               // ... of Rt's tiles
   std::vector<double> dinv;        // [NRn]
   std::vector<int> gsrc;           // [NB] global row (this level) of each real row, -1 for ghosts
   std::vector<int> cg_row0, cg_n, cg_dense;  // coarse grids: first row, size, dense offset
@@ -145,6 +158,13 @@ struct Setup {
   // grouped composite rows: lanes per row = smallest power of two with at
   // most this many entries per lane (rows of up to 20 entries keep one lane)
   double comp_lane_target = 16.0;
+  // separate reordered layouts of P and R for the level-synchronous passes
+  // (see BatchLevel::Pt / Rt); the per-grid schedule keeps P and R
+  bool tight = true;
+  int tight_window = 128;  // their sort windows (rows)
+  // LDS bands of the composite operators (at most band_cap values per tile)
+  bool bands = true;
+  int band_cap = 8192;
   // AMG components: coarsen 0 = RS first pass, 1 = HMIS; interp 0 = direct,
   // 1 = extended+i
   int coarsen = 0, interp = 0;

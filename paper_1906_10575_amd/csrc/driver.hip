@@ -107,9 +107,12 @@ struct DSell {
   int lg = 0;           // lanes per row (log2)
   int vlg = 0;          // log2 entries per lane in the widest steps
   long long entries = 0;
+  unsigned short *colL = nullptr;  // LDS bands (composite operators)
+  int *tiles = nullptr;
+  int ntiles = 0;
   template <typename T>
   dev::SellD<T> as() const {
-    return dev::SellD<T>{sptr, col, (const T *)val, lg, col16, base, vlg};
+    return dev::SellD<T>{sptr, col, (const T *)val, lg, col16, base, vlg, colL, tiles, ntiles};
   }
 };
 
@@ -118,7 +121,17 @@ struct DLevel {
   int NRn = 0, NBn = 0, NB = 0;
   int lg = 0, glg = 0;  // lanes per row (log2) of composite / global rows
   int wg = dev::BLOCK;  // workgroup size of the level's composite passes (256, 512 or 1024)
+  // the passes with the composite operator run in 1024-thread workgroups that
+  // stage the gathered vector's band in LDS (band_max values at most)
+  bool lds = false;
+  int band_max = 0;
+  bool rlds = false;  // same for the reordered restriction pass (w_{l-1}'s band)
+  int rband_max = 0;
   DSell A, P, R;
+  // reordered P / R_{l-1} of the normal rows (Setup::tight): position k holds
+  // row pperm[k] / rperm[k]; ppos / rpos are the inverse maps (per-grid tail)
+  DSell Pt, Rt;
+  int *pperm = nullptr, *rperm = nullptr, *ppos = nullptr, *rpos = nullptr;
   void *dinv = nullptr;
   void *u[2] = {nullptr, nullptr};
   void *t = nullptr, *sw = nullptr, *f = nullptr;  // f points into the level-f arena
@@ -228,6 +241,7 @@ struct amgdd_ctx {
   int sched_level = -2, sched_block = 256;
   int sched_cached = 0;  // schedule taken from the schedule cache
   bool wg_fixed = false;  // composite-pass workgroup sizes set by the environment (not tuned)
+  bool lds_fixed = false; // LDS staging set by the environment (not tuned)
   double autotune_s = 0.0;
   hipGraphExec_t g_dd = nullptr, g_v = nullptr;
   hipGraph_t gr_dd = nullptr, gr_v = nullptr;
@@ -282,6 +296,11 @@ struct amgdd_ctx {
     } else if ((st = upload(&d.col, s.col.data(), s.col.size()))) {
       return st;
     }
+    if (!s.tiles.empty()) {
+      if ((st = upload(&d.colL, (const unsigned short *)s.colL.data(), s.colL.size()))) return st;
+      if ((st = upload(&d.tiles, s.tiles.data(), s.tiles.size()))) return st;
+      d.ntiles = (int)(s.tiles.size() / 8);
+    }
     return upload_vals(&d.val, s.val, as_float);
   }
 
@@ -320,6 +339,12 @@ inline int nblocks(long long n) { return (int)((n + dev::BLOCK - 1) / dev::BLOCK
 inline int nblocks_wg(long long n, int wg) { return (int)((n + wg - 1) / wg); }
 // instantiation of a composite pass for a level's workgroup size
 #define WGK(K, T, wg) ((wg) == 1024 ? K<T, 1024> : (wg) == 512 ? K<T, 512> : K<T, 256>)
+// passes with the level's composite operator: 1024-thread workgroups staging
+// the gathered vector's LDS band when the level uses bands
+#define AK(K, T, B) ((B).lds ? K<T, 1024, true> : WGK(K, T, (B).wg))
+inline int a_wg(const DLevel &B) { return B.lds ? 1024 : B.wg; }
+template <typename T>
+size_t a_lds(const DLevel &B) { return B.lds ? (size_t)B.band_max * sizeof(T) : 0; }
 
 // Algorithmic bytes of one stored matrix entry: its value (w bytes) and its
 // column index (2 bytes when the layout holds 16-bit columns, else 4).
@@ -369,6 +394,23 @@ amgdd_status upload_all(amgdd_ctx *h) {
       D.wg = (v == 512 || v == 1024) ? v : dev::BLOCK;
       if (e) h->wg_fixed = true;
     }
+    D.band_max = B.band_max;
+    D.rband_max = B.rband_max;
+    {
+      int lim = 0;
+      const bool ok = hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) == hipSuccess;
+      // bands that do not fit one workgroup's LDS: not used
+      if (!ok || (long long)D.band_max * (h->mixed() ? 4 : 8) > lim) D.band_max = 0;
+      if (!ok || (long long)D.rband_max * (h->mixed() ? 4 : 8) > lim) D.rband_max = 0;
+    }
+    {
+      // measurement: AMGDD_LDS=1|0 stages the bands on every level that has
+      // them / on none (otherwise the autotuner decides per level)
+      const char *e = std::getenv("AMGDD_LDS");
+      D.lds = e && std::atoi(e) == 1 && D.band_max > 0;
+      D.rlds = e && std::atoi(e) == 1 && D.rband_max > 0;
+      if (e) h->lds_fixed = true;
+    }
     D.NB = B.NB;
     D.lg = B.lg;
     D.glg = B.glg;
@@ -391,8 +433,24 @@ amgdd_status upload_all(amgdd_ctx *h) {
       if ((st = h->upload((int8_t **)&D.gcls, B.gcls.data(), B.gcls.size()))) return st;
     }
     if ((st = h->upload_sell(D.A, B.A, fl))) return st;
-    if ((st = h->upload_sell(D.P, B.P, fl))) return st;
+    // with a reordered P every pass uses it (the original is not uploaded)
+    if (B.pperm.empty()) {
+      if ((st = h->upload_sell(D.P, B.P, fl))) return st;
+    } else {
+      if ((st = h->upload_sell(D.Pt, B.Pt, fl))) return st;
+      std::vector<int> pos(B.pperm.size());
+      for (size_t k = 0; k < pos.size(); ++k) pos[B.pperm[k]] = (int)k;
+      if ((st = h->upload(&D.pperm, B.pperm.data(), B.pperm.size()))) return st;
+      if ((st = h->upload(&D.ppos, pos.data(), pos.size()))) return st;
+    }
     if ((st = h->upload_sell(D.R, B.R, fl))) return st;
+    if (!B.rperm.empty()) {
+      if ((st = h->upload_sell(D.Rt, B.Rt, fl))) return st;
+      std::vector<int> pos(B.rperm.size());
+      for (size_t k = 0; k < pos.size(); ++k) pos[B.rperm[k]] = (int)k;
+      if ((st = h->upload(&D.rperm, B.rperm.data(), B.rperm.size()))) return st;
+      if ((st = h->upload(&D.rpos, pos.data(), pos.size()))) return st;
+    }
     if ((st = h->upload_vals(&D.dinv, B.dinv, fl))) return st;
     for (int k = 0; k < 2; ++k)
       if ((st = h->alloc(&D.u[k], (size_t)B.NB * tsz))) return st;
@@ -483,7 +541,7 @@ amgdd_status upload_all(amgdd_ctx *h) {
       for (int l = 0; l < nlev; ++l) {
         DLevel &D = h->L[l];
         v[l] = dev::LevelDev<T>{D.A.as<T>(), D.P.as<T>(), D.R.as<T>(), (const T *)D.dinv, (T *)D.u[0], (T *)D.u[1],
-                                (T *)D.t, (T *)D.sw, (T *)D.f, D.cls};
+                                (T *)D.t, (T *)D.sw, (T *)D.f, D.cls, D.Pt.as<T>(), D.Rt.as<T>(), D.ppos, D.rpos};
       }
       dev::LevelDev<T> *d = nullptr;
       amgdd_status s2 = h->upload(&d, v.data(), v.size());
@@ -544,10 +602,21 @@ void enqueue_fac_down(amgdd_ctx *h, hipStream_t s, int *cur, int l, int first) {
       PLAUNCH(h, "relax0", 0, nrc * 4.0 * w + (B.NBn - nrc) * w + (cf ? B.NRn : 0), dev::k_relax_zero<T>, nblocks(B.NBn), dev::BLOCK, 0, s, B.NRn, B.NBn, (const T *)B.f,
              (const T *)B.dinv, uout, (T *)B.t, (const signed char *)B.cls);
     else
-      PLAUNCH(h, "relax_pre", 0, nzc * ent(B.A, w) + nrc * 4.0 * w + B.NBn * 2.0 * w + (cf ? B.NRn : 0), WGK(dev::k_relax, T, B.wg), nblocks_wg((long long)B.NBn << B.lg, B.wg), B.wg, 0, s, B.A.as<T>(), B.NRn, B.NBn, (const T *)B.f,
+      PLAUNCH(h, "relax_pre", 0, nzc * ent(B.A, w) + nrc * 4.0 * w + B.NBn * 2.0 * w + (cf ? B.NRn : 0), AK(dev::k_relax, T, B), nblocks_wg((long long)B.NBn << B.lg, a_wg(B)), a_wg(B), a_lds<T>(B), s, B.A.as<T>(), B.NRn, B.NBn, (const T *)B.f,
              (const T *)B.dinv, (const T *)uin, uout, (T *)B.t, 1, (const signed char *)B.cls, 1);
   } else {
     DLevel &Bp = h->L[l - 1];
+    if (B.rperm) {
+      // restriction in R's own row order, then the rest of the down pass at real rows
+      const int rwg = B.rlds ? 1024 : B.wg;
+      PLAUNCH(h, "restrict_s", l, B.nnzR_n * ent(B.Rt, w) + Bp.NBn * w + B.NBn * (w + 4.0) + (B.NBn - B.NRn) * w,
+              (B.rlds ? dev::k_restrict_rows<T, 1024, true> : WGK(dev::k_restrict_rows, T, B.wg)),
+              nblocks_wg((long long)B.NBn << B.Rt.lg, rwg), rwg, B.rlds ? (size_t)B.rband_max * sizeof(T) : 0, s,
+              B.Rt.as<T>(), B.rperm, B.NBn, B.NRn, (const T *)Bp.sw, (T *)B.sw, uout);
+      PLAUNCH(h, "down", l, (first ? 0.0 : B.nnzA_r * ent(B.A, w) + B.NBn * w) + B.NRn * ((first ? 4.0 : 5.0) + 2.0) * w + (cf ? B.NRn : 0),
+              AK(dev::k_down_real, T, B), nblocks_wg((long long)B.NRn << B.lg, a_wg(B)), a_wg(B), a_lds<T>(B), s, B.A.as<T>(), B.NRn,
+              (const T *)B.sw, (T *)B.f, (const T *)B.dinv, (const T *)uin, uout, (T *)B.t, first, (const signed char *)B.cls);
+    } else
     PLAUNCH(h, "down", l, B.nnzR_n * ent(B.R, w) + Bp.NBn * w + B.NBn * 2.0 * w + (first ? 0.0 : B.nnzA_r * ent(B.A, w) + B.NBn * w) + B.NRn * (first ? 4.0 : 5.0) * w + (cf ? B.NRn : 0), WGK(dev::k_down, T, B.wg), nblocks_wg((long long)B.NBn << B.lg, B.wg), B.wg, 0, s, B.R.as<T>(), B.A.as<T>(), B.NRn, B.NBn,
            (const T *)Bp.sw, (T *)B.sw, (T *)B.f, (const T *)B.dinv, (const T *)uin, uout, (T *)B.t, first, (const signed char *)B.cls);
     PLAUNCH(h, "coarse", l, (B.nnzR - B.nnzR_n) * ent(B.R, w) + (B.NB - B.NBn) * 3.0 * w, dev::k_coarse<T>, B.ncg, dev::BLOCK, 2 * B.cg_maxn * sizeof(double), s, B.R.as<T>(), 1,
@@ -560,12 +629,12 @@ void enqueue_fac_down(amgdd_ctx *h, hipStream_t s, int *cur, int l, int first) {
     // this level keep their solve, copied along)
     const int nrf = B.NRn - B.NRc;
     T *ui = (T *)B.u[cur[l]], *uo = (T *)B.u[cur[l] ^ 1];
-    PLAUNCH(h, "relax_f", l, (B.nnzA_r - B.nnzA_c) * ent(B.A, w) + nrf * 4.0 * w + B.NB * 2.0 * w + B.NRn, WGK(dev::k_relax, T, B.wg), nblocks_wg((long long)B.NB << B.lg, B.wg), B.wg, 0, s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
+    PLAUNCH(h, "relax_f", l, (B.nnzA_r - B.nnzA_c) * ent(B.A, w) + nrf * 4.0 * w + B.NB * 2.0 * w + B.NRn, AK(dev::k_relax, T, B), nblocks_wg((long long)B.NB << B.lg, a_wg(B)), a_wg(B), a_lds<T>(B), s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
             (const T *)B.dinv, (const T *)ui, uo, (T *)B.t, 1, (const signed char *)B.cls, -1);
     cur[l] ^= 1;
   }
   if (B.NBn > 0 && l < maxL)
-    PLAUNCH(h, "w", l, B.nnzA * ent(B.A, w) + B.NBn * (l > 0 ? 3.0 : 2.0) * w, WGK(dev::k_w, T, B.wg), nblocks_wg((long long)B.NBn << B.lg, B.wg), B.wg, 0, s, B.A.as<T>(), B.NBn, (T *)B.sw, (const T *)B.t, l > 0);
+    PLAUNCH(h, "w", l, B.nnzA * ent(B.A, w) + B.NBn * (l > 0 ? 3.0 : 2.0) * w, AK(dev::k_w, T, B), nblocks_wg((long long)B.NBn << B.lg, a_wg(B)), a_wg(B), a_lds<T>(B), s, B.A.as<T>(), B.NBn, (T *)B.sw, (const T *)B.t, l > 0);
 }
 
 template <typename T>
@@ -574,17 +643,22 @@ void enqueue_fac_up(amgdd_ctx *h, hipStream_t s, int *cur, int l) {
   DLevel &B = h->L[l];
   if (B.NBn == 0) return;
   DLevel &Bc = h->L[l + 1];
+  if (B.pperm)
+    PLAUNCH(h, "interp", l, B.nnzP * ent(B.Pt, w) + B.NBn * (2.0 * w + 4.0) + Bc.NB * w,
+            WGK(dev::k_interp_rows, T, B.wg), nblocks_wg((long long)B.NBn << B.Pt.lg, B.wg), B.wg, 0, s, B.Pt.as<T>(),
+            B.pperm, B.NBn, (T *)B.u[cur[l]], (const T *)Bc.u[cur[l + 1]]);
+  else
   PLAUNCH(h, "interp", l, B.nnzP * ent(B.P, w) + B.NBn * 2.0 * w + Bc.NB * w, WGK(dev::k_interp, T, B.wg), nblocks_wg((long long)B.NBn << B.P.lg, B.wg), B.wg, 0, s, B.P.as<T>(), B.NBn, (T *)B.u[cur[l]],
          (const T *)Bc.u[cur[l + 1]]);
   if (B.cls) {
     const int nrf = B.NRn - B.NRc;
-    PLAUNCH(h, "relax_post_f", l, (B.nnzA_r - B.nnzA_c) * ent(B.A, w) + nrf * 3.0 * w + B.NRc * w + B.NB * 2.0 * w + B.NRn, WGK(dev::k_relax, T, B.wg), nblocks_wg((long long)B.NB << B.lg, B.wg), B.wg, 0, s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
+    PLAUNCH(h, "relax_post_f", l, (B.nnzA_r - B.nnzA_c) * ent(B.A, w) + nrf * 3.0 * w + B.NRc * w + B.NB * 2.0 * w + B.NRn, AK(dev::k_relax, T, B), nblocks_wg((long long)B.NB << B.lg, a_wg(B)), a_wg(B), a_lds<T>(B), s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
             (const T *)B.dinv, (const T *)B.u[cur[l]], (T *)B.u[cur[l] ^ 1], (T *)B.t, 0, (const signed char *)B.cls, -1);
     cur[l] ^= 1;
-    PLAUNCH(h, "relax_post_c", l, B.nnzA_c * ent(B.A, w) + B.NRc * 4.0 * w + B.NB * 2.0 * w + B.NRn, WGK(dev::k_relax, T, B.wg), nblocks_wg((long long)B.NB << B.lg, B.wg), B.wg, 0, s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
+    PLAUNCH(h, "relax_post_c", l, B.nnzA_c * ent(B.A, w) + B.NRc * 4.0 * w + B.NB * 2.0 * w + B.NRn, AK(dev::k_relax, T, B), nblocks_wg((long long)B.NB << B.lg, a_wg(B)), a_wg(B), a_lds<T>(B), s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
             (const T *)B.dinv, (const T *)B.u[cur[l]], (T *)B.u[cur[l] ^ 1], (T *)B.t, 1, (const signed char *)B.cls, 1);
   } else {
-    PLAUNCH(h, "relax_post", l, B.nnzA_r * ent(B.A, w) + B.NRn * 3.0 * w + B.NB * 2.0 * w, WGK(dev::k_relax, T, B.wg), nblocks_wg((long long)B.NB << B.lg, B.wg), B.wg, 0, s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
+    PLAUNCH(h, "relax_post", l, B.nnzA_r * ent(B.A, w) + B.NRn * 3.0 * w + B.NB * 2.0 * w, AK(dev::k_relax, T, B), nblocks_wg((long long)B.NB << B.lg, a_wg(B)), a_wg(B), a_lds<T>(B), s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
            (const T *)B.dinv, (const T *)B.u[cur[l]], (T *)B.u[cur[l] ^ 1], (T *)B.t, 0, (const signed char *)nullptr, 1);
   }
   cur[l] ^= 1;
@@ -599,10 +673,10 @@ double tail_bytes(amgdd_ctx *h, int lt, int first) {
   for (int l = lt; l <= maxL; ++l) {
     DLevel &B = h->L[l];
     if (l == 0) b += first ? B.NRn * 4.0 * w + (B.NBn - B.NRn) * w : B.nnzA_r * ent(B.A, w) + B.NRn * 4.0 * w + B.NBn * 2.0 * w;
-    else b += B.nnzR * ent(B.R, w) + h->L[l - 1].NBn * w + B.NBn * 2.0 * w + (first ? 0.0 : B.nnzA_r * ent(B.A, w) + B.NBn * w) + B.NRn * (first ? 4.0 : 5.0) * w;
+    else b += (B.rperm ? B.nnzR_n * ent(B.Rt, w) + (B.nnzR - B.nnzR_n) * ent(B.R, w) : B.nnzR * ent(B.R, w)) + h->L[l - 1].NBn * w + B.NBn * 2.0 * w + (first ? 0.0 : B.nnzA_r * ent(B.A, w) + B.NBn * w) + B.NRn * (first ? 4.0 : 5.0) * w;
     if (l < maxL) {
       b += B.nnzA * ent(B.A, w) + B.NBn * (l > 0 ? 3.0 : 2.0) * w;
-      b += B.nnzP * ent(B.P, w) + B.NBn * 2.0 * w + h->L[l + 1].NB * w;
+      b += B.nnzP * ent(B.pperm ? B.Pt : B.P, w) + B.NBn * 2.0 * w + h->L[l + 1].NB * w;
       b += B.nnzA_r * ent(B.A, w) + B.NRn * 3.0 * w + B.NB * 2.0 * w;
       // CF order: the extra half-sweeps re-read and re-write the vectors
       if (B.cls) b += 2.0 * (B.NBn * 2.0 * w + B.NRn) + (B.nnzA_r - B.nnzA_c) * ent(B.A, w);
@@ -842,10 +916,12 @@ uint64_t schedule_key(amgdd_ctx *h) {
   k.add((int)h->S.cf);
   k.add((int)h->S.grids.size());
   k.add(h->tail_maxn);
+  k.add((int)h->wg_fixed);
+  k.add((int)h->lds_fixed);
   for (const DLevel &D : h->L) {
     k.add(D.NRn); k.add(D.NBn); k.add(D.NB); k.add(D.lg); k.add(D.ncg); k.add(D.cg_maxn);
-    for (const DSell *M : {&D.A, &D.P, &D.R}) { k.add(M->entries); k.add(M->lg); k.add(M->vlg); k.add((int)(M->col16 != nullptr)); }
-    k.add(D.nnzA); k.add(D.nnzP); k.add(D.nnzR);
+    for (const DSell *M : {&D.A, &D.P, &D.R, &D.Pt, &D.Rt}) { k.add(M->entries); k.add(M->lg); k.add(M->vlg); k.add((int)(M->col16 != nullptr)); }
+    k.add(D.nnzA); k.add(D.nnzP); k.add(D.nnzR); k.add(D.band_max); k.add(D.A.ntiles); k.add(D.rband_max);
   }
   for (int c : h->tail_cnt) k.add(c);
   return k.h;
@@ -855,6 +931,8 @@ struct SchedEntry {
   int level, block;
   double ms;
   unsigned wide = 0;  // levels whose composite passes use 512-thread workgroups (bit l)
+  unsigned lds = 0;   // levels whose operator passes stage LDS bands (bit l)
+  unsigned rlds = 0;  // levels whose restriction pass stages LDS bands (bit l)
 };
 
 std::string sched_cache_path() {
@@ -875,9 +953,12 @@ std::vector<std::pair<uint64_t, SchedEntry>> read_sched_file(const std::string &
   while (std::fgets(line, sizeof line, f)) {
     unsigned long long key;
     SchedEntry e;
-    const int k = std::sscanf(line, " \"%16llx\": [%d, %d, %lf, %u]", &key, &e.level, &e.block, &e.ms, &e.wide);
+    const int k = std::sscanf(line, " \"%16llx\": [%d, %d, %lf, %u, %u, %u]", &key, &e.level, &e.block, &e.ms,
+                              &e.wide, &e.lds, &e.rlds);
     if (k >= 4) {
       if (k == 4) e.wide = 0;
+      if (k <= 5) e.lds = 0;
+      if (k <= 6) e.rlds = 0;
       out.push_back({(uint64_t)key, e});
     }
   }
@@ -906,8 +987,9 @@ void write_sched_file(const std::string &path, uint64_t key, const SchedEntry &e
   if (!f) return;
   std::fprintf(f, "{\n");
   for (size_t i = 0; i < ent.size(); ++i)
-    std::fprintf(f, "\"%016llx\": [%d, %d, %.6f, %u]%s\n", (unsigned long long)ent[i].first, ent[i].second.level,
-                 ent[i].second.block, ent[i].second.ms, ent[i].second.wide, i + 1 < ent.size() ? "," : "");
+    std::fprintf(f, "\"%016llx\": [%d, %d, %.6f, %u, %u, %u]%s\n", (unsigned long long)ent[i].first,
+                 ent[i].second.level, ent[i].second.block, ent[i].second.ms, ent[i].second.wide, ent[i].second.lds,
+                 ent[i].second.rlds, i + 1 < ent.size() ? "," : "");
   std::fprintf(f, "}\n");
   const bool ok = std::fclose(f) == 0;
   if (!ok || std::rename(tmp.c_str(), path.c_str()) != 0) (void)std::remove(tmp.c_str());
@@ -947,16 +1029,27 @@ amgdd_status autotune(amgdd_ctx *h) {
   const double t0 = now_s();
   const int nlev = (int)h->L.size();
   const uint64_t key = schedule_key(h);
-  auto set_wide = [&](unsigned mask) {
-    if (h->wg_fixed) return;
-    for (int l = 0; l < nlev; ++l) h->L[l].wg = (mask >> l) & 1u ? 512 : dev::BLOCK;
+  // per-level modes of the level-synchronous passes: 512-thread workgroups
+  // (bit l of m.w), LDS bands for the operator passes (bit l of m.a) and for
+  // the restriction pass (bit l of m.r)
+  struct Modes {
+    unsigned w = 0, a = 0, r = 0;
+  };
+  auto set_modes = [&](Modes m) {
+    for (int l = 0; l < nlev; ++l) {
+      if (!h->wg_fixed) h->L[l].wg = l < 32 && (m.w >> l) & 1u ? 512 : dev::BLOCK;
+      if (!h->lds_fixed) {
+        h->L[l].lds = l < 32 && (m.a >> l) & 1u && h->L[l].band_max > 0;
+        h->L[l].rlds = l < 32 && (m.r >> l) & 1u && h->L[l].rband_max > 0;
+      }
+    }
   };
   {
     SchedEntry e;
     if (sched_lookup(key, e) && e.level >= -1 && e.level < nlev && (e.block == 256 || e.block == 512 || e.block == 1024)) {
       h->sched_level = e.level;
       h->sched_block = e.block;
-      set_wide(e.wide);
+      set_modes(Modes{e.wide, e.lds, e.rlds});
       h->sched_cached = 1;
       h->autotune_s = now_s() - t0;
       return AMGDD_OK;
@@ -996,7 +1089,7 @@ amgdd_status autotune(amgdd_ctx *h) {
   };
   double best = 1e300;
   int best_l = -1, best_b = 256;
-  set_wide(0);
+  set_modes(Modes{});
   for (int lt : levels)
     for (int bs : blocks) {
       if (lt < 0 && bs != blocks[0]) continue;
@@ -1008,31 +1101,60 @@ amgdd_status autotune(amgdd_ctx *h) {
     }
   h->sched_level = best_l;
   h->sched_block = best_b;
-  // then, level by level, 512-thread workgroups for the level-synchronous
-  // passes of that level (more rows per workgroup share the L1 cache's
-  // gathered vector lines): the current and the candidate schedule are timed
-  // alternately, twice each, and the candidate is kept when its faster time
-  // beats the current one's by more than 0.1%
-  unsigned wide = 0;
-  if (!h->wg_fixed) {
+  // then, level by level, the modes of its level-synchronous passes: the
+  // current modes, 512-thread workgroups (more rows per workgroup share the L1
+  // cache's gathered vector lines) and LDS bands (the operator passes gather
+  // from LDS) are timed alternately, twice each, and a candidate is kept when
+  // its faster time beats the current one's by more than 0.1%.  Every mode
+  // computes the same sums in the same order.
+  Modes cur;
+  if (!h->wg_fixed || !h->lds_fixed) {
     const int cut = best_l < 0 ? nlev : best_l;
     for (int l = 0; l < std::min(cut, nlev) && l < 32; ++l) {
       if (h->L[l].NBn == 0) continue;
-      double base = 1e300, cand = 1e300;
-      for (int rep = 0; rep < 2; ++rep) {
-        double ms = 0;
-        set_wide(wide);
-        if ((st = time_iteration(ms))) return st;
-        base = std::min(base, ms);
-        set_wide(wide | (1u << l));
-        if ((st = time_iteration(ms))) return st;
-        cand = std::min(cand, ms);
+      const unsigned bit = 1u << l;
+      std::vector<Modes> cand = {cur};
+      if (!h->wg_fixed) cand.push_back(Modes{cur.w | bit, cur.a, cur.r});
+      if (!h->lds_fixed && h->L[l].band_max > 0) cand.push_back(Modes{cur.w, cur.a | bit, cur.r});
+      if (!h->lds_fixed && h->L[l].rband_max > 0 && h->L[l].rperm) cand.push_back(Modes{cur.w, cur.a, cur.r | bit});
+      if (cand.size() == 1) continue;
+      std::vector<double> t(cand.size(), 1e300);
+      for (int rep = 0; rep < 2; ++rep)
+        for (size_t c = 0; c < cand.size(); ++c) {
+          double ms = 0;
+          set_modes(cand[c]);
+          if ((st = time_iteration(ms))) return st;
+          t[c] = std::min(t[c], ms);
+        }
+      size_t bi = 0;
+      for (size_t c = 1; c < cand.size(); ++c)
+        if (t[c] < t[bi] && t[c] < t[0] * 0.999) bi = c;
+      // a second mode of the same level on top of the first one's gain
+      if (bi) {
+        Modes both = cand[bi];
+        for (size_t c = 1; c < cand.size(); ++c)
+          if (c != bi && t[c] < t[0] * 0.999) both = Modes{both.w | cand[c].w, both.a | cand[c].a, both.r | cand[c].r};
+        if (both.w != cand[bi].w || both.a != cand[bi].a || both.r != cand[bi].r) {
+          double tb = 1e300, tc = 1e300;
+          for (int rep = 0; rep < 2; ++rep) {
+            double ms = 0;
+            set_modes(cand[bi]);
+            if ((st = time_iteration(ms))) return st;
+            tc = std::min(tc, ms);
+            set_modes(both);
+            if ((st = time_iteration(ms))) return st;
+            tb = std::min(tb, ms);
+          }
+          t[bi] = tc;
+          if (tb < tc * 0.999) {
+            cand[bi] = both;
+            t[bi] = tb;
+          }
+        }
       }
-      if (cand < base * 0.999) {
-        wide |= 1u << l;
-        best = cand;
-      }
-      set_wide(wide);
+      cur = cand[bi];
+      if (bi) best = t[bi];
+      set_modes(cur);
     }
   }
   h->sched_cached = 0;
@@ -1040,7 +1162,9 @@ amgdd_status autotune(amgdd_ctx *h) {
   HIP_TRY(hipStreamSynchronize(s));
   h->drop_graphs();
   SchedEntry e{best_l, best_b, best / 3.0};
-  e.wide = wide;
+  e.wide = cur.w;
+  e.lds = cur.a;
+  e.rlds = cur.r;
   sched_store(key, e);
   h->autotune_s = now_s() - t0;
   return AMGDD_OK;
@@ -1325,6 +1449,8 @@ amgdd_status make_handle(const std::vector<ProblemInput> &in, const amgdd_params
   if (std::getenv("AMGDD_UNPAIRED")) h->S.step_log2 = h->S.comp_step_log2 = 0;
   if (const char *e = std::getenv("AMGDD_SORT_WINDOW")) h->S.sort_window = std::max(0, std::atoi(e));
   if (const char *e = std::getenv("AMGDD_LANE_TARGET")) h->S.comp_lane_target = std::max(1.0, std::atof(e));
+  if (std::getenv("AMGDD_FUSED_R")) h->S.tight = false;
+  if (const char *e = std::getenv("AMGDD_TIGHT_WINDOW")) h->S.tight_window = std::max(0, std::atoi(e));
   std::string err;
   Setup inner_S;
   int st;
@@ -1515,8 +1641,12 @@ amgdd_status amgdd_get_stats(amgdd_handle h, amgdd_stats *st) {
   st->composite_real_nnz = S.composite_real_nnz;
   st->composite_rows = S.composite_rows;
   st->composite_real_rows = S.composite_real_rows;
+  // entries stored on the device, padding included (a reordered P replaces P)
+  auto stored = [](const BatchLevel &B) {
+    return B.A.entries() + (B.pperm.empty() ? B.P.entries() : B.Pt.entries()) + B.R.entries() + B.Rt.entries();
+  };
   long long e = 0;
-  for (auto &B : S.lv) e += B.A.entries() + B.P.entries() + B.R.entries();
+  for (auto &B : S.lv) e += stored(B);
   st->composite_stored_nnz = e;
   long long u = 0;
   for (auto &B : S.lv) u += B.nnzA + B.nnzP + B.nnzR;
@@ -1532,8 +1662,11 @@ amgdd_status amgdd_get_stats(amgdd_handle h, amgdd_stats *st) {
   st->tail_block = h->sched_block;
   st->autotune_s = h->autotune_s;
   st->schedule_cached = h->sched_cached;
-  for (int l = 0; l < (int)h->L.size() && l < 32; ++l)
+  for (int l = 0; l < (int)h->L.size() && l < 32; ++l) {
     if (h->L[l].wg == 512) st->wide_levels |= 1 << l;
+    if (h->L[l].lds) st->lds_levels |= 1 << l;
+    if (h->L[l].rlds) st->restrict_lds_levels |= 1 << l;
+  }
   if (h->hybrid_lt > 0) {
     // composite figures of the level-L~ problems; levels above L~ (and whole
     // hierarchies that end at or above L~) are cycled on the global grids
@@ -1559,7 +1692,7 @@ amgdd_status amgdd_get_stats(amgdd_handle h, amgdd_stats *st) {
       st->omissions = I.omissions;
       long long e2 = 0, u2 = 0;
       for (auto &B : I.lv) {
-        e2 += B.A.entries() + B.P.entries() + B.R.entries();
+        e2 += stored(B);
         u2 += B.nnzA + B.nnzP + B.nnzR;
       }
       st->composite_stored_nnz = e2;
@@ -1571,9 +1704,12 @@ amgdd_status amgdd_get_stats(amgdd_handle h, amgdd_stats *st) {
       st->tail_block = in->sched_block;
       st->autotune_s = in->autotune_s;
       st->schedule_cached = in->sched_cached;
-      st->wide_levels = 0;
-      for (int l = 0; l < (int)in->L.size() && l + h->hybrid_lt < 32; ++l)
+      st->wide_levels = st->lds_levels = st->restrict_lds_levels = 0;
+      for (int l = 0; l < (int)in->L.size() && l + h->hybrid_lt < 32; ++l) {
         if (in->L[l].wg == 512) st->wide_levels |= 1 << (l + h->hybrid_lt);
+        if (in->L[l].lds) st->lds_levels |= 1 << (l + h->hybrid_lt);
+        if (in->L[l].rlds) st->restrict_lds_levels |= 1 << (l + h->hybrid_lt);
+      }
     }
     st->composite_overhead = S.global_nnz ? (double)(upper + st->composite_real_nnz) / (double)S.global_nnz : 0.0;
   }

@@ -70,6 +70,13 @@ struct SellD {
   const unsigned short *col16;
   const int *base;
   int vlg;  // log2 entries per lane in the widest steps (see sell_dotw)
+  // LDS bands (composite operators): tile t = the 16 slices [16t, 16t + 16),
+  // one 1024-thread workgroup; tiles[8t .. 8t+3] window starts, [8t+4 ..
+  // 8t+7] cumulative window lengths (0: no band); colL = each entry's
+  // position in its tile's band
+  const unsigned short *colL;
+  const int *tiles;
+  int ntiles;
 };
 
 // Workgroups are dispatched round-robin over the 8 XCDs; remap so that each
@@ -103,7 +110,8 @@ __device__ __forceinline__ V group_sum(V acc, int lg) {
 // share, i.e. entries jW .. jW + W-1 of the row): one W-wide value load
 // (16 bytes for two FP64 or four FP32 values) and one W-wide load of 16-bit
 // indices per lane and step.  Each lane accumulates in storage order.
-template <typename T, typename V, int VL>
+// L: x is the tile's band in LDS and the columns are band positions (colL).
+template <typename T, typename V, int VL, bool L = false>
 __device__ __forceinline__ V sell_dotw(const SellD<T> &M, int s, int beg, int r, int sub, const V *__restrict__ x) {
   constexpr int W = 1 << VL;
   typedef T TW __attribute__((ext_vector_type(W)));
@@ -123,10 +131,11 @@ __device__ __forceinline__ V sell_dotw(const SellD<T> &M, int s, int beg, int r,
   constexpr int U = AMGDD_UNROLL / W > 0 ? AMGDD_UNROLL / W : 1;  // steps in flight
   V acc = V(0);
   int k = 0;
-  if (M.col16) {
-    const CW *__restrict__ c = (const CW *)(M.col16 + beg + W * p);
-    const int b0 = M.base[2 * s], b1 = M.base[2 * s + 1];
-    auto dec = [&](unsigned short q) { return ((q & 0x8000) ? b1 : b0) + (int)(q & 0x7fff); };
+  if (L || M.col16) {
+    const unsigned short *__restrict__ C16 = L ? M.colL : M.col16;
+    const CW *__restrict__ c = (const CW *)(C16 + beg + W * p);
+    const int b0 = L ? 0 : M.base[2 * s], b1 = L ? 0 : M.base[2 * s + 1];
+    auto dec = [&](unsigned short q) { return L ? (int)q : ((q & 0x8000) ? b1 : b0) + (int)(q & 0x7fff); };
     if (k + U <= w) {
       CW cn[U];
       TW vn[U];
@@ -168,14 +177,14 @@ __device__ __forceinline__ V sell_dotw(const SellD<T> &M, int s, int beg, int r,
       for (int e = 0; e < W; ++e) acc = fma((V)vq[e], xx[e], acc);
     }
     if (has2) {
-      const C2 cq = __builtin_nontemporal_load((const C2 *)(M.col16 + off2 + 2 * p));
+      const C2 cq = __builtin_nontemporal_load((const C2 *)(C16 + off2 + 2 * p));
       const T2 vq = __builtin_nontemporal_load((const T2 *)(M.val + off2 + 2 * p));
       const V x0 = x[dec(cq.x)], x1 = x[dec(cq.y)];
       acc = fma((V)vq.x, x0, acc);
       acc = fma((V)vq.y, x1, acc);
     }
     if (u & 1)
-      acc = fma((V)__builtin_nontemporal_load(M.val + off1 + p), x[dec(__builtin_nontemporal_load(M.col16 + off1 + p))], acc);
+      acc = fma((V)__builtin_nontemporal_load(M.val + off1 + p), x[dec(__builtin_nontemporal_load(C16 + off1 + p))], acc);
   } else {
     const IW *__restrict__ c = (const IW *)(M.col + beg + W * p);
     for (; k + U <= w; k += U) {
@@ -222,14 +231,15 @@ __device__ __forceinline__ V sell_dotw(const SellD<T> &M, int s, int beg, int r,
 // full sum.
 // ALIGNED: the wavefront lies in one slice (threads assigned 64-aligned), so
 // the slice bounds are wave-uniform scalars.
-template <typename T, typename V, bool ALIGNED = true>
+// L: x is the tile's band in LDS, read through colL (see stage_band).
+template <typename T, typename V, bool ALIGNED = true, bool L = false>
 __device__ __forceinline__ V sell_dot(const SellD<T> &M, int r, int sub, const V *__restrict__ x) {
   const int lg = M.lg;
   int s = r >> (6 - lg);
   if (ALIGNED) s = __builtin_amdgcn_readfirstlane(s);
   const int beg = M.sptr[s];
-  if (M.vlg == 1) return sell_dotw<T, V, 1>(M, s, beg, r, sub, x);
-  if (M.vlg == 2) return sell_dotw<T, V, 2>(M, s, beg, r, sub, x);
+  if (M.vlg == 1) return sell_dotw<T, V, 1, L>(M, s, beg, r, sub, x);
+  if (M.vlg == 2) return sell_dotw<T, V, 2, L>(M, s, beg, r, sub, x);
   const int w = (M.sptr[s + 1] - beg) >> 6;
   const int off = beg + ((r & ((64 >> lg) - 1)) << lg) + sub;
   const T *__restrict__ v = M.val + off;
@@ -240,10 +250,10 @@ __device__ __forceinline__ V sell_dot(const SellD<T> &M, int r, int sub, const V
   // U entries in flight per lane: all index and value loads of a group are
   // issued before its gathers; the sum stays in storage order.
   constexpr int U = AMGDD_UNROLL;
-  if (M.col16) {
-    const unsigned short *__restrict__ c = M.col16 + off;
-    const int b0 = M.base[2 * s], b1 = M.base[2 * s + 1];
-    auto dec = [&](unsigned short q) { return ((q & 0x8000) ? b1 : b0) + (int)(q & 0x7fff); };
+  if (L || M.col16) {
+    const unsigned short *__restrict__ c = (L ? M.colL : M.col16) + off;
+    const int b0 = L ? 0 : M.base[2 * s], b1 = L ? 0 : M.base[2 * s + 1];
+    auto dec = [&](unsigned short q) { return L ? (int)q : ((q & 0x8000) ? b1 : b0) + (int)(q & 0x7fff); };
 #if AMGDD_PIPE
     // software pipelined: the next group's index / value loads are issued
     // before this group's gathers
@@ -314,6 +324,35 @@ __device__ __forceinline__ V sell_dot(const SellD<T> &M, int r, int sub, const V
 
 __device__ __forceinline__ bool relaxes(const signed char *__restrict__ cls, int want, int i) {
   return cls == nullptr || cls[i] == want;
+}
+
+// LDS band of the workgroup's tile (1024-thread workgroups of an operator with
+// bands): copies the tile's windows of x into `band` (coalesced loads) and
+// returns true, or returns false when the tile has no band (it then gathers
+// from memory).  The result is the same for every thread of the workgroup,
+// and so is the barrier.
+template <typename T, int WG>
+__device__ __forceinline__ bool stage_band(const SellD<T> &A, const T *__restrict__ x, T *band) {
+  const int tile = xcd_block();
+  if (tile >= A.ntiles) return false;
+  const int *d = A.tiles + 8 * tile;
+  const int n = d[7];
+  if (n == 0) return false;
+  const int lo0 = d[0], lo1 = d[1], lo2 = d[2], lo3 = d[3], e0 = d[4], e1 = d[5], e2 = d[6];
+  for (int k = threadIdx.x; k < n; k += WG)
+    band[k] = x[k < e0 ? lo0 + k : k < e1 ? lo1 + (k - e0) : k < e2 ? lo2 + (k - e1) : lo3 + (k - e2)];
+  __syncthreads();
+  return true;
+}
+
+extern __shared__ double lds_band[];
+
+// Row i of A times x: from the staged band when `staged`, else from memory.
+template <typename T, bool LDS>
+__device__ __forceinline__ T a_dot(const SellD<T> &A, int i, int sub, const T *__restrict__ x, bool staged) {
+  if constexpr (LDS)
+    if (staged) return sell_dot<T, T, true, true>(A, i, sub, (const T *)lds_band);
+  return sell_dot<T, T>(A, i, sub, x);
 }
 
 template <typename T>
@@ -429,14 +468,17 @@ __global__ __launch_bounds__(BLOCK) void k_relax_zero(int nr, int nb, const T *_
 // null); other rows of [0, nb) are copied.
 // tmode: 0 t = delta (t = 0 at real rows of the other class), 1 t += delta,
 // 2 no t.
-template <typename T, int WG = BLOCK>
+// LDS: 1024-thread workgroups staging u_in's band of the tile (see stage_band).
+template <typename T, int WG = BLOCK, bool LDS = false>
 __global__ __launch_bounds__(WG) void k_relax(SellD<T> A, int nr, int nb, const T *__restrict__ f,
                                                   const T *__restrict__ dinv, const T *__restrict__ u_in,
                                                   T *__restrict__ u_out, T *__restrict__ t, int tmode,
                                                   const signed char *__restrict__ cls, int want) {
   const int th = thread_id_wg<WG>(), i = th >> A.lg, sub = th & ((1 << A.lg) - 1);
+  // tiles of rows >= nr relax nothing: no band
+  const bool staged = LDS && (xcd_block() * (WG >> A.lg) < nr) && stage_band<T, WG>(A, u_in, (T *)lds_band);
   if (i < nr && relaxes(cls, want, i)) {
-    const T d = (f[i] - sell_dot<T, T>(A, i, sub, u_in)) * dinv[i];
+    const T d = (f[i] - a_dot<T, LDS>(A, i, sub, u_in, staged)) * dinv[i];
     if (sub == 0) {
       u_out[i] = u_in[i] + d;
       if (tmode == 0) t[i] = d;
@@ -450,12 +492,13 @@ __global__ __launch_bounds__(WG) void k_relax(SellD<T> A, int nr, int nb, const 
 
 // w = s + A t over rows [0, nb), in place in the s buffer (s is absent on
 // level 0).  t is zero at ghost points, so ghost rows store real columns only.
-template <typename T, int WG = BLOCK>
+template <typename T, int WG = BLOCK, bool LDS = false>
 __global__ __launch_bounds__(WG) void k_w(SellD<T> A, int nb, T *__restrict__ sw, const T *__restrict__ t,
                                               int has_s) {
   const int th = thread_id_wg<WG>(), i = th >> A.lg, sub = th & ((1 << A.lg) - 1);
+  const bool staged = LDS && stage_band<T, WG>(A, t, (T *)lds_band);
   if (i < nb) {
-    const T at = sell_dot<T, T>(A, i, sub, t);
+    const T at = a_dot<T, LDS>(A, i, sub, t, staged);
     if (sub == 0) sw[i] = has_s ? sw[i] + at : at;
   }
 }
@@ -488,6 +531,66 @@ __global__ __launch_bounds__(WG) void k_down(SellD<T> R, SellD<T> A, int nr, int
   } else if (sub == 0) {
     sw[i] = s;
     u_out[i] = T(0);
+  }
+}
+
+// Restriction of the level-synchronous down pass on its own, for level l >= 1
+// with R_{l-1} stored in a row order of its own (position k holds row
+// perm[k]): s = R w_prev at every normal row (stored for the down and w
+// passes), and u = 0 at ghost rows [nr, nb) (the down pass then covers the
+// real rows only).
+// LDS: 1024-thread workgroups staging w_prev's band of the tile (see stage_band).
+template <typename T, int WG = BLOCK, bool LDS = false>
+__global__ __launch_bounds__(WG) void k_restrict_rows(SellD<T> Rt, const int *__restrict__ perm, int nb, int nr,
+                                                          const T *__restrict__ w_prev, T *__restrict__ sw,
+                                                          T *__restrict__ u_out) {
+  const int th = thread_id_wg<WG>(), k = th >> Rt.lg, sub = th & ((1 << Rt.lg) - 1);
+  const bool staged = LDS && stage_band<T, WG>(Rt, w_prev, (T *)lds_band);
+  if (k < nb) {
+    const T s = a_dot<T, LDS>(Rt, k, sub, w_prev, staged);
+    if (sub == 0) {
+      const int i = perm[k];
+      sw[i] = s;
+      if (i >= nr) u_out[i] = T(0);
+    }
+  }
+}
+
+// Down pass of level l >= 1 at real rows [0, nr) once s = R w_prev is in sw
+// (k_restrict_rows): f <- (f - A u) - s (A u skipped in the first cycle),
+// u <- 0 and the first relaxation from zero (CF order: the C half).  Same
+// per-row arithmetic as k_down.
+template <typename T, int WG = BLOCK, bool LDS = false>
+__global__ __launch_bounds__(WG) void k_down_real(SellD<T> A, int nr, const T *__restrict__ sw, T *__restrict__ f,
+                                                      const T *__restrict__ dinv, const T *__restrict__ u_in,
+                                                      T *__restrict__ u_out, T *__restrict__ t, int first,
+                                                      const signed char *__restrict__ cls) {
+  const int th = thread_id_wg<WG>(), i = th >> A.lg, sub = th & ((1 << A.lg) - 1);
+  const bool staged = LDS && !first && stage_band<T, WG>(A, u_in, (T *)lds_band);
+  if (i < nr) {
+    T fi = f[i];
+    if (!first) fi -= a_dot<T, LDS>(A, i, sub, u_in, staged);
+    fi -= sw[i];
+    if (sub == 0) {
+      f[i] = fi;
+      const T d = relaxes(cls, 1, i) ? fi * dinv[i] : T(0);
+      u_out[i] = d;
+      t[i] = first ? d : t[i] + d;
+    }
+  }
+}
+
+// u += P u_c with P in a row order of its own (position k holds row perm[k]).
+template <typename T, int WG = BLOCK>
+__global__ __launch_bounds__(WG) void k_interp_rows(SellD<T> Pt, const int *__restrict__ perm, int nb,
+                                                        T *__restrict__ u, const T *__restrict__ uc) {
+  const int th = thread_id_wg<WG>(), k = th >> Pt.lg, sub = th & ((1 << Pt.lg) - 1);
+  if (k < nb) {
+    const T v = sell_dot<T, T>(Pt, k, sub, uc);
+    if (sub == 0) {
+      const int i = perm[k];
+      u[i] += v;
+    }
   }
 }
 
@@ -557,13 +660,18 @@ __global__ __launch_bounds__(WG) void k_interp(SellD<T> P, int nb, T *__restrict
 // ---------------------------------------------------------------- per-grid schedule
 
 // Pointers of one batched composite level (A and R share the lane grouping;
-// P has its own).
+// P has its own).  Pt / Rt (when Pt.sptr / Rt.sptr are set): P and R of the
+// normal rows in row orders of their own, row i at position ppos[i] /
+// rpos[i]; R is then applied in a step of its own before the rest of the
+// down pass, and the coarse-grid rows of R keep using R.
 template <typename T>
 struct LevelDev {
   SellD<T> A, P, R;
   const T *dinv;
   T *u0, *u1, *t, *sw, *f;
   const signed char *cls;  // C/F class of the real rows (CF order), or null
+  SellD<T> Pt, Rt;
+  const int *ppos, *rpos;
 };
 
 // Row ranges of one grid on one level (see the batched layout).
@@ -624,6 +732,31 @@ __global__ __launch_bounds__(1024) void k_fac_tail(const LevelDev<T> *__restrict
             }
           } else if (sub == 0) {
             B.u1[i] = first ? T(0) : B.u0[i];
+          }
+        }
+      } else if (B.Rt.sptr) {
+        // as k_restrict_rows then k_down_real
+        const T *wprev = lv[l - 1].sw;
+        const int rg = B.Rt.lg, rsub = tid & ((1 << rg) - 1);
+        for (int j = tid >> rg; j < nb; j += nt >> rg) {
+          const int i = grid_row(d, j);
+          const T s = sell_dot<T, T, false>(B.Rt, B.rpos[i], rsub, wprev);
+          if (rsub == 0) {
+            B.sw[i] = s;
+            if (j >= d.nreal) B.u1[i] = T(0);
+          }
+        }
+        __syncthreads();
+        for (int j = j0; j < d.nreal; j += js) {
+          const int i = grid_row(d, j);
+          T fi = B.f[i];
+          if (!first) fi -= sell_dot<T, T, false>(B.A, i, sub, B.u0);
+          fi -= B.sw[i];
+          if (sub == 0) {
+            B.f[i] = fi;
+            const T dl = relaxes(B.cls, 1, i) ? fi * B.dinv[i] : T(0);
+            B.u1[i] = dl;
+            B.t[i] = first ? dl : B.t[i] + dl;
           }
         }
       } else {
@@ -713,7 +846,15 @@ __global__ __launch_bounds__(1024) void k_fac_tail(const LevelDev<T> *__restrict
       const int lg = B.A.lg, sub = tid & ((1 << lg) - 1), j0 = tid >> lg, js = nt >> lg;
       const T *uc = lv[l + 1].u0;
       T *ucur = B.cls ? B.u0 : B.u1;
-      {
+      if (B.Pt.sptr) {
+        // as k_interp_rows
+        const int pg = B.Pt.lg, psub = tid & ((1 << pg) - 1);
+        for (int j = tid >> pg; j < nb; j += nt >> pg) {
+          const int i = grid_row(d, j);
+          const T v = sell_dot<T, T, false>(B.Pt, B.ppos[i], psub, uc);
+          if (psub == 0) ucur[i] += v;
+        }
+      } else {
         // interpolation rows have their own lane count
         const int pg = B.P.lg, psub = tid & ((1 << pg) - 1);
         for (int j = tid >> pg; j < nb; j += nt >> pg) {

@@ -328,6 +328,136 @@ struct SellBuilder {
   }
 };
 
+// Copy of rows [0, nrows) of a filled layout into a layout of their own in
+// which the rows are reordered: inside consecutive windows of `win` rows,
+// by decreasing length (stable), so a slice holds rows of similar length.
+// perm[k] = row held by position k.  own[r]: a column of row r's grid for its
+// padding (rows of no grid: any, they hold zeros).
+Sell permuted_layout(const SellBuilder &src, int nrows, int lg, int step_log2, int win, const std::vector<int> &own,
+                     std::vector<int> &perm) {
+  perm.resize(nrows);
+  for (int r = 0; r < nrows; ++r) perm[r] = r;
+  if (win > 0)
+    parallel_for((nrows + win - 1) / win, [&](long long b, long long e, int) {
+      for (long long w = b; w < e; ++w) {
+        const int r0 = (int)w * win, r1 = std::min(nrows, r0 + win);
+        std::stable_sort(perm.begin() + r0, perm.begin() + r1, [&](int x, int y) { return src.len[x] > src.len[y]; });
+      }
+    }, 64);
+  SellBuilder dst;
+  dst.init(nrows, lg, step_log2);
+  for (int k = 0; k < nrows; ++k) dst.len[k] = src.len[perm[k]];
+  dst.shape();
+  parallel_for(nrows, [&](long long b, long long e, int) {
+    for (long long k = b; k < e; ++k) {
+      const int r = perm[k];
+      for (int j = 0; j < src.len[r]; ++j) {
+        const size_t a = src.at(r, j);
+        dst.put((int)k, j, src.S.col[a], src.S.val[a]);
+      }
+      dst.pad((int)k, own[r]);
+    }
+  }, 4096);
+  return dst.take();
+}
+
+// LDS bands of a composite operator, for its level-synchronous passes run in
+// 1024-thread workgroups that stage the gathered vector in LDS.  Tile t is
+// the 16 slices [16t, 16t + 16) (1024 >> lg rows, one workgroup).  Its band
+// is the set of columns of its nonzero entries, covered by at most four
+// windows: the span split at its three largest gaps.  tiles[8t .. 8t+3] are
+// the window starts, tiles[8t+4 .. 8t+7] the cumulative window lengths (the
+// last one is the band size); a band of more than `cap` values is dropped
+// (all lengths 0: that tile gathers from memory).  colL[a] is the position of
+// entry a's column in its tile's band (0 for zero entries).  Returns the
+// largest band kept.
+int build_bands(Sell &S, int cap) {
+  const int ns = (int)S.sptr.size() - 1;
+  S.colL.clear();
+  S.tiles.clear();
+  if (ns <= 0) return 0;
+  const int nt = (ns + 15) / 16;
+  S.colL.assign(S.col.size(), 0);
+  S.tiles.assign(8 * (size_t)nt, 0);
+  std::vector<int> bmax(n_threads(), 0);
+  parallel_for(nt, [&](long long b, long long e, int tid) {
+    std::vector<int> cs;
+    std::vector<std::pair<int, int>> gaps;
+    for (long long t = b; t < e; ++t) {
+      const int e0 = S.sptr[16 * t], e1 = S.sptr[std::min<long long>(ns, 16 * t + 16)];
+      cs.clear();
+      for (int a = e0; a < e1; ++a)
+        if (S.val[a] != 0.0) cs.push_back(S.col[a]);
+      if (cs.empty()) continue;
+      std::sort(cs.begin(), cs.end());
+      cs.erase(std::unique(cs.begin(), cs.end()), cs.end());
+      gaps.clear();
+      for (size_t k = 1; k < cs.size(); ++k)
+        if (cs[k] - cs[k - 1] > 1) gaps.push_back({cs[k] - cs[k - 1], (int)k});
+      const size_t ng = std::min<size_t>(3, gaps.size());
+      std::partial_sort(gaps.begin(), gaps.begin() + ng, gaps.end(),
+                        [](const std::pair<int, int> &x, const std::pair<int, int> &y) {
+                          return x.first > y.first || (x.first == y.first && x.second < y.second);
+                        });
+      std::vector<int> cut;  // first index in cs of windows 1..
+      for (size_t k = 0; k < ng; ++k) cut.push_back(gaps[k].second);
+      std::sort(cut.begin(), cut.end());
+      int lo[4] = {0, 0, 0, 0}, end[4] = {0, 0, 0, 0};
+      int first = 0, acc = 0;
+      for (size_t w = 0; w <= cut.size(); ++w) {
+        const int last = (w < cut.size() ? cut[w] : (int)cs.size()) - 1;
+        lo[w] = cs[first];
+        acc += cs[last] - cs[first] + 1;
+        end[w] = acc;
+        first = last + 1;
+      }
+      for (size_t w = cut.size() + 1; w < 4; ++w) end[w] = acc;
+      if (acc > cap) continue;
+      int *d = &S.tiles[8 * (size_t)t];
+      for (int w = 0; w < 4; ++w) {
+        d[w] = lo[w];
+        d[4 + w] = end[w];
+      }
+      bmax[tid] = std::max(bmax[tid], acc);
+      for (int a = e0; a < e1; ++a) {
+        if (S.val[a] == 0.0) continue;
+        const int c = S.col[a];
+        int w = 3;
+        while (w > 0 && (end[w - 1] == end[w] || c < lo[w])) --w;
+        S.colL[a] = (uint16_t)((w ? end[w - 1] : 0) + c - lo[w]);
+      }
+    }
+  }, 1);
+  return *std::max_element(bmax.begin(), bmax.end());
+}
+
+// Check of build_bands: every nonzero entry of a banded tile decodes back to
+// its column through its window.
+bool bands_valid(const Sell &S, int cap) {
+  const int ns = (int)S.sptr.size() - 1;
+  const int nt = (ns + 15) / 16;
+  if (ns <= 0) return true;
+  if (S.colL.size() != S.col.size() || S.tiles.size() != 8 * (size_t)nt) return false;
+  std::atomic<bool> ok{true};
+  parallel_for(nt, [&](long long b, long long e, int) {
+    for (long long t = b; t < e; ++t) {
+      const int *d = &S.tiles[8 * (size_t)t];
+      const int n = d[7];
+      if (n == 0) continue;
+      if (n > cap || d[4] < 0 || d[4] > d[5] || d[5] > d[6] || d[6] > d[7]) { ok = false; return; }
+      const int e0 = S.sptr[16 * t], e1 = S.sptr[std::min<long long>(ns, 16 * t + 16)];
+      for (int a = e0; a < e1; ++a) {
+        const int q = S.colL[a];
+        if (q >= n) { ok = false; return; }
+        if (S.val[a] == 0.0) continue;
+        const int w = q < d[4] ? 0 : q < d[5] ? 1 : q < d[6] ? 2 : 3;
+        if (d[w] + q - (w ? d[3 + w] : 0) != S.col[a]) { ok = false; return; }
+      }
+    }
+  }, 1);
+  return ok;
+}
+
 // 16-bit column compression of a checked block-diagonal layout (see Sell).
 // Per slice, the columns of its nonzero entries are split at their largest gap
 // into two windows of at most 32768 columns (one window of 65536 when they
@@ -1418,6 +1548,16 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
       }
     }
     B.nnzP = bP.nnz_rows(0, B.NBn);
+    if (S.tight && B.NBn > 0) {
+      // interpolation rows in an order of their own for the level-synchronous
+      // pass (C rows inject one value, F rows interpolate from several)
+      std::vector<int> own(B.NBn, 0);
+      parallel_items(nn, [&](int k, int) {
+        const int g = normal[k];
+        for (int i = 0; i < std::max(1, S.grids[g].lv[l].nbar()); ++i) own[bidx(g, l, i)] = bidx(g, l + 1, 0);
+      });
+      B.Pt = permuted_layout(bP, B.NBn, B.plg, S.comp_step_log2, S.tight_window, own, B.pperm);
+    }
     B.A = bA.take();
     B.P = bP.take();
     vlog("pack: composite A, P", tp);
@@ -1449,6 +1589,19 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
       });
       Bn.nnzR_n = bR.nnz_rows(0, Bn.NBn);
       Bn.nnzR = bR.nnz_rows(0, Bn.NB);
+      if (S.tight && Bn.NBn > 0) {
+        // restriction rows of the normal grids in an order and a lane count
+        // of their own, for a restriction pass of its own (the operator's
+        // rows are several times longer and differently distributed)
+        std::vector<int> own(Bn.NBn, 0);
+        parallel_items(nn, [&](int k, int) {
+          const int g = normal[k];
+          if (roff[l + 1][g] < 0) return;
+          for (int J = 0; J < std::max(1, S.grids[g].lv[l + 1].nbar()); ++J) own[bidx(g, l + 1, J)] = bidx(g, l, 0);
+        });
+        Bn.rlg = lanes_log2((double)Bn.nnzR_n / Bn.NBn, S.comp_lane_target);
+        Bn.Rt = permuted_layout(bR, Bn.NBn, Bn.rlg, S.comp_step_log2, S.tight_window, own, Bn.rperm);
+      }
       Bn.R = bR.take();
     }
     // local operators of this level are no longer needed
@@ -1562,9 +1715,13 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
   if (verbose())
     for (int l = 0; l <= maxL; ++l) {
       const BatchLevel &B = S.lv[l];
-      std::fprintf(stderr, "[amgdd setup] level %d rows %d/%d/%d G %d/%d  A %lld/%lld  P %lld/%lld  R %lld/%lld\n", l,
-                   B.NRn, B.NBn, B.NB, 1 << B.lg, 1 << B.glg, B.nnzA, B.A.entries(), B.nnzP, B.P.entries(), B.nnzR,
-                   B.R.entries());
+      std::fprintf(stderr,
+                   "[amgdd setup] level %d rows %d/%d/%d G %d/%d  A %lld/%lld  P %lld/%lld (reordered %lld, G %d)  R "
+                   "%lld/%lld (normal rows %lld/%lld, reordered %lld, G %d)\n",
+                   l, B.NRn, B.NBn, B.NB, 1 << B.lg, 1 << B.glg, B.nnzA, B.A.entries(), B.nnzP, B.P.entries(),
+                   B.Pt.entries(), 1 << B.plg, B.nnzR, B.R.entries(), B.nnzR_n,
+                   B.R.sptr.empty() ? 0LL : (long long)B.R.sptr[(size_t)B.NBn >> (6 - B.R.lg)], B.Rt.entries(),
+                   1 << B.rlg);
     }
   for (int l = 0; l <= maxL; ++l) {
     const BatchLevel &B = S.lv[l];
@@ -1573,6 +1730,8 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
     bool ok = sell_in_bounds(B.A, B.NBn, B.NB) && sell_in_bounds(B.P, B.NBn, std::max(nbn, 1)) &&
               sell_in_bounds(B.GA, B.GN, B.GN) && sell_in_bounds(B.GP, B.GNn, std::max(gnn, 1));
     if (l > 0) ok = ok && sell_in_bounds(B.R, B.NB, nbp) && sell_in_bounds(B.GR, B.GN, gnp);
+    if (!B.pperm.empty()) ok = ok && sell_in_bounds(B.Pt, B.NBn, std::max(nbn, 1));
+    if (!B.rperm.empty()) ok = ok && sell_in_bounds(B.Rt, B.NBn, nbp);
     if (!ok) { err = "internal: batched layout check failed on level " + std::to_string(l); return ST_EINVAL; }
   }
   {
@@ -1593,8 +1752,39 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
       bool ok = sell_block_diagonal(B.A, cown[l], cown[l]) && sell_block_diagonal(B.GA, gown[l], gown[l]);
       if (l < maxL) ok = ok && sell_block_diagonal(B.P, cown[l], cown[l + 1]) && sell_block_diagonal(B.GP, gown[l], gown[l + 1]);
       if (l > 0) ok = ok && sell_block_diagonal(B.R, cown[l], cown[l - 1]) && sell_block_diagonal(B.GR, gown[l], gown[l - 1]);
+      // the reordered layouts: owner of position k = owner of the row it holds
+      if (!B.pperm.empty() || !B.rperm.empty()) {
+        std::vector<int> po(B.pperm.size()), ro(B.rperm.size());
+        for (size_t k = 0; k < po.size(); ++k) po[k] = cown[l][B.pperm[k]];
+        for (size_t k = 0; k < ro.size(); ++k) ro[k] = cown[l][B.rperm[k]];
+        if (!B.pperm.empty()) ok = ok && sell_block_diagonal(B.Pt, po, cown[l + 1]);
+        if (!B.rperm.empty()) ok = ok && sell_block_diagonal(B.Rt, ro, cown[l - 1]);
+      }
       if (!ok) { err = "internal: batched layout is not block-diagonal on level " + std::to_string(l); return ST_EINVAL; }
     }
+    // LDS bands of the composite operators (level-synchronous passes)
+    const double tb = now_s();
+    if (S.bands)
+      for (int l = 0; l <= maxL; ++l) {
+        BatchLevel &B = S.lv[l];
+        if (B.Rt.entries() > 0) {
+          // the reordered restriction gathers from the finer level
+          B.rband_max = build_bands(B.Rt, S.band_cap);
+          if (!bands_valid(B.Rt, S.band_cap)) { err = "internal: LDS band check failed on level " + std::to_string(l); return ST_EINVAL; }
+        }
+        if (B.A.entries() == 0) continue;
+        B.band_max = build_bands(B.A, S.band_cap);
+        if (!bands_valid(B.A, S.band_cap)) { err = "internal: LDS band check failed on level " + std::to_string(l); return ST_EINVAL; }
+        if (verbose()) {
+          long long nb = 0, sum = 0;
+          const int nt = (int)B.A.tiles.size() / 8;
+          for (int t = 0; t < nt; ++t)
+            if (B.A.tiles[8 * t + 7]) { ++nb; sum += B.A.tiles[8 * t + 7]; }
+          std::fprintf(stderr, "[amgdd setup] level %d LDS bands: %lld of %d tiles, %.2f values per row, largest %d (R: %d)\n",
+                       l, nb, nt, nb ? (double)sum / nb / (1024 >> B.A.lg) : 0.0, B.band_max, B.rband_max);
+        }
+      }
+    vlog("pack: LDS bands", tb);
     // 16-bit column indices where every slice fits (checked by decoding)
     if (S.compress) {
       std::vector<char> done(6 * (maxL + 1), 0);
@@ -1607,6 +1797,19 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
         if (m == 3) done[k] = compress_columns(B.GA, gown[l], gown[l]);
         if (m == 4 && l < maxL) done[k] = compress_columns(B.GP, gown[l], gown[l + 1]);
         if (m == 5 && l > 0) done[k] = compress_columns(B.GR, gown[l], gown[l - 1]);
+      }
+      for (int l = 0; l <= maxL; ++l) {
+        BatchLevel &B = S.lv[l];
+        if (!B.pperm.empty()) {
+          std::vector<int> po(B.pperm.size());
+          for (size_t k = 0; k < po.size(); ++k) po[k] = cown[l][B.pperm[k]];
+          compress_columns(B.Pt, po, cown[l + 1]);
+        }
+        if (!B.rperm.empty()) {
+          std::vector<int> ro(B.rperm.size());
+          for (size_t k = 0; k < ro.size(); ++k) ro[k] = cown[l][B.rperm[k]];
+          compress_columns(B.Rt, ro, cown[l - 1]);
+        }
       }
       if (verbose())
         for (int l = 0; l <= maxL; ++l)

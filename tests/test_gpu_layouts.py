@@ -2,7 +2,9 @@
 column indices (AMGDD_INDEX32), rows of grouped levels sorted by length or
 kept in local order (AMGDD_SORT_WINDOW), one, two or four entries per lane
 and load step (AMGDD_UNPAIRED, default, AMGDD_QUAD), lanes per composite row
-(AMGDD_LANE_TARGET), one or two streams per iteration (AMGDD_SERIAL).
+(AMGDD_LANE_TARGET), one or two streams per iteration (AMGDD_SERIAL), operator
+passes that gather from an LDS copy of their tile's band of the vector or
+from memory (AMGDD_LDS).
 
 Index width changes neither the entries of a row nor the order in which each
 lane adds them (padding adds exact zeros), so iterates are bitwise identical
@@ -31,7 +33,7 @@ amgdd = pytest.importorskip("paper_1906_10575_amd.amgdd")
 
 DEV = "cuda:0"
 ENV = ("AMGDD_INDEX32", "AMGDD_SORT_WINDOW", "AMGDD_UNPAIRED", "AMGDD_QUAD", "AMGDD_SERIAL", "AMGDD_LANE_TARGET",
-       "AMGDD_WG")
+       "AMGDD_WG", "AMGDD_LDS")
 
 CASES = {
     "3d_20_var_eta2": lambda: make_problem((20, 18, 20), (2, 2, 3), eta=2, n_fac=2,
@@ -50,12 +52,13 @@ def _t(x):
     return torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64), device=DEV)
 
 
-def _run(p, monkeypatch, env, precision="fp64", hybrid=0, iters=4):
+def _run(p, monkeypatch, env, precision="fp64", hybrid=0, iters=4, relax="l1"):
     for k in ENV:
         monkeypatch.delenv(k, raising=False)
     for k, v in env.items():
         monkeypatch.setenv(k, v)
-    s = amgdd.Solver(p.A, p.part, p.nparts, padding=p.eta, n_fac=p.n_fac, precision=precision, hybrid_level=hybrid)
+    s = amgdd.Solver(p.A, p.part, p.nparts, padding=p.eta, n_fac=p.n_fac, precision=precision, hybrid_level=hybrid,
+                     relax=relax)
     b = _t(p.b)
     x, info, st = s.solve(b, rtol=0, maxit=iters)
     assert st == amgdd.OK and info.iters == iters
@@ -120,7 +123,8 @@ def test_every_layout_matches_the_oracle(name, monkeypatch):
         xvo = cycles.vcycle(H, xvo, p.b, coarse=coarse)
     for env in ({}, {"AMGDD_SORT_WINDOW": "0"}, {"AMGDD_SORT_WINDOW": "32"}, {"AMGDD_UNPAIRED": "1"},
                 {"AMGDD_UNPAIRED": "1", "AMGDD_INDEX32": "1"}, {"AMGDD_QUAD": "1"}, {"AMGDD_QUAD": "1", "AMGDD_INDEX32": "1"},
-                {"AMGDD_LANE_TARGET": "6"}, {"AMGDD_LANE_TARGET": "40"}):
+                {"AMGDD_LANE_TARGET": "6"}, {"AMGDD_LANE_TARGET": "40"}, {"AMGDD_LDS": "1"},
+                {"AMGDD_LDS": "1", "AMGDD_QUAD": "1"}):
         x, xv = _run(p, monkeypatch, env, iters=3)
         err = rel_inf(x, xo)
         errv = rel_inf(xv, xvo)
@@ -140,6 +144,35 @@ def test_workgroup_size_is_bitwise_neutral(precision, monkeypatch):
         got = _run(p, monkeypatch, {"AMGDD_WG": wg}, precision)
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), wg
     got = _run(p, monkeypatch, {}, precision)  # tuned per level
+    assert np.array_equal(got[0], ref[0])
+
+
+@pytest.mark.parametrize("relax", ["l1", "cf"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", ["3d_20_var_eta2", "3d_30_ragged_4x4x4"])
+def test_lds_bands_are_bitwise_neutral(name, precision, relax, monkeypatch):
+    """The operator passes in 1024-thread workgroups that first copy their
+    tile's band of the gathered vector into LDS (AMGDD_LDS=1, every level
+    with bands; chosen per level by the autotuner otherwise) read the same
+    values through band positions instead of columns: iterates are bitwise
+    identical, in natural and CF order, with paired and four-wide steps."""
+    p = CASES[name]()
+    say("LDS bands", name, precision, relax, p.n)
+    refs = []
+    for base in ({}, {"AMGDD_QUAD": "1"}):
+        ref = _run(p, monkeypatch, dict(base, AMGDD_LDS="0"), precision, relax=relax)
+        got = _run(p, monkeypatch, dict(base, AMGDD_LDS="1"), precision, relax=relax)
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), base
+        refs.append(ref)
+    got = _run(p, monkeypatch, {}, precision, relax=relax)  # tuned per level, default layout
+    assert np.array_equal(got[0], refs[0][0])
+
+
+def test_lds_bands_hybrid_cycle_is_bitwise_neutral(monkeypatch):
+    p = CASES["3d_30_ragged_4x4x4"]()
+    say("LDS bands, hybrid", p.n)
+    ref = _run(p, monkeypatch, {"AMGDD_LDS": "0"}, hybrid=2)
+    got = _run(p, monkeypatch, {"AMGDD_LDS": "1"}, hybrid=2)
     assert np.array_equal(got[0], ref[0])
 
 
