@@ -217,29 +217,44 @@ def _pmc_means(path):
     return agg
 
 
-# launch sites of amgdd_profile -> kernel names in the counter output
-SITE_KERNEL = {"relax_pre": "k_relax", "relax_post": "k_relax", "relax_f": "k_relax", "relax_post_f": "k_relax",
-               "relax_post_c": "k_relax", "w": "k_w", "down": "k_down", "interp": "k_interp", "restrict": "k_spmv",
-               "resid": "k_resid", "gather": "k_gather", "patch": "k_patch", "relax0": "k_relax_zero"}
+# launch sites of amgdd_profile -> kernel names in the counter output (a site
+# runs one of these kernels, depending on the layout)
+SITE_KERNEL = {"relax_pre": ("k_relax",), "relax_post": ("k_relax",), "relax_f": ("k_relax",),
+               "relax_post_f": ("k_relax",), "relax_post_c": ("k_relax",), "w": ("k_w",),
+               "down": ("k_down", "k_down_real"), "interp": ("k_interp", "k_interp_rows"), "restrict": ("k_spmv",),
+               "restrict_s": ("k_restrict_rows",), "resid": ("k_resid",), "gather": ("k_gather",),
+               "patch": ("k_patch",), "relax0": ("k_relax_zero",)}
+KERNEL_REGEX = "k_w|k_relax|k_down|k_interp|k_restrict|k_spmv|k_resid|k_gather|k_patch|elementwise"
+# third pass: L1->L2 read latency, addresser and wave activity
+EXTRA_COUNTERS = ("GRBM_GUI_ACTIVE", "TA_TA_BUSY", "TA_ADDR_STALLED_BY_TC_CYCLES", "TCP_TCC_READ_REQ",
+                  "TCP_TCC_READ_REQ_LATENCY", "SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_WAIT_INST_ANY")
+N_CU, N_XCD = 256, 8
 
 
-def traffic_records(fetch_csv, write_csv, sites_log, workload, top=3):
-    """HBM traffic records of the `top` longest launch sites of one iteration:
+def traffic_records(fetch_csv, write_csv, sites_log, workload, top=3, levels=None, names=None, extra_csv=None):
+    """HBM traffic records of launch sites of one iteration: the `top` longest
+    ones, or every site named in `names` on the composite levels in `levels`.
     FETCH_SIZE and WRITE_SIZE (KiB per dispatch, one rocprofv3 --pmc pass
-    each, run with --calibrate-copy) scaled by the same counters on the
+    each, run with --calibrate-copy) are scaled by the same counters on the
     calibration kernel (y = x + 1 over 2^25 doubles: 256 MiB read, 256 MiB
-    written), matched to the sites of a `bench.py --sites` log by kernel and
-    workgroup count.  Returns the records (dicts)."""
+    written) and matched to the sites of a `bench.py --sites` log by kernel and
+    workgroup count.  With `extra_csv` (a third pass over EXTRA_COUNTERS) the
+    record also gives the mean L1->L2 read latency, the addresser's busy and
+    stalled fractions and the waves' waiting fraction.  Returns the records."""
     import hashlib
     f = _pmc_means(fetch_csv)
     w = _pmc_means(write_csv)
+    x = _pmc_means(extra_csv) if extra_csv else {}
 
-    def mean(agg, kern, wgs, ctr):
-        vals = [v for (k, g, _, c), vs in agg.items() if k.startswith(kern + "<") and g == wgs and c == ctr for v in vs]
+    def mean(agg, kerns, wgs, ctr):
+        vals = [v for (k, g, _, c), vs in agg.items()
+                if any(k.startswith(kn + "<") for kn in kerns) and g == wgs and c == ctr for v in vs]
         return sum(vals) / len(vals) if vals else None
 
     def calib(agg, ctr):
-        vals = [v for (k, g, _, c), vs in agg.items() if "elementwise" in k and g == 32768 and c == ctr for v in vs]
+        # the y = x + 1 kernel only (fills of the same size run beside it)
+        vals = [v for (k, g, _, c), vs in agg.items()
+                if "elementwise" in k and "_add" in k and g == 32768 and c == ctr for v in vs]
         return sum(vals) / len(vals) if vals else None
     cf, cw = calib(f, "FETCH_SIZE"), calib(w, "WRITE_SIZE")
     if not cf or not cw:
@@ -254,27 +269,49 @@ def traffic_records(fetch_csv, write_csv, sites_log, workload, top=3):
             sites.append(dict(name=name, level=lvl, launches=n, ms=ms, mb=mb, workgroups=wg))
     sha = hashlib.sha256(open(os.path.join(ROOT, "paper_1906_10575_amd", "csrc", "kernels.hpp"), "rb").read()).hexdigest()
     recs = []
-    for st in sorted(sites, key=lambda r: -r["ms"])[:top]:
+    if levels is not None:
+        chosen = [st for st in sites if st["level"] in levels and (names is None or st["name"] in names)]
+    else:
+        chosen = sorted(sites, key=lambda r: -r["ms"])[:top]
+    for st in chosen:
         kern = SITE_KERNEL[st["name"]]
         fk, wk = mean(f, kern, st["workgroups"], "FETCH_SIZE"), mean(w, kern, st["workgroups"], "WRITE_SIZE")
         if fk is None or wk is None:
             continue
         traffic = (fk / (cf / exp) + wk / (cw / exp)) * 1024
+        extra = None
+        if x:
+            c = {k: mean(x, kern, st["workgroups"], k) for k in EXTRA_COUNTERS}
+            if all(v is not None for v in c.values()) and c["GRBM_GUI_ACTIVE"] > 0:
+                cyc = c["GRBM_GUI_ACTIVE"] / N_XCD  # kernel cycles (per XCD)
+                extra = {"counters": {k: round(v, 1) for k, v in c.items()},
+                         "l2_read_latency_cycles": round(c["TCP_TCC_READ_REQ_LATENCY"] / max(c["TCP_TCC_READ_REQ"], 1), 1),
+                         "ta_busy_frac": round(c["TA_TA_BUSY"] / N_CU / cyc, 3),
+                         "ta_stalled_by_l1_frac": round(c["TA_ADDR_STALLED_BY_TC_CYCLES"] / N_CU / cyc, 3),
+                         "wave_wait_frac": round(c["SQ_WAIT_INST_ANY"] / max(c["SQ_WAVE_CYCLES"], 1), 3),
+                         "l2_read_requests_per_alg_kib": round(c["TCP_TCC_READ_REQ"] /
+                                                               (st["mb"] * 1e6 / st["launches"] / 1024), 2)}
         recs.append({
             "what": f"HBM traffic per launch of the {st['name']} site on composite level {st['level']} of the "
                     f"{workload} AMG-DD iteration, from two rocprofv3 --pmc passes, scaled by the same counters on "
                     f"a known-size elementwise kernel (y = x + 1 over 2^25 doubles: 256 MiB read + 256 MiB written)",
-            "kernels_sha256": sha, "site": st["name"], "level": st["level"], "kernel": kern + "<...>",
+            "kernels_sha256": sha, "site": st["name"], "level": st["level"], "kernel": " | ".join(k + "<...>" for k in kern),
             "workgroups": st["workgroups"], "fetch_size_kib": round(fk, 1), "write_size_kib": round(wk, 1),
             "calibration": {"fetch_size_kib": round(cf, 1), "write_size_kib": round(cw, 1), "expected_kib": exp,
                             "fetch_factor": round(cf / exp, 5), "write_factor": round(cw / exp, 5)},
             "traffic_bytes": int(round(traffic)), "algorithmic_bytes": st["mb"] * 1e6 / st["launches"],
-            "commands": [f"rocprofv3 --pmc FETCH_SIZE --kernel-include-regex 'k_w|k_relax|k_down|k_interp|k_spmv|"
-                         f"k_resid|k_gather|k_patch|elementwise' -f csv -d <dir> -o run -- python3 bench.py --config "
-                         f"{workload} --precision fp64 --steps 1 --warmup 1 --no-cpu-baseline --no-extras "
-                         f"--calibrate-copy --sites", "rocprofv3 --pmc WRITE_SIZE (same options)",
-                         "python3 bench.py --traffic-records <fetch csv> <write csv> <sites log> --config "
-                         f"{workload}"]})
+            "traffic_over_algorithmic": round(traffic / (st["mb"] * 1e6 / st["launches"]), 3),
+            "commands": [f"rocprofv3 --pmc FETCH_SIZE --kernel-include-regex '{KERNEL_REGEX}' -f csv -d <dir> -o run "
+                         f"-- python3 bench.py --config {workload} --precision fp64 --steps 1 --warmup 1 "
+                         f"--no-cpu-baseline --no-extras --calibrate-copy --sites",
+                         "rocprofv3 --pmc WRITE_SIZE (same options)"] +
+                        ([f"rocprofv3 --pmc {' '.join(EXTRA_COUNTERS)} (same options)"] if x else []) +
+                        ["python3 bench.py --traffic-records <fetch csv> <write csv> <sites log> --config "
+                         f"{workload}" + (" --traffic-extra <third csv>" if x else "") +
+                         (f" --traffic-levels {','.join(map(str, sorted(levels)))}" if levels is not None else "") +
+                         (f" --traffic-sites {','.join(sorted(names))}" if names else "")]})
+        if extra:
+            recs[-1]["l1_l2_path"] = extra
     return recs
 
 
@@ -410,6 +447,10 @@ def main():
     ap.add_argument("--traffic-records", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "SITES_LOG"),
                     help="write profiles/traffic_<site>_l<level>_<config>.json for the longest launch sites from "
                          "FETCH_SIZE / WRITE_SIZE --pmc output and a --sites log (host only)")
+    ap.add_argument("--traffic-extra", metavar="CSV", help="third --pmc pass (EXTRA_COUNTERS) for --traffic-records")
+    ap.add_argument("--traffic-levels", default=None,
+                    help="comma-separated composite levels: records for every site there instead of the longest")
+    ap.add_argument("--traffic-sites", default=None, help="comma-separated site names for --traffic-levels")
     ap.add_argument("--relax", default="l1", choices=["l1", "cf"], help="l1-Jacobi order (natural / CF)")
     ap.add_argument("--coarsen", default="rs", choices=["rs", "hmis"])
     ap.add_argument("--interp", default="direct", choices=["direct", "ext+i"])
@@ -438,12 +479,18 @@ def main():
         print(summarize_pmc(args.summarize_pmc))
         return
     if args.traffic_records:
-        for rec in traffic_records(*args.traffic_records, workload=args.config):
+        lv = None if args.traffic_levels is None else {int(v) for v in args.traffic_levels.split(",")}
+        nm = None if args.traffic_sites is None else set(args.traffic_sites.split(","))
+        for rec in traffic_records(*args.traffic_records, workload=args.config, levels=lv, names=nm,
+                                   extra_csv=args.traffic_extra):
             path = os.path.join(ROOT, "profiles", f"traffic_{rec['site']}_l{rec['level']}_{args.config}.json")
             with open(path, "w") as fh:
                 json.dump(rec, fh, indent=1)
+            ex = rec.get("l1_l2_path")
             print(f"{path}: {rec['traffic_bytes'] / 1e6:.1f} MB traffic, {rec['algorithmic_bytes'] / 1e6:.1f} MB "
-                  f"algorithmic per launch")
+                  f"algorithmic per launch" + (f"; L2 latency {ex['l2_read_latency_cycles']} cycles, TA busy "
+                                               f"{ex['ta_busy_frac']}, waves waiting {ex['wave_wait_frac']}"
+                                               if ex else ""))
         return
     if args.gpus != 1:
         print(f"bench.py: the solver runs on one GPU (the multi-GPU exchange is a design only); --gpus {args.gpus} "

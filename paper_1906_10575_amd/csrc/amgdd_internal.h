@@ -165,6 +165,7 @@ struct Setup {
   // LDS bands of the composite operators (at most band_cap values per tile)
   bool bands = true;
   int band_cap = 8192;
+  int band_tile = 16;  // slices per tile (one workgroup of 64 band_tile threads)
   // AMG components: coarsen 0 = RS first pass, 1 = HMIS; interp 0 = direct,
   // 1 = extended+i
   int coarsen = 0, interp = 0;

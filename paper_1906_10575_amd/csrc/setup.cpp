@@ -371,12 +371,12 @@ Sell permuted_layout(const SellBuilder &src, int nrows, int lg, int step_log2, i
 // (all lengths 0: that tile gathers from memory).  colL[a] is the position of
 // entry a's column in its tile's band (0 for zero entries).  Returns the
 // largest band kept.
-int build_bands(Sell &S, int cap) {
+int build_bands(Sell &S, int cap, int ts) {
   const int ns = (int)S.sptr.size() - 1;
   S.colL.clear();
   S.tiles.clear();
   if (ns <= 0) return 0;
-  const int nt = (ns + 15) / 16;
+  const int nt = (ns + ts - 1) / ts;
   S.colL.assign(S.col.size(), 0);
   S.tiles.assign(8 * (size_t)nt, 0);
   std::vector<int> bmax(n_threads(), 0);
@@ -384,7 +384,7 @@ int build_bands(Sell &S, int cap) {
     std::vector<int> cs;
     std::vector<std::pair<int, int>> gaps;
     for (long long t = b; t < e; ++t) {
-      const int e0 = S.sptr[16 * t], e1 = S.sptr[std::min<long long>(ns, 16 * t + 16)];
+      const int e0 = S.sptr[(long long)ts * t], e1 = S.sptr[std::min<long long>(ns, (long long)ts * t + ts)];
       cs.clear();
       for (int a = e0; a < e1; ++a)
         if (S.val[a] != 0.0) cs.push_back(S.col[a]);
@@ -433,9 +433,9 @@ int build_bands(Sell &S, int cap) {
 
 // Check of build_bands: every nonzero entry of a banded tile decodes back to
 // its column through its window.
-bool bands_valid(const Sell &S, int cap) {
+bool bands_valid(const Sell &S, int cap, int ts) {
   const int ns = (int)S.sptr.size() - 1;
-  const int nt = (ns + 15) / 16;
+  const int nt = (ns + ts - 1) / ts;
   if (ns <= 0) return true;
   if (S.colL.size() != S.col.size() || S.tiles.size() != 8 * (size_t)nt) return false;
   std::atomic<bool> ok{true};
@@ -445,7 +445,7 @@ bool bands_valid(const Sell &S, int cap) {
       const int n = d[7];
       if (n == 0) continue;
       if (n > cap || d[4] < 0 || d[4] > d[5] || d[5] > d[6] || d[6] > d[7]) { ok = false; return; }
-      const int e0 = S.sptr[16 * t], e1 = S.sptr[std::min<long long>(ns, 16 * t + 16)];
+      const int e0 = S.sptr[(long long)ts * t], e1 = S.sptr[std::min<long long>(ns, (long long)ts * t + ts)];
       for (int a = e0; a < e1; ++a) {
         const int q = S.colL[a];
         if (q >= n) { ok = false; return; }
@@ -1769,19 +1769,19 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
         BatchLevel &B = S.lv[l];
         if (B.Rt.entries() > 0) {
           // the reordered restriction gathers from the finer level
-          B.rband_max = build_bands(B.Rt, S.band_cap);
-          if (!bands_valid(B.Rt, S.band_cap)) { err = "internal: LDS band check failed on level " + std::to_string(l); return ST_EINVAL; }
+          B.rband_max = build_bands(B.Rt, S.band_cap, S.band_tile);
+          if (!bands_valid(B.Rt, S.band_cap, S.band_tile)) { err = "internal: LDS band check failed on level " + std::to_string(l); return ST_EINVAL; }
         }
         if (B.A.entries() == 0) continue;
-        B.band_max = build_bands(B.A, S.band_cap);
-        if (!bands_valid(B.A, S.band_cap)) { err = "internal: LDS band check failed on level " + std::to_string(l); return ST_EINVAL; }
+        B.band_max = build_bands(B.A, S.band_cap, S.band_tile);
+        if (!bands_valid(B.A, S.band_cap, S.band_tile)) { err = "internal: LDS band check failed on level " + std::to_string(l); return ST_EINVAL; }
         if (verbose()) {
           long long nb = 0, sum = 0;
           const int nt = (int)B.A.tiles.size() / 8;
           for (int t = 0; t < nt; ++t)
             if (B.A.tiles[8 * t + 7]) { ++nb; sum += B.A.tiles[8 * t + 7]; }
           std::fprintf(stderr, "[amgdd setup] level %d LDS bands: %lld of %d tiles, %.2f values per row, largest %d (R: %d)\n",
-                       l, nb, nt, nb ? (double)sum / nb / (1024 >> B.A.lg) : 0.0, B.band_max, B.rband_max);
+                       l, nb, nt, nb ? (double)sum / nb / ((64 * S.band_tile) >> B.A.lg) : 0.0, B.band_max, B.rband_max);
         }
       }
     vlog("pack: LDS bands", tb);

@@ -71,7 +71,11 @@ def test_traffic_records_are_consistent_and_used_only_while_current():
         assert cal["write_factor"] == pytest.approx(cal["write_size_kib"] / cal["expected_kib"], abs=1e-4)
         t = (r["fetch_size_kib"] / cal["fetch_factor"] + r["write_size_kib"] / cal["write_factor"]) * 1024
         assert r["traffic_bytes"] == pytest.approx(t, rel=1e-3)
-        assert 0.95 <= r["traffic_bytes"] / r["algorithmic_bytes"] <= 1.25
+        # operator passes stay near their algorithmic bytes; the reordered
+        # interpolation and restriction rows carry slice padding (up to ~2.2x)
+        assert 0.95 <= r["traffic_bytes"] / r["algorithmic_bytes"] <= 2.5
+        if r["site"] in ("relax_post", "w", "down") and r["level"] <= 4:
+            assert r["traffic_bytes"] / r["algorithmic_bytes"] <= 1.2
         # bench.py finds the record for its launch site
         assert bench.measured_traffic(dom) == r["traffic_bytes"]
 
@@ -90,10 +94,11 @@ def test_traffic_records_from_counter_output(tmp_path):
     counters (256 MiB read and written), matched to the --sites log by kernel
     and workgroup count."""
     head = "Kernel_Name,Grid_Size,Workgroup_Size,Counter_Name,Counter_Value\n"
-    cal = "void at::native::vectorized_elementwise_kernel<4>(x),8388608,256,{c},{v}\n"
+    cal = '"void at::native::vectorized_elementwise_kernel<4, at::native::CUDAFunctorOnSelf_add<double> >(x)",8388608,256,{c},{v}\n'
+    fill = '"void at::native::vectorized_elementwise_kernel<4, at::native::FillFunctor<double> >(x)",8388608,256,{c},12.5\n'
     fetch = tmp_path / "f.csv"
     write = tmp_path / "w.csv"
-    fetch.write_text(head + cal.format(c="FETCH_SIZE", v=131072.0) +
+    fetch.write_text(head + cal.format(c="FETCH_SIZE", v=131072.0) + fill.format(c="FETCH_SIZE") +
                      '"void amgdd::dev::k_w<double, 256>(x)",11389696,256,FETCH_SIZE,1000000\n'
                      '"void amgdd::dev::k_w<double, 256>(x)",11389696,256,FETCH_SIZE,1100000\n'
                      '"void amgdd::dev::k_relax<double, 256>(x)",11389696,256,FETCH_SIZE,999\n')
@@ -108,3 +113,20 @@ def test_traffic_records_from_counter_output(tmp_path):
     # fetch factor 0.5: 1.05e6 KiB counted = 2.1e6 KiB read; write factor 1
     assert recs[0]["traffic_bytes"] == round((1.05e6 / 0.5 + 90000.0) * 1024)
     assert recs[0]["algorithmic_bytes"] == 4126.3e6 / 2
+    # every named site of chosen levels, with the third counter pass
+    extra = tmp_path / "x.csv"
+    rows = {"GRBM_GUI_ACTIVE": 800000, "TA_TA_BUSY": 256 * 50000, "TA_ADDR_STALLED_BY_TC_CYCLES": 256 * 10000,
+            "TCP_TCC_READ_REQ": 2000000, "TCP_TCC_READ_REQ_LATENCY": 1.6e9, "SQ_WAVES": 100,
+            "SQ_WAVE_CYCLES": 1000, "SQ_WAIT_INST_ANY": 400}
+    extra.write_text(head + "".join(f'"void amgdd::dev::k_w<double, 256>(x)",11389696,256,{k},{v}\n'
+                                    for k, v in rows.items()))
+    recs = bench.traffic_records(str(fetch), str(write), str(log), "cfg3", levels={1}, names={"w"},
+                                 extra_csv=str(extra))
+    assert [r["site"] for r in recs] == ["w"]
+    ex = recs[0]["l1_l2_path"]
+    assert ex["l2_read_latency_cycles"] == 800.0
+    assert ex["ta_busy_frac"] == pytest.approx(50000 / 100000, abs=1e-3)  # 800000 / 8 XCDs = 100000 cycles
+    assert ex["ta_stalled_by_l1_frac"] == pytest.approx(0.1, abs=1e-3)
+    assert ex["wave_wait_frac"] == 0.4
+    assert recs[0]["traffic_over_algorithmic"] == pytest.approx(recs[0]["traffic_bytes"] / recs[0]["algorithmic_bytes"],
+                                                                abs=1e-3)
