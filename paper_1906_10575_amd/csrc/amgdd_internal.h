@@ -70,6 +70,9 @@ struct ProblemHost {
 // i.e. each slice's columns lie in at most two windows of 32768 (a grid's
 // real rows and its ghost rows sit in different regions of the level).  col
 // is then emptied.
+// windows of an LDS band (the kernels read the same tile descriptor)
+constexpr int kBandWindows = 8;
+
 struct Sell {
   int nrows = 0;
   int lg = 0;
@@ -79,10 +82,11 @@ struct Sell {
   std::vector<double> val;
   std::vector<uint16_t> col16;
   std::vector<int> base;
-  // LDS bands (composite operators; see build_bands): 8 ints per tile of 16
-  // slices, and each entry's position in its tile's band
+  // LDS bands (composite operators; see build_bands): 2 kBandWindows ints per
+  // tile of 16 slices, and each entry's position in its tile's band
   std::vector<int> tiles;
   std::vector<uint16_t> colL;
+  std::vector<int> bidx;  // column lists of listed tiles
   long long entries() const { return sptr.empty() ? 0 : sptr.back(); }
   bool compressed() const { return !col16.empty(); }
 };
@@ -161,11 +165,11 @@ struct Setup {
   // separate reordered layouts of P and R for the level-synchronous passes
   // (see BatchLevel::Pt / Rt); the per-grid schedule keeps P and R
   bool tight = true;
-  int tight_window = 128;  // their sort windows (rows)
+  int tight_window = 256;    // their sort windows (rows): P
+  int tight_window_r = 512;  // R
   // LDS bands of the composite operators (at most band_cap values per tile)
   bool bands = true;
   int band_cap = 8192;
-  int band_tile = 16;  // slices per tile (one workgroup of 64 band_tile threads)
   // AMG components: coarsen 0 = RS first pass, 1 = HMIS; interp 0 = direct,
   // 1 = extended+i
   int coarsen = 0, interp = 0;

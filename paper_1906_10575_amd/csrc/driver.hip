@@ -109,10 +109,11 @@ struct DSell {
   long long entries = 0;
   unsigned short *colL = nullptr;  // LDS bands (composite operators)
   int *tiles = nullptr;
+  int *bidx = nullptr;
   int ntiles = 0;
   template <typename T>
   dev::SellD<T> as() const {
-    return dev::SellD<T>{sptr, col, (const T *)val, lg, col16, base, vlg, colL, tiles, ntiles};
+    return dev::SellD<T>{sptr, col, (const T *)val, lg, col16, base, vlg, colL, tiles, bidx, ntiles};
   }
 };
 
@@ -127,7 +128,6 @@ struct DLevel {
   int band_max = 0;
   bool rlds = false;  // same for the reordered restriction pass (w_{l-1}'s band)
   int rband_max = 0;
-  int band_wg = 1024;  // workgroup size of the LDS passes (one band tile)
   DSell A, P, R;
   // reordered P / R_{l-1} of the normal rows (Setup::tight): position k holds
   // row pperm[k] / rperm[k]; ppos / rpos are the inverse maps (per-grid tail)
@@ -300,7 +300,9 @@ struct amgdd_ctx {
     if (!s.tiles.empty()) {
       if ((st = upload(&d.colL, (const unsigned short *)s.colL.data(), s.colL.size()))) return st;
       if ((st = upload(&d.tiles, s.tiles.data(), s.tiles.size()))) return st;
-      d.ntiles = (int)(s.tiles.size() / 8);
+      if (!s.bidx.empty() && (st = upload(&d.bidx, s.bidx.data(), s.bidx.size()))) return st;
+      static_assert(kBandWindows == dev::BAND_WINDOWS, "tile descriptor layout");
+      d.ntiles = (int)(s.tiles.size() / (2 * kBandWindows));
     }
     return upload_vals(&d.val, s.val, as_float);
   }
@@ -342,9 +344,9 @@ inline int nblocks_wg(long long n, int wg) { return (int)((n + wg - 1) / wg); }
 #define WGK(K, T, wg) ((wg) == 1024 ? K<T, 1024> : (wg) == 512 ? K<T, 512> : K<T, 256>)
 // passes with the level's composite operator: 1024-thread workgroups staging
 // the gathered vector's LDS band when the level uses bands
-#define LK(K, T, wg) ((wg) == 512 ? K<T, 512, true> : K<T, 1024, true>)
-#define AK(K, T, B) ((B).lds ? LK(K, T, (B).band_wg) : WGK(K, T, (B).wg))
-inline int a_wg(const DLevel &B) { return B.lds ? B.band_wg : B.wg; }
+#define LK(K, T, vl) ((vl) == 2 ? K<T, dev::LDS_WG, 2> : (vl) == 1 ? K<T, dev::LDS_WG, 1> : K<T, dev::LDS_WG, 0>)
+#define AK(K, T, B) ((B).lds ? LK(K, T, (B).A.vlg) : WGK(K, T, (B).wg))
+inline int a_wg(const DLevel &B) { return B.lds ? dev::LDS_WG : B.wg; }
 template <typename T>
 size_t a_lds(const DLevel &B) { return B.lds ? (size_t)B.band_max * sizeof(T) : 0; }
 
@@ -398,13 +400,15 @@ amgdd_status upload_all(amgdd_ctx *h) {
     }
     D.band_max = B.band_max;
     D.rband_max = B.rband_max;
-    D.band_wg = 64 * S.band_tile;
     {
       int lim = 0;
       const bool ok = hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) == hipSuccess;
-      // bands that do not fit one workgroup's LDS: not used
-      if (!ok || (long long)D.band_max * (h->mixed() ? 4 : 8) > lim) D.band_max = 0;
-      if (!ok || (long long)D.rband_max * (h->mixed() ? 4 : 8) > lim) D.rband_max = 0;
+      // bands that do not fit one workgroup's LDS: not used; nor with
+      // four-wide FP64 steps (their LDS variant exceeds the register budget
+      // of two workgroups per CU)
+      if (!ok || (long long)D.band_max * (h->mixed() ? 4 : 8) > lim || (!h->mixed() && B.A.vlg == 2)) D.band_max = 0;
+      if (!ok || (long long)D.rband_max * (h->mixed() ? 4 : 8) > lim || (!h->mixed() && B.Rt.vlg == 2))
+        D.rband_max = 0;
     }
     {
       // measurement: AMGDD_LDS=1|0 stages the bands on every level that has
@@ -611,9 +615,9 @@ void enqueue_fac_down(amgdd_ctx *h, hipStream_t s, int *cur, int l, int first) {
     DLevel &Bp = h->L[l - 1];
     if (B.rperm) {
       // restriction in R's own row order, then the rest of the down pass at real rows
-      const int rwg = B.rlds ? B.band_wg : B.wg;
+      const int rwg = B.rlds ? dev::LDS_WG : B.wg;
       PLAUNCH(h, "restrict_s", l, B.nnzR_n * ent(B.Rt, w) + Bp.NBn * w + B.NBn * (w + 4.0) + (B.NBn - B.NRn) * w,
-              (B.rlds ? LK(dev::k_restrict_rows, T, B.band_wg) : WGK(dev::k_restrict_rows, T, B.wg)),
+              (B.rlds ? LK(dev::k_restrict_rows, T, B.Rt.vlg) : WGK(dev::k_restrict_rows, T, B.wg)),
               nblocks_wg((long long)B.NBn << B.Rt.lg, rwg), rwg, B.rlds ? (size_t)B.rband_max * sizeof(T) : 0, s,
               B.Rt.as<T>(), B.rperm, B.NBn, B.NRn, (const T *)Bp.sw, (T *)B.sw, uout);
       PLAUNCH(h, "down", l, (first ? 0.0 : B.nnzA_r * ent(B.A, w) + B.NBn * w) + B.NRn * ((first ? 4.0 : 5.0) + 2.0) * w + (cf ? B.NRn : 0),
@@ -1453,8 +1457,8 @@ amgdd_status make_handle(const std::vector<ProblemInput> &in, const amgdd_params
   if (const char *e = std::getenv("AMGDD_SORT_WINDOW")) h->S.sort_window = std::max(0, std::atoi(e));
   if (const char *e = std::getenv("AMGDD_LANE_TARGET")) h->S.comp_lane_target = std::max(1.0, std::atof(e));
   if (std::getenv("AMGDD_FUSED_R")) h->S.tight = false;
-  if (const char *e = std::getenv("AMGDD_TIGHT_WINDOW")) h->S.tight_window = std::max(0, std::atoi(e));
-  if (const char *e = std::getenv("AMGDD_BAND_TILE")) h->S.band_tile = std::atoi(e) == 8 ? 8 : 16;
+  if (const char *e = std::getenv("AMGDD_TIGHT_WINDOW")) h->S.tight_window = h->S.tight_window_r = std::max(0, std::atoi(e));
+  if (const char *e = std::getenv("AMGDD_TIGHT_WINDOW_R")) h->S.tight_window_r = std::max(0, std::atoi(e));
   std::string err;
   Setup inner_S;
   int st;

@@ -48,6 +48,7 @@ namespace dev {
 
 constexpr int BLOCK = 256;
 constexpr int NXCD = 8;
+constexpr int BAND_WINDOWS = 8;  // windows of an LDS band (see SellD)
 
 #ifndef AMGDD_UNROLL
 #define AMGDD_UNROLL 4
@@ -71,11 +72,14 @@ struct SellD {
   const int *base;
   int vlg;  // log2 entries per lane in the widest steps (see sell_dotw)
   // LDS bands (composite operators): tile t = the 16 slices [16t, 16t + 16),
-  // one 1024-thread workgroup; tiles[8t .. 8t+3] window starts, [8t+4 ..
-  // 8t+7] cumulative window lengths (0: no band); colL = each entry's
-  // position in its tile's band
+  // one 1024-thread workgroup; with W = BAND_WINDOWS, tiles[2Wt .. 2Wt+W-1]
+  // window starts, [2Wt+W .. 2Wt+2W-1] cumulative window lengths (the last
+  // one is the band size); a first start -1 - o < 0 marks a listed tile
+  // whose band is bidx[o .. o + size); colL = each entry's position in its
+  // tile's band
   const unsigned short *colL;
   const int *tiles;
+  const int *bidx;
   int ntiles;
 };
 
@@ -110,8 +114,7 @@ __device__ __forceinline__ V group_sum(V acc, int lg) {
 // share, i.e. entries jW .. jW + W-1 of the row): one W-wide value load
 // (16 bytes for two FP64 or four FP32 values) and one W-wide load of 16-bit
 // indices per lane and step.  Each lane accumulates in storage order.
-// L: x is the tile's band in LDS and the columns are band positions (colL).
-template <typename T, typename V, int VL, bool L = false>
+template <typename T, typename V, int VL>
 __device__ __forceinline__ V sell_dotw(const SellD<T> &M, int s, int beg, int r, int sub, const V *__restrict__ x) {
   constexpr int W = 1 << VL;
   typedef T TW __attribute__((ext_vector_type(W)));
@@ -131,11 +134,10 @@ __device__ __forceinline__ V sell_dotw(const SellD<T> &M, int s, int beg, int r,
   constexpr int U = AMGDD_UNROLL / W > 0 ? AMGDD_UNROLL / W : 1;  // steps in flight
   V acc = V(0);
   int k = 0;
-  if (L || M.col16) {
-    const unsigned short *__restrict__ C16 = L ? M.colL : M.col16;
-    const CW *__restrict__ c = (const CW *)(C16 + beg + W * p);
-    const int b0 = L ? 0 : M.base[2 * s], b1 = L ? 0 : M.base[2 * s + 1];
-    auto dec = [&](unsigned short q) { return L ? (int)q : ((q & 0x8000) ? b1 : b0) + (int)(q & 0x7fff); };
+  if (M.col16) {
+    const CW *__restrict__ c = (const CW *)(M.col16 + beg + W * p);
+    const int b0 = M.base[2 * s], b1 = M.base[2 * s + 1];
+    auto dec = [&](unsigned short q) { return ((q & 0x8000) ? b1 : b0) + (int)(q & 0x7fff); };
     if (k + U <= w) {
       CW cn[U];
       TW vn[U];
@@ -177,14 +179,14 @@ __device__ __forceinline__ V sell_dotw(const SellD<T> &M, int s, int beg, int r,
       for (int e = 0; e < W; ++e) acc = fma((V)vq[e], xx[e], acc);
     }
     if (has2) {
-      const C2 cq = __builtin_nontemporal_load((const C2 *)(C16 + off2 + 2 * p));
+      const C2 cq = __builtin_nontemporal_load((const C2 *)(M.col16 + off2 + 2 * p));
       const T2 vq = __builtin_nontemporal_load((const T2 *)(M.val + off2 + 2 * p));
       const V x0 = x[dec(cq.x)], x1 = x[dec(cq.y)];
       acc = fma((V)vq.x, x0, acc);
       acc = fma((V)vq.y, x1, acc);
     }
     if (u & 1)
-      acc = fma((V)__builtin_nontemporal_load(M.val + off1 + p), x[dec(__builtin_nontemporal_load(C16 + off1 + p))], acc);
+      acc = fma((V)__builtin_nontemporal_load(M.val + off1 + p), x[dec(__builtin_nontemporal_load(M.col16 + off1 + p))], acc);
   } else {
     const IW *__restrict__ c = (const IW *)(M.col + beg + W * p);
     for (; k + U <= w; k += U) {
@@ -231,15 +233,14 @@ __device__ __forceinline__ V sell_dotw(const SellD<T> &M, int s, int beg, int r,
 // full sum.
 // ALIGNED: the wavefront lies in one slice (threads assigned 64-aligned), so
 // the slice bounds are wave-uniform scalars.
-// L: x is the tile's band in LDS, read through colL (see stage_band).
-template <typename T, typename V, bool ALIGNED = true, bool L = false>
+template <typename T, typename V, bool ALIGNED = true>
 __device__ __forceinline__ V sell_dot(const SellD<T> &M, int r, int sub, const V *__restrict__ x) {
   const int lg = M.lg;
   int s = r >> (6 - lg);
   if (ALIGNED) s = __builtin_amdgcn_readfirstlane(s);
   const int beg = M.sptr[s];
-  if (M.vlg == 1) return sell_dotw<T, V, 1, L>(M, s, beg, r, sub, x);
-  if (M.vlg == 2) return sell_dotw<T, V, 2, L>(M, s, beg, r, sub, x);
+  if (M.vlg == 1) return sell_dotw<T, V, 1>(M, s, beg, r, sub, x);
+  if (M.vlg == 2) return sell_dotw<T, V, 2>(M, s, beg, r, sub, x);
   const int w = (M.sptr[s + 1] - beg) >> 6;
   const int off = beg + ((r & ((64 >> lg) - 1)) << lg) + sub;
   const T *__restrict__ v = M.val + off;
@@ -250,10 +251,10 @@ __device__ __forceinline__ V sell_dot(const SellD<T> &M, int r, int sub, const V
   // U entries in flight per lane: all index and value loads of a group are
   // issued before its gathers; the sum stays in storage order.
   constexpr int U = AMGDD_UNROLL;
-  if (L || M.col16) {
-    const unsigned short *__restrict__ c = (L ? M.colL : M.col16) + off;
-    const int b0 = L ? 0 : M.base[2 * s], b1 = L ? 0 : M.base[2 * s + 1];
-    auto dec = [&](unsigned short q) { return L ? (int)q : ((q & 0x8000) ? b1 : b0) + (int)(q & 0x7fff); };
+  if (M.col16) {
+    const unsigned short *__restrict__ c = M.col16 + off;
+    const int b0 = M.base[2 * s], b1 = M.base[2 * s + 1];
+    auto dec = [&](unsigned short q) { return ((q & 0x8000) ? b1 : b0) + (int)(q & 0x7fff); };
 #if AMGDD_PIPE
     // software pipelined: the next group's index / value loads are issued
     // before this group's gathers
@@ -326,34 +327,137 @@ __device__ __forceinline__ bool relaxes(const signed char *__restrict__ cls, int
   return cls == nullptr || cls[i] == want;
 }
 
-// LDS band of the workgroup's tile (1024-thread workgroups of an operator with
-// bands): copies the tile's windows of x into `band` (coalesced loads) and
-// returns true, or returns false when the tile has no band (it then gathers
-// from memory).  The result is the same for every thread of the workgroup,
-// and so is the barrier.
-template <typename T, int WG>
-__device__ __forceinline__ bool stage_band(const SellD<T> &A, const T *__restrict__ x, T *band) {
-  const int tile = xcd_block();
-  if (tile >= A.ntiles) return false;
-  const int *d = A.tiles + 8 * tile;
-  const int n = d[7];
-  if (n == 0) return false;
-  const int lo0 = d[0], lo1 = d[1], lo2 = d[2], lo3 = d[3], e0 = d[4], e1 = d[5], e2 = d[6];
-  for (int k = threadIdx.x; k < n; k += WG)
-    band[k] = x[k < e0 ? lo0 + k : k < e1 ? lo1 + (k - e0) : k < e2 ? lo2 + (k - e1) : lo3 + (k - e2)];
-  __syncthreads();
-  return true;
-}
-
 extern __shared__ double lds_band[];
 
-// Row i of A times x: from the staged band when `staged`, else from memory.
-template <typename T, bool LDS>
-__device__ __forceinline__ T a_dot(const SellD<T> &A, int i, int sub, const T *__restrict__ x, bool staged) {
-  if constexpr (LDS)
-    if (staged) return sell_dot<T, T, true, true>(A, i, sub, (const T *)lds_band);
-  return sell_dot<T, T>(A, i, sub, x);
+// LDS variants (template argument LV = the operator's step width, >= 0):
+// 1024-thread workgroups, one tile of 16 slices each, compiled for two
+// workgroups per CU (8 waves per SIMD, at most 64 VGPRs) so that one
+// workgroup's staging phase overlaps the other's mat-vec.  They are used only
+// on levels every tile of which has a band (and the tile's descriptor is
+// A.tiles + 8 * tile).
+constexpr int LDS_WAVES = 8;
+constexpr int LDS_WG = 1024;
+
+// Row r of M times x through the tile's band.  Every thread of the workgroup
+// calls it (it holds the workgroup barrier); `act` says whether the calling
+// lane's row needs the product (the G lanes of a row agree).  The row's first
+// group of index / value loads is issued before the band is copied into LDS
+// (coalesced loads of its windows of x), so the two latencies overlap; the
+// entries are then gathered from LDS through their band positions (colL).
+// Same accumulation order as sell_dot / sell_dotw: each lane adds its
+// entries in storage order, then the group's xor tree.
+template <typename T, int WG, int VL>
+__device__ __forceinline__ T lds_dot(const SellD<T> &M, int r, int sub, bool act, const T *__restrict__ x) {
+  constexpr int NW = BAND_WINDOWS;
+  const int *__restrict__ d = M.tiles + 2 * NW * xcd_block();
+  // a tile without nonzero entries: every product is +0 (as the sum of zero
+  // terms from +0 is), no staging
+  if (d[2 * NW - 1] == 0) return T(0);
+  constexpr int W = 1 << VL;
+  typedef T TW __attribute__((ext_vector_type(W)));
+  typedef T T2 __attribute__((ext_vector_type(2)));
+  typedef unsigned short CW __attribute__((ext_vector_type(W)));
+  typedef unsigned short C2 __attribute__((ext_vector_type(2)));
+  // steps in flight (the gathers come from LDS: fewer than in sell_dotw, for
+  // the register budget of two workgroups per CU)
+  constexpr int U = sizeof(T) == 8 && W > 1 ? 1 : (AMGDD_UNROLL / W > 0 ? AMGDD_UNROLL / W : 1);
+  const int lg = M.lg;
+  const int s = __builtin_amdgcn_readfirstlane(r >> (6 - lg));
+  int w = 0, u = 0, off2 = 0, off1 = 0, has2 = 0, p = 0;
+  const CW *__restrict__ c = nullptr;
+  const TW *__restrict__ v = nullptr;
+  CW cn[U];
+  TW vn[U];
+  if (act) {
+    const int beg = M.sptr[s];
+    u = (M.sptr[s + 1] - beg) >> 6;
+    w = u >> VL;
+    p = ((r & ((64 >> lg) - 1)) << lg) + sub;
+    c = (const CW *)(M.colL + beg + W * p);
+    v = (const TW *)(M.val + beg + W * p);
+    off2 = beg + (w << (6 + VL));
+    has2 = VL == 2 ? (u >> 1) & 1 : 0;
+    off1 = off2 + (has2 << 7);
+    if (U <= w) {
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        cn[j] = __builtin_nontemporal_load(c + 64 * j);
+        vn[j] = __builtin_nontemporal_load(v + 64 * j);
+      }
+    }
+  }
+  // the band: windows [lo_k, lo_k + len_k) of x, back to back (window k
+  // holds band positions [end_{k-1}, end_k))
+  T *band = (T *)lds_band;
+  {
+    int lo[NW], end[NW];
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      lo[k] = d[k];
+      end[k] = d[NW + k];
+    }
+    const int n = end[NW - 1];
+    if (lo[0] < 0) {
+      const int *__restrict__ ix = M.bidx + (-1 - lo[0]);
+      for (int k = threadIdx.x; k < n; k += WG) band[k] = x[ix[k]];
+    } else {
+      for (int k = threadIdx.x; k < n; k += WG) {
+        int base = lo[0] + k;
+#pragma unroll
+        for (int q = 1; q < NW; ++q)
+          if (k >= end[q - 1]) base = lo[q] + (k - end[q - 1]);
+        band[k] = x[base];
+      }
+    }
+  }
+  __syncthreads();
+  T acc = T(0);
+  if (act) {
+    int k = 0;
+    if (U <= w) {
+      for (; k + U <= w; k += U) {
+        T vv[W * U], xx[W * U];
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+#pragma unroll
+          for (int e = 0; e < W; ++e) {
+            xx[W * j + e] = band[cn[j][e]];
+            vv[W * j + e] = vn[j][e];
+          }
+        if (k + 2 * U <= w) {
+#pragma unroll
+          for (int j = 0; j < U; ++j) {
+            cn[j] = __builtin_nontemporal_load(c + 64 * (k + U + j));
+            vn[j] = __builtin_nontemporal_load(v + 64 * (k + U + j));
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < W * U; ++j) acc = fma(vv[j], xx[j], acc);
+      }
+    }
+    for (; k < w; ++k) {
+      const CW cq = __builtin_nontemporal_load(c + 64 * k);
+      const TW vq = __builtin_nontemporal_load(v + 64 * k);
+      T xx[W];
+#pragma unroll
+      for (int e = 0; e < W; ++e) xx[e] = band[cq[e]];
+#pragma unroll
+      for (int e = 0; e < W; ++e) acc = fma(vq[e], xx[e], acc);
+    }
+    if (VL == 2 && has2) {
+      const C2 cq = __builtin_nontemporal_load((const C2 *)(M.colL + off2 + 2 * p));
+      const T2 vq = __builtin_nontemporal_load((const T2 *)(M.val + off2 + 2 * p));
+      const T x0 = band[cq.x], x1 = band[cq.y];
+      acc = fma(vq.x, x0, acc);
+      acc = fma(vq.y, x1, acc);
+    }
+    if (VL >= 1 && (u & 1))
+      acc = fma(__builtin_nontemporal_load(M.val + off1 + p), band[__builtin_nontemporal_load(M.colL + off1 + p)], acc);
+    acc = group_sum(acc, lg);
+  }
+  return acc;
 }
+
 
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
@@ -468,17 +572,26 @@ __global__ __launch_bounds__(BLOCK) void k_relax_zero(int nr, int nb, const T *_
 // null); other rows of [0, nb) are copied.
 // tmode: 0 t = delta (t = 0 at real rows of the other class), 1 t += delta,
 // 2 no t.
-// LDS: 1024-thread workgroups staging u_in's band of the tile (see stage_band).
-template <typename T, int WG = BLOCK, bool LDS = false>
-__global__ __launch_bounds__(WG) void k_relax(SellD<T> A, int nr, int nb, const T *__restrict__ f,
-                                                  const T *__restrict__ dinv, const T *__restrict__ u_in,
-                                                  T *__restrict__ u_out, T *__restrict__ t, int tmode,
-                                                  const signed char *__restrict__ cls, int want) {
+// LV >= 0: LDS variant staging u_in's band of the tile (see lds_dot).
+template <typename T, int WG = BLOCK, int LV = -1>
+__global__ __launch_bounds__(WG, LV >= 0 ? LDS_WAVES : 1) void k_relax(SellD<T> A, int nr, int nb,
+                                                                        const T *__restrict__ f,
+                                                                        const T *__restrict__ dinv,
+                                                                        const T *__restrict__ u_in,
+                                                                        T *__restrict__ u_out, T *__restrict__ t,
+                                                                        int tmode,
+                                                                        const signed char *__restrict__ cls,
+                                                                        int want) {
   const int th = thread_id_wg<WG>(), i = th >> A.lg, sub = th & ((1 << A.lg) - 1);
-  // tiles of rows >= nr relax nothing: no band
-  const bool staged = LDS && (xcd_block() * (WG >> A.lg) < nr) && stage_band<T, WG>(A, u_in, (T *)lds_band);
-  if (i < nr && relaxes(cls, want, i)) {
-    const T d = (f[i] - a_dot<T, LDS>(A, i, sub, u_in, staged)) * dinv[i];
+  const bool act = i < nr && relaxes(cls, want, i);
+  T au = T(0);
+  if constexpr (LV >= 0) {
+    // tiles of rows >= nr relax nothing: no staging
+    if (xcd_block() * (WG >> A.lg) < nr) au = lds_dot<T, WG, LV>(A, i, sub, act, u_in);
+  }
+  if (act) {
+    if constexpr (LV < 0) au = sell_dot<T, T>(A, i, sub, u_in);
+    const T d = (f[i] - au) * dinv[i];
     if (sub == 0) {
       u_out[i] = u_in[i] + d;
       if (tmode == 0) t[i] = d;
@@ -492,13 +605,14 @@ __global__ __launch_bounds__(WG) void k_relax(SellD<T> A, int nr, int nb, const 
 
 // w = s + A t over rows [0, nb), in place in the s buffer (s is absent on
 // level 0).  t is zero at ghost points, so ghost rows store real columns only.
-template <typename T, int WG = BLOCK, bool LDS = false>
-__global__ __launch_bounds__(WG) void k_w(SellD<T> A, int nb, T *__restrict__ sw, const T *__restrict__ t,
-                                              int has_s) {
+template <typename T, int WG = BLOCK, int LV = -1>
+__global__ __launch_bounds__(WG, LV >= 0 ? LDS_WAVES : 1) void k_w(SellD<T> A, int nb, T *__restrict__ sw,
+                                                                    const T *__restrict__ t, int has_s) {
   const int th = thread_id_wg<WG>(), i = th >> A.lg, sub = th & ((1 << A.lg) - 1);
-  const bool staged = LDS && stage_band<T, WG>(A, t, (T *)lds_band);
+  T at = T(0);
+  if constexpr (LV >= 0) at = lds_dot<T, WG, LV>(A, i, sub, i < nb, t);
   if (i < nb) {
-    const T at = a_dot<T, LDS>(A, i, sub, t, staged);
+    if constexpr (LV < 0) at = sell_dot<T, T>(A, i, sub, t);
     if (sub == 0) sw[i] = has_s ? sw[i] + at : at;
   }
 }
@@ -539,15 +653,18 @@ __global__ __launch_bounds__(WG) void k_down(SellD<T> R, SellD<T> A, int nr, int
 // perm[k]): s = R w_prev at every normal row (stored for the down and w
 // passes), and u = 0 at ghost rows [nr, nb) (the down pass then covers the
 // real rows only).
-// LDS: 1024-thread workgroups staging w_prev's band of the tile (see stage_band).
-template <typename T, int WG = BLOCK, bool LDS = false>
-__global__ __launch_bounds__(WG) void k_restrict_rows(SellD<T> Rt, const int *__restrict__ perm, int nb, int nr,
-                                                          const T *__restrict__ w_prev, T *__restrict__ sw,
-                                                          T *__restrict__ u_out) {
+// LV >= 0: LDS variant staging w_prev's band of the tile (see lds_dot).
+template <typename T, int WG = BLOCK, int LV = -1>
+__global__ __launch_bounds__(WG, LV >= 0 ? LDS_WAVES : 1) void k_restrict_rows(SellD<T> Rt,
+                                                                                const int *__restrict__ perm, int nb,
+                                                                                int nr, const T *__restrict__ w_prev,
+                                                                                T *__restrict__ sw,
+                                                                                T *__restrict__ u_out) {
   const int th = thread_id_wg<WG>(), k = th >> Rt.lg, sub = th & ((1 << Rt.lg) - 1);
-  const bool staged = LDS && stage_band<T, WG>(Rt, w_prev, (T *)lds_band);
+  T s = T(0);
+  if constexpr (LV >= 0) s = lds_dot<T, WG, LV>(Rt, k, sub, k < nb, w_prev);
   if (k < nb) {
-    const T s = a_dot<T, LDS>(Rt, k, sub, w_prev, staged);
+    if constexpr (LV < 0) s = sell_dot<T, T>(Rt, k, sub, w_prev);
     if (sub == 0) {
       const int i = perm[k];
       sw[i] = s;
@@ -560,16 +677,26 @@ __global__ __launch_bounds__(WG) void k_restrict_rows(SellD<T> Rt, const int *__
 // (k_restrict_rows): f <- (f - A u) - s (A u skipped in the first cycle),
 // u <- 0 and the first relaxation from zero (CF order: the C half).  Same
 // per-row arithmetic as k_down.
-template <typename T, int WG = BLOCK, bool LDS = false>
-__global__ __launch_bounds__(WG) void k_down_real(SellD<T> A, int nr, const T *__restrict__ sw, T *__restrict__ f,
-                                                      const T *__restrict__ dinv, const T *__restrict__ u_in,
-                                                      T *__restrict__ u_out, T *__restrict__ t, int first,
-                                                      const signed char *__restrict__ cls) {
+template <typename T, int WG = BLOCK, int LV = -1>
+__global__ __launch_bounds__(WG, LV >= 0 ? LDS_WAVES : 1) void k_down_real(SellD<T> A, int nr,
+                                                                            const T *__restrict__ sw,
+                                                                            T *__restrict__ f,
+                                                                            const T *__restrict__ dinv,
+                                                                            const T *__restrict__ u_in,
+                                                                            T *__restrict__ u_out,
+                                                                            T *__restrict__ t, int first,
+                                                                            const signed char *__restrict__ cls) {
   const int th = thread_id_wg<WG>(), i = th >> A.lg, sub = th & ((1 << A.lg) - 1);
-  const bool staged = LDS && !first && stage_band<T, WG>(A, u_in, (T *)lds_band);
+  T au = T(0);
+  if constexpr (LV >= 0) {
+    if (!first) au = lds_dot<T, WG, LV>(A, i, sub, i < nr, u_in);
+  }
   if (i < nr) {
     T fi = f[i];
-    if (!first) fi -= a_dot<T, LDS>(A, i, sub, u_in, staged);
+    if constexpr (LV < 0) {
+      if (!first) au = sell_dot<T, T>(A, i, sub, u_in);
+    }
+    if (!first) fi -= au;
     fi -= sw[i];
     if (sub == 0) {
       f[i] = fi;

@@ -363,27 +363,38 @@ Sell permuted_layout(const SellBuilder &src, int nrows, int lg, int step_log2, i
 
 // LDS bands of a composite operator, for its level-synchronous passes run in
 // 1024-thread workgroups that stage the gathered vector in LDS.  Tile t is
-// the 16 slices [16t, 16t + 16) (1024 >> lg rows, one workgroup).  Its band
-// is the set of columns of its nonzero entries, covered by at most four
-// windows: the span split at its three largest gaps.  tiles[8t .. 8t+3] are
-// the window starts, tiles[8t+4 .. 8t+7] the cumulative window lengths (the
-// last one is the band size); a band of more than `cap` values is dropped
-// (all lengths 0: that tile gathers from memory).  colL[a] is the position of
-// entry a's column in its tile's band (0 for zero entries).  Returns the
-// largest band kept.
-int build_bands(Sell &S, int cap, int ts) {
+// the 16 slices [16t, 16t + 16) (1024 threads, one workgroup).  Its band is
+// the set of columns of its nonzero entries, covered by at most kBandWindows
+// windows: the span split at its kBandWindows - 1 largest gaps.  With
+// W = kBandWindows, tiles[2W t .. 2W t + W-1] are the window starts and
+// tiles[2W t + W .. 2W t + 2W-1] the cumulative window lengths (the last one
+// is the band size, 0 for a tile without nonzero entries).  A tile whose
+// windows would exceed `cap` values (rows that touch many scattered columns,
+// e.g. ghost rows along a grid's boundary) lists its distinct columns
+// instead: its first start is -1 - (offset of the list in bidx) and its
+// band is the list.  colL[a] is the position of entry a's column in its
+// tile's band (0 for zero entries).  Returns the largest band, or 0 with no
+// bands kept when some tile's list still exceeds `cap` (the layout's passes
+// then gather from memory).
+int build_bands(Sell &S, int cap) {
+  constexpr int ts = 16, W = kBandWindows;
   const int ns = (int)S.sptr.size() - 1;
   S.colL.clear();
   S.tiles.clear();
+  S.bidx.clear();
   if (ns <= 0) return 0;
   const int nt = (ns + ts - 1) / ts;
   S.colL.assign(S.col.size(), 0);
-  S.tiles.assign(8 * (size_t)nt, 0);
+  S.tiles.assign(2 * W * (size_t)nt, 0);
   std::vector<int> bmax(n_threads(), 0);
+  std::atomic<bool> over{false};
+  // listed tiles: (tile, its distinct columns), per thread, placed in bidx
+  // in tile order afterwards
+  std::vector<std::vector<std::pair<long long, std::vector<int>>>> lists(n_threads());
   parallel_for(nt, [&](long long b, long long e, int tid) {
     std::vector<int> cs;
     std::vector<std::pair<int, int>> gaps;
-    for (long long t = b; t < e; ++t) {
+    for (long long t = b; t < e && !over.load(std::memory_order_relaxed); ++t) {
       const int e0 = S.sptr[(long long)ts * t], e1 = S.sptr[std::min<long long>(ns, (long long)ts * t + ts)];
       cs.clear();
       for (int a = e0; a < e1; ++a)
@@ -394,7 +405,7 @@ int build_bands(Sell &S, int cap, int ts) {
       gaps.clear();
       for (size_t k = 1; k < cs.size(); ++k)
         if (cs[k] - cs[k - 1] > 1) gaps.push_back({cs[k] - cs[k - 1], (int)k});
-      const size_t ng = std::min<size_t>(3, gaps.size());
+      const size_t ng = std::min<size_t>(W - 1, gaps.size());
       std::partial_sort(gaps.begin(), gaps.begin() + ng, gaps.end(),
                         [](const std::pair<int, int> &x, const std::pair<int, int> &y) {
                           return x.first > y.first || (x.first == y.first && x.second < y.second);
@@ -402,7 +413,7 @@ int build_bands(Sell &S, int cap, int ts) {
       std::vector<int> cut;  // first index in cs of windows 1..
       for (size_t k = 0; k < ng; ++k) cut.push_back(gaps[k].second);
       std::sort(cut.begin(), cut.end());
-      int lo[4] = {0, 0, 0, 0}, end[4] = {0, 0, 0, 0};
+      int lo[W] = {}, end[W] = {};
       int first = 0, acc = 0;
       for (size_t w = 0; w <= cut.size(); ++w) {
         const int last = (w < cut.size() ? cut[w] : (int)cs.size()) - 1;
@@ -411,47 +422,84 @@ int build_bands(Sell &S, int cap, int ts) {
         end[w] = acc;
         first = last + 1;
       }
-      for (size_t w = cut.size() + 1; w < 4; ++w) end[w] = acc;
-      if (acc > cap) continue;
-      int *d = &S.tiles[8 * (size_t)t];
-      for (int w = 0; w < 4; ++w) {
+      for (size_t w = cut.size() + 1; w < (size_t)W; ++w) end[w] = acc;
+      int *d = &S.tiles[2 * W * (size_t)t];
+      if (acc > cap) {
+        const int n = (int)cs.size();
+        if (n > cap) {
+          over = true;
+          return;
+        }
+        for (int w = 0; w < W; ++w) d[W + w] = n;
+        bmax[tid] = std::max(bmax[tid], n);
+        for (int a = e0; a < e1; ++a)
+          if (S.val[a] != 0.0) S.colL[a] = (uint16_t)(std::lower_bound(cs.begin(), cs.end(), S.col[a]) - cs.begin());
+        lists[tid].push_back({t, cs});
+        continue;
+      }
+      for (int w = 0; w < W; ++w) {
         d[w] = lo[w];
-        d[4 + w] = end[w];
+        d[W + w] = end[w];
       }
       bmax[tid] = std::max(bmax[tid], acc);
       for (int a = e0; a < e1; ++a) {
         if (S.val[a] == 0.0) continue;
         const int c = S.col[a];
-        int w = 3;
+        int w = W - 1;
         while (w > 0 && (end[w - 1] == end[w] || c < lo[w])) --w;
         S.colL[a] = (uint16_t)((w ? end[w - 1] : 0) + c - lo[w]);
       }
     }
   }, 1);
+  if (over) {
+    std::vector<uint16_t>().swap(S.colL);
+    std::vector<int>().swap(S.tiles);
+    return 0;
+  }
+  std::vector<std::pair<long long, std::vector<int>>> all;
+  for (auto &v : lists)
+    for (auto &x : v) all.push_back(std::move(x));
+  std::sort(all.begin(), all.end(), [](const auto &x, const auto &y) { return x.first < y.first; });
+  for (auto &x : all) {
+    S.tiles[2 * W * (size_t)x.first] = -1 - (int)S.bidx.size();
+    S.bidx.insert(S.bidx.end(), x.second.begin(), x.second.end());
+  }
   return *std::max_element(bmax.begin(), bmax.end());
 }
 
 // Check of build_bands: every nonzero entry of a banded tile decodes back to
-// its column through its window.
-bool bands_valid(const Sell &S, int cap, int ts) {
+// its column through its window, and every entry's position lies in the band.
+bool bands_valid(const Sell &S, int cap) {
+  constexpr int ts = 16, W = kBandWindows;
   const int ns = (int)S.sptr.size() - 1;
+  if (S.tiles.empty()) return S.colL.empty();
   const int nt = (ns + ts - 1) / ts;
   if (ns <= 0) return true;
-  if (S.colL.size() != S.col.size() || S.tiles.size() != 8 * (size_t)nt) return false;
+  if (S.colL.size() != S.col.size() || S.tiles.size() != 2 * W * (size_t)nt) return false;
   std::atomic<bool> ok{true};
   parallel_for(nt, [&](long long b, long long e, int) {
     for (long long t = b; t < e; ++t) {
-      const int *d = &S.tiles[8 * (size_t)t];
-      const int n = d[7];
+      const int *d = &S.tiles[2 * W * (size_t)t];
+      const int n = d[2 * W - 1];
       if (n == 0) continue;
-      if (n > cap || d[4] < 0 || d[4] > d[5] || d[5] > d[6] || d[6] > d[7]) { ok = false; return; }
+      if (n > cap || d[W] < 0) { ok = false; return; }
+      for (int w = 1; w < W; ++w)
+        if (d[W + w - 1] > d[W + w]) { ok = false; return; }
+      const bool listed = d[0] < 0;
+      const long long off = listed ? -1LL - d[0] : 0;
+      if (listed && (off + n > (long long)S.bidx.size() || d[W] != n)) { ok = false; return; }
       const int e0 = S.sptr[(long long)ts * t], e1 = S.sptr[std::min<long long>(ns, (long long)ts * t + ts)];
       for (int a = e0; a < e1; ++a) {
         const int q = S.colL[a];
         if (q >= n) { ok = false; return; }
         if (S.val[a] == 0.0) continue;
-        const int w = q < d[4] ? 0 : q < d[5] ? 1 : q < d[6] ? 2 : 3;
-        if (d[w] + q - (w ? d[3 + w] : 0) != S.col[a]) { ok = false; return; }
+        if (listed) {
+          if (S.bidx[off + q] != S.col[a]) { ok = false; return; }
+          continue;
+        }
+        int w = 0;
+        while (q >= d[W + w]) ++w;
+        if (d[w] + q - (w ? d[W + w - 1] : 0) != S.col[a]) { ok = false; return; }
       }
     }
   }, 1);
@@ -1600,7 +1648,7 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
           for (int J = 0; J < std::max(1, S.grids[g].lv[l + 1].nbar()); ++J) own[bidx(g, l + 1, J)] = bidx(g, l, 0);
         });
         Bn.rlg = lanes_log2((double)Bn.nnzR_n / Bn.NBn, S.comp_lane_target);
-        Bn.Rt = permuted_layout(bR, Bn.NBn, Bn.rlg, S.comp_step_log2, S.tight_window, own, Bn.rperm);
+        Bn.Rt = permuted_layout(bR, Bn.NBn, Bn.rlg, S.comp_step_log2, S.tight_window_r, own, Bn.rperm);
       }
       Bn.R = bR.take();
     }
@@ -1769,19 +1817,19 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
         BatchLevel &B = S.lv[l];
         if (B.Rt.entries() > 0) {
           // the reordered restriction gathers from the finer level
-          B.rband_max = build_bands(B.Rt, S.band_cap, S.band_tile);
-          if (!bands_valid(B.Rt, S.band_cap, S.band_tile)) { err = "internal: LDS band check failed on level " + std::to_string(l); return ST_EINVAL; }
+          B.rband_max = build_bands(B.Rt, S.band_cap);
+          if (!bands_valid(B.Rt, S.band_cap)) { err = "internal: LDS band check failed on level " + std::to_string(l); return ST_EINVAL; }
         }
         if (B.A.entries() == 0) continue;
-        B.band_max = build_bands(B.A, S.band_cap, S.band_tile);
-        if (!bands_valid(B.A, S.band_cap, S.band_tile)) { err = "internal: LDS band check failed on level " + std::to_string(l); return ST_EINVAL; }
+        B.band_max = build_bands(B.A, S.band_cap);
+        if (!bands_valid(B.A, S.band_cap)) { err = "internal: LDS band check failed on level " + std::to_string(l); return ST_EINVAL; }
         if (verbose()) {
           long long nb = 0, sum = 0;
-          const int nt = (int)B.A.tiles.size() / 8;
+          const int nt = (int)B.A.tiles.size() / (2 * kBandWindows);
           for (int t = 0; t < nt; ++t)
-            if (B.A.tiles[8 * t + 7]) { ++nb; sum += B.A.tiles[8 * t + 7]; }
+            if (const int n = B.A.tiles[2 * kBandWindows * t + 2 * kBandWindows - 1]) { ++nb; sum += n; }
           std::fprintf(stderr, "[amgdd setup] level %d LDS bands: %lld of %d tiles, %.2f values per row, largest %d (R: %d)\n",
-                       l, nb, nt, nb ? (double)sum / nb / ((64 * S.band_tile) >> B.A.lg) : 0.0, B.band_max, B.rband_max);
+                       l, nb, nt, nb ? (double)sum / nb / (1024 >> B.A.lg) : 0.0, B.band_max, B.rband_max);
         }
       }
     vlog("pack: LDS bands", tb);
