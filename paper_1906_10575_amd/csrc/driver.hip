@@ -1164,6 +1164,33 @@ amgdd_status autotune(amgdd_ctx *h) {
       set_modes(cur);
     }
   }
+  // last, the neighbouring cut levels (and tail workgroup sizes) again, now
+  // with the chosen modes: faster level-synchronous passes can move the best
+  // cut (the current schedule is timed alternately with them, twice each)
+  if (h->prm.tail_level < -1 && best_l >= 0) {
+    std::vector<std::pair<int, int>> cand = {{best_l, best_b}};
+    for (int lt : {best_l - 1, best_l + 1})
+      if (lt >= 0 && lt < nlev)
+        for (int bs : blocks) cand.push_back({lt, bs});
+    if (best_l + 1 >= nlev) cand.push_back({-1, blocks[0]});
+    std::vector<double> t(cand.size(), 1e300);
+    for (int rep = 0; rep < 2; ++rep)
+      for (size_t c = 0; c < cand.size(); ++c) {
+        h->sched_level = cand[c].first;
+        h->sched_block = cand[c].second;
+        double ms = 0;
+        if ((st = time_iteration(ms))) return st;
+        t[c] = std::min(t[c], ms);
+      }
+    size_t bi = 0;
+    for (size_t c = 1; c < cand.size(); ++c)
+      if (t[c] < t[bi] && t[c] < t[0] * 0.999) bi = c;
+    best_l = cand[bi].first;
+    best_b = cand[bi].second;
+    best = t[bi];
+    h->sched_level = best_l;
+    h->sched_block = best_b;
+  }
   h->sched_cached = 0;
   HIP_TRY(hipMemcpyAsync(h->x, xsave, (size_t)h->N0 * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));

@@ -1851,12 +1851,14 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
         if (!B.pperm.empty()) {
           std::vector<int> po(B.pperm.size());
           for (size_t k = 0; k < po.size(); ++k) po[k] = cown[l][B.pperm[k]];
-          compress_columns(B.Pt, po, cown[l + 1]);
+          const bool okp = compress_columns(B.Pt, po, cown[l + 1]);
+          if (verbose()) std::fprintf(stderr, "[amgdd setup] level %d reordered P 16-bit columns %d\n", l, (int)okp);
         }
         if (!B.rperm.empty()) {
           std::vector<int> ro(B.rperm.size());
           for (size_t k = 0; k < ro.size(); ++k) ro[k] = cown[l][B.rperm[k]];
-          compress_columns(B.Rt, ro, cown[l - 1]);
+          const bool okr = compress_columns(B.Rt, ro, cown[l - 1]);
+          if (verbose()) std::fprintf(stderr, "[amgdd setup] level %d reordered R 16-bit columns %d\n", l, (int)okr);
         }
       }
       if (verbose())
