@@ -4,7 +4,9 @@ kept in local order (AMGDD_SORT_WINDOW), one, two or four entries per lane
 and load step (AMGDD_UNPAIRED, default, AMGDD_QUAD), lanes per composite row
 (AMGDD_LANE_TARGET), one or two streams per iteration (AMGDD_SERIAL), operator
 passes that gather from an LDS copy of their tile's band of the vector or
-from memory (AMGDD_LDS).
+from memory (AMGDD_LDS), the restriction fused into the down pass with the
+operator's rows or run over R in a row order of its own (AMGDD_FUSED_R), and
+the reordered P and R layouts' sort window (AMGDD_TIGHT_WINDOW).
 
 Index width changes neither the entries of a row nor the order in which each
 lane adds them (padding adds exact zeros), so iterates are bitwise identical
@@ -33,7 +35,7 @@ amgdd = pytest.importorskip("paper_1906_10575_amd.amgdd")
 
 DEV = "cuda:0"
 ENV = ("AMGDD_INDEX32", "AMGDD_SORT_WINDOW", "AMGDD_UNPAIRED", "AMGDD_QUAD", "AMGDD_SERIAL", "AMGDD_LANE_TARGET",
-       "AMGDD_WG", "AMGDD_LDS")
+       "AMGDD_WG", "AMGDD_LDS", "AMGDD_FUSED_R", "AMGDD_TIGHT_WINDOW")
 
 CASES = {
     "3d_20_var_eta2": lambda: make_problem((20, 18, 20), (2, 2, 3), eta=2, n_fac=2,
@@ -124,7 +126,8 @@ def test_every_layout_matches_the_oracle(name, monkeypatch):
     for env in ({}, {"AMGDD_SORT_WINDOW": "0"}, {"AMGDD_SORT_WINDOW": "32"}, {"AMGDD_UNPAIRED": "1"},
                 {"AMGDD_UNPAIRED": "1", "AMGDD_INDEX32": "1"}, {"AMGDD_QUAD": "1"}, {"AMGDD_QUAD": "1", "AMGDD_INDEX32": "1"},
                 {"AMGDD_LANE_TARGET": "6"}, {"AMGDD_LANE_TARGET": "40"}, {"AMGDD_LDS": "1"},
-                {"AMGDD_LDS": "1", "AMGDD_QUAD": "1"}):
+                {"AMGDD_LDS": "1", "AMGDD_QUAD": "1"}, {"AMGDD_FUSED_R": "1"}, {"AMGDD_FUSED_R": "1", "AMGDD_LDS": "1"},
+                {"AMGDD_TIGHT_WINDOW": "2048"}, {"AMGDD_TIGHT_WINDOW": "0", "AMGDD_LDS": "1"}):
         x, xv = _run(p, monkeypatch, env, iters=3)
         err = rel_inf(x, xo)
         errv = rel_inf(xv, xvo)
