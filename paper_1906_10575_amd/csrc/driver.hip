@@ -1094,29 +1094,20 @@ amgdd_status autotune(amgdd_ctx *h) {
     (void)hipGraphDestroy(gr);
     return AMGDD_OK;
   };
-  double best = 1e300;
-  int best_l = -1, best_b = 256;
-  set_modes(Modes{});
-  for (int lt : levels)
-    for (int bs : blocks) {
-      if (lt < 0 && bs != blocks[0]) continue;
-      h->sched_level = lt;
-      h->sched_block = bs;
-      double ms = 0;
-      if ((st = time_iteration(ms))) return st;
-      if (ms < best) { best = ms; best_l = lt; best_b = bs; }
-    }
-  h->sched_level = best_l;
-  h->sched_block = best_b;
-  // then, level by level, the modes of its level-synchronous passes: the
+  // first, level by level, the modes of its level-synchronous passes, with
+  // every level level-synchronous (or the cut fixed by the caller): the
   // current modes, 512-thread workgroups (more rows per workgroup share the L1
-  // cache's gathered vector lines) and LDS bands (the operator passes gather
-  // from LDS) are timed alternately, twice each, and a candidate is kept when
-  // its faster time beats the current one's by more than 0.1%.  Every mode
-  // computes the same sums in the same order.
+  // cache's gathered vector lines) and LDS bands (the operator passes and the
+  // restriction gather from LDS) are timed alternately, twice each, and a
+  // candidate is kept when its faster time beats the current one's by more
+  // than 0.1%.  Every mode computes the same sums in the same order.
+  const int mode_cut = levels.size() == 1 ? levels[0] : -1;
+  h->sched_level = mode_cut;
+  h->sched_block = blocks[0];
+  set_modes(Modes{});
   Modes cur;
   if (!h->wg_fixed || !h->lds_fixed) {
-    const int cut = best_l < 0 ? nlev : best_l;
+    const int cut = mode_cut < 0 ? nlev : mode_cut;
     for (int l = 0; l < std::min(cut, nlev) && l < 32; ++l) {
       if (h->L[l].NBn == 0) continue;
       const unsigned bit = 1u << l;
@@ -1160,37 +1151,23 @@ amgdd_status autotune(amgdd_ctx *h) {
         }
       }
       cur = cand[bi];
-      if (bi) best = t[bi];
       set_modes(cur);
     }
   }
-  // last, the neighbouring cut levels (and tail workgroup sizes) again, now
-  // with the chosen modes: faster level-synchronous passes can move the best
-  // cut (the current schedule is timed alternately with them, twice each)
-  if (h->prm.tail_level < -1 && best_l >= 0) {
-    std::vector<std::pair<int, int>> cand = {{best_l, best_b}};
-    for (int lt : {best_l - 1, best_l + 1})
-      if (lt >= 0 && lt < nlev)
-        for (int bs : blocks) cand.push_back({lt, bs});
-    if (best_l + 1 >= nlev) cand.push_back({-1, blocks[0]});
-    std::vector<double> t(cand.size(), 1e300);
-    for (int rep = 0; rep < 2; ++rep)
-      for (size_t c = 0; c < cand.size(); ++c) {
-        h->sched_level = cand[c].first;
-        h->sched_block = cand[c].second;
-        double ms = 0;
-        if ((st = time_iteration(ms))) return st;
-        t[c] = std::min(t[c], ms);
-      }
-    size_t bi = 0;
-    for (size_t c = 1; c < cand.size(); ++c)
-      if (t[c] < t[bi] && t[c] < t[0] * 0.999) bi = c;
-    best_l = cand[bi].first;
-    best_b = cand[bi].second;
-    best = t[bi];
-    h->sched_level = best_l;
-    h->sched_block = best_b;
-  }
+  // then the cut level and the tail's workgroup size under those modes
+  double best = 1e300;
+  int best_l = -1, best_b = blocks[0];
+  for (int lt : levels)
+    for (int bs : blocks) {
+      if (lt < 0 && bs != blocks[0]) continue;
+      h->sched_level = lt;
+      h->sched_block = bs;
+      double ms = 0;
+      if ((st = time_iteration(ms))) return st;
+      if (ms < best) { best = ms; best_l = lt; best_b = bs; }
+    }
+  h->sched_level = best_l;
+  h->sched_block = best_b;
   h->sched_cached = 0;
   HIP_TRY(hipMemcpyAsync(h->x, xsave, (size_t)h->N0 * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
