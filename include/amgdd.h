@@ -57,7 +57,7 @@
  *   AMGDD_FUSED_R         restriction fused into the down pass with the
  *                         operator's row order and lanes (no reordered P, R)
  *   AMGDD_TIGHT_WINDOW=n  sort window of the reordered P and R (defaults 256
- *                         for P, 1024 for R); AMGDD_TIGHT_WINDOW_R=n for R only
+ *                         for P, 512 for R); AMGDD_TIGHT_WINDOW_R=n for R only
  * and when a handle's schedule is tuned:
  *   AMGDD_TUNE_CACHE=path schedule cache file (JSON, one entry per line,
  *                         keyed by a hash of the layout, device and library

@@ -166,7 +166,7 @@ struct Setup {
   // (see BatchLevel::Pt / Rt); the per-grid schedule keeps P and R
   bool tight = true;
   int tight_window = 256;    // their sort windows (rows): P
-  int tight_window_r = 1024;  // R
+  int tight_window_r = 512;  // R
   // LDS bands of the composite operators (at most band_cap values per tile)
   bool bands = true;
   int band_cap = 8192;

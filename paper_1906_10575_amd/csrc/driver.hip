@@ -1079,35 +1079,56 @@ amgdd_status autotune(amgdd_ctx *h) {
   else enqueue_residual<double>(h, s, false);
   // host-clock time of three replays of one captured iteration (after one
   // warm replay) with the handle's current schedule
-  auto time_iteration = [&](double &ms) -> amgdd_status {
-    hipGraph_t gr = nullptr;
-    hipGraphExec_t ex = nullptr;
-    amgdd_status cs = capture(h, true, &gr, &ex);
-    if (cs) return cs;
+  // one captured iteration of the handle's current schedule, and the host-clock
+  // time of three replays of it (after one warm replay)
+  struct Captured {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t e = nullptr;
+    void drop() {
+      if (e) (void)hipGraphExecDestroy(e);
+      if (g) (void)hipGraphDestroy(g);
+      e = nullptr;
+      g = nullptr;
+    }
+  };
+  auto time_exec = [&](hipGraphExec_t ex, double &ms) -> amgdd_status {
     HIP_TRY(hipGraphLaunch(ex, s));
     HIP_TRY(hipStreamSynchronize(s));
     const double tc = now_s();
     for (int r = 0; r < 3; ++r) HIP_TRY(hipGraphLaunch(ex, s));
     HIP_TRY(hipStreamSynchronize(s));
     ms = (now_s() - tc) * 1e3;
-    (void)hipGraphExecDestroy(ex);
-    (void)hipGraphDestroy(gr);
     return AMGDD_OK;
   };
-  // first, level by level, the modes of its level-synchronous passes, with
-  // every level level-synchronous (or the cut fixed by the caller): the
-  // current modes, 512-thread workgroups (more rows per workgroup share the L1
-  // cache's gathered vector lines) and LDS bands (the operator passes and the
-  // restriction gather from LDS) are timed alternately, twice each, and a
-  // candidate is kept when its faster time beats the current one's by more
-  // than 0.1%.  Every mode computes the same sums in the same order.
-  const int mode_cut = levels.size() == 1 ? levels[0] : -1;
-  h->sched_level = mode_cut;
-  h->sched_block = blocks[0];
+  // first the cut level and the tail's workgroup size (default modes)
+  double best = 1e300;
+  int best_l = -1, best_b = 256;
   set_modes(Modes{});
+  for (int lt : levels)
+    for (int bs : blocks) {
+      if (lt < 0 && bs != blocks[0]) continue;
+      h->sched_level = lt;
+      h->sched_block = bs;
+      Captured c;
+      double ms = 0;
+      st = capture(h, true, &c.g, &c.e);
+      if (!st) st = time_exec(c.e, ms);
+      c.drop();
+      if (st) return st;
+      if (ms < best) { best = ms; best_l = lt; best_b = bs; }
+    }
+  h->sched_level = best_l;
+  h->sched_block = best_b;
+  // then, level by level above the cut, the modes of its level-synchronous
+  // passes: the current modes, 512-thread workgroups (more rows per workgroup
+  // share the L1 cache's gathered vector lines) and LDS bands (the operator
+  // passes and the restriction gather from LDS).  Each candidate is captured
+  // once; the captures are timed alternately, twice each, and a candidate is
+  // kept when its faster time beats the current one's by more than 0.1%.
+  // Every mode computes the same sums in the same order.
   Modes cur;
   if (!h->wg_fixed || !h->lds_fixed) {
-    const int cut = mode_cut < 0 ? nlev : mode_cut;
+    const int cut = best_l < 0 ? nlev : best_l;
     for (int l = 0; l < std::min(cut, nlev) && l < 32; ++l) {
       if (h->L[l].NBn == 0) continue;
       const unsigned bit = 1u << l;
@@ -1116,58 +1137,48 @@ amgdd_status autotune(amgdd_ctx *h) {
       if (!h->lds_fixed && h->L[l].band_max > 0) cand.push_back(Modes{cur.w, cur.a | bit, cur.r});
       if (!h->lds_fixed && h->L[l].rband_max > 0 && h->L[l].rperm) cand.push_back(Modes{cur.w, cur.a, cur.r | bit});
       if (cand.size() == 1) continue;
+      std::vector<Captured> cap(cand.size());
       std::vector<double> t(cand.size(), 1e300);
-      for (int rep = 0; rep < 2; ++rep)
-        for (size_t c = 0; c < cand.size(); ++c) {
-          double ms = 0;
+      auto time_all = [&](size_t from) -> amgdd_status {
+        for (size_t c = from; c < cand.size(); ++c) {
           set_modes(cand[c]);
-          if ((st = time_iteration(ms))) return st;
-          t[c] = std::min(t[c], ms);
+          amgdd_status cs = capture(h, true, &cap[c].g, &cap[c].e);
+          if (cs) return cs;
         }
-      size_t bi = 0;
-      for (size_t c = 1; c < cand.size(); ++c)
-        if (t[c] < t[bi] && t[c] < t[0] * 0.999) bi = c;
-      // a second mode of the same level on top of the first one's gain
-      if (bi) {
-        Modes both = cand[bi];
-        for (size_t c = 1; c < cand.size(); ++c)
-          if (c != bi && t[c] < t[0] * 0.999) both = Modes{both.w | cand[c].w, both.a | cand[c].a, both.r | cand[c].r};
-        if (both.w != cand[bi].w || both.a != cand[bi].a || both.r != cand[bi].r) {
-          double tb = 1e300, tc = 1e300;
-          for (int rep = 0; rep < 2; ++rep) {
+        for (int rep = 0; rep < 2; ++rep)
+          for (size_t c = 0; c < cand.size(); ++c) {
             double ms = 0;
-            set_modes(cand[bi]);
-            if ((st = time_iteration(ms))) return st;
-            tc = std::min(tc, ms);
-            set_modes(both);
-            if ((st = time_iteration(ms))) return st;
-            tb = std::min(tb, ms);
+            amgdd_status ts = time_exec(cap[c].e, ms);
+            if (ts) return ts;
+            t[c] = std::min(t[c], ms);
           }
-          t[bi] = tc;
-          if (tb < tc * 0.999) {
-            cand[bi] = both;
-            t[bi] = tb;
-          }
+        return AMGDD_OK;
+      };
+      st = time_all(0);
+      size_t bi = 0;
+      if (!st) {
+        for (size_t c = 1; c < cand.size(); ++c)
+          if (t[c] < t[bi] && t[c] < t[0] * 0.999) bi = c;
+        // one more candidate: the modes that beat the current one, together
+        Modes both = cand[bi];
+        for (size_t c = 1; bi && c < cand.size(); ++c)
+          if (c != bi && t[c] < t[0] * 0.999) both = Modes{both.w | cand[c].w, both.a | cand[c].a, both.r | cand[c].r};
+        if (bi && (both.w != cand[bi].w || both.a != cand[bi].a || both.r != cand[bi].r)) {
+          cand.push_back(both);
+          cap.emplace_back();
+          t.push_back(1e300);
+          for (double &x : t) x = 1e300;
+          st = time_all(cand.size() - 1);
+          if (!st && t.back() < t[bi] * 0.999 && t.back() < t[0] * 0.999) bi = cand.size() - 1;
         }
       }
+      for (auto &c : cap) c.drop();
+      if (st) return st;
       cur = cand[bi];
+      if (bi) best = t[bi];
       set_modes(cur);
     }
   }
-  // then the cut level and the tail's workgroup size under those modes
-  double best = 1e300;
-  int best_l = -1, best_b = blocks[0];
-  for (int lt : levels)
-    for (int bs : blocks) {
-      if (lt < 0 && bs != blocks[0]) continue;
-      h->sched_level = lt;
-      h->sched_block = bs;
-      double ms = 0;
-      if ((st = time_iteration(ms))) return st;
-      if (ms < best) { best = ms; best_l = lt; best_b = bs; }
-    }
-  h->sched_level = best_l;
-  h->sched_block = best_b;
   h->sched_cached = 0;
   HIP_TRY(hipMemcpyAsync(h->x, xsave, (size_t)h->N0 * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
