@@ -1130,7 +1130,10 @@ amgdd_status autotune(amgdd_ctx *h) {
   if (!h->wg_fixed || !h->lds_fixed) {
     const int cut = best_l < 0 ? nlev : best_l;
     for (int l = 0; l < std::min(cut, nlev) && l < 32; ++l) {
-      if (h->L[l].NBn == 0) continue;
+      // levels of fewer rows than this take a few microseconds per pass
+      // whichever mode they run in: not tuned
+      constexpr int kTuneMinRows = 32768;
+      if (h->L[l].NBn < kTuneMinRows) continue;
       const unsigned bit = 1u << l;
       std::vector<Modes> cand = {cur};
       if (!h->wg_fixed) cand.push_back(Modes{cur.w | bit, cur.a, cur.r});
