@@ -70,8 +70,11 @@ struct ProblemHost {
 // i.e. each slice's columns lie in at most two windows of 32768 (a grid's
 // real rows and its ghost rows sit in different regions of the level).  col
 // is then emptied.
-// windows of an LDS band (the kernels read the same tile descriptor)
+// windows of an LDS band and slices of an LDS tile (the kernels read the
+// same tile descriptors)
 constexpr int kBandWindows = 8;
+constexpr int kTileSlices = 32;   // operators
+constexpr int kTileSlicesR = 16;  // reordered restriction
 
 struct Sell {
   int nrows = 0;
@@ -83,7 +86,7 @@ struct Sell {
   std::vector<uint16_t> col16;
   std::vector<int> base;
   // LDS bands (composite operators; see build_bands): 2 kBandWindows ints per
-  // tile of 16 slices, and each entry's position in its tile's band
+  // tile of kTileSlices slices, and each entry's position in its tile's band
   std::vector<int> tiles;
   std::vector<uint16_t> colL;
   std::vector<int> bidx;  // column lists of listed tiles

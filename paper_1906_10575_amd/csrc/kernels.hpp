@@ -71,8 +71,9 @@ struct SellD {
   const unsigned short *col16;
   const int *base;
   int vlg;  // log2 entries per lane in the widest steps (see sell_dotw)
-  // LDS bands (composite operators): tile t = the 16 slices [16t, 16t + 16),
-  // one 1024-thread workgroup; with W = BAND_WINDOWS, tiles[2Wt .. 2Wt+W-1]
+  // LDS bands (composite operators): tile t = the TS slices from TS t on
+  // (TS = TILE_SLICES, TILE_SLICES_R for the restriction), one 1024-thread
+  // workgroup; with W = BAND_WINDOWS, tiles[2Wt .. 2Wt+W-1]
   // window starts, [2Wt+W .. 2Wt+2W-1] cumulative window lengths (the last
   // one is the band size); a first start -1 - o < 0 marks a listed tile
   // whose band is bidx[o .. o + size); colL = each entry's position in its
@@ -81,6 +82,7 @@ struct SellD {
   const int *tiles;
   const int *bidx;
   int ntiles;
+  int nslices;
 };
 
 // Workgroups are dispatched round-robin over the 8 XCDs; remap so that each
@@ -330,29 +332,27 @@ __device__ __forceinline__ bool relaxes(const signed char *__restrict__ cls, int
 extern __shared__ double lds_band[];
 
 // LDS variants (template argument LV = the operator's step width, >= 0):
-// 1024-thread workgroups, one tile of 16 slices each, compiled for two
-// workgroups per CU (8 waves per SIMD, at most 64 VGPRs) so that one
-// workgroup's staging phase overlaps the other's mat-vec.  They are used only
-// on levels every tile of which has a band (and the tile's descriptor is
-// A.tiles + 8 * tile).
+// 1024-thread workgroups (16 waves), one tile of TILE_SLICES (operator) or
+// TILE_SLICES_R (restriction) slices each,
+// compiled for two workgroups per CU (8 waves per SIMD, at most 64 VGPRs) so
+// that one workgroup's staging phase overlaps the other's mat-vecs.  The
+// workgroup copies its tile's band into LDS once, then each wave takes the
+// tile's slices one after another from a counter in LDS: slices of one tile
+// differ in length (rows are sorted by length in windows), and a wave that
+// finishes a short slice takes the next one instead of idling until the
+// longest is done.  They are used only on levels every tile of which has a
+// band.
 constexpr int LDS_WAVES = 8;
 constexpr int LDS_WG = 1024;
+constexpr int TILE_SLICES = 32;    // operator passes
+constexpr int TILE_SLICES_R = 16;  // restriction (its rows gather from the finer level)
 
-// Row r of M times x through the tile's band.  Every thread of the workgroup
-// calls it (it holds the workgroup barrier); `act` says whether the calling
-// lane's row needs the product (the G lanes of a row agree).  The row's first
-// group of index / value loads is issued before the band is copied into LDS
-// (coalesced loads of its windows of x), so the two latencies overlap; the
-// entries are then gathered from LDS through their band positions (colL).
-// Same accumulation order as sell_dot / sell_dotw: each lane adds its
-// entries in storage order, then the group's xor tree.
-template <typename T, int WG, int VL>
-__device__ __forceinline__ T lds_dot(const SellD<T> &M, int r, int sub, bool act, const T *__restrict__ x) {
-  constexpr int NW = BAND_WINDOWS;
-  const int *__restrict__ d = M.tiles + 2 * NW * xcd_block();
-  // a tile without nonzero entries: every product is +0 (as the sum of zero
-  // terms from +0 is), no staging
-  if (d[2 * NW - 1] == 0) return T(0);
+// Slice s of M (the calling wave's 64 lanes) times the band: row r, lane
+// `sub` of its group; entries gathered from LDS through their band
+// positions (colL).  Same accumulation order as sell_dot / sell_dotw: each
+// lane adds its entries in storage order, then the group's xor tree.
+template <typename T, int VL>
+__device__ __forceinline__ T lds_row_dot(const SellD<T> &M, int s, int r, int sub, const T *band) {
   constexpr int W = 1 << VL;
   typedef T TW __attribute__((ext_vector_type(W)));
   typedef T T2 __attribute__((ext_vector_type(2)));
@@ -362,46 +362,92 @@ __device__ __forceinline__ T lds_dot(const SellD<T> &M, int r, int sub, bool act
   // the register budget of two workgroups per CU)
   constexpr int U = sizeof(T) == 8 && W > 1 ? 1 : (AMGDD_UNROLL / W > 0 ? AMGDD_UNROLL / W : 1);
   const int lg = M.lg;
-  const int s = __builtin_amdgcn_readfirstlane(r >> (6 - lg));
-  int w = 0, u = 0, off2 = 0, off1 = 0, has2 = 0, p = 0;
-  const CW *__restrict__ c = nullptr;
-  const TW *__restrict__ v = nullptr;
-  CW cn[U];
-  TW vn[U];
-  if (act) {
-    const int beg = M.sptr[s];
-    u = (M.sptr[s + 1] - beg) >> 6;
-    w = u >> VL;
-    p = ((r & ((64 >> lg) - 1)) << lg) + sub;
-    c = (const CW *)(M.colL + beg + W * p);
-    v = (const TW *)(M.val + beg + W * p);
-    off2 = beg + (w << (6 + VL));
-    has2 = VL == 2 ? (u >> 1) & 1 : 0;
-    off1 = off2 + (has2 << 7);
-    if (U <= w) {
+  const int beg = M.sptr[s];
+  const int u = (M.sptr[s + 1] - beg) >> 6, w = u >> VL;
+  const int p = ((r & ((64 >> lg) - 1)) << lg) + sub;
+  const CW *__restrict__ c = (const CW *)(M.colL + beg + W * p);
+  const TW *__restrict__ v = (const TW *)(M.val + beg + W * p);
+  const int off2 = beg + (w << (6 + VL));
+  const int has2 = VL == 2 ? (u >> 1) & 1 : 0;
+  const int off1 = off2 + (has2 << 7);
+  T acc = T(0);
+  int k = 0;
+  if (U <= w) {
+    CW cn[U];
+    TW vn[U];
 #pragma unroll
-      for (int j = 0; j < U; ++j) {
-        cn[j] = __builtin_nontemporal_load(c + 64 * j);
-        vn[j] = __builtin_nontemporal_load(v + 64 * j);
+    for (int j = 0; j < U; ++j) {
+      cn[j] = __builtin_nontemporal_load(c + 64 * j);
+      vn[j] = __builtin_nontemporal_load(v + 64 * j);
+    }
+    for (; k + U <= w; k += U) {
+      T vv[W * U], xx[W * U];
+#pragma unroll
+      for (int j = 0; j < U; ++j)
+#pragma unroll
+        for (int e = 0; e < W; ++e) {
+          xx[W * j + e] = band[cn[j][e]];
+          vv[W * j + e] = vn[j][e];
+        }
+      if (k + 2 * U <= w) {
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+          cn[j] = __builtin_nontemporal_load(c + 64 * (k + U + j));
+          vn[j] = __builtin_nontemporal_load(v + 64 * (k + U + j));
+        }
       }
+#pragma unroll
+      for (int j = 0; j < W * U; ++j) acc = fma(vv[j], xx[j], acc);
     }
   }
-  // the band: windows [lo_k, lo_k + len_k) of x, back to back (window k
-  // holds band positions [end_{k-1}, end_k))
+  for (; k < w; ++k) {
+    const CW cq = __builtin_nontemporal_load(c + 64 * k);
+    const TW vq = __builtin_nontemporal_load(v + 64 * k);
+    T xx[W];
+#pragma unroll
+    for (int e = 0; e < W; ++e) xx[e] = band[cq[e]];
+#pragma unroll
+    for (int e = 0; e < W; ++e) acc = fma(vq[e], xx[e], acc);
+  }
+  if (VL == 2 && has2) {
+    const C2 cq = __builtin_nontemporal_load((const C2 *)(M.colL + off2 + 2 * p));
+    const T2 vq = __builtin_nontemporal_load((const T2 *)(M.val + off2 + 2 * p));
+    const T x0 = band[cq.x], x1 = band[cq.y];
+    acc = fma(vq.x, x0, acc);
+    acc = fma(vq.y, x1, acc);
+  }
+  if (VL >= 1 && (u & 1))
+    acc = fma(__builtin_nontemporal_load(M.val + off1 + p), band[__builtin_nontemporal_load(M.colL + off1 + p)], acc);
+  return group_sum(acc, lg);
+}
+
+// One LDS tile of TS slices (every thread of the workgroup calls it; it holds
+// the workgroup barrier): when `stage`, the tile's band of x is copied into LDS
+// (coalesced loads of its windows, or of its listed columns); then the waves
+// take the tile's slices from a counter and call op(r, sub, dot) for each
+// lane's row r (group lane `sub`), dot = row r of M times x (0 when the tile
+// is not staged or the slice lies beyond M).
+template <typename T, int VL, int TS, typename Op>
+__device__ __forceinline__ void lds_tile(const SellD<T> &M, const T *__restrict__ x, bool stage, Op op) {
+  constexpr int NW = BAND_WINDOWS;
+  __shared__ int next_slice;
+  const int tile = xcd_block(), lane = threadIdx.x & 63, lg = M.lg;
+  const int *__restrict__ d = M.tiles + 2 * NW * tile;
+  const int n = stage && tile < M.ntiles ? d[2 * NW - 1] : 0;
   T *band = (T *)lds_band;
-  {
+  if (threadIdx.x == 0) next_slice = 0;
+  if (n > 0) {
     int lo[NW], end[NW];
 #pragma unroll
     for (int k = 0; k < NW; ++k) {
       lo[k] = d[k];
       end[k] = d[NW + k];
     }
-    const int n = end[NW - 1];
     if (lo[0] < 0) {
       const int *__restrict__ ix = M.bidx + (-1 - lo[0]);
-      for (int k = threadIdx.x; k < n; k += WG) band[k] = x[ix[k]];
+      for (int k = threadIdx.x; k < n; k += LDS_WG) band[k] = x[ix[k]];
     } else {
-      for (int k = threadIdx.x; k < n; k += WG) {
+      for (int k = threadIdx.x; k < n; k += LDS_WG) {
         int base = lo[0] + k;
 #pragma unroll
         for (int q = 1; q < NW; ++q)
@@ -411,53 +457,20 @@ __device__ __forceinline__ T lds_dot(const SellD<T> &M, int r, int sub, bool act
     }
   }
   __syncthreads();
-  T acc = T(0);
-  if (act) {
-    int k = 0;
-    if (U <= w) {
-      for (; k + U <= w; k += U) {
-        T vv[W * U], xx[W * U];
-#pragma unroll
-        for (int j = 0; j < U; ++j)
-#pragma unroll
-          for (int e = 0; e < W; ++e) {
-            xx[W * j + e] = band[cn[j][e]];
-            vv[W * j + e] = vn[j][e];
-          }
-        if (k + 2 * U <= w) {
-#pragma unroll
-          for (int j = 0; j < U; ++j) {
-            cn[j] = __builtin_nontemporal_load(c + 64 * (k + U + j));
-            vn[j] = __builtin_nontemporal_load(v + 64 * (k + U + j));
-          }
-        }
-#pragma unroll
-        for (int j = 0; j < W * U; ++j) acc = fma(vv[j], xx[j], acc);
-      }
-    }
-    for (; k < w; ++k) {
-      const CW cq = __builtin_nontemporal_load(c + 64 * k);
-      const TW vq = __builtin_nontemporal_load(v + 64 * k);
-      T xx[W];
-#pragma unroll
-      for (int e = 0; e < W; ++e) xx[e] = band[cq[e]];
-#pragma unroll
-      for (int e = 0; e < W; ++e) acc = fma(vq[e], xx[e], acc);
-    }
-    if (VL == 2 && has2) {
-      const C2 cq = __builtin_nontemporal_load((const C2 *)(M.colL + off2 + 2 * p));
-      const T2 vq = __builtin_nontemporal_load((const T2 *)(M.val + off2 + 2 * p));
-      const T x0 = band[cq.x], x1 = band[cq.y];
-      acc = fma(vq.x, x0, acc);
-      acc = fma(vq.y, x1, acc);
-    }
-    if (VL >= 1 && (u & 1))
-      acc = fma(__builtin_nontemporal_load(M.val + off1 + p), band[__builtin_nontemporal_load(M.colL + off1 + p)], acc);
-    acc = group_sum(acc, lg);
+  for (;;) {
+    int sl = 0;
+    if (lane == 0) sl = atomicAdd(&next_slice, 1);
+    sl = __builtin_amdgcn_readfirstlane(__shfl(sl, 0));
+    if (sl >= TS) break;
+    const int s = tile * TS + sl;
+    const int r = s * (64 >> lg) + (lane >> lg), sub = lane & ((1 << lg) - 1);
+    T dot = T(0);
+    // a tile without nonzero entries: every product is +0 (as the sum of
+    // zero terms from +0 is)
+    if (n > 0 && s < M.nslices) dot = lds_row_dot<T, VL>(M, s, r, sub, band);
+    op(r, sub, dot);
   }
-  return acc;
 }
-
 
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
@@ -572,7 +585,7 @@ __global__ __launch_bounds__(BLOCK) void k_relax_zero(int nr, int nb, const T *_
 // null); other rows of [0, nb) are copied.
 // tmode: 0 t = delta (t = 0 at real rows of the other class), 1 t += delta,
 // 2 no t.
-// LV >= 0: LDS variant staging u_in's band of the tile (see lds_dot).
+// LV >= 0: LDS variant (see lds_tile).
 template <typename T, int WG = BLOCK, int LV = -1>
 __global__ __launch_bounds__(WG, LV >= 0 ? LDS_WAVES : 1) void k_relax(SellD<T> A, int nr, int nb,
                                                                         const T *__restrict__ f,
@@ -582,24 +595,28 @@ __global__ __launch_bounds__(WG, LV >= 0 ? LDS_WAVES : 1) void k_relax(SellD<T> 
                                                                         int tmode,
                                                                         const signed char *__restrict__ cls,
                                                                         int want) {
-  const int th = thread_id_wg<WG>(), i = th >> A.lg, sub = th & ((1 << A.lg) - 1);
-  const bool act = i < nr && relaxes(cls, want, i);
-  T au = T(0);
+  auto row = [&](int i, int sub, bool act, T au) {
+    if (act) {
+      const T d = (f[i] - au) * dinv[i];
+      if (sub == 0) {
+        u_out[i] = u_in[i] + d;
+        if (tmode == 0) t[i] = d;
+        else if (tmode == 1) t[i] += d;
+      }
+    } else if (i < nb && sub == 0) {
+      u_out[i] = u_in[i];
+      if (i < nr && tmode == 0) t[i] = T(0);
+    }
+  };
   if constexpr (LV >= 0) {
     // tiles of rows >= nr relax nothing: no staging
-    if (xcd_block() * (WG >> A.lg) < nr) au = lds_dot<T, WG, LV>(A, i, sub, act, u_in);
-  }
-  if (act) {
-    if constexpr (LV < 0) au = sell_dot<T, T>(A, i, sub, u_in);
-    const T d = (f[i] - au) * dinv[i];
-    if (sub == 0) {
-      u_out[i] = u_in[i] + d;
-      if (tmode == 0) t[i] = d;
-      else if (tmode == 1) t[i] += d;
-    }
-  } else if (i < nb && sub == 0) {
-    u_out[i] = u_in[i];
-    if (i < nr && tmode == 0) t[i] = T(0);
+    const bool stage = xcd_block() * ((64 * TILE_SLICES) >> A.lg) < nr;
+    lds_tile<T, LV, TILE_SLICES>(A, u_in, stage,
+                                 [&](int i, int sub, T au) { row(i, sub, i < nr && relaxes(cls, want, i), au); });
+  } else {
+    const int th = thread_id_wg<WG>(), i = th >> A.lg, sub = th & ((1 << A.lg) - 1);
+    const bool act = i < nr && relaxes(cls, want, i);
+    row(i, sub, act, act ? sell_dot<T, T>(A, i, sub, u_in) : T(0));
   }
 }
 
@@ -608,12 +625,14 @@ __global__ __launch_bounds__(WG, LV >= 0 ? LDS_WAVES : 1) void k_relax(SellD<T> 
 template <typename T, int WG = BLOCK, int LV = -1>
 __global__ __launch_bounds__(WG, LV >= 0 ? LDS_WAVES : 1) void k_w(SellD<T> A, int nb, T *__restrict__ sw,
                                                                     const T *__restrict__ t, int has_s) {
-  const int th = thread_id_wg<WG>(), i = th >> A.lg, sub = th & ((1 << A.lg) - 1);
-  T at = T(0);
-  if constexpr (LV >= 0) at = lds_dot<T, WG, LV>(A, i, sub, i < nb, t);
-  if (i < nb) {
-    if constexpr (LV < 0) at = sell_dot<T, T>(A, i, sub, t);
-    if (sub == 0) sw[i] = has_s ? sw[i] + at : at;
+  auto row = [&](int i, int sub, T at) {
+    if (i < nb && sub == 0) sw[i] = has_s ? sw[i] + at : at;
+  };
+  if constexpr (LV >= 0) {
+    lds_tile<T, LV, TILE_SLICES>(A, t, true, row);
+  } else {
+    const int th = thread_id_wg<WG>(), i = th >> A.lg, sub = th & ((1 << A.lg) - 1);
+    if (i < nb) row(i, sub, sell_dot<T, T>(A, i, sub, t));
   }
 }
 
@@ -653,23 +672,25 @@ __global__ __launch_bounds__(WG) void k_down(SellD<T> R, SellD<T> A, int nr, int
 // perm[k]): s = R w_prev at every normal row (stored for the down and w
 // passes), and u = 0 at ghost rows [nr, nb) (the down pass then covers the
 // real rows only).
-// LV >= 0: LDS variant staging w_prev's band of the tile (see lds_dot).
+// LV >= 0: LDS variant (see lds_tile).
 template <typename T, int WG = BLOCK, int LV = -1>
 __global__ __launch_bounds__(WG, LV >= 0 ? LDS_WAVES : 1) void k_restrict_rows(SellD<T> Rt,
                                                                                 const int *__restrict__ perm, int nb,
                                                                                 int nr, const T *__restrict__ w_prev,
                                                                                 T *__restrict__ sw,
                                                                                 T *__restrict__ u_out) {
-  const int th = thread_id_wg<WG>(), k = th >> Rt.lg, sub = th & ((1 << Rt.lg) - 1);
-  T s = T(0);
-  if constexpr (LV >= 0) s = lds_dot<T, WG, LV>(Rt, k, sub, k < nb, w_prev);
-  if (k < nb) {
-    if constexpr (LV < 0) s = sell_dot<T, T>(Rt, k, sub, w_prev);
-    if (sub == 0) {
+  auto row = [&](int k, int sub, T s) {
+    if (k < nb && sub == 0) {
       const int i = perm[k];
       sw[i] = s;
       if (i >= nr) u_out[i] = T(0);
     }
+  };
+  if constexpr (LV >= 0) {
+    lds_tile<T, LV, TILE_SLICES_R>(Rt, w_prev, true, row);
+  } else {
+    const int th = thread_id_wg<WG>(), k = th >> Rt.lg, sub = th & ((1 << Rt.lg) - 1);
+    if (k < nb) row(k, sub, sell_dot<T, T>(Rt, k, sub, w_prev));
   }
 }
 
@@ -686,24 +707,24 @@ __global__ __launch_bounds__(WG, LV >= 0 ? LDS_WAVES : 1) void k_down_real(SellD
                                                                             T *__restrict__ u_out,
                                                                             T *__restrict__ t, int first,
                                                                             const signed char *__restrict__ cls) {
-  const int th = thread_id_wg<WG>(), i = th >> A.lg, sub = th & ((1 << A.lg) - 1);
-  T au = T(0);
+  auto row = [&](int i, int sub, T au) {
+    if (i < nr) {
+      T fi = f[i];
+      if (!first) fi -= au;
+      fi -= sw[i];
+      if (sub == 0) {
+        f[i] = fi;
+        const T d = relaxes(cls, 1, i) ? fi * dinv[i] : T(0);
+        u_out[i] = d;
+        t[i] = first ? d : t[i] + d;
+      }
+    }
+  };
   if constexpr (LV >= 0) {
-    if (!first) au = lds_dot<T, WG, LV>(A, i, sub, i < nr, u_in);
-  }
-  if (i < nr) {
-    T fi = f[i];
-    if constexpr (LV < 0) {
-      if (!first) au = sell_dot<T, T>(A, i, sub, u_in);
-    }
-    if (!first) fi -= au;
-    fi -= sw[i];
-    if (sub == 0) {
-      f[i] = fi;
-      const T d = relaxes(cls, 1, i) ? fi * dinv[i] : T(0);
-      u_out[i] = d;
-      t[i] = first ? d : t[i] + d;
-    }
+    lds_tile<T, LV, TILE_SLICES>(A, u_in, !first, row);
+  } else {
+    const int th = thread_id_wg<WG>(), i = th >> A.lg, sub = th & ((1 << A.lg) - 1);
+    if (i < nr) row(i, sub, first ? T(0) : sell_dot<T, T>(A, i, sub, u_in));
   }
 }
 

@@ -363,7 +363,7 @@ Sell permuted_layout(const SellBuilder &src, int nrows, int lg, int step_log2, i
 
 // LDS bands of a composite operator, for its level-synchronous passes run in
 // 1024-thread workgroups that stage the gathered vector in LDS.  Tile t is
-// the 16 slices [16t, 16t + 16) (1024 threads, one workgroup).  Its band is
+// the ts slices from ts t on (one workgroup).  Its band is
 // the set of columns of its nonzero entries, covered by at most kBandWindows
 // windows: the span split at its kBandWindows - 1 largest gaps.  With
 // W = kBandWindows, tiles[2W t .. 2W t + W-1] are the window starts and
@@ -376,8 +376,8 @@ Sell permuted_layout(const SellBuilder &src, int nrows, int lg, int step_log2, i
 // tile's band (0 for zero entries).  Returns the largest band, or 0 with no
 // bands kept when some tile's list still exceeds `cap` (the layout's passes
 // then gather from memory).
-int build_bands(Sell &S, int cap) {
-  constexpr int ts = 16, W = kBandWindows;
+int build_bands(Sell &S, int cap, int ts) {
+  constexpr int W = kBandWindows;
   const int ns = (int)S.sptr.size() - 1;
   S.colL.clear();
   S.tiles.clear();
@@ -469,8 +469,8 @@ int build_bands(Sell &S, int cap) {
 
 // Check of build_bands: every nonzero entry of a banded tile decodes back to
 // its column through its window, and every entry's position lies in the band.
-bool bands_valid(const Sell &S, int cap) {
-  constexpr int ts = 16, W = kBandWindows;
+bool bands_valid(const Sell &S, int cap, int ts) {
+  constexpr int W = kBandWindows;
   const int ns = (int)S.sptr.size() - 1;
   if (S.tiles.empty()) return S.colL.empty();
   const int nt = (ns + ts - 1) / ts;
@@ -1817,19 +1817,19 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
         BatchLevel &B = S.lv[l];
         if (B.Rt.entries() > 0) {
           // the reordered restriction gathers from the finer level
-          B.rband_max = build_bands(B.Rt, S.band_cap);
-          if (!bands_valid(B.Rt, S.band_cap)) { err = "internal: LDS band check failed on level " + std::to_string(l); return ST_EINVAL; }
+          B.rband_max = build_bands(B.Rt, S.band_cap, kTileSlicesR);
+          if (!bands_valid(B.Rt, S.band_cap, kTileSlicesR)) { err = "internal: LDS band check failed on level " + std::to_string(l); return ST_EINVAL; }
         }
         if (B.A.entries() == 0) continue;
-        B.band_max = build_bands(B.A, S.band_cap);
-        if (!bands_valid(B.A, S.band_cap)) { err = "internal: LDS band check failed on level " + std::to_string(l); return ST_EINVAL; }
+        B.band_max = build_bands(B.A, S.band_cap, kTileSlices);
+        if (!bands_valid(B.A, S.band_cap, kTileSlices)) { err = "internal: LDS band check failed on level " + std::to_string(l); return ST_EINVAL; }
         if (verbose()) {
           long long nb = 0, sum = 0;
           const int nt = (int)B.A.tiles.size() / (2 * kBandWindows);
           for (int t = 0; t < nt; ++t)
             if (const int n = B.A.tiles[2 * kBandWindows * t + 2 * kBandWindows - 1]) { ++nb; sum += n; }
           std::fprintf(stderr, "[amgdd setup] level %d LDS bands: %lld of %d tiles, %.2f values per row, largest %d (R: %d)\n",
-                       l, nb, nt, nb ? (double)sum / nb / (1024 >> B.A.lg) : 0.0, B.band_max, B.rband_max);
+                       l, nb, nt, nb ? (double)sum / nb / ((64 * kTileSlices) >> B.A.lg) : 0.0, B.band_max, B.rband_max);
         }
       }
     vlog("pack: LDS bands", tb);
