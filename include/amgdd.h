@@ -58,6 +58,10 @@
  *                         operator's row order and lanes (no reordered P, R)
  *   AMGDD_TIGHT_WINDOW=n  sort window of the reordered P and R (defaults 256
  *                         for P, 512 for R); AMGDD_TIGHT_WINDOW_R=n for R only
+ *   AMGDD_TILE_SLICES_MAX=n, AMGDD_WIDE_TILES_MIN=m  LDS tiles of a level's
+ *                         operator hold the largest power of two of slices
+ *                         from n (16 to 128, default 32) down that leaves the
+ *                         level at least m tiles (default 0), else 16
  * and when a handle's schedule is tuned:
  *   AMGDD_TUNE_CACHE=path schedule cache file (JSON, one entry per line,
  *                         keyed by a hash of the layout, device and library

@@ -73,7 +73,8 @@ struct ProblemHost {
 // windows of an LDS band and slices of an LDS tile (the kernels read the
 // same tile descriptors)
 constexpr int kBandWindows = 8;
-constexpr int kTileSlices = 32;   // operators
+constexpr int kTileSlices = 32;   // operators: default largest tile
+constexpr int kTileSlicesS = 16;  // operators: smallest tile
 constexpr int kTileSlicesR = 16;  // reordered restriction
 
 struct Sell {
@@ -86,7 +87,8 @@ struct Sell {
   std::vector<uint16_t> col16;
   std::vector<int> base;
   // LDS bands (composite operators; see build_bands): 2 kBandWindows ints per
-  // tile of kTileSlices slices, and each entry's position in its tile's band
+  // tile of ts slices, and each entry's position in its tile's band
+  int ts = 0;
   std::vector<int> tiles;
   std::vector<uint16_t> colL;
   std::vector<int> bidx;  // column lists of listed tiles
@@ -173,6 +175,12 @@ struct Setup {
   // LDS bands of the composite operators (at most band_cap values per tile)
   bool bands = true;
   int band_cap = 8192;
+  // operator tiles hold the largest power of two of slices from
+  // tile_slices_max down that leaves the level at least wide_tiles_min tiles
+  // (default: every level), and kTileSlicesS slices on levels of fewer; a
+  // level whose bands overflow the cap at that size takes smaller tiles
+  int tile_slices_max = kTileSlices;
+  int wide_tiles_min = 0;
   // AMG components: coarsen 0 = RS first pass, 1 = HMIS; interp 0 = direct,
   // 1 = extended+i
   int coarsen = 0, interp = 0;

@@ -111,9 +111,10 @@ struct DSell {
   int *tiles = nullptr;
   int *bidx = nullptr;
   int ntiles = 0, nslices = 0;
+  int ts = 0;  // slices per LDS tile
   template <typename T>
   dev::SellD<T> as() const {
-    return dev::SellD<T>{sptr, col, (const T *)val, lg, col16, base, vlg, colL, tiles, bidx, ntiles, nslices};
+    return dev::SellD<T>{sptr, col, (const T *)val, lg, col16, base, vlg, colL, tiles, bidx, ntiles, nslices, ts};
   }
 };
 
@@ -302,10 +303,9 @@ struct amgdd_ctx {
       if ((st = upload(&d.colL, (const unsigned short *)s.colL.data(), s.colL.size()))) return st;
       if ((st = upload(&d.tiles, s.tiles.data(), s.tiles.size()))) return st;
       if (!s.bidx.empty() && (st = upload(&d.bidx, s.bidx.data(), s.bidx.size()))) return st;
-      static_assert(kBandWindows == dev::BAND_WINDOWS && kTileSlices == dev::TILE_SLICES &&
-                        kTileSlicesR == dev::TILE_SLICES_R,
-                    "tile descriptor layout");
+      static_assert(kBandWindows == dev::BAND_WINDOWS, "tile descriptor layout");
       d.ntiles = (int)(s.tiles.size() / (2 * kBandWindows));
+      d.ts = s.ts;
     }
     return upload_vals(&d.val, s.val, as_float);
   }
@@ -352,7 +352,7 @@ inline int nblocks_wg(long long n, int wg) { return (int)((n + wg - 1) / wg); }
 inline int a_wg(const DLevel &B) { return B.lds ? dev::LDS_WG : B.wg; }
 // workgroups of a pass over `rows` rows with lg lanes each: one per LDS tile
 // of ts slices, or one per wg threads
-inline int a_blocks(long long rows, int lg, bool lds, int wg, int ts = dev::TILE_SLICES) {
+inline int a_blocks(long long rows, int lg, bool lds, int wg, int ts) {
   return lds ? nblocks_wg(rows << lg, 64 * ts) : nblocks_wg(rows << lg, wg);
 }
 template <typename T>
@@ -617,7 +617,7 @@ void enqueue_fac_down(amgdd_ctx *h, hipStream_t s, int *cur, int l, int first) {
       PLAUNCH(h, "relax0", 0, nrc * 4.0 * w + (B.NBn - nrc) * w + (cf ? B.NRn : 0), dev::k_relax_zero<T>, nblocks(B.NBn), dev::BLOCK, 0, s, B.NRn, B.NBn, (const T *)B.f,
              (const T *)B.dinv, uout, (T *)B.t, (const signed char *)B.cls);
     else
-      PLAUNCH(h, "relax_pre", 0, nzc * ent(B.A, w) + nrc * 4.0 * w + B.NBn * 2.0 * w + (cf ? B.NRn : 0), AK(dev::k_relax, T, B), a_blocks(B.NBn, B.lg, B.lds, a_wg(B)), a_wg(B), a_lds<T>(B), s, B.A.as<T>(), B.NRn, B.NBn, (const T *)B.f,
+      PLAUNCH(h, "relax_pre", 0, nzc * ent(B.A, w) + nrc * 4.0 * w + B.NBn * 2.0 * w + (cf ? B.NRn : 0), AK(dev::k_relax, T, B), a_blocks(B.NBn, B.lg, B.lds, a_wg(B), B.A.ts), a_wg(B), a_lds<T>(B), s, B.A.as<T>(), B.NRn, B.NBn, (const T *)B.f,
              (const T *)B.dinv, (const T *)uin, uout, (T *)B.t, 1, (const signed char *)B.cls, 1);
   } else {
     DLevel &Bp = h->L[l - 1];
@@ -626,10 +626,10 @@ void enqueue_fac_down(amgdd_ctx *h, hipStream_t s, int *cur, int l, int first) {
       const int rwg = B.rlds ? dev::LDS_WG : B.wg;
       PLAUNCH(h, "restrict_s", l, B.nnzR_n * ent(B.Rt, w) + Bp.NBn * w + B.NBn * (w + 4.0) + (B.NBn - B.NRn) * w,
               (B.rlds ? LK(dev::k_restrict_rows, T, B.Rt.vlg) : WGK(dev::k_restrict_rows, T, B.wg)),
-              a_blocks(B.NBn, B.Rt.lg, B.rlds, rwg, dev::TILE_SLICES_R), rwg, B.rlds ? (size_t)B.rband_max * sizeof(T) : 0, s,
+              a_blocks(B.NBn, B.Rt.lg, B.rlds, rwg, B.Rt.ts), rwg, B.rlds ? (size_t)B.rband_max * sizeof(T) : 0, s,
               B.Rt.as<T>(), B.rperm, B.NBn, B.NRn, (const T *)Bp.sw, (T *)B.sw, uout);
       PLAUNCH(h, "down", l, (first ? 0.0 : B.nnzA_r * ent(B.A, w) + B.NBn * w) + B.NRn * ((first ? 4.0 : 5.0) + 2.0) * w + (cf ? B.NRn : 0),
-              AK(dev::k_down_real, T, B), a_blocks(B.NRn, B.lg, B.lds, a_wg(B)), a_wg(B), a_lds<T>(B), s, B.A.as<T>(), B.NRn,
+              AK(dev::k_down_real, T, B), a_blocks(B.NRn, B.lg, B.lds, a_wg(B), B.A.ts), a_wg(B), a_lds<T>(B), s, B.A.as<T>(), B.NRn,
               (const T *)B.sw, (T *)B.f, (const T *)B.dinv, (const T *)uin, uout, (T *)B.t, first, (const signed char *)B.cls);
     } else
     PLAUNCH(h, "down", l, B.nnzR_n * ent(B.R, w) + Bp.NBn * w + B.NBn * 2.0 * w + (first ? 0.0 : B.nnzA_r * ent(B.A, w) + B.NBn * w) + B.NRn * (first ? 4.0 : 5.0) * w + (cf ? B.NRn : 0), WGK(dev::k_down, T, B.wg), nblocks_wg((long long)B.NBn << B.lg, B.wg), B.wg, 0, s, B.R.as<T>(), B.A.as<T>(), B.NRn, B.NBn,
@@ -644,12 +644,12 @@ void enqueue_fac_down(amgdd_ctx *h, hipStream_t s, int *cur, int l, int first) {
     // this level keep their solve, copied along)
     const int nrf = B.NRn - B.NRc;
     T *ui = (T *)B.u[cur[l]], *uo = (T *)B.u[cur[l] ^ 1];
-    PLAUNCH(h, "relax_f", l, (B.nnzA_r - B.nnzA_c) * ent(B.A, w) + nrf * 4.0 * w + B.NB * 2.0 * w + B.NRn, AK(dev::k_relax, T, B), a_blocks(B.NB, B.lg, B.lds, a_wg(B)), a_wg(B), a_lds<T>(B), s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
+    PLAUNCH(h, "relax_f", l, (B.nnzA_r - B.nnzA_c) * ent(B.A, w) + nrf * 4.0 * w + B.NB * 2.0 * w + B.NRn, AK(dev::k_relax, T, B), a_blocks(B.NB, B.lg, B.lds, a_wg(B), B.A.ts), a_wg(B), a_lds<T>(B), s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
             (const T *)B.dinv, (const T *)ui, uo, (T *)B.t, 1, (const signed char *)B.cls, -1);
     cur[l] ^= 1;
   }
   if (B.NBn > 0 && l < maxL)
-    PLAUNCH(h, "w", l, B.nnzA * ent(B.A, w) + B.NBn * (l > 0 ? 3.0 : 2.0) * w, AK(dev::k_w, T, B), a_blocks(B.NBn, B.lg, B.lds, a_wg(B)), a_wg(B), a_lds<T>(B), s, B.A.as<T>(), B.NBn, (T *)B.sw, (const T *)B.t, l > 0);
+    PLAUNCH(h, "w", l, B.nnzA * ent(B.A, w) + B.NBn * (l > 0 ? 3.0 : 2.0) * w, AK(dev::k_w, T, B), a_blocks(B.NBn, B.lg, B.lds, a_wg(B), B.A.ts), a_wg(B), a_lds<T>(B), s, B.A.as<T>(), B.NBn, (T *)B.sw, (const T *)B.t, l > 0);
 }
 
 template <typename T>
@@ -667,13 +667,13 @@ void enqueue_fac_up(amgdd_ctx *h, hipStream_t s, int *cur, int l) {
          (const T *)Bc.u[cur[l + 1]]);
   if (B.cls) {
     const int nrf = B.NRn - B.NRc;
-    PLAUNCH(h, "relax_post_f", l, (B.nnzA_r - B.nnzA_c) * ent(B.A, w) + nrf * 3.0 * w + B.NRc * w + B.NB * 2.0 * w + B.NRn, AK(dev::k_relax, T, B), a_blocks(B.NB, B.lg, B.lds, a_wg(B)), a_wg(B), a_lds<T>(B), s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
+    PLAUNCH(h, "relax_post_f", l, (B.nnzA_r - B.nnzA_c) * ent(B.A, w) + nrf * 3.0 * w + B.NRc * w + B.NB * 2.0 * w + B.NRn, AK(dev::k_relax, T, B), a_blocks(B.NB, B.lg, B.lds, a_wg(B), B.A.ts), a_wg(B), a_lds<T>(B), s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
             (const T *)B.dinv, (const T *)B.u[cur[l]], (T *)B.u[cur[l] ^ 1], (T *)B.t, 0, (const signed char *)B.cls, -1);
     cur[l] ^= 1;
-    PLAUNCH(h, "relax_post_c", l, B.nnzA_c * ent(B.A, w) + B.NRc * 4.0 * w + B.NB * 2.0 * w + B.NRn, AK(dev::k_relax, T, B), a_blocks(B.NB, B.lg, B.lds, a_wg(B)), a_wg(B), a_lds<T>(B), s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
+    PLAUNCH(h, "relax_post_c", l, B.nnzA_c * ent(B.A, w) + B.NRc * 4.0 * w + B.NB * 2.0 * w + B.NRn, AK(dev::k_relax, T, B), a_blocks(B.NB, B.lg, B.lds, a_wg(B), B.A.ts), a_wg(B), a_lds<T>(B), s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
             (const T *)B.dinv, (const T *)B.u[cur[l]], (T *)B.u[cur[l] ^ 1], (T *)B.t, 1, (const signed char *)B.cls, 1);
   } else {
-    PLAUNCH(h, "relax_post", l, B.nnzA_r * ent(B.A, w) + B.NRn * 3.0 * w + B.NB * 2.0 * w, AK(dev::k_relax, T, B), a_blocks(B.NB, B.lg, B.lds, a_wg(B)), a_wg(B), a_lds<T>(B), s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
+    PLAUNCH(h, "relax_post", l, B.nnzA_r * ent(B.A, w) + B.NRn * 3.0 * w + B.NB * 2.0 * w, AK(dev::k_relax, T, B), a_blocks(B.NB, B.lg, B.lds, a_wg(B), B.A.ts), a_wg(B), a_lds<T>(B), s, B.A.as<T>(), B.NRn, B.NB, (const T *)B.f,
            (const T *)B.dinv, (const T *)B.u[cur[l]], (T *)B.u[cur[l] ^ 1], (T *)B.t, 0, (const signed char *)nullptr, 1);
   }
   cur[l] ^= 1;
@@ -1485,6 +1485,11 @@ amgdd_status make_handle(const std::vector<ProblemInput> &in, const amgdd_params
   if (std::getenv("AMGDD_FUSED_R")) h->S.tight = false;
   if (const char *e = std::getenv("AMGDD_TIGHT_WINDOW")) h->S.tight_window = h->S.tight_window_r = std::max(0, std::atoi(e));
   if (const char *e = std::getenv("AMGDD_TIGHT_WINDOW_R")) h->S.tight_window_r = std::max(0, std::atoi(e));
+  if (const char *e = std::getenv("AMGDD_WIDE_TILES_MIN")) h->S.wide_tiles_min = std::max(0, std::atoi(e));
+  if (const char *e = std::getenv("AMGDD_TILE_SLICES_MAX")) {
+    const int v = std::atoi(e);
+    h->S.tile_slices_max = v >= 128 ? 128 : v >= 64 ? 64 : v >= 32 ? 32 : 16;
+  }
   std::string err;
   Setup inner_S;
   int st;

@@ -71,9 +71,8 @@ struct SellD {
   const unsigned short *col16;
   const int *base;
   int vlg;  // log2 entries per lane in the widest steps (see sell_dotw)
-  // LDS bands (composite operators): tile t = the TS slices from TS t on
-  // (TS = TILE_SLICES, TILE_SLICES_R for the restriction), one 1024-thread
-  // workgroup; with W = BAND_WINDOWS, tiles[2Wt .. 2Wt+W-1]
+  // LDS bands (composite operators): tile t = the ts slices from ts t on,
+  // one 1024-thread workgroup; with W = BAND_WINDOWS, tiles[2Wt .. 2Wt+W-1]
   // window starts, [2Wt+W .. 2Wt+2W-1] cumulative window lengths (the last
   // one is the band size); a first start -1 - o < 0 marks a listed tile
   // whose band is bidx[o .. o + size); colL = each entry's position in its
@@ -83,6 +82,7 @@ struct SellD {
   const int *bidx;
   int ntiles;
   int nslices;
+  int ts;  // slices per LDS tile
 };
 
 // Workgroups are dispatched round-robin over the 8 XCDs; remap so that each
@@ -332,8 +332,8 @@ __device__ __forceinline__ bool relaxes(const signed char *__restrict__ cls, int
 extern __shared__ double lds_band[];
 
 // LDS variants (template argument LV = the operator's step width, >= 0):
-// 1024-thread workgroups (16 waves), one tile of TILE_SLICES (operator) or
-// TILE_SLICES_R (restriction) slices each,
+// 1024-thread workgroups (16 waves), one tile (16 or 32 slices, a property of
+// the layout) each,
 // compiled for two workgroups per CU (8 waves per SIMD, at most 64 VGPRs) so
 // that one workgroup's staging phase overlaps the other's mat-vecs.  The
 // workgroup copies its tile's band into LDS once, then each wave takes the
@@ -344,8 +344,30 @@ extern __shared__ double lds_band[];
 // band.
 constexpr int LDS_WAVES = 8;
 constexpr int LDS_WG = 1024;
-constexpr int TILE_SLICES = 32;    // operator passes
-constexpr int TILE_SLICES_R = 16;  // restriction (its rows gather from the finer level)
+
+// H consecutive load steps of W entries per lane (64 lanes apart) times the
+// band: all loads first, then the gathers and the lane's fused multiply-adds
+// in storage order.
+template <typename T, int W, int H>
+__device__ __forceinline__ void lds_steps(const unsigned short *c, const T *v, const T *band, T &acc) {
+  typedef T TW __attribute__((ext_vector_type(W)));
+  typedef unsigned short CW __attribute__((ext_vector_type(W)));
+  CW cn[H];
+  TW vn[H];
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    cn[j] = __builtin_nontemporal_load((const CW *)c + 64 * j);
+    vn[j] = __builtin_nontemporal_load((const TW *)v + 64 * j);
+  }
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    T xx[W];
+#pragma unroll
+    for (int e = 0; e < W; ++e) xx[e] = band[cn[j][e]];
+#pragma unroll
+    for (int e = 0; e < W; ++e) acc = fma(vn[j][e], xx[e], acc);
+  }
+}
 
 // Slice s of M (the calling wave's 64 lanes) times the band: row r, lane
 // `sub` of its group; entries gathered from LDS through their band
@@ -354,61 +376,36 @@ constexpr int TILE_SLICES_R = 16;  // restriction (its rows gather from the fine
 template <typename T, int VL>
 __device__ __forceinline__ T lds_row_dot(const SellD<T> &M, int s, int r, int sub, const T *band) {
   constexpr int W = 1 << VL;
-  typedef T TW __attribute__((ext_vector_type(W)));
   typedef T T2 __attribute__((ext_vector_type(2)));
-  typedef unsigned short CW __attribute__((ext_vector_type(W)));
   typedef unsigned short C2 __attribute__((ext_vector_type(2)));
-  // steps in flight (the gathers come from LDS: fewer than in sell_dotw, for
-  // the register budget of two workgroups per CU)
-  constexpr int U = sizeof(T) == 8 && W > 1 ? 1 : (AMGDD_UNROLL / W > 0 ? AMGDD_UNROLL / W : 1);
+  // The widest steps go in batches of B (eight entries per lane), then the
+  // rest in batches of B/2, B/4, ... steps: every load of a batch is issued
+  // before its first gather, so a wave keeps a batch of matrix data in flight.
+  constexpr int B = 8 / W > 0 ? 8 / W : 1;
   const int lg = M.lg;
   const int beg = M.sptr[s];
   const int u = (M.sptr[s + 1] - beg) >> 6, w = u >> VL;
   const int p = ((r & ((64 >> lg) - 1)) << lg) + sub;
-  const CW *__restrict__ c = (const CW *)(M.colL + beg + W * p);
-  const TW *__restrict__ v = (const TW *)(M.val + beg + W * p);
+  const unsigned short *__restrict__ c = M.colL + beg + W * p;
+  const T *__restrict__ v = M.val + beg + W * p;
   const int off2 = beg + (w << (6 + VL));
   const int has2 = VL == 2 ? (u >> 1) & 1 : 0;
   const int off1 = off2 + (has2 << 7);
   T acc = T(0);
   int k = 0;
-  if (U <= w) {
-    CW cn[U];
-    TW vn[U];
-#pragma unroll
-    for (int j = 0; j < U; ++j) {
-      cn[j] = __builtin_nontemporal_load(c + 64 * j);
-      vn[j] = __builtin_nontemporal_load(v + 64 * j);
+  for (; k + B <= w; k += B) lds_steps<T, W, B>(c + 64 * W * k, v + 64 * W * k, band, acc);
+  if constexpr (B >= 8)
+    if ((w - k) & 4) {
+      lds_steps<T, W, 4>(c + 64 * W * k, v + 64 * W * k, band, acc);
+      k += 4;
     }
-    for (; k + U <= w; k += U) {
-      T vv[W * U], xx[W * U];
-#pragma unroll
-      for (int j = 0; j < U; ++j)
-#pragma unroll
-        for (int e = 0; e < W; ++e) {
-          xx[W * j + e] = band[cn[j][e]];
-          vv[W * j + e] = vn[j][e];
-        }
-      if (k + 2 * U <= w) {
-#pragma unroll
-        for (int j = 0; j < U; ++j) {
-          cn[j] = __builtin_nontemporal_load(c + 64 * (k + U + j));
-          vn[j] = __builtin_nontemporal_load(v + 64 * (k + U + j));
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < W * U; ++j) acc = fma(vv[j], xx[j], acc);
+  if constexpr (B >= 4)
+    if ((w - k) & 2) {
+      lds_steps<T, W, 2>(c + 64 * W * k, v + 64 * W * k, band, acc);
+      k += 2;
     }
-  }
-  for (; k < w; ++k) {
-    const CW cq = __builtin_nontemporal_load(c + 64 * k);
-    const TW vq = __builtin_nontemporal_load(v + 64 * k);
-    T xx[W];
-#pragma unroll
-    for (int e = 0; e < W; ++e) xx[e] = band[cq[e]];
-#pragma unroll
-    for (int e = 0; e < W; ++e) acc = fma(vq[e], xx[e], acc);
-  }
+  if constexpr (B >= 2)
+    if ((w - k) & 1) lds_steps<T, W, 1>(c + 64 * W * k, v + 64 * W * k, band, acc);
   if (VL == 2 && has2) {
     const C2 cq = __builtin_nontemporal_load((const C2 *)(M.colL + off2 + 2 * p));
     const T2 vq = __builtin_nontemporal_load((const T2 *)(M.val + off2 + 2 * p));
@@ -421,13 +418,13 @@ __device__ __forceinline__ T lds_row_dot(const SellD<T> &M, int s, int r, int su
   return group_sum(acc, lg);
 }
 
-// One LDS tile of TS slices (every thread of the workgroup calls it; it holds
+// One LDS tile of M.ts slices (every thread of the workgroup calls it; it holds
 // the workgroup barrier): when `stage`, the tile's band of x is copied into LDS
 // (coalesced loads of its windows, or of its listed columns); then the waves
 // take the tile's slices from a counter and call op(r, sub, dot) for each
 // lane's row r (group lane `sub`), dot = row r of M times x (0 when the tile
 // is not staged or the slice lies beyond M).
-template <typename T, int VL, int TS, typename Op>
+template <typename T, int VL, typename Op>
 __device__ __forceinline__ void lds_tile(const SellD<T> &M, const T *__restrict__ x, bool stage, Op op) {
   constexpr int NW = BAND_WINDOWS;
   __shared__ int next_slice;
@@ -443,16 +440,35 @@ __device__ __forceinline__ void lds_tile(const SellD<T> &M, const T *__restrict_
       lo[k] = d[k];
       end[k] = d[NW + k];
     }
+    // SB values per thread in flight: the loads of a batch go out before its
+    // stores (positions past the band load and store its last value again)
+    constexpr int SB = 4;
     if (lo[0] < 0) {
       const int *__restrict__ ix = M.bidx + (-1 - lo[0]);
-      for (int k = threadIdx.x; k < n; k += LDS_WG) band[k] = x[ix[k]];
-    } else {
-      for (int k = threadIdx.x; k < n; k += LDS_WG) {
-        int base = lo[0] + k;
+      for (int k0 = threadIdx.x; k0 < n; k0 += SB * LDS_WG) {
+        int c[SB];
+        T t[SB];
 #pragma unroll
-        for (int q = 1; q < NW; ++q)
-          if (k >= end[q - 1]) base = lo[q] + (k - end[q - 1]);
-        band[k] = x[base];
+        for (int j = 0; j < SB; ++j) c[j] = ix[min(k0 + j * LDS_WG, n - 1)];
+#pragma unroll
+        for (int j = 0; j < SB; ++j) t[j] = x[c[j]];
+#pragma unroll
+        for (int j = 0; j < SB; ++j) band[min(k0 + j * LDS_WG, n - 1)] = t[j];
+      }
+    } else {
+      for (int k0 = threadIdx.x; k0 < n; k0 += SB * LDS_WG) {
+        T t[SB];
+#pragma unroll
+        for (int j = 0; j < SB; ++j) {
+          const int k = min(k0 + j * LDS_WG, n - 1);
+          int base = lo[0] + k;
+#pragma unroll
+          for (int q = 1; q < NW; ++q)
+            if (k >= end[q - 1]) base = lo[q] + (k - end[q - 1]);
+          t[j] = x[base];
+        }
+#pragma unroll
+        for (int j = 0; j < SB; ++j) band[min(k0 + j * LDS_WG, n - 1)] = t[j];
       }
     }
   }
@@ -461,8 +477,8 @@ __device__ __forceinline__ void lds_tile(const SellD<T> &M, const T *__restrict_
     int sl = 0;
     if (lane == 0) sl = atomicAdd(&next_slice, 1);
     sl = __builtin_amdgcn_readfirstlane(__shfl(sl, 0));
-    if (sl >= TS) break;
-    const int s = tile * TS + sl;
+    if (sl >= M.ts) break;
+    const int s = tile * M.ts + sl;
     const int r = s * (64 >> lg) + (lane >> lg), sub = lane & ((1 << lg) - 1);
     T dot = T(0);
     // a tile without nonzero entries: every product is +0 (as the sum of
@@ -610,8 +626,8 @@ __global__ __launch_bounds__(WG, LV >= 0 ? LDS_WAVES : 1) void k_relax(SellD<T> 
   };
   if constexpr (LV >= 0) {
     // tiles of rows >= nr relax nothing: no staging
-    const bool stage = xcd_block() * ((64 * TILE_SLICES) >> A.lg) < nr;
-    lds_tile<T, LV, TILE_SLICES>(A, u_in, stage,
+    const bool stage = xcd_block() * ((64 * A.ts) >> A.lg) < nr;
+    lds_tile<T, LV>(A, u_in, stage,
                                  [&](int i, int sub, T au) { row(i, sub, i < nr && relaxes(cls, want, i), au); });
   } else {
     const int th = thread_id_wg<WG>(), i = th >> A.lg, sub = th & ((1 << A.lg) - 1);
@@ -629,7 +645,7 @@ __global__ __launch_bounds__(WG, LV >= 0 ? LDS_WAVES : 1) void k_w(SellD<T> A, i
     if (i < nb && sub == 0) sw[i] = has_s ? sw[i] + at : at;
   };
   if constexpr (LV >= 0) {
-    lds_tile<T, LV, TILE_SLICES>(A, t, true, row);
+    lds_tile<T, LV>(A, t, true, row);
   } else {
     const int th = thread_id_wg<WG>(), i = th >> A.lg, sub = th & ((1 << A.lg) - 1);
     if (i < nb) row(i, sub, sell_dot<T, T>(A, i, sub, t));
@@ -687,7 +703,7 @@ __global__ __launch_bounds__(WG, LV >= 0 ? LDS_WAVES : 1) void k_restrict_rows(S
     }
   };
   if constexpr (LV >= 0) {
-    lds_tile<T, LV, TILE_SLICES_R>(Rt, w_prev, true, row);
+    lds_tile<T, LV>(Rt, w_prev, true, row);
   } else {
     const int th = thread_id_wg<WG>(), k = th >> Rt.lg, sub = th & ((1 << Rt.lg) - 1);
     if (k < nb) row(k, sub, sell_dot<T, T>(Rt, k, sub, w_prev));
@@ -721,7 +737,7 @@ __global__ __launch_bounds__(WG, LV >= 0 ? LDS_WAVES : 1) void k_down_real(SellD
     }
   };
   if constexpr (LV >= 0) {
-    lds_tile<T, LV, TILE_SLICES>(A, u_in, !first, row);
+    lds_tile<T, LV>(A, u_in, !first, row);
   } else {
     const int th = thread_id_wg<WG>(), i = th >> A.lg, sub = th & ((1 << A.lg) - 1);
     if (i < nr) row(i, sub, first ? T(0) : sell_dot<T, T>(A, i, sub, u_in));

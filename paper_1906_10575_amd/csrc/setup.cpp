@@ -382,6 +382,7 @@ int build_bands(Sell &S, int cap, int ts) {
   S.colL.clear();
   S.tiles.clear();
   S.bidx.clear();
+  S.ts = 0;
   if (ns <= 0) return 0;
   const int nt = (ns + ts - 1) / ts;
   S.colL.assign(S.col.size(), 0);
@@ -464,6 +465,7 @@ int build_bands(Sell &S, int cap, int ts) {
     S.tiles[2 * W * (size_t)x.first] = -1 - (int)S.bidx.size();
     S.bidx.insert(S.bidx.end(), x.second.begin(), x.second.end());
   }
+  S.ts = ts;
   return *std::max_element(bmax.begin(), bmax.end());
 }
 
@@ -1821,15 +1823,29 @@ int setup_layouts(Setup &S, bool composite, std::string &err) {
           if (!bands_valid(B.Rt, S.band_cap, kTileSlicesR)) { err = "internal: LDS band check failed on level " + std::to_string(l); return ST_EINVAL; }
         }
         if (B.A.entries() == 0) continue;
-        B.band_max = build_bands(B.A, S.band_cap, kTileSlices);
-        if (!bands_valid(B.A, S.band_cap, kTileSlices)) { err = "internal: LDS band check failed on level " + std::to_string(l); return ST_EINVAL; }
+        // the largest tile (tile_slices_max halved down to kTileSlicesS
+        // slices) that leaves the level wide_tiles_min tiles, or a smaller one
+        // when some tile's band would not fit the cap
+        const long long nsl = (long long)B.A.sptr.size() - 1;
+        int ts = kTileSlicesS;
+        for (int c = S.tile_slices_max; c > kTileSlicesS; c >>= 1)
+          if (nsl >= (long long)c * S.wide_tiles_min) {
+            ts = c;
+            break;
+          }
+        B.band_max = build_bands(B.A, S.band_cap, ts);
+        while (B.A.tiles.empty() && ts > kTileSlicesS) {
+          ts >>= 1;
+          B.band_max = build_bands(B.A, S.band_cap, ts);
+        }
+        if (!bands_valid(B.A, S.band_cap, ts)) { err = "internal: LDS band check failed on level " + std::to_string(l); return ST_EINVAL; }
         if (verbose()) {
           long long nb = 0, sum = 0;
           const int nt = (int)B.A.tiles.size() / (2 * kBandWindows);
           for (int t = 0; t < nt; ++t)
             if (const int n = B.A.tiles[2 * kBandWindows * t + 2 * kBandWindows - 1]) { ++nb; sum += n; }
-          std::fprintf(stderr, "[amgdd setup] level %d LDS bands: %lld of %d tiles, %.2f values per row, largest %d (R: %d)\n",
-                       l, nb, nt, nb ? (double)sum / nb / ((64 * kTileSlices) >> B.A.lg) : 0.0, B.band_max, B.rband_max);
+          std::fprintf(stderr, "[amgdd setup] level %d LDS bands: %lld of %d tiles of %d slices, %.2f values per row, largest %d (R: %d)\n",
+                       l, nb, nt, ts, nb ? (double)sum / nb / ((64 * ts) >> B.A.lg) : 0.0, B.band_max, B.rband_max);
         }
       }
     vlog("pack: LDS bands", tb);

@@ -35,7 +35,8 @@ amgdd = pytest.importorskip("paper_1906_10575_amd.amgdd")
 
 DEV = "cuda:0"
 ENV = ("AMGDD_INDEX32", "AMGDD_SORT_WINDOW", "AMGDD_UNPAIRED", "AMGDD_QUAD", "AMGDD_SERIAL", "AMGDD_LANE_TARGET",
-       "AMGDD_WG", "AMGDD_LDS", "AMGDD_FUSED_R", "AMGDD_TIGHT_WINDOW")
+       "AMGDD_WG", "AMGDD_LDS", "AMGDD_FUSED_R", "AMGDD_TIGHT_WINDOW", "AMGDD_TILE_SLICES_MAX",
+       "AMGDD_WIDE_TILES_MIN")
 
 CASES = {
     "3d_20_var_eta2": lambda: make_problem((20, 18, 20), (2, 2, 3), eta=2, n_fac=2,
@@ -169,6 +170,22 @@ def test_lds_bands_are_bitwise_neutral(name, precision, relax, monkeypatch):
         refs.append(ref)
     got = _run(p, monkeypatch, {}, precision, relax=relax)  # tuned per level, default layout
     assert np.array_equal(got[0], refs[0][0])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", ["3d_20_var_eta2", "3d_30_ragged_4x4x4"])
+def test_lds_tile_size_is_bitwise_neutral(name, precision, monkeypatch):
+    """LDS tiles of 16 to 128 slices (AMGDD_TILE_SLICES_MAX, with
+    AMGDD_WIDE_TILES_MIN=0 so that levels of few tiles take the large ones
+    too; a level whose bands overflow at that size falls back to smaller
+    tiles) give the same iterates as the memory-gathering passes."""
+    p = CASES[name]()
+    say("LDS tile size", name, precision, p.n)
+    ref = _run(p, monkeypatch, {"AMGDD_LDS": "0"}, precision)
+    for ts in ("16", "32", "64", "128"):
+        got = _run(p, monkeypatch, {"AMGDD_LDS": "1", "AMGDD_TILE_SLICES_MAX": ts, "AMGDD_WIDE_TILES_MIN": "0"},
+                   precision)
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), ts
 
 
 def test_lds_bands_hybrid_cycle_is_bitwise_neutral(monkeypatch):
