@@ -140,6 +140,30 @@ __device__ __forceinline__ V sell_dotw(const SellD<T> &M, int s, int beg, int r,
     const CW *__restrict__ c = (const CW *)(M.col16 + beg + W * p);
     const int b0 = M.base[2 * s], b1 = M.base[2 * s + 1];
     auto dec = [&](unsigned short q) { return ((q & 0x8000) ? b1 : b0) + (int)(q & 0x7fff); };
+    // The slice's last pieces (the widest steps after the last group of U,
+    // the two-wide step, the odd entry) are loaded first, so their loads
+    // overlap the groups' instead of following them.
+    const int rem = w % U, kr = w - rem;
+    CW cr[U];
+    TW vr[U];
+    C2 c2 = {0, 0};
+    T2 v2 = {T(0), T(0)};
+    unsigned short c1 = 0;
+    T v1 = T(0);
+#pragma unroll
+    for (int j = 0; j < U - 1; ++j)
+      if (j < rem) {
+        cr[j] = __builtin_nontemporal_load(c + 64 * (kr + j));
+        vr[j] = __builtin_nontemporal_load(v + 64 * (kr + j));
+      }
+    if (has2) {
+      c2 = __builtin_nontemporal_load((const C2 *)(M.col16 + off2 + 2 * p));
+      v2 = __builtin_nontemporal_load((const T2 *)(M.val + off2 + 2 * p));
+    }
+    if (u & 1) {
+      c1 = __builtin_nontemporal_load(M.col16 + off1 + p);
+      v1 = __builtin_nontemporal_load(M.val + off1 + p);
+    }
     if (k + U <= w) {
       CW cn[U];
       TW vn[U];
@@ -171,24 +195,28 @@ __device__ __forceinline__ V sell_dotw(const SellD<T> &M, int s, int beg, int r,
         for (int j = 0; j < W * U; ++j) acc = fma(vv[j], xx[j], acc);
       }
     }
-    for (; k < w; ++k) {
-      const CW cq = __builtin_nontemporal_load(c + 64 * k);
-      const TW vq = __builtin_nontemporal_load(v + 64 * k);
-      V xx[W];
+    // the pieces' gathers, then their products in storage order
+    V xr[W * U], x2[2], x1 = V(0);
 #pragma unroll
-      for (int e = 0; e < W; ++e) xx[e] = x[dec(cq[e])];
+    for (int j = 0; j < U - 1; ++j)
+      if (j < rem)
 #pragma unroll
-      for (int e = 0; e < W; ++e) acc = fma((V)vq[e], xx[e], acc);
-    }
+        for (int e = 0; e < W; ++e) xr[W * j + e] = x[dec(cr[j][e])];
     if (has2) {
-      const C2 cq = __builtin_nontemporal_load((const C2 *)(M.col16 + off2 + 2 * p));
-      const T2 vq = __builtin_nontemporal_load((const T2 *)(M.val + off2 + 2 * p));
-      const V x0 = x[dec(cq.x)], x1 = x[dec(cq.y)];
-      acc = fma((V)vq.x, x0, acc);
-      acc = fma((V)vq.y, x1, acc);
+      x2[0] = x[dec(c2.x)];
+      x2[1] = x[dec(c2.y)];
     }
-    if (u & 1)
-      acc = fma((V)__builtin_nontemporal_load(M.val + off1 + p), x[dec(__builtin_nontemporal_load(M.col16 + off1 + p))], acc);
+    if (u & 1) x1 = x[dec(c1)];
+#pragma unroll
+    for (int j = 0; j < U - 1; ++j)
+      if (j < rem)
+#pragma unroll
+        for (int e = 0; e < W; ++e) acc = fma((V)vr[j][e], xr[W * j + e], acc);
+    if (has2) {
+      acc = fma((V)v2.x, x2[0], acc);
+      acc = fma((V)v2.y, x2[1], acc);
+    }
+    if (u & 1) acc = fma((V)v1, x1, acc);
   } else {
     const IW *__restrict__ c = (const IW *)(M.col + beg + W * p);
     for (; k + U <= w; k += U) {
@@ -421,11 +449,16 @@ __device__ __forceinline__ T lds_row_dot(const SellD<T> &M, int s, int r, int su
 // One LDS tile of M.ts slices (every thread of the workgroup calls it; it holds
 // the workgroup barrier): when `stage`, the tile's band of x is copied into LDS
 // (coalesced loads of its windows, or of its listed columns); then the waves
-// take the tile's slices from a counter and call op(r, sub, dot) for each
-// lane's row r (group lane `sub`), dot = row r of M times x (0 when the tile
-// is not staged or the slice lies beyond M).
-template <typename T, int VL, typename Op>
-__device__ __forceinline__ void lds_tile(const SellD<T> &M, const T *__restrict__ x, bool stage, Op op) {
+// take the tile's slices from a counter and, for each lane's row r (group lane
+// `sub`), call pre(r, sub, q) (it loads the operands of the row's update into
+// q, so that their loads overlap the mat-vec's) and op(r, sub, dot, q), dot =
+// row r of M times x (0 when the tile is not staged or the slice lies beyond
+// M).  q lives across the slices (a field that pre leaves alone keeps its
+// earlier value): resetting it per slice would overwrite the registers of the
+// previous slice's loads and make the wave wait for all its memory operations,
+// stores included, first.
+template <typename T, int VL, typename Q, typename Pre, typename Op>
+__device__ __forceinline__ void lds_tile(const SellD<T> &M, const T *__restrict__ x, bool stage, Pre pre, Op op) {
   constexpr int NW = BAND_WINDOWS;
   __shared__ int next_slice;
   const int tile = xcd_block(), lane = threadIdx.x & 63, lg = M.lg;
@@ -433,6 +466,7 @@ __device__ __forceinline__ void lds_tile(const SellD<T> &M, const T *__restrict_
   const int n = stage && tile < M.ntiles ? d[2 * NW - 1] : 0;
   T *band = (T *)lds_band;
   if (threadIdx.x == 0) next_slice = 0;
+  Q q{};
   if (n > 0) {
     int lo[NW], end[NW];
 #pragma unroll
@@ -480,11 +514,12 @@ __device__ __forceinline__ void lds_tile(const SellD<T> &M, const T *__restrict_
     if (sl >= M.ts) break;
     const int s = tile * M.ts + sl;
     const int r = s * (64 >> lg) + (lane >> lg), sub = lane & ((1 << lg) - 1);
+    pre(r, sub, q);
     T dot = T(0);
     // a tile without nonzero entries: every product is +0 (as the sum of
     // zero terms from +0 is)
     if (n > 0 && s < M.nslices) dot = lds_row_dot<T, VL>(M, s, r, sub, band);
-    op(r, sub, dot);
+    op(r, sub, dot, q);
   }
 }
 
@@ -627,8 +662,37 @@ __global__ __launch_bounds__(WG, LV >= 0 ? LDS_WAVES : 1) void k_relax(SellD<T> 
   if constexpr (LV >= 0) {
     // tiles of rows >= nr relax nothing: no staging
     const bool stage = xcd_block() * ((64 * A.ts) >> A.lg) < nr;
-    lds_tile<T, LV>(A, u_in, stage,
-                                 [&](int i, int sub, T au) { row(i, sub, i < nr && relaxes(cls, want, i), au); });
+    struct Q {
+      bool act;
+      T f, d, u, t;
+    };
+    lds_tile<T, LV, Q>(
+        A, u_in, stage,
+        [&](int i, int sub, Q &q) {
+          q.act = false;
+          if (i < nb && sub == 0) {
+            q.u = u_in[i];
+            q.act = i < nr && relaxes(cls, want, i);
+            if (q.act) {
+              q.f = f[i];
+              q.d = dinv[i];
+              if (tmode == 1) q.t = t[i];
+            }
+          }
+        },
+        [&](int i, int sub, T au, const Q &q) {
+          // row() with the operands loaded beforehand (q.act only in the
+          // group's first lane, the one that stores)
+          if (q.act) {
+            const T d = (q.f - au) * q.d;
+            u_out[i] = q.u + d;
+            if (tmode == 0) t[i] = d;
+            else if (tmode == 1) t[i] = q.t + d;
+          } else if (i < nb && sub == 0) {
+            u_out[i] = q.u;
+            if (i < nr && tmode == 0) t[i] = T(0);
+          }
+        });
   } else {
     const int th = thread_id_wg<WG>(), i = th >> A.lg, sub = th & ((1 << A.lg) - 1);
     const bool act = i < nr && relaxes(cls, want, i);
@@ -645,7 +709,14 @@ __global__ __launch_bounds__(WG, LV >= 0 ? LDS_WAVES : 1) void k_w(SellD<T> A, i
     if (i < nb && sub == 0) sw[i] = has_s ? sw[i] + at : at;
   };
   if constexpr (LV >= 0) {
-    lds_tile<T, LV>(A, t, true, row);
+    lds_tile<T, LV, T>(
+        A, t, true,
+        [&](int i, int sub, T &s0) {
+          if (has_s && i < nb && sub == 0) s0 = sw[i];
+        },
+        [&](int i, int sub, T at, T s0) {
+          if (i < nb && sub == 0) sw[i] = has_s ? s0 + at : at;
+        });
   } else {
     const int th = thread_id_wg<WG>(), i = th >> A.lg, sub = th & ((1 << A.lg) - 1);
     if (i < nb) row(i, sub, sell_dot<T, T>(A, i, sub, t));
@@ -703,10 +774,27 @@ __global__ __launch_bounds__(WG, LV >= 0 ? LDS_WAVES : 1) void k_restrict_rows(S
     }
   };
   if constexpr (LV >= 0) {
-    lds_tile<T, LV>(Rt, w_prev, true, row);
+    lds_tile<T, LV, int>(
+        Rt, w_prev, true,
+        [&](int k, int sub, int &i) {
+          if (k < nb && sub == 0) i = perm[k];
+        },
+        [&](int k, int sub, T s, int i) {
+          if (k < nb && sub == 0) {
+            sw[i] = s;
+            if (i >= nr) u_out[i] = T(0);
+          }
+        });
   } else {
     const int th = thread_id_wg<WG>(), k = th >> Rt.lg, sub = th & ((1 << Rt.lg) - 1);
-    if (k < nb) row(k, sub, sell_dot<T, T>(Rt, k, sub, w_prev));
+    if (k < nb) {
+      const int i = perm[k];  // loaded before the mat-vec
+      const T s = sell_dot<T, T>(Rt, k, sub, w_prev);
+      if (sub == 0) {
+        sw[i] = s;
+        if (i >= nr) u_out[i] = T(0);
+      }
+    }
   }
 }
 
@@ -737,7 +825,33 @@ __global__ __launch_bounds__(WG, LV >= 0 ? LDS_WAVES : 1) void k_down_real(SellD
     }
   };
   if constexpr (LV >= 0) {
-    lds_tile<T, LV>(A, u_in, !first, row);
+    struct Q {
+      bool rel;
+      T f, s, d, t;
+    };
+    lds_tile<T, LV, Q>(
+        A, u_in, !first,
+        [&](int i, int sub, Q &q) {
+          if (i < nr && sub == 0) {
+            q.f = f[i];
+            q.s = sw[i];
+            q.rel = relaxes(cls, 1, i);
+            if (q.rel) q.d = dinv[i];
+            if (!first) q.t = t[i];
+          }
+        },
+        [&](int i, int sub, T au, const Q &q) {
+          // row() with the operands loaded beforehand
+          if (i < nr && sub == 0) {
+            T fi = q.f;
+            if (!first) fi -= au;
+            fi -= q.s;
+            f[i] = fi;
+            const T d = q.rel ? fi * q.d : T(0);
+            u_out[i] = d;
+            t[i] = first ? d : q.t + d;
+          }
+        });
   } else {
     const int th = thread_id_wg<WG>(), i = th >> A.lg, sub = th & ((1 << A.lg) - 1);
     if (i < nr) row(i, sub, first ? T(0) : sell_dot<T, T>(A, i, sub, u_in));
@@ -750,11 +864,11 @@ __global__ __launch_bounds__(WG) void k_interp_rows(SellD<T> Pt, const int *__re
                                                         T *__restrict__ u, const T *__restrict__ uc) {
   const int th = thread_id_wg<WG>(), k = th >> Pt.lg, sub = th & ((1 << Pt.lg) - 1);
   if (k < nb) {
+    // the row's target and old value are loaded before the mat-vec
+    const int i = perm[k];
+    const T ui = u[i];
     const T v = sell_dot<T, T>(Pt, k, sub, uc);
-    if (sub == 0) {
-      const int i = perm[k];
-      u[i] += v;
-    }
+    if (sub == 0) u[i] = ui + v;
   }
 }
 
