@@ -652,7 +652,10 @@ def main():
                        "dof_cycles_per_s": round(n * sum(ith) / dth, 1), "grids": sth["n_grids"],
                        "composite_overhead": round(sth["composite_overhead"], 4), "setup_s": round(hsetup, 2),
                        "device_gib": round(sth["device_bytes"] / 2**30, 3),
-                       "final_relres_fp64": residual_rel(p, xh.cpu().numpy())}
+                       "final_relres_fp64": residual_rel(p, xh.cpu().numpy()),
+                       "schedule": {"tail_level": sth["tail_level"], "tail_block": sth["tail_block"],
+                                    **{k: [l for l in range(32) if (sth[k] >> l) & 1]
+                                       for k in ("wide_levels", "lds_levels", "restrict_lds_levels")}}}
                 out["hybrid"].append(rec)
                 log(f"hybrid L~={lt}: {rec}")
                 del sh

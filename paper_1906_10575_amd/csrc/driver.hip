@@ -1108,10 +1108,22 @@ amgdd_status autotune(amgdd_ctx *h) {
     ms = (now_s() - tc) * 1e3;
     return AMGDD_OK;
   };
-  // first the cut level and the tail's workgroup size (default modes)
+  // levels of fewer rows than this take a few microseconds per pass whichever
+  // mode they run in: not tuned, left in the default modes
+  constexpr int kTuneMinRows = 32768;
+  // first the cut level and the tail's workgroup size, with LDS bands on the
+  // larger levels that have them (the modes that usually win there: cuts are
+  // compared against level-synchronous passes as the second phase is likely
+  // to leave them, not against their slowest form)
+  Modes base;
+  for (int l = 0; l < nlev && l < 32; ++l) {
+    if (h->lds_fixed || h->L[l].NBn < kTuneMinRows) continue;
+    if (h->L[l].band_max > 0) base.a |= 1u << l;
+    if (h->L[l].rband_max > 0 && h->L[l].rperm) base.r |= 1u << l;
+  }
   double best = 1e300;
   int best_l = -1, best_b = 256;
-  set_modes(Modes{});
+  set_modes(base);
   for (int lt : levels)
     for (int bs : blocks) {
       if (lt < 0 && bs != blocks[0]) continue;
@@ -1127,26 +1139,32 @@ amgdd_status autotune(amgdd_ctx *h) {
     }
   h->sched_level = best_l;
   h->sched_block = best_b;
+  {
+    // levels from the cut on run in the per-grid tail kernel: no modes
+    const int cut = best_l < 0 ? nlev : best_l;
+    const unsigned keep = cut >= 32 ? ~0u : (1u << cut) - 1u;
+    base.a &= keep;
+    base.r &= keep;
+    set_modes(base);
+  }
   // then, level by level above the cut, the modes of its level-synchronous
-  // passes: the current modes, 512-thread workgroups (more rows per workgroup
-  // share the L1 cache's gathered vector lines) and LDS bands (the operator
-  // passes and the restriction gather from LDS).  Each candidate is captured
-  // once; the captures are timed alternately, twice each, and a candidate is
-  // kept when its faster time beats the current one's by more than 0.1%.
-  // Every mode computes the same sums in the same order.
-  Modes cur;
+  // passes: the current modes, and each of them with one mode switched —
+  // 512-thread workgroups (more rows per workgroup share the L1 cache's
+  // gathered vector lines), LDS bands for the operator passes, LDS bands for
+  // the restriction.  Each candidate is captured once; the captures are timed
+  // alternately, twice each, and a candidate is kept when its faster time
+  // beats the current one's by more than 0.1%.  Every mode computes the same
+  // sums in the same order.
+  Modes cur = base;
   if (!h->wg_fixed || !h->lds_fixed) {
     const int cut = best_l < 0 ? nlev : best_l;
     for (int l = 0; l < std::min(cut, nlev) && l < 32; ++l) {
-      // levels of fewer rows than this take a few microseconds per pass
-      // whichever mode they run in: not tuned
-      constexpr int kTuneMinRows = 32768;
       if (h->L[l].NBn < kTuneMinRows) continue;
       const unsigned bit = 1u << l;
       std::vector<Modes> cand = {cur};
-      if (!h->wg_fixed) cand.push_back(Modes{cur.w | bit, cur.a, cur.r});
-      if (!h->lds_fixed && h->L[l].band_max > 0) cand.push_back(Modes{cur.w, cur.a | bit, cur.r});
-      if (!h->lds_fixed && h->L[l].rband_max > 0 && h->L[l].rperm) cand.push_back(Modes{cur.w, cur.a, cur.r | bit});
+      if (!h->wg_fixed) cand.push_back(Modes{cur.w ^ bit, cur.a, cur.r});
+      if (!h->lds_fixed && h->L[l].band_max > 0) cand.push_back(Modes{cur.w, cur.a ^ bit, cur.r});
+      if (!h->lds_fixed && h->L[l].rband_max > 0 && h->L[l].rperm) cand.push_back(Modes{cur.w, cur.a, cur.r ^ bit});
       if (cand.size() == 1) continue;
       std::vector<Captured> cap(cand.size());
       std::vector<double> t(cand.size(), 1e300);
@@ -1170,10 +1188,11 @@ amgdd_status autotune(amgdd_ctx *h) {
       if (!st) {
         for (size_t c = 1; c < cand.size(); ++c)
           if (t[c] < t[bi] && t[c] < t[0] * 0.999) bi = c;
-        // one more candidate: the modes that beat the current one, together
+        // one more candidate: the switches that beat the current modes, together
         Modes both = cand[bi];
         for (size_t c = 1; bi && c < cand.size(); ++c)
-          if (c != bi && t[c] < t[0] * 0.999) both = Modes{both.w | cand[c].w, both.a | cand[c].a, both.r | cand[c].r};
+          if (c != bi && t[c] < t[0] * 0.999)
+            both = Modes{both.w ^ (cand[c].w ^ cur.w), both.a ^ (cand[c].a ^ cur.a), both.r ^ (cand[c].r ^ cur.r)};
         if (bi && (both.w != cand[bi].w || both.a != cand[bi].a || both.r != cand[bi].r)) {
           cand.push_back(both);
           cap.emplace_back();
