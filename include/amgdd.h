@@ -45,7 +45,8 @@
  *   AMGDD_INDEX32         int32 column indices everywhere
  *   AMGDD_UNPAIRED        one entry per lane and load step everywhere
  *   AMGDD_QUAD            four entries per lane and load step everywhere
- *   AMGDD_SORT_WINDOW=n   row-sorting window on grouped levels (0: local order)
+ *   AMGDD_SORT_WINDOW=n   row-sorting window on grouped levels (default 512;
+ *                         0: local order)
  *   AMGDD_LANE_TARGET=x   entries per lane that set the lanes per composite row
  *   AMGDD_SERIAL          one stream per iteration (no side-stream branch)
  *   AMGDD_TEST_MAX_BYTES=n  device-memory cap (failure-path tests)

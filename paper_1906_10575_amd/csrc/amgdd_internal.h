@@ -163,7 +163,7 @@ struct Setup {
   int comp_step_log2 = 1;
   // on levels with grouped rows, each grid's real and ghost rows are sorted
   // by decreasing length within windows of this many rows (0: local order)
-  int sort_window = 128;
+  int sort_window = 512;
   // grouped composite rows: lanes per row = smallest power of two with at
   // most this many entries per lane (rows of up to 20 entries keep one lane)
   double comp_lane_target = 16.0;
