@@ -57,8 +57,8 @@
  *                         LDS / none does, instead of the tuned choice
  *   AMGDD_FUSED_R         restriction fused into the down pass with the
  *                         operator's row order and lanes (no reordered P, R)
- *   AMGDD_TIGHT_WINDOW=n  sort window of the reordered P and R (defaults 256
- *                         for P, 512 for R); AMGDD_TIGHT_WINDOW_R=n for R only
+ *   AMGDD_TIGHT_WINDOW=n  sort window of the reordered P and R (defaults 512
+ *                         for P, 1024 for R); AMGDD_TIGHT_WINDOW_R=n for R only
  *   AMGDD_TILE_SLICES_MAX=n, AMGDD_WIDE_TILES_MIN=m  LDS tiles of a level's
  *                         operator hold the largest power of two of slices
  *                         from n (16 to 128, default 32) down that leaves the

@@ -170,8 +170,8 @@ struct Setup {
   // separate reordered layouts of P and R for the level-synchronous passes
   // (see BatchLevel::Pt / Rt); the per-grid schedule keeps P and R
   bool tight = true;
-  int tight_window = 256;    // their sort windows (rows): P
-  int tight_window_r = 512;  // R
+  int tight_window = 512;     // their sort windows (rows): P
+  int tight_window_r = 1024;  // R
   // LDS bands of the composite operators (at most band_cap values per tile)
   bool bands = true;
   int band_cap = 8192;
