@@ -68,8 +68,12 @@ int main() {
           const int k = runs % 4;
           S.step_log2 = k == 1 ? 0 : (k == 2 ? 2 : 1);
           S.comp_step_log2 = k == 3 ? 2 : S.step_log2;
-          S.sort_window = k == 2 ? 0 : 128;
+          S.sort_window = k == 2 ? 0 : (k == 1 ? 512 : 128);
           S.compress = k != 3;
+          // LDS tiles of 16 to 128 slices on every level (bands that
+          // overflow the cap at the larger sizes fall back to smaller tiles)
+          S.tile_slices_max = 16 << (runs % 4);
+          S.wide_tiles_min = runs % 2 ? 0 : 2048;
           std::string err;
           int st;
           if (hybrid == 0) {
